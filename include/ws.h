@@ -1,0 +1,185 @@
+/*
+ * ws.h -- C ABI of the MI355X (gfx950) watershed / waterfall library.
+ *
+ * Implements the hot path of "Parallel Watershed Partitioning: GPU-Based
+ * Hierarchical Image Segmentation" (arXiv 2410.08946): gradient pre-processing,
+ * the watershed transform of Alg. 1 (Steps I-IV) and repeated waterfall levels
+ * (Section 4, Alg. 4 Step V and the hierarchical loop of Alg. 5).
+ *
+ * General conventions (every entry point):
+ *   - Images are C-contiguous with x fastest: pixel p = x + nx*(y + ny*z)
+ *     (the row-major pixel order Step I requires, Section 3.1). nz == 1 is a
+ *     2D image; ny == nz == 1 a 1D row (only the +-x neighbours exist).
+ *   - Pointers named img/grad/labels/out/mag/nregions are DEVICE pointers on
+ *     the context's device, allocated and owned by the caller. The library
+ *     never frees them and keeps no reference to them after the work it
+ *     enqueued has completed.
+ *   - `stream` is a hipStream_t (NULL = the default stream). Calls validate
+ *     their arguments synchronously, then enqueue work on `stream` and return.
+ *     Some calls wait on `stream` internally to read a convergence counter
+ *     (documented per call). Results are ready once `stream` has completed.
+ *   - Return value: WS_OK or a negative ws_status. On WS_EINVAL nothing was
+ *     written and nothing was launched. ws_last_error() gives a message.
+ *   - Calls on one context are not thread-safe; use one context per thread.
+ *   - Maximum size: nx*ny*nz < 2^31 (labels are int32 pixel indices).
+ */
+#ifndef WS_H
+#define WS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum ws_status {
+    WS_OK = 0,
+    WS_EINVAL = -1,       /* bad argument: nothing written, nothing launched */
+    WS_ENOMEM = -2,       /* device workspace allocation failed */
+    WS_EDEVICE = -3,      /* a HIP runtime call failed */
+    WS_ENOCONV = -4,      /* the Step II sweep cap was reached before convergence */
+    WS_EUNSUPPORTED = -5  /* valid request the library does not implement */
+};
+
+/* Grey-value types of a quantised gradient image. */
+enum ws_dtype {
+    WS_U8 = 1,   /* uint8_t,  values 0..255   */
+    WS_U16 = 2   /* uint16_t, values 0..65535 */
+};
+
+typedef struct ws_ctx ws_ctx;
+
+/*
+ * Create a context bound to HIP device `device`. The context owns all device
+ * scratch memory (grow-only; freed by ws_destroy). Returns WS_EINVAL for a bad
+ * device index or NULL ctx, WS_EDEVICE if the device cannot be used.
+ */
+int ws_create(ws_ctx **ctx, int device);
+
+/* Free the context and its device scratch memory. NULL is ignored. The
+ * caller must make sure no work of this context is still running. */
+void ws_destroy(ws_ctx *ctx);
+
+/* Message of the last failed call on this context ("" if none). With a NULL
+ * context: the message of the last argument error seen with no context. */
+const char *ws_last_error(const ws_ctx *ctx);
+
+/* Wait for `stream`; returns WS_EDEVICE if the device reported an error. */
+int ws_sync(ws_ctx *ctx, void *stream);
+
+/*
+ * Device bytes one watershed + waterfall job of this size needs beyond its
+ * inputs and outputs (the context's scratch), plus the job's own buffers
+ * (gradient, NL label layers). Pure host arithmetic; 0 on invalid sizes.
+ */
+size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int dtype, int NL);
+
+/*
+ * Gradient magnitude pre-processing (Introduction: smooth, then gradient
+ * magnitude; Fig. "PRUF pipeline" caption: both optional before Step I).
+ *   img    float32[N] input image.
+ *   sigma  Gaussian blur sigma; <= 0 skips the blur. The blur is separable,
+ *          radius floor(4*sigma + 0.5) (at most 64), weights exp(-k^2/2s^2)
+ *          normalised, borders mirrored half-sample-symmetrically.
+ *   dtype  WS_U8 or WS_U16: quantisation to 0..Q (Q = 255 or 65535) as
+ *          rint(mag * Q / max(mag)) (ties to even), all zero if max is 0.
+ *   grad   uint8_t[N] or uint16_t[N] output (device).
+ *   mag    optional float32[N] output of the unquantised magnitude.
+ * The magnitude is the unnormalised Sobel magnitude: per axis the taps
+ * [-1, 0, 1] along it and [1, 2, 1] along every other axis (2D: 3x3, 3D:
+ * 3x3x3), borders replicated. Arithmetic in float32; summation order per
+ * pixel is fixed, so results do not depend on launch configuration.
+ * Fully asynchronous (the maximum stays on the device).
+ */
+int ws_gradient(ws_ctx *ctx, const float *img, int64_t nx, int64_t ny, int64_t nz, float sigma,
+                int dtype, void *grad, float *mag_or_null, void *stream);
+
+/*
+ * Watershed transform (Alg. 1, Steps I-IV) of an integer gradient image.
+ *   grad    uint8_t[N] / uint16_t[N] grey values (read only).
+ *   conn    4 or 8 when nz == 1; 6 or 26 when nz > 1 (von Neumann / Moore
+ *           neighbourhoods of Section 3.1; out-of-image pixels are not
+ *           neighbours).
+ *   labels  int32[N] output: every pixel's catchment basin, named by the
+ *           smallest linear pixel index in that basin (canonical label).
+ * Arrows follow Eq. (1) (largest index among the lowest neighbours).
+ * Non-minimal plateau pixels point to the equal neighbour one geodesic step
+ * closer to the plateau's lower border, the smallest index among several
+ * (the fair split of Sections 3.3-3.4). Minimal plateaux form one basin each
+ * (Step IV). The result is a pure function of (grad, dims, conn).
+ * Waits on `stream` a few times to read the Step II convergence counter.
+ * Returns WS_ENOCONV if the sweep cap set with ws_set_option was reached.
+ */
+int ws_watershed(ws_ctx *ctx, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz,
+                 int conn, int32_t *labels, void *stream);
+
+/*
+ * Hierarchical waterfall (Section 4 / Alg. 5 layer loop): NL layers.
+ *   labels     int32[N] canonical watershed labels (layer 0); may alias out.
+ *   grad       the grey values the watershed was computed from (read only).
+ *   NL         number of layers >= 1, layer 0 included.
+ *   out        int32[NL*N] output, layer k at out + k*N, canonical labels.
+ *   nregions   optional int64[NL] device output: region count per layer.
+ * Layer k joins every region of layer k-1 with the region across its lowest
+ * boundary pass: key(R) = min over pixel pairs (p in R, q in N(p) outside R)
+ * of (max(I(p), I(q)), label(q)) compared lexicographically (Alg. 4 Step V
+ * height; ties broken by the smaller neighbouring label). Joined groups take
+ * their smallest label. Layers are nested and counts at least halve while
+ * more than one region remains. Fully asynchronous.
+ */
+int ws_waterfall(ws_ctx *ctx, const int32_t *labels, const void *grad, int dtype, int64_t nx,
+                 int64_t ny, int64_t nz, int conn, int NL, int32_t *out, int64_t *nregions_or_null,
+                 void *stream);
+
+/*
+ * Step-level outputs of the watershed for verification (Alg. 1, Steps I-II;
+ * balanced encoding of Section 3.4).
+ *   bal    int32[N]: -d for a non-minimal plateau pixel resolved at geodesic
+ *          distance d >= 1 from its plateau's lower border; otherwise the
+ *          Step I state (0 lower neighbour, 1 local minimum, 2/3 minimal
+ *          plateau pixel with / without an equal neighbour after it).
+ *   arrow  int32[N]: the pointer L after Step II (Eq. (1) target for states 0
+ *          and 2, itself for states 1 and 3, the chosen equal neighbour for a
+ *          resolved plateau pixel).
+ * Same waiting behaviour and errors as ws_watershed.
+ */
+int ws_watershed_stages(ws_ctx *ctx, const void *grad, int dtype, int64_t nx, int64_t ny,
+                        int64_t nz, int conn, int32_t *bal, int32_t *arrow, void *stream);
+
+/*
+ * Schedule options. None of them changes any result, only time.
+ *   "step3"        0 = per-pixel Find (APRUF, Section 3.2), 1 = RR pointer
+ *                  jumps per synchronisation (PRUF, Alg. 1 Step III).
+ *   "rr"           reduction rate for step3 = 1 (default 6, Section 5).
+ *   "sweep_batch"  Step II sweeps launched per convergence read (default 4).
+ *   "max_sweeps"   cap on Step II sweeps; reaching it returns WS_ENOCONV
+ *                  (default 2^31-1).
+ *   "timing"       1 = record a HIP event pair around every kernel launch.
+ * Returns WS_EINVAL for an unknown name or out-of-range value.
+ */
+int ws_set_option(ws_ctx *ctx, const char *name, int64_t value);
+
+/*
+ * Counters of the last ws_watershed call: out[0] Step II sweeps launched
+ * (including the initial tile pass), out[1] sweeps that changed a tile
+ * border, out[2] Step III synchronisations (step3 = 1), out[3] tiles.
+ * Returns the number of counters written (<= n).
+ */
+int ws_get_stats(const ws_ctx *ctx, int64_t *out, int n);
+
+/*
+ * Per-kernel timings recorded while the "timing" option was on, summed by
+ * kernel name since the last ws_timing_reset. Waits for all recorded events.
+ * Writes up to `cap` entries (name copied into names + i*name_len), returns
+ * the number of kernel names recorded, or a negative ws_status.
+ */
+int ws_timing_read(ws_ctx *ctx, char *names, int name_len, double *total_ms, int64_t *launches, int cap);
+int ws_timing_reset(ws_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WS_H */

@@ -1,0 +1,441 @@
+// api.hip -- the C ABI of libws (declared in include/ws.h): argument
+// validation, the context's grow-only device scratch, and the host-side
+// orchestration of the watershed (Alg. 1), waterfall (Section 4, Alg. 5 layer
+// loop) and gradient kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+
+#include "ws.h"
+#include "ws_kernels.h"
+
+using wsk::Geom;
+using wsk::Launch;
+
+namespace {
+
+constexpr int kCounterSlots = 64;   // Step II per-sweep change counters (ring)
+constexpr int kMaxSweepBatch = 32;
+
+struct Buf {
+    void *p = nullptr;
+    size_t n = 0;
+};
+
+thread_local std::string g_noctx_error;
+
+}  // namespace
+
+struct ws_ctx {
+    int device = 0;
+    std::string err;
+    Buf D, stamp, cnt;                    // watershed scratch
+    Buf key, par, lista, listb, wfcnt;    // waterfall scratch
+    Buf g0, g1, mag, gmax;                // gradient scratch
+    int32_t *host_cnt = nullptr;          // pinned readback of counters
+    int step3 = 0, rr = 6, sweep_batch = 4;
+    int64_t max_sweeps = 0x7fffffff;
+    bool timing = false;
+    wsk::TimingSink sink;
+    int64_t stats[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+int fail(ws_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    else g_noctx_error = msg;
+    return code;
+}
+
+int hip_fail(ws_ctx *c, hipError_t e, const char *where) {
+    return fail(c, WS_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int ensure(ws_ctx *c, Buf &b, size_t bytes, const char *what) {
+    if (bytes == 0) bytes = 256;
+    if (b.n >= bytes) return WS_OK;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.n = 0;
+        if (e != hipSuccess) return hip_fail(c, e, "hipFree");
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(c, WS_ENOMEM, std::string("cannot allocate ") + std::to_string(bytes) + " bytes for " + what);
+    }
+    b.n = bytes;
+    return WS_OK;
+}
+
+// Sizes: every dim >= 1, N < 2^31, and the tile grid fits the launch limits.
+bool valid_dims(int64_t nx, int64_t ny, int64_t nz, std::string &why) {
+    if (nx < 1 || ny < 1 || nz < 1) { why = "every dimension must be >= 1"; return false; }
+    if (nx >= (1LL << 31) || ny >= (1LL << 31) || nz >= (1LL << 31)) { why = "dimension too large"; return false; }
+    if (nx * ny >= (1LL << 31) || nx * ny * nz >= (1LL << 31)) { why = "nx*ny*nz must be < 2^31"; return false; }
+    return true;
+}
+
+bool valid_conn(int64_t nz, int conn) {
+    return nz == 1 ? (conn == 4 || conn == 8) : (conn == 6 || conn == 26);
+}
+
+Geom make_geom(int64_t nx, int64_t ny, int64_t nz, int ndim) {
+    Geom g;
+    g.nx = (int32_t)nx;
+    g.ny = (int32_t)ny;
+    g.nz = (int32_t)nz;
+    g.n = (int32_t)(nx * ny * nz);
+    int TX = ndim == 3 ? wsk::TileShape<3>::X : wsk::TileShape<2>::X;
+    int TY = ndim == 3 ? wsk::TileShape<3>::Y : wsk::TileShape<2>::Y;
+    int TZ = ndim == 3 ? wsk::TileShape<3>::Z : wsk::TileShape<2>::Z;
+    g.ntx = (int32_t)((nx + TX - 1) / TX);
+    g.nty = (int32_t)((ny + TY - 1) / TY);
+    g.ntz = (int32_t)((nz + TZ - 1) / TZ);
+    g.dnx = wsk::FastDiv((uint32_t)nx);
+    g.dny = wsk::FastDiv((uint32_t)ny);
+    return g;
+}
+
+int set_device(ws_ctx *c) {
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    return WS_OK;
+}
+
+Launch make_launch(ws_ctx *c, void *stream) {
+    Launch lc;
+    lc.stream = (hipStream_t)stream;
+    lc.timing = c->timing ? &c->sink : nullptr;
+    return lc;
+}
+
+#define WS_TRY(expr)                                                      \
+    do {                                                                  \
+        int _rc = (expr);                                                 \
+        if (_rc != 0) {                                                   \
+            if (_rc == -3) return hip_fail(c, lc.last, "kernel launch");  \
+            return fail(c, WS_EINVAL, "unsupported configuration");       \
+        }                                                                 \
+    } while (0)
+
+// Step II to convergence: the initial tile pass, then batches of sweeps with
+// one counter read-back per batch. Leaves D converged in c->D.
+int run_distances(ws_ctx *c, Launch &lc, const Geom &g, int conn, bool u16, const void *grad) {
+    int32_t ntiles = g.ntx * g.nty * g.ntz;
+    size_t N = (size_t)g.n;
+    int rc;
+    if ((rc = ensure(c, c->D, N * 4, "distances")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->stamp, (size_t)ntiles * 4, "tile stamps")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->cnt, kCounterSlots * 4, "counters")) != WS_OK) return rc;
+    int32_t *D = (int32_t *)c->D.p, *stamp = (int32_t *)c->stamp.p, *cnt = (int32_t *)c->cnt.p;
+    WS_TRY(wsk::launch_fill_i32(lc, stamp, ntiles, -1));
+    WS_TRY(wsk::launch_fill_i32(lc, cnt, kCounterSlots, 0));
+    WS_TRY(wsk::launch_ws_init(lc, g, conn, u16, grad, D, stamp, cnt));
+    int64_t launched = 1, changing = 0;
+    int32_t s = 1;
+    bool first = true;
+    int batch = std::max(1, std::min(c->sweep_batch, kMaxSweepBatch));
+    for (;;) {
+        if (!first) WS_TRY(wsk::launch_fill_i32(lc, cnt, kCounterSlots, 0));
+        int32_t s0 = s;
+        for (int b = 0; b < batch; ++b, ++s) WS_TRY(wsk::launch_ws_sweep(lc, g, conn, u16, grad, D, stamp, cnt + (s % kCounterSlots), s));
+        launched += batch;
+        hipError_t e = hipMemcpyAsync(c->host_cnt, cnt, kCounterSlots * 4, hipMemcpyDeviceToHost, lc.stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+        e = hipStreamSynchronize(lc.stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+        bool done = false;
+        if (first) {
+            if (c->host_cnt[0] == 0) done = true;
+            else changing = 1;
+        }
+        for (int32_t t = s0; !done && t < s; ++t) {
+            if (c->host_cnt[t % kCounterSlots] == 0) done = true;
+            else ++changing;
+        }
+        first = false;
+        if (done) break;
+        if (changing >= c->max_sweeps) {
+            c->stats[0] = launched;
+            c->stats[1] = changing;
+            return fail(c, WS_ENOCONV, "Step II did not converge within max_sweeps");
+        }
+    }
+    c->stats[0] = launched;
+    c->stats[1] = changing;
+    c->stats[3] = ntiles;
+    return WS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ws_create(ws_ctx **out, int device) {
+    if (!out) return fail(nullptr, WS_EINVAL, "ws_create: ctx is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return fail(nullptr, WS_EDEVICE, std::string("hipGetDeviceCount: ") + hipGetErrorString(e));
+    if (device < 0 || device >= n) return fail(nullptr, WS_EINVAL, "ws_create: bad device index");
+    ws_ctx *c = new ws_ctx();
+    c->device = device;
+    if ((e = hipSetDevice(device)) != hipSuccess) {
+        delete c;
+        return fail(nullptr, WS_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    }
+    if ((e = hipHostMalloc((void **)&c->host_cnt, kCounterSlots * 4, hipHostMallocDefault)) != hipSuccess) {
+        delete c;
+        return fail(nullptr, WS_EDEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return WS_OK;
+}
+
+void ws_destroy(ws_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    Buf *bufs[] = {&c->D, &c->stamp, &c->cnt, &c->key, &c->par, &c->lista, &c->listb, &c->wfcnt,
+                   &c->g0, &c->g1, &c->mag, &c->gmax};
+    for (Buf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    for (auto &r : c->sink.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (auto e : c->sink.pool) (void)hipEventDestroy(e);
+    if (c->host_cnt) (void)hipHostFree(c->host_cnt);
+    delete c;
+}
+
+const char *ws_last_error(const ws_ctx *c) { return c ? c->err.c_str() : g_noctx_error.c_str(); }
+
+int ws_sync(ws_ctx *c, void *stream) {
+    if (!c) return fail(nullptr, WS_EINVAL, "ws_sync: ctx is NULL");
+    int rc = set_device(c);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    return WS_OK;
+}
+
+size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int dtype, int NL) {
+    std::string why;
+    if (!valid_dims(nx, ny, nz, why) || (dtype != WS_U8 && dtype != WS_U16) || NL < 1) return 0;
+    size_t N = (size_t)(nx * ny * nz);
+    size_t b = dtype == WS_U8 ? 1 : 2;
+    size_t job = N * (b + 4 * (size_t)NL);
+    size_t scratch = N * 4 /* D */ + N * 8 /* keys */ + N * 4 /* parents */ + N * 8 /* region lists */;
+    return job + scratch + (1 << 20);
+}
+
+int ws_set_option(ws_ctx *c, const char *name, int64_t v) {
+    if (!c || !name) return fail(c, WS_EINVAL, "ws_set_option: NULL argument");
+    std::string k(name);
+    if (k == "step3" && (v == 0 || v == 1)) c->step3 = (int)v;
+    else if (k == "rr" && v >= 1 && v <= 64) c->rr = (int)v;
+    else if (k == "sweep_batch" && v >= 1 && v <= kMaxSweepBatch) c->sweep_batch = (int)v;
+    else if (k == "max_sweeps" && v >= 1) c->max_sweeps = v;
+    else if (k == "timing" && (v == 0 || v == 1)) c->timing = v != 0;
+    else return fail(c, WS_EINVAL, "ws_set_option: unknown option or value out of range: " + k);
+    return WS_OK;
+}
+
+int ws_get_stats(const ws_ctx *c, int64_t *out, int n) {
+    if (!c || !out || n < 0) return WS_EINVAL;
+    int m = std::min(n, 4);
+    for (int i = 0; i < m; ++i) out[i] = c->stats[i];
+    return m;
+}
+
+int ws_gradient(ws_ctx *c, const float *img, int64_t nx, int64_t ny, int64_t nz, float sigma, int dtype, void *grad,
+                float *mag_or_null, void *stream) {
+    std::string why;
+    if (!c) return fail(c, WS_EINVAL, "ws_gradient: ctx is NULL");
+    if (!img || !grad) return fail(c, WS_EINVAL, "ws_gradient: NULL buffer");
+    if (!valid_dims(nx, ny, nz, why)) return fail(c, WS_EINVAL, "ws_gradient: " + why);
+    if (dtype != WS_U8 && dtype != WS_U16) return fail(c, WS_EINVAL, "ws_gradient: dtype must be WS_U8 or WS_U16");
+    if (!(sigma == sigma)) return fail(c, WS_EINVAL, "ws_gradient: sigma is NaN");
+    int r = sigma > 0.f ? (int)(4.0 * (double)sigma + 0.5) : 0;
+    if (r > 64) return fail(c, WS_EUNSUPPORTED, "ws_gradient: blur radius above 64 (sigma > 15.9)");
+    int rc = set_device(c);
+    if (rc) return rc;
+    int ndim = nz > 1 ? 3 : 2;
+    Geom g = make_geom(nx, ny, nz, ndim);
+    size_t N = (size_t)g.n;
+    Launch lc = make_launch(c, stream);
+    const float *src = img;
+    if (r > 0) {
+        if ((rc = ensure(c, c->g0, N * 4, "blur buffer")) != WS_OK) return rc;
+        if ((rc = ensure(c, c->g1, N * 4, "blur buffer")) != WS_OK) return rc;
+        wsk::BlurTaps taps;
+        taps.r = r;
+        double w[129], sum = 0.0;
+        for (int k = -r; k <= r; ++k) { w[k + r] = exp(-0.5 * (double)k * (double)k / ((double)sigma * (double)sigma)); sum += w[k + r]; }
+        for (int k = 0; k <= 2 * r; ++k) taps.w[k] = (float)(w[k] / sum);
+        float *bufs[2] = {(float *)c->g0.p, (float *)c->g1.p};
+        for (int ax = 0; ax < ndim; ++ax) {
+            float *dst = bufs[ax & 1];
+            WS_TRY(wsk::launch_grad_blur(lc, g, src, dst, ax, taps));
+            src = dst;
+        }
+    }
+    float *mag = mag_or_null;
+    if (!mag) {
+        if ((rc = ensure(c, c->mag, N * 4, "magnitude buffer")) != WS_OK) return rc;
+        mag = (float *)c->mag.p;
+    }
+    if ((rc = ensure(c, c->gmax, 256, "maximum")) != WS_OK) return rc;
+    unsigned int *mx = (unsigned int *)c->gmax.p;
+    WS_TRY(wsk::launch_grad_zero_max(lc, mx));
+    WS_TRY(wsk::launch_grad_sobel(lc, g, ndim, src, mag, mx));
+    WS_TRY(wsk::launch_grad_quant(lc, g.n, dtype == WS_U16, mag, grad, mx));
+    return WS_OK;
+}
+
+static int ws_validate_ws(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz, int conn,
+                          const void *out, const char *who) {
+    std::string why;
+    if (!c) return fail(c, WS_EINVAL, std::string(who) + ": ctx is NULL");
+    if (!grad || !out) return fail(c, WS_EINVAL, std::string(who) + ": NULL buffer");
+    if (!valid_dims(nx, ny, nz, why)) return fail(c, WS_EINVAL, std::string(who) + ": " + why);
+    if (dtype != WS_U8 && dtype != WS_U16) return fail(c, WS_EINVAL, std::string(who) + ": dtype must be WS_U8 or WS_U16");
+    if (!valid_conn(nz, conn))
+        return fail(c, WS_EINVAL, std::string(who) + ": conn must be 4 or 8 for 2D (nz == 1) and 6 or 26 for 3D");
+    return WS_OK;
+}
+
+int ws_watershed(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz, int conn, int32_t *labels,
+                 void *stream) {
+    int rc = ws_validate_ws(c, grad, dtype, nx, ny, nz, conn, labels, "ws_watershed");
+    if (rc) return rc;
+    if ((rc = set_device(c))) return rc;
+    int ndim = nz > 1 ? 3 : 2;
+    Geom g = make_geom(nx, ny, nz, ndim);
+    Launch lc = make_launch(c, stream);
+    bool u16 = dtype == WS_U16;
+    c->stats[2] = 0;
+    if ((rc = run_distances(c, lc, g, conn, u16, grad)) != WS_OK) return rc;
+    const int32_t *D = (const int32_t *)c->D.p;
+    WS_TRY(wsk::launch_ws_label(lc, g, conn, u16, grad, D, labels));
+    WS_TRY(wsk::launch_ws_merge(lc, g, conn, u16, grad, D, labels));
+    if (c->step3 == 0) {
+        WS_TRY(wsk::launch_ws_find(lc, g.n, labels));
+    } else {
+        int32_t *cnt = (int32_t *)c->cnt.p;
+        int64_t syncs = 0;
+        for (;;) {
+            WS_TRY(wsk::launch_fill_i32(lc, cnt, 1, 0));
+            WS_TRY(wsk::launch_ws_jump(lc, g.n, labels, c->rr, cnt));
+            hipError_t e = hipMemcpyAsync(c->host_cnt, cnt, 4, hipMemcpyDeviceToHost, lc.stream);
+            if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+            if ((e = hipStreamSynchronize(lc.stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+            if (c->host_cnt[0] == 0) break;
+            ++syncs;
+        }
+        c->stats[2] = syncs;
+    }
+    return WS_OK;
+}
+
+int ws_watershed_stages(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz, int conn,
+                        int32_t *bal, int32_t *arrow, void *stream) {
+    int rc = ws_validate_ws(c, grad, dtype, nx, ny, nz, conn, bal, "ws_watershed_stages");
+    if (rc) return rc;
+    if (!arrow) return fail(c, WS_EINVAL, "ws_watershed_stages: NULL buffer");
+    if ((rc = set_device(c))) return rc;
+    int ndim = nz > 1 ? 3 : 2;
+    Geom g = make_geom(nx, ny, nz, ndim);
+    Launch lc = make_launch(c, stream);
+    bool u16 = dtype == WS_U16;
+    if ((rc = run_distances(c, lc, g, conn, u16, grad)) != WS_OK) return rc;
+    WS_TRY(wsk::launch_ws_stages(lc, g, conn, u16, grad, (const int32_t *)c->D.p, bal, arrow));
+    return WS_OK;
+}
+
+int ws_waterfall(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz,
+                 int conn, int NL, int32_t *out, int64_t *nregions, void *stream) {
+    int rc = ws_validate_ws(c, grad, dtype, nx, ny, nz, conn, out, "ws_waterfall");
+    if (rc) return rc;
+    if (!labels) return fail(c, WS_EINVAL, "ws_waterfall: NULL labels");
+    if (NL < 1) return fail(c, WS_EINVAL, "ws_waterfall: NL must be >= 1");
+    if ((rc = set_device(c))) return rc;
+    int ndim = nz > 1 ? 3 : 2;
+    Geom g = make_geom(nx, ny, nz, ndim);
+    size_t N = (size_t)g.n;
+    Launch lc = make_launch(c, stream);
+    bool u16 = dtype == WS_U16;
+    if ((rc = ensure(c, c->key, N * 8, "region keys")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->par, N * 4, "region parents")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->lista, N * 4, "region list")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->listb, N * 4, "region list")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->wfcnt, (size_t)NL * 4, "region counts")) != WS_OK) return rc;
+    uint64_t *key = (uint64_t *)c->key.p;
+    int32_t *par = (int32_t *)c->par.p, *cnt = (int32_t *)c->wfcnt.p;
+    int32_t *lists[2] = {(int32_t *)c->lista.p, (int32_t *)c->listb.p};
+    if (labels != out) {
+        hipError_t e = hipMemcpyAsync(out, labels, N * 4, hipMemcpyDeviceToDevice, lc.stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+    }
+    WS_TRY(wsk::launch_fill_i32(lc, cnt, NL, 0));
+    WS_TRY(wsk::launch_wf_init(lc, g.n, out, lists[0], cnt, key, par));
+    for (int k = 1; k < NL; ++k) {
+        const int32_t *prev = out + (size_t)(k - 1) * N;
+        int32_t *cur = out + (size_t)k * N;
+        int32_t *lin = lists[(k - 1) & 1], *lout = lists[k & 1];
+        WS_TRY(wsk::launch_wf_edge(lc, g, conn, u16, grad, prev, key));
+        WS_TRY(wsk::launch_wf_union(lc, g.n, lin, cnt + k - 1, key, par));
+        WS_TRY(wsk::launch_wf_compress(lc, g.n, lin, cnt + k - 1, par));
+        WS_TRY(wsk::launch_wf_compact(lc, g.n, lin, cnt + k - 1, lout, cnt + k, par, key));
+        WS_TRY(wsk::launch_wf_relabel(lc, g.n, prev, cur, par));
+    }
+    if (nregions) WS_TRY(wsk::launch_wf_counts(lc, NL, cnt, nregions));
+    return WS_OK;
+}
+
+int ws_timing_reset(ws_ctx *c) {
+    if (!c) return WS_EINVAL;
+    for (auto &r : c->sink.recs) {
+        c->sink.pool.push_back(r.a);
+        c->sink.pool.push_back(r.b);
+    }
+    c->sink.recs.clear();
+    return WS_OK;
+}
+
+int ws_timing_read(ws_ctx *c, char *names, int name_len, double *total_ms, int64_t *launches, int cap) {
+    if (!c) return WS_EINVAL;
+    std::map<std::string, std::pair<double, int64_t>> agg;
+    std::vector<std::string> order;
+    for (auto &r : c->sink.recs) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+        if (!agg.count(r.name)) order.push_back(r.name);
+        agg[r.name].first += ms;
+        agg[r.name].second += 1;
+    }
+    int i = 0;
+    for (auto &nm : order) {
+        if (i < cap) {
+            if (names && name_len > 0) {
+                strncpy(names + (size_t)i * name_len, nm.c_str(), name_len - 1);
+                names[(size_t)i * name_len + name_len - 1] = 0;
+            }
+            if (total_ms) total_ms[i] = agg[nm].first;
+            if (launches) launches[i] = agg[nm].second;
+        }
+        ++i;
+    }
+    return i;
+}
+
+}  // extern "C"

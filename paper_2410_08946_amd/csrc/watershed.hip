@@ -1,0 +1,512 @@
+// watershed.hip -- gfx950 kernels of the watershed transform (Alg. 1).
+//
+// Data on the device (all int32 unless noted, N pixels each):
+//   I  grey values (uint8/uint16), read only
+//   D  Step II distance field: 0 for pixels with a lower neighbour (state 0)
+//      and for strict local minima (state 1); d >= 1 for a non-minimal
+//      plateau pixel at geodesic distance d from its plateau's lower border;
+//      INF for pixels of minimal plateaux (states 2/3 that Step II never
+//      resolves).
+//   L  labels / union-find parents (parent <= pixel, roots are self loops).
+//
+// Step II is computed as the unique fixpoint of
+//   D(p) = 1 + min{ D(q) : q in N(p), I(q) = I(p) }      (plateau pixels)
+// which both the synchronous sweeps of Section 3.3 and the balanced
+// block-asynchronous sweeps of Section 3.4 (Alg. 3) converge to. Tiles relax
+// to a local fixpoint in LDS with frozen halos; a tile re-runs only when a
+// neighbouring tile changed one of its border distances (tile "stamps").
+//
+// Arrows (Eq. (1) for pixels with a lower neighbour; the equal neighbour at
+// distance d-1 with the smallest index for resolved plateau pixels) and the
+// adjacency of minimal-plateau pixels (Step IV's union pairs) are then
+// contracted by union-find: inside each tile in LDS, then across tile borders
+// in global memory, then a final Find (path reduction, Step III). Because
+// unions always hook the larger root below the smaller, every basin ends with
+// its smallest pixel index as root: the canonical label.
+#include "ws_device.h"
+#include "ws_kernels.h"
+
+namespace wsk {
+
+// ---------------------------------------------------------------------------
+// Tile helpers
+// ---------------------------------------------------------------------------
+template <int NDIM>
+__device__ __forceinline__ void tile_origin(const Geom &g, int t, int &ox, int &oy, int &oz) {
+    using TS = TileShape<NDIM>;
+    int tx = t % g.ntx;
+    int r = t / g.ntx;
+    int ty = r % g.nty;
+    int tz = r / g.nty;
+    ox = tx * TS::X;
+    oy = ty * TS::Y;
+    oz = tz * TS::Z;
+}
+
+// Loads grey values of the tile plus a ring of width R into LDS as int32;
+// cells outside the image get SENT.
+template <int NDIM, int R, typename T>
+__device__ __forceinline__ void load_grey(const Geom &g, const T *__restrict__ I, int *sI, int ox, int oy, int oz) {
+    using S = Lds<NDIM, R>;
+    for (int c = threadIdx.x; c < S::CELLS; c += NTHREADS) {
+        int cx = c % S::SX, cy = (c / S::SX) % S::SY, cz = c / (S::SX * S::SY);
+        int x = ox + cx - R, y = oy + cy - R, z = oz + cz - S::RZ;
+        int v = SENT;
+        if (in_image(g, x, y, z)) v = (int)I[x + g.nx * (y + g.ny * z)];
+        sI[c] = v;
+    }
+}
+
+// Loads D of the tile plus a ring of width 1; cells outside the image get INF.
+template <int NDIM>
+__device__ __forceinline__ void load_dist(const Geom &g, const int32_t *__restrict__ D, int *sD, int ox, int oy, int oz) {
+    using S = Lds<NDIM, 1>;
+    for (int c = threadIdx.x; c < S::CELLS; c += NTHREADS) {
+        int cx = c % S::SX, cy = (c / S::SX) % S::SY, cz = c / (S::SX * S::SY);
+        int x = ox + cx - 1, y = oy + cy - 1, z = oz + cz - S::RZ;
+        int v = INF;
+        if (in_image(g, x, y, z)) v = D[x + g.nx * (y + g.ny * z)];
+        sD[c] = v;
+    }
+}
+
+// Relaxes the plateau distances of the tile's pixels to a local fixpoint
+// (ring cells frozen). Returns after an iteration in which no thread changed
+// anything. Gauss-Seidel order inside LDS; any order reaches the same fixpoint
+// because distances only decrease and every value stays an upper bound.
+template <int NDIM, int CONN, int R>
+__device__ __forceinline__ void relax_tile(int *sI, int *sD) {
+    using TS = TileShape<NDIM>;
+    using S = Lds<NDIM, R>;
+    constexpr int PIX = TS::X * TS::Y * TS::Z;
+    constexpr int NB = CONN;
+    for (;;) {
+        int changed = 0;
+        for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
+            int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+            int s = S::at(x, y, z);
+            int d = sD[s];
+            if (d == 0) continue;          // fixed (lower neighbour / minimum) or
+            int v = sI[s];                 // out of image (d == INF, v == SENT)
+            if (v == SENT) continue;
+            int best = d;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                int o = s + S::template off<CONN>(k);
+                int dq = sD[o];
+                if (sI[o] == v && dq != INF && dq + 1 < best) best = dq + 1;
+            }
+            if (best < d) { sD[s] = best; changed = 1; }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+}
+
+template <int NDIM>
+__device__ __forceinline__ bool on_tile_border(int x, int y, int z) {
+    using TS = TileShape<NDIM>;
+    bool b = x == 0 || x == TS::X - 1 || y == 0 || y == TS::Y - 1;
+    if (NDIM == 3) b = b || z == 0 || z == TS::Z - 1;
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// Step I + first Step II pass: initial distances of the tile and its ring
+// (0 = has a lower neighbour or no equal one, INF = plateau pixel), then a
+// local fixpoint. Stamps the tile with sweep 0 when a border pixel obtained a
+// finite distance its neighbours could not have known.
+// ---------------------------------------------------------------------------
+template <int NDIM, int CONN, typename T>
+__global__ __launch_bounds__(NTHREADS) void k_ws_init(Geom g, const T *__restrict__ I, int32_t *__restrict__ D,
+                                                      int32_t *__restrict__ stamp, int32_t *__restrict__ changed) {
+    using TS = TileShape<NDIM>;
+    using S2 = Lds<NDIM, 2>;
+    constexpr int PIX = TS::X * TS::Y * TS::Z;
+    __shared__ int sI[S2::CELLS];
+    __shared__ int sD[S2::CELLS];
+    int ox, oy, oz;
+    tile_origin<NDIM>(g, blockIdx.x, ox, oy, oz);
+    load_grey<NDIM, 2, T>(g, I, sI, ox, oy, oz);
+    __syncthreads();
+    // Initial distances on the tile plus a ring of width 1 (Step I state test).
+    using S1 = Lds<NDIM, 1>;
+    for (int c = threadIdx.x; c < S1::CELLS; c += NTHREADS) {
+        int cx = c % S1::SX, cy = (c / S1::SX) % S1::SY, cz = c / (S1::SX * S1::SY);
+        int s = S2::at(cx - 1, cy - 1, cz - S1::RZ);
+        int v = sI[s];
+        int d = INF;
+        if (v != SENT) {
+            int m = SENT;
+#pragma unroll
+            for (int k = 0; k < CONN; ++k) m = min(m, sI[s + S2::template off<CONN>(k)]);
+            d = (m == v) ? INF : 0;
+        }
+        sD[s] = d;
+    }
+    __syncthreads();
+    relax_tile<NDIM, CONN, 2>(sI, sD);
+    int border = 0;
+    for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
+        int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+        int gx = ox + x, gy = oy + y, gz = oz + z;
+        if (!in_image(g, gx, gy, gz)) continue;
+        int d = sD[S2::at(x, y, z)];
+        D[gx + g.nx * (gy + g.ny * gz)] = d;
+        if (d != 0 && d != INF && on_tile_border<NDIM>(x, y, z)) border = 1;
+    }
+    if (__syncthreads_or(border) && threadIdx.x == 0) {
+        stamp[blockIdx.x] = 0;
+        atomicAdd(changed, 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step II sweep s >= 1: tiles next to a tile stamped in sweep s-1 reload their
+// ring from global memory and relax again.
+// ---------------------------------------------------------------------------
+template <int NDIM, int CONN, typename T>
+__global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Geom g, const T *__restrict__ I, int32_t *__restrict__ D,
+                                                       int32_t *__restrict__ stamp, int32_t *__restrict__ changed,
+                                                       int32_t s) {
+    using TS = TileShape<NDIM>;
+    using S = Lds<NDIM, 1>;
+    constexpr int PIX = TS::X * TS::Y * TS::Z;
+    constexpr int PER = (PIX + NTHREADS - 1) / NTHREADS;
+    __shared__ int sI[S::CELLS];
+    __shared__ int sD[S::CELLS];
+    int t = blockIdx.x;
+    int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+    int active = 0;
+    {
+        int j = threadIdx.x;  // one neighbouring tile per thread
+        if (j < 27) {
+            int dx = j % 3 - 1, dy = (j / 3) % 3 - 1, dz = j / 9 - 1;
+            int ux = tx + dx, uy = ty + dy, uz = tz + dz;
+            bool used = (NDIM == 3 || dz == 0) && (dx != 0 || dy != 0 || dz != 0);
+            if (used && ux >= 0 && ux < g.ntx && uy >= 0 && uy < g.nty && uz >= 0 && uz < g.ntz)
+                active = stamp[ux + g.ntx * (uy + g.nty * uz)] == s - 1;
+        }
+    }
+    if (!__syncthreads_or(active)) return;
+    int ox = tx * TS::X, oy = ty * TS::Y, oz = tz * TS::Z;
+    load_grey<NDIM, 1, T>(g, I, sI, ox, oy, oz);
+    load_dist<NDIM>(g, D, sD, ox, oy, oz);
+    __syncthreads();
+    int before[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int i = threadIdx.x + j * NTHREADS;
+        before[j] = INF;
+        if (i < PIX) {
+            int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+            before[j] = sD[S::at(x, y, z)];
+        }
+    }
+    relax_tile<NDIM, CONN, 1>(sI, sD);
+    int border = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int i = threadIdx.x + j * NTHREADS;
+        if (i >= PIX) continue;
+        int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+        int gx = ox + x, gy = oy + y, gz = oz + z;
+        if (!in_image(g, gx, gy, gz)) continue;
+        int d = sD[S::at(x, y, z)];
+        if (d != before[j]) {
+            D[gx + g.nx * (gy + g.ny * gz)] = d;
+            if (on_tile_border<NDIM>(x, y, z)) border = 1;
+        }
+    }
+    if (__syncthreads_or(border) && threadIdx.x == 0) {
+        stamp[t] = s;
+        atomicAdd(changed, 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Arrow of one pixel from LDS (ring width 1). Returns the neighbour index k
+// the pixel points to, -1 for a root (local minimum), -2 for a minimal
+// plateau pixel (joined with its equal neighbours instead).
+// ---------------------------------------------------------------------------
+template <int NDIM, int CONN>
+__device__ __forceinline__ int lds_arrow(const int *sI, const int *sD, int s) {
+    using S = Lds<NDIM, 1>;
+    int v = sI[s], d = sD[s];
+    if (d == INF) return -2;
+    if (d == 0) {
+        int m = SENT, kq = -1;
+#pragma unroll
+        for (int k = 0; k < CONN; ++k) {
+            int w = sI[s + S::template off<CONN>(k)];
+            if (w <= m) { m = w; kq = k; }     // Eq. (1): last of the lowest
+        }
+        return (m < v) ? kq : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < CONN; ++k) {           // first (smallest index) equal
+        int o = s + S::template off<CONN>(k);  // neighbour one step closer
+        if (sI[o] == v && sD[o] == d - 1) return k;
+    }
+    return -1;  // unreachable for a converged distance field
+}
+
+// ---------------------------------------------------------------------------
+// Tile-local union-find of arrows and minimal-plateau adjacencies; writes the
+// tile-local root (as a global pixel index) of every pixel into L.
+// ---------------------------------------------------------------------------
+template <int NDIM, int CONN, typename T>
+__global__ __launch_bounds__(NTHREADS) void k_ws_label(Geom g, const T *__restrict__ I, const int32_t *__restrict__ D,
+                                                       int32_t *__restrict__ L) {
+    using TS = TileShape<NDIM>;
+    using S = Lds<NDIM, 1>;
+    constexpr int PIX = TS::X * TS::Y * TS::Z;
+    __shared__ int sI[S::CELLS];
+    __shared__ int sD[S::CELLS];
+    __shared__ int sP[PIX];
+    int ox, oy, oz;
+    tile_origin<NDIM>(g, blockIdx.x, ox, oy, oz);
+    load_grey<NDIM, 1, T>(g, I, sI, ox, oy, oz);
+    load_dist<NDIM>(g, D, sD, ox, oy, oz);
+    for (int i = threadIdx.x; i < PIX; i += NTHREADS) sP[i] = i;
+    __syncthreads();
+    for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
+        int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+        if (!in_image(g, ox + x, oy + y, oz + z)) continue;
+        int s = S::at(x, y, z);
+        int k = lds_arrow<NDIM, CONN>(sI, sD, s);
+        if (k >= 0) {
+            int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
+            if (xx >= 0 && xx < TS::X && yy >= 0 && yy < TS::Y && zz >= 0 && zz < TS::Z)
+                lunion(sP, i, xx + TS::X * (yy + TS::Y * zz));
+        } else if (k == -2) {
+            int v = sI[s];
+#pragma unroll
+            for (int k2 = CONN / 2; k2 < CONN; ++k2) {  // neighbours after p only
+                int xx = x + nb_dx<CONN>(k2), yy = y + nb_dy<CONN>(k2), zz = z + nb_dz<CONN>(k2);
+                if (xx < 0 || xx >= TS::X || yy < 0 || yy >= TS::Y || zz < 0 || zz >= TS::Z) continue;
+                if (sI[s + S::template off<CONN>(k2)] == v) lunion(sP, i, xx + TS::X * (yy + TS::Y * zz));
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
+        int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+        int gx = ox + x, gy = oy + y, gz = oz + z;
+        if (!in_image(g, gx, gy, gz)) continue;
+        int r = lfind(sP, i);
+        int rx = r % TS::X, ry = (r / TS::X) % TS::Y, rz = r / (TS::X * TS::Y);
+        L[gx + g.nx * (gy + g.ny * gz)] = (ox + rx) + g.nx * ((oy + ry) + g.ny * (oz + rz));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Arrow of one pixel from global memory (same rules as lds_arrow).
+// Returns the target pixel, -1 for a root, -2 for a minimal plateau pixel.
+// ---------------------------------------------------------------------------
+template <int CONN, typename T>
+__device__ __forceinline__ int32_t glb_arrow(const Geom &g, const T *__restrict__ I, const int32_t *__restrict__ D,
+                                             int x, int y, int z, int32_t p, int32_t *state_out) {
+    int v = I[p], d = D[p];
+    int m = SENT;
+    int32_t q = -1;
+#pragma unroll
+    for (int k = 0; k < CONN; ++k) {
+        int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
+        if (!in_image(g, xx, yy, zz)) continue;
+        int32_t r = xx + g.nx * (yy + g.ny * zz);
+        int w = I[r];
+        if (w <= m) { m = w; q = r; }
+    }
+    int state = (m > v) ? 1 : (m < v) ? 0 : (q > p ? 2 : 3);
+    if (state_out) *state_out = state;
+    if (d == INF) return -2;
+    if (d == 0) return state == 0 ? q : -1;
+#pragma unroll
+    for (int k = 0; k < CONN; ++k) {
+        int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
+        if (!in_image(g, xx, yy, zz)) continue;
+        int32_t r = xx + g.nx * (yy + g.ny * zz);
+        if (I[r] == v && D[r] == d - 1) return r;
+    }
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// Unions for every arrow / minimal-plateau adjacency that crosses a tile
+// border. One workgroup per tile; only the tile's border pixels work.
+// ---------------------------------------------------------------------------
+template <int NDIM, int CONN, typename T>
+__global__ __launch_bounds__(NTHREADS) void k_ws_merge(Geom g, const T *__restrict__ I, const int32_t *__restrict__ D,
+                                                       int32_t *__restrict__ L) {
+    using TS = TileShape<NDIM>;
+    constexpr int PIX = TS::X * TS::Y * TS::Z;
+    int ox, oy, oz;
+    tile_origin<NDIM>(g, blockIdx.x, ox, oy, oz);
+    for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
+        int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+        if (!on_tile_border<NDIM>(x, y, z)) continue;
+        int gx = ox + x, gy = oy + y, gz = oz + z;
+        if (!in_image(g, gx, gy, gz)) continue;
+        int32_t p = gx + g.nx * (gy + g.ny * gz);
+        int32_t q = glb_arrow<CONN, T>(g, I, D, gx, gy, gz, p, nullptr);
+        if (q >= 0) {
+            int qx, qy, qz;
+            pixel_coords(g, q, qx, qy, qz);
+            if (qx < ox || qx >= ox + TS::X || qy < oy || qy >= oy + TS::Y || qz < oz || qz >= oz + TS::Z)
+                gunion(L, p, q);
+        } else if (q == -2) {
+            int v = I[p];
+#pragma unroll
+            for (int k = CONN / 2; k < CONN; ++k) {
+                int xx = gx + nb_dx<CONN>(k), yy = gy + nb_dy<CONN>(k), zz = gz + nb_dz<CONN>(k);
+                if (!in_image(g, xx, yy, zz)) continue;
+                if (xx >= ox && xx < ox + TS::X && yy >= oy && yy < oy + TS::Y && zz >= oz && zz < oz + TS::Z) continue;
+                int32_t r = xx + g.nx * (yy + g.ny * zz);
+                if ((int)I[r] == v) gunion(L, p, r);
+            }
+        }
+    }
+}
+
+// Final Find of every pixel (per-pixel path reduction, APRUF form).
+__global__ __launch_bounds__(NTHREADS) void k_ws_find(int32_t n, int32_t *__restrict__ L) {
+    int32_t p = blockIdx.x * NTHREADS + threadIdx.x;
+    if (p >= n) return;
+    int32_t r = L[p];
+    for (;;) {
+        int32_t rr = L[r];
+        if (rr == r) break;
+        r = rr;
+    }
+    L[p] = r;
+}
+
+// RR pointer jumps per synchronisation (PRUF form of Step III).
+__global__ __launch_bounds__(NTHREADS) void k_ws_jump(int32_t n, int32_t *__restrict__ L, int32_t rr,
+                                                      int32_t *__restrict__ changed) {
+    int32_t p = blockIdx.x * NTHREADS + threadIdx.x;
+    int ch = 0;
+    if (p < n) {
+        int32_t l = L[p];
+        for (int i = 0; i < rr; ++i) {
+            int32_t ll = ld_relaxed(L + l);
+            if (ll == l) break;
+            l = ll;
+            ch = 1;
+        }
+        if (ch) L[p] = l;
+    }
+    if (__syncthreads_or(ch) && threadIdx.x == 0) atomicAdd(changed, 1);
+}
+
+// Step-level outputs (balanced state encoding and arrows) for verification.
+template <int CONN, typename T>
+__global__ __launch_bounds__(NTHREADS) void k_ws_stages(Geom g, const T *__restrict__ I, const int32_t *__restrict__ D,
+                                                        int32_t *__restrict__ bal, int32_t *__restrict__ arrow) {
+    int32_t p = blockIdx.x * NTHREADS + threadIdx.x;
+    if (p >= g.n) return;
+    int x, y, z;
+    pixel_coords(g, p, x, y, z);
+    int state = 1;
+    int32_t q = glb_arrow<CONN, T>(g, I, D, x, y, z, p, &state);
+    int d = D[p];
+    if (d != 0 && d != INF) {
+        bal[p] = -d;
+        arrow[p] = q;
+        return;
+    }
+    bal[p] = state;
+    if (state == 0) arrow[p] = q;
+    else if (state == 2) {  // minimal plateau pixel: Eq. (1) target
+        int m = SENT;
+        int32_t qq = p;
+#pragma unroll
+        for (int k = 0; k < CONN; ++k) {
+            int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
+            if (!in_image(g, xx, yy, zz)) continue;
+            int32_t r = xx + g.nx * (yy + g.ny * zz);
+            int w = I[r];
+            if (w <= m) { m = w; qq = r; }
+        }
+        arrow[p] = qq;
+    } else arrow[p] = p;
+}
+
+__global__ void k_fill_i32(int32_t *a, int32_t n, int32_t v) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (instantiated per connectivity and grey type).
+// ---------------------------------------------------------------------------
+template <int CONN, typename T>
+static int launch_ws_init_t(Launch &lc, const Geom &g, const void *I, int32_t *D, int32_t *stamp, int32_t *changed) {
+    constexpr int ND = ndim_of<CONN>();
+    return lc.run("ws_init", k_ws_init<ND, CONN, T>, dim3(g.ntx * g.nty * g.ntz), dim3(NTHREADS), g,
+                  (const T *)I, D, stamp, changed);
+}
+template <int CONN, typename T>
+static int launch_ws_sweep_t(Launch &lc, const Geom &g, const void *I, int32_t *D, int32_t *stamp, int32_t *changed,
+                             int32_t s) {
+    constexpr int ND = ndim_of<CONN>();
+    return lc.run("ws_sweep", k_ws_sweep<ND, CONN, T>, dim3(g.ntx * g.nty * g.ntz), dim3(NTHREADS), g,
+                  (const T *)I, D, stamp, changed, s);
+}
+template <int CONN, typename T>
+static int launch_ws_label_t(Launch &lc, const Geom &g, const void *I, const int32_t *D, int32_t *L) {
+    constexpr int ND = ndim_of<CONN>();
+    return lc.run("ws_label", k_ws_label<ND, CONN, T>, dim3(g.ntx * g.nty * g.ntz), dim3(NTHREADS), g,
+                  (const T *)I, D, L);
+}
+template <int CONN, typename T>
+static int launch_ws_merge_t(Launch &lc, const Geom &g, const void *I, const int32_t *D, int32_t *L) {
+    constexpr int ND = ndim_of<CONN>();
+    return lc.run("ws_merge", k_ws_merge<ND, CONN, T>, dim3(g.ntx * g.nty * g.ntz), dim3(NTHREADS), g,
+                  (const T *)I, D, L);
+}
+template <int CONN, typename T>
+static int launch_ws_stages_t(Launch &lc, const Geom &g, const void *I, const int32_t *D, int32_t *bal, int32_t *arrow) {
+    return lc.run("ws_stages", k_ws_stages<CONN, T>, dim3((g.n + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), g,
+                  (const T *)I, D, bal, arrow);
+}
+
+#define WS_DISPATCH(FN, conn, u16, ...)                                        \
+    switch (conn) {                                                            \
+    case 4: return u16 ? FN<4, uint16_t>(__VA_ARGS__) : FN<4, uint8_t>(__VA_ARGS__);     \
+    case 8: return u16 ? FN<8, uint16_t>(__VA_ARGS__) : FN<8, uint8_t>(__VA_ARGS__);     \
+    case 6: return u16 ? FN<6, uint16_t>(__VA_ARGS__) : FN<6, uint8_t>(__VA_ARGS__);     \
+    case 26: return u16 ? FN<26, uint16_t>(__VA_ARGS__) : FN<26, uint8_t>(__VA_ARGS__);  \
+    default: return -1;                                                        \
+    }
+
+int launch_ws_init(Launch &lc, const Geom &g, int conn, bool u16, const void *I, int32_t *D, int32_t *stamp,
+                   int32_t *changed) {
+    WS_DISPATCH(launch_ws_init_t, conn, u16, lc, g, I, D, stamp, changed)
+}
+int launch_ws_sweep(Launch &lc, const Geom &g, int conn, bool u16, const void *I, int32_t *D, int32_t *stamp,
+                    int32_t *changed, int32_t s) {
+    WS_DISPATCH(launch_ws_sweep_t, conn, u16, lc, g, I, D, stamp, changed, s)
+}
+int launch_ws_label(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *L) {
+    WS_DISPATCH(launch_ws_label_t, conn, u16, lc, g, I, D, L)
+}
+int launch_ws_merge(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *L) {
+    WS_DISPATCH(launch_ws_merge_t, conn, u16, lc, g, I, D, L)
+}
+int launch_ws_stages(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *bal,
+                     int32_t *arrow) {
+    WS_DISPATCH(launch_ws_stages_t, conn, u16, lc, g, I, D, bal, arrow)
+}
+int launch_ws_find(Launch &lc, int32_t n, int32_t *L) {
+    return lc.run("ws_find", k_ws_find, dim3((n + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), n, L);
+}
+int launch_ws_jump(Launch &lc, int32_t n, int32_t *L, int32_t rr, int32_t *changed) {
+    return lc.run("ws_jump", k_ws_jump, dim3((n + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), n, L, rr, changed);
+}
+int launch_fill_i32(Launch &lc, int32_t *a, int32_t n, int32_t v) {
+    if (n <= 0) return 0;
+    return lc.run("fill", k_fill_i32, dim3((n + 255) / 256), dim3(256), a, n, v);
+}
+
+}  // namespace wsk

@@ -1,0 +1,160 @@
+// ws_device.h -- device-side helpers shared by the gfx950 kernels of libws.
+//
+// Pixel order: p = x + nx*(y + ny*z) (row-major order required by Step I of
+// Alg. 1). Neighbourhoods are enumerated in increasing linear index, which for
+// in-image pixels is the lexicographic order of (dz, dy, dx).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wsk {
+
+constexpr int32_t INF = 0x7fffffff;   // unresolved plateau distance
+constexpr int32_t SENT = 0x10000;     // grey value of out-of-image cells (> any uint16)
+constexpr int NTHREADS = 256;          // threads of every tile kernel (4 waves of 64)
+
+// Unsigned division by a runtime constant for dividends below 2^31
+// (multiply-high with a rounded-up magic number, shift s = ceil(log2 d)).
+struct FastDiv {
+    uint32_t d = 1, m = 1, s = 0;
+    FastDiv() = default;
+    explicit FastDiv(uint32_t div) : d(div) {
+        s = 0;
+        while ((1ull << s) < div) ++s;
+        m = (uint32_t)((((1ull << 32) * ((1ull << s) - div)) / div) + 1);
+    }
+    __device__ __forceinline__ uint32_t div(uint32_t n) const { return (__umulhi(n, m) + n) >> s; }
+};
+
+// Image geometry passed by value to every kernel.
+struct Geom {
+    int32_t nx, ny, nz, n;     // sizes, n = nx*ny*nz < 2^31
+    int32_t ntx, nty, ntz;     // tile grid
+    FastDiv dnx, dny;          // division by nx and ny
+};
+
+// Neighbour k of a connectivity, as an index j into the 3x3x3 cube
+// (j = 9*(dz+1) + 3*(dy+1) + (dx+1)); increasing k gives increasing j, hence
+// increasing linear pixel index.
+template <int CONN>
+__host__ __device__ constexpr int nb_j(int k) {
+    return CONN == 4 ? 10 + 2 * k
+         : CONN == 8 ? (k < 4 ? 9 + k : 10 + k)
+         : CONN == 6 ? (k == 0 ? 4 : (k == 5 ? 22 : 10 + 2 * (k - 1)))
+         : (k < 13 ? k : k + 1);
+}
+template <int CONN> __host__ __device__ constexpr int nb_dx(int k) { return nb_j<CONN>(k) % 3 - 1; }
+template <int CONN> __host__ __device__ constexpr int nb_dy(int k) { return (nb_j<CONN>(k) / 3) % 3 - 1; }
+template <int CONN> __host__ __device__ constexpr int nb_dz(int k) { return nb_j<CONN>(k) / 9 - 1; }
+template <int CONN> __host__ __device__ constexpr int ndim_of() { return (CONN == 4 || CONN == 8) ? 2 : 3; }
+
+// Tile shapes (pixels per workgroup) and LDS layout with a ring of width R.
+template <int NDIM> struct TileShape;
+template <> struct TileShape<2> { static constexpr int X = 64, Y = 32, Z = 1; };
+template <> struct TileShape<3> { static constexpr int X = 32, Y = 8, Z = 8; };
+
+template <int NDIM, int R>
+struct Lds {
+    using T = TileShape<NDIM>;
+    static constexpr int SX = T::X + 2 * R;
+    static constexpr int SY = T::Y + 2 * R;
+    static constexpr int SZ = NDIM == 3 ? T::Z + 2 * R : 1;
+    static constexpr int RZ = NDIM == 3 ? R : 0;
+    static constexpr int CELLS = SX * SY * SZ;
+    __device__ static constexpr int at(int x, int y, int z) { return ((z + RZ) * SY + (y + R)) * SX + (x + R); }
+    template <int CONN> __device__ static constexpr int off(int k) {
+        return nb_dx<CONN>(k) + SX * (nb_dy<CONN>(k) + SY * nb_dz<CONN>(k));
+    }
+};
+
+__device__ __forceinline__ void pixel_coords(const Geom &g, int32_t p, int &x, int &y, int &z) {
+    uint32_t q1 = g.dnx.div((uint32_t)p);
+    x = p - (int32_t)q1 * g.nx;
+    uint32_t q2 = g.dny.div(q1);
+    y = (int32_t)q1 - (int32_t)q2 * g.ny;
+    z = (int32_t)q2;
+}
+
+__device__ __forceinline__ bool in_image(const Geom &g, int x, int y, int z) {
+    return x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+}
+
+// Relaxed loads that always go to the coherent level of the memory hierarchy
+// (other workgroups of the same kernel may be updating the same words).
+__device__ __forceinline__ int32_t ld_relaxed(const int32_t *a) {
+    return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Union-find over a parent array in global memory with parent[x] <= x:
+// roots are self loops, and a union always hooks the larger root below the
+// smaller one, so a tree's root is the smallest index in it.
+__device__ __forceinline__ int32_t gfind(int32_t *par, int32_t x) {
+    for (;;) {
+        int32_t px = ld_relaxed(par + x);
+        if (px == x) return x;
+        int32_t ppx = ld_relaxed(par + px);
+        if (ppx != px) __hip_atomic_store(par + x, ppx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = px;
+    }
+}
+
+// Root of x without writing: safe while other threads store final roots into
+// the same array (a path-halving write could replace a final root by an
+// intermediate ancestor).
+__device__ __forceinline__ int32_t gfind_ro(const int32_t *par, int32_t x) {
+    for (;;) {
+        int32_t px = ld_relaxed(par + x);
+        if (px == x) return x;
+        x = px;
+    }
+}
+
+__device__ __forceinline__ void gunion(int32_t *par, int32_t a, int32_t b) {
+    a = gfind(par, a);
+    b = gfind(par, b);
+    while (a != b) {
+        if (a < b) { int32_t t = a; a = b; b = t; }
+        int32_t old = atomicCAS(par + a, a, b);
+        if (old == a) return;
+        a = gfind(par, old);
+        b = gfind(par, b);
+    }
+}
+
+// Same union-find on a tile-local parent array in LDS.
+__device__ __forceinline__ int lfind(int *par, int x) {
+    for (;;) {
+        int px = par[x];
+        if (px == x) return x;
+        int ppx = par[px];
+        if (ppx != px) par[x] = ppx;
+        x = px;
+    }
+}
+
+__device__ __forceinline__ void lunion(int *par, int a, int b) {
+    a = lfind(par, a);
+    b = lfind(par, b);
+    while (a != b) {
+        if (a < b) { int t = a; a = b; b = t; }
+        int old = atomicCAS(par + a, a, b);
+        if (old == a) return;
+        a = lfind(par, old);
+        b = lfind(par, b);
+    }
+}
+
+// Appends `value` to list[] for every lane with pred set; one atomic per wave.
+__device__ __forceinline__ void wave_append(bool pred, int32_t value, int32_t *list, int32_t *counter) {
+    uint64_t m = __ballot(pred);
+    if (m == 0) return;
+    int lane = __lane_id();
+    int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader);
+    if (pred) list[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
+}
+
+}  // namespace wsk

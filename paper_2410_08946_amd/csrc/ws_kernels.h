@@ -1,0 +1,90 @@
+// ws_kernels.h -- host-side launchers of the libws kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "ws_device.h"
+
+namespace wsk {
+
+// Collects (name, start event, stop event) triples when kernel timing is on.
+struct TimingSink {
+    struct Rec { std::string name; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+// A kernel launch on one stream; records a HIP event pair around it when a
+// timing sink is attached. Returns 0 or WS_EDEVICE (-3).
+struct Launch {
+    hipStream_t stream = nullptr;
+    TimingSink *timing = nullptr;
+    hipError_t last = hipSuccess;
+
+    template <typename K, typename... A>
+    int run(const char *name, K kernel, dim3 grid, dim3 block, A... args) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timing) {
+            e0 = timing->get();
+            e1 = timing->get();
+            if (e0) (void)hipEventRecord(e0, stream);
+        }
+        hipLaunchKernelGGL(kernel, grid, block, 0, stream, args...);
+        hipError_t err = hipGetLastError();
+        if (timing && e0 && e1) {
+            (void)hipEventRecord(e1, stream);
+            timing->recs.push_back({name, e0, e1});
+        }
+        if (err != hipSuccess) {
+            last = err;
+            return -3;
+        }
+        return 0;
+    }
+};
+
+struct BlurTaps {
+    int r;
+    float w[129];
+};
+
+// watershed.hip
+int launch_ws_init(Launch &lc, const Geom &g, int conn, bool u16, const void *I, int32_t *D, int32_t *stamp,
+                   int32_t *changed);
+int launch_ws_sweep(Launch &lc, const Geom &g, int conn, bool u16, const void *I, int32_t *D, int32_t *stamp,
+                    int32_t *changed, int32_t s);
+int launch_ws_label(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *L);
+int launch_ws_merge(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *L);
+int launch_ws_stages(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *bal,
+                     int32_t *arrow);
+int launch_ws_find(Launch &lc, int32_t n, int32_t *L);
+int launch_ws_jump(Launch &lc, int32_t n, int32_t *L, int32_t rr, int32_t *changed);
+int launch_fill_i32(Launch &lc, int32_t *a, int32_t n, int32_t v);
+
+// waterfall.hip
+int launch_wf_init(Launch &lc, int32_t n, const int32_t *lab, int32_t *list, int32_t *count, uint64_t *key, int32_t *par);
+int launch_wf_edge(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *lab, uint64_t *key);
+int launch_wf_union(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, const uint64_t *key, int32_t *par);
+int launch_wf_compress(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, int32_t *par);
+int launch_wf_compact(Launch &lc, int32_t bound, const int32_t *list_in, const int32_t *count_in, int32_t *list_out,
+                      int32_t *count_out, const int32_t *par, uint64_t *key);
+int launch_wf_relabel(Launch &lc, int32_t n, const int32_t *prev, int32_t *cur, const int32_t *par);
+int launch_wf_counts(Launch &lc, int32_t nl, const int32_t *counts, int64_t *out);
+
+// gradient.hip
+int launch_grad_blur(Launch &lc, const Geom &g, const float *in, float *out, int axis, const BlurTaps &taps);
+int launch_grad_sobel(Launch &lc, const Geom &g, int ndim, const float *a, float *mag, unsigned int *maxbits);
+int launch_grad_quant(Launch &lc, int32_t n, bool u16, const float *mag, void *out, const unsigned int *maxbits);
+int launch_grad_zero_max(Launch &lc, unsigned int *maxbits);
+
+}  // namespace wsk

@@ -1,0 +1,266 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer stages must match bit for bit on the same quantised bytes; the float32
+gradient must stay within 1e-5 of max|oracle| (the oracle is float64), and its
+quantised bytes may differ by one level only where the oracle's unrounded
+value lies within that tolerance of a rounding boundary.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+GRAD_RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2410_08946_amd as ws
+    c = ws.Context(0)
+    yield c
+    c.close()
+
+
+def to_dev(a):
+    import torch
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint16:
+        return torch.from_numpy(a.view(np.int16)).to("cuda:0").view(torch.uint16)
+    return torch.from_numpy(a).to("cuda:0")
+
+
+def to_host(t):
+    import torch
+    torch.cuda.synchronize()
+    if t.dtype == torch.uint16:
+        return t.view(torch.int16).cpu().numpy().view(np.uint16)
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def gpu_ws(ctx, grad, conn):
+    say("  watershed", grad.shape, grad.dtype, "conn", conn)
+    return to_host(ctx.watershed(to_dev(grad), conn))
+
+
+def check_ws(ctx, grad, conn):
+    got = gpu_ws(ctx, grad, conn)
+    ref = oracle.watershed(grad, conn)
+    if not np.array_equal(got, ref):
+        bad = np.argwhere(got != ref)
+        raise AssertionError("labels differ at %d pixels, first %s: gpu %s oracle %s" %
+                             (len(bad), bad[0].tolist(), got[tuple(bad[0])], ref[tuple(bad[0])]))
+    return got
+
+
+def check_stages(ctx, grad, conn):
+    say("  stages", grad.shape, "conn", conn)
+    bal, arrow = ctx.watershed_stages(to_dev(grad), conn)
+    _, st = oracle.watershed(grad, conn, full=True)
+    assert np.array_equal(to_host(bal), st["bal"])
+    assert np.array_equal(to_host(arrow), st["arrow"])
+
+
+def check_wf(ctx, grad, conn, NL):
+    import torch
+    g = to_dev(grad)
+    say("  waterfall", grad.shape, "conn", conn, "NL", NL)
+    lab = ctx.watershed(g, conn)
+    out, nreg = ctx.waterfall(lab, g, conn, NL)
+    ref0 = oracle.watershed(grad, conn)
+    ref, refn = oracle.waterfall_g1(ref0, grad, conn, NL)
+    assert np.array_equal(to_host(out), ref)
+    assert to_host(nreg).tolist() == refn.tolist()
+    torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------
+def test_tiny_images(ctx):
+    for img, conn in [(np.array([[7]], np.uint8), 4), (np.array([[3, 1, 4, 1, 5]], np.uint8), 4),
+                      (np.array([[3], [1], [4], [1], [5]], np.uint8), 8), (np.array([[2, 2], [2, 2]], np.uint8), 8),
+                      (np.array([[[1]], [[0]]], np.uint8), 6)]:
+        check_ws(ctx, img, conn)
+
+
+@pytest.mark.parametrize("n", [2, 5, 33, 100, 2000])
+def test_paper_rows(ctx, n):
+    row = gen.paper_row(n)
+    lab = check_ws(ctx, row, 4)
+    assert lab[0].tolist() == [0] * (n + 1) + [n + 1] * (n + 1)
+    check_stages(ctx, row, 4)
+    check_ws(ctx, np.ascontiguousarray(row.T), 8)
+
+
+def test_paper_bal14(ctx):
+    row = np.array([[75] + [89] * 12 + [81]], np.uint8)
+    bal, arrow = ctx.watershed_stages(to_dev(row), 4)
+    assert to_host(bal)[0].tolist() == [1, 0, -1, -2, -3, -4, -5, -5, -4, -3, -2, -1, 0, 1]
+
+
+@pytest.mark.parametrize("shape", [(7, 9), (32, 64), (33, 65), (64, 130), (100, 37), (1, 300), (300, 1), (97, 203)])
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_random_2d(ctx, shape, conn, dtype):
+    rng = np.random.default_rng(hash((shape, conn)) % (2 ** 32))
+    for levels in (2, 4, 50):
+        img = rng.integers(0, levels, size=shape).astype(dtype)
+        check_ws(ctx, img, conn)
+        check_stages(ctx, img, conn)
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (8, 8, 32), (9, 17, 33), (20, 10, 70), (1, 9, 40)])
+@pytest.mark.parametrize("conn", [6, 26])
+def test_random_3d(ctx, shape, conn):
+    if shape[0] == 1:
+        conn = 4 if conn == 6 else 8
+        shape = shape[1:]
+    rng = np.random.default_rng(7)
+    for levels in (2, 4, 50):
+        img = rng.integers(0, levels, size=shape).astype(np.uint8)
+        check_ws(ctx, img, conn)
+        check_stages(ctx, img, conn)
+
+
+def test_plateau_structures(ctx):
+    check_ws(ctx, gen.serpentine(70, 150), 4)
+    check_stages(ctx, gen.serpentine(70, 150), 8)
+    check_ws(ctx, np.full((300, 200), 5, np.uint8), 8)
+    check_ws(ctx, np.full((20, 40, 70), 9, np.uint16), 6)
+    yy, xx = np.mgrid[0:200, 0:300]
+    check_ws(ctx, ((yy // 37 + xx // 53) % 3).astype(np.uint8), 4)   # large flat blocks
+    zz, yy, xx = np.mgrid[0:24, 0:40, 0:70]
+    check_ws(ctx, ((zz // 7 + yy // 9 + xx // 11) % 4).astype(np.uint8), 26)
+
+
+def test_blob_images_and_waterfall(ctx):
+    img = gen.blobs2d(256, 256, seed=0)
+    grad = oracle.gradient(img, 0.0, "u8")
+    check_ws(ctx, grad, 4)
+    check_wf(ctx, grad, 4, 3)
+    check_wf(ctx, grad, 8, 8)
+    vol = gen.blobs3d(40, 48, 56, seed=2, n_blobs=12, sigma=(3.0, 8.0))
+    g3 = oracle.gradient(vol, 0.0, "u8")
+    check_ws(ctx, g3, 6)
+    check_wf(ctx, g3, 6, 6)
+    check_wf(ctx, g3, 26, 4)
+
+
+@pytest.mark.parametrize("shape,conn", [((45, 61), 4), ((45, 61), 8), ((9, 11, 13), 6), ((9, 11, 13), 26)])
+def test_waterfall_random(ctx, shape, conn):
+    rng = np.random.default_rng(41)
+    for levels in (3, 40, 1000):
+        img = rng.integers(0, levels, size=shape).astype(np.uint16)
+        check_wf(ctx, img, conn, 12)
+    check_wf(ctx, np.full(shape, 4, np.uint8), conn, 3)
+
+
+def test_schedule_invariance(ctx):
+    img = gen.blobs2d(300, 280, seed=5)
+    grad = oracle.gradient(img, 0.0, "u8")
+    ref = oracle.watershed(grad, 8)
+    serp = gen.serpentine(66, 130)
+    ref_s = oracle.watershed(serp, 4)
+    try:
+        for step3 in (0, 1):
+            for rr in (1, 2, 6):
+                for batch in (1, 3, 32):
+                    ctx.set_option("step3", step3)
+                    ctx.set_option("rr", rr)
+                    ctx.set_option("sweep_batch", batch)
+                    assert np.array_equal(gpu_ws(ctx, grad, 8), ref)
+                    assert np.array_equal(gpu_ws(ctx, serp, 4), ref_s)
+    finally:
+        ctx.set_option("step3", 0)
+        ctx.set_option("rr", 6)
+        ctx.set_option("sweep_batch", 4)
+
+
+def _check_gradient(ctx, img, sigma, dtype):
+    import torch
+    say("  gradient", img.shape, "sigma", sigma, dtype)
+    q_ref, mag_ref = oracle.gradient(img, sigma, dtype, return_mag=True)
+    d_img = torch.from_numpy(img).to("cuda:0")
+    mag = torch.empty(img.shape, dtype=torch.float32, device="cuda:0")
+    q = ctx.gradient(d_img, sigma, dtype, mag=mag)
+    m = to_host(mag).astype(np.float64)
+    mx = mag_ref.max()
+    assert np.abs(m - mag_ref).max() <= GRAD_RTOL * mx
+    Q = 255 if dtype == "u8" else 65535
+    exact = mag_ref * Q / mx if mx > 0 else np.zeros_like(mag_ref)
+    dq = np.abs(to_host(q).astype(np.int64) - q_ref.astype(np.int64))
+    near = np.abs(exact - np.floor(exact) - 0.5) <= 2 * GRAD_RTOL * Q
+    assert dq.max() <= 1
+    assert (dq[~near] == 0).all()
+    return to_host(q)
+
+
+def test_gradient(ctx):
+    rng = np.random.default_rng(13)
+    _check_gradient(ctx, gen.blobs2d(256, 256, seed=0), 0.0, "u8")
+    _check_gradient(ctx, (rng.normal(0, 100, (61, 77)) + 500).astype(np.float32), 1.0, "u16")
+    _check_gradient(ctx, (rng.normal(0, 100, (61, 77)) + 500).astype(np.float32), 2.5, "u8")
+    _check_gradient(ctx, gen.blobs3d(30, 34, 38, seed=4, n_blobs=8, sigma=(3.0, 6.0)), 0.0, "u8")
+    _check_gradient(ctx, (rng.normal(0, 10, (17, 19, 23))).astype(np.float32), 1.0, "u16")
+    _check_gradient(ctx, (rng.normal(0, 10, (1, 300))).astype(np.float32), 1.0, "u16")
+    _check_gradient(ctx, np.full((20, 30), 3.0, np.float32), 1.0, "u8")
+
+
+def test_argument_errors(ctx):
+    import torch
+    import paper_2410_08946_amd as ws
+    g = torch.zeros((16, 16), dtype=torch.uint8, device="cuda:0")
+    for conn in (0, 5, 6, 26):
+        with pytest.raises(ws.WSError) as e:
+            ctx.watershed(g, conn)
+        assert e.value.code == ws.binding.WS_EINVAL
+    g3 = torch.zeros((4, 16, 16), dtype=torch.uint8, device="cuda:0")
+    for conn in (4, 8):
+        with pytest.raises(ws.WSError):
+            ctx.watershed(g3, conn)
+    lab = ctx.watershed(g, 4)
+    with pytest.raises(ws.WSError):
+        ctx.waterfall(lab, g, 4, 0)
+    with pytest.raises(ws.WSError):
+        ctx.set_option("no_such_option", 1)
+    # the Step II sweep cap surfaces as WS_ENOCONV (a plateau crossing tiles)
+    ctx.set_option("max_sweeps", 1)
+    try:
+        with pytest.raises(ws.WSError) as e:
+            ctx.watershed(to_dev(gen.serpentine(70, 150)), 4)
+        assert e.value.code == ws.binding.WS_ENOCONV
+    finally:
+        ctx.set_option("max_sweeps", 2 ** 31 - 1)
+    check_ws(ctx, gen.serpentine(70, 150), 4)
+
+
+def test_c1_full_size(ctx):
+    """4096 x 4096 u16, blur sigma 1 + Sobel, 8-conn, NL = 6: every stage
+    compared in full with the oracle, in the launch configuration of the
+    benchmark."""
+    import torch
+    img = gen.config_image("c1")
+    q = _check_gradient(ctx, img, 1.0, "u16")
+    grad = oracle.gradient(img, 1.0, "u16")
+    say("  c1 watershed + waterfall")
+    g = to_dev(grad)
+    lab = ctx.watershed(g, 8)
+    out, nreg = ctx.waterfall(lab, g, 8, 6)
+    ref0 = oracle.watershed(grad, 8)
+    ref, refn = oracle.waterfall_g1(ref0, grad, 8, 6)
+    assert np.array_equal(to_host(lab), ref0)
+    assert np.array_equal(to_host(out), ref)
+    assert to_host(nreg).tolist() == refn.tolist()
+    # the bench feeds the GPU's own quantised gradient forward: its labels are
+    # those of the oracle on the same bytes
+    g2 = to_dev(q)
+    lab2 = ctx.watershed(g2, 8)
+    assert np.array_equal(to_host(lab2), oracle.watershed(q, 8))
+    torch.cuda.synchronize()
