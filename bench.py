@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 256 MiB device-to-device copy first (counter calibration)")
     return ap.parse_args()
 
 
@@ -81,6 +83,14 @@ def main():
     out_d = torch.empty((NL, ny, nx), dtype=torch.int32, device=dev)
     nreg_d = torch.zeros(NL, dtype=torch.int64, device=dev)
     ctx = ws.Context(0)
+    if args.calib_copy:
+        a = torch.empty(64 << 20, dtype=torch.int32, device=dev)
+        bb = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        bb.copy_(a)
+        torch.cuda.synchronize()
+        del a, bb
 
     def step():
         ctx.gradient(img_d, sigma, "u16", out=grad_d)

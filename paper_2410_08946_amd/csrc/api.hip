@@ -34,9 +34,10 @@ thread_local std::string g_noctx_error;
 struct ws_ctx {
     int device = 0;
     std::string err;
-    Buf D, stamp, cnt;                    // watershed scratch
+    Buf D, stamp, cnt, rec;               // watershed scratch
     Buf key, par, lista, listb, wfcnt;    // waterfall scratch
     Buf g0, g1, mag, gmax;                // gradient scratch
+    Buf chunks;                           // compaction offsets
     int32_t *host_cnt = nullptr;          // pinned readback of counters
     int step3 = 0, rr = 6, sweep_batch = 4;
     int64_t max_sweeps = 0x7fffffff;
@@ -204,8 +205,8 @@ int ws_create(ws_ctx **out, int device) {
 void ws_destroy(ws_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    Buf *bufs[] = {&c->D, &c->stamp, &c->cnt, &c->key, &c->par, &c->lista, &c->listb, &c->wfcnt,
-                   &c->g0, &c->g1, &c->mag, &c->gmax};
+    Buf *bufs[] = {&c->D, &c->stamp, &c->cnt, &c->rec, &c->key, &c->par, &c->lista, &c->listb, &c->wfcnt,
+                   &c->g0, &c->g1, &c->mag, &c->gmax, &c->chunks};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &r : c->sink.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
@@ -270,32 +271,41 @@ int ws_gradient(ws_ctx *c, const float *img, int64_t nx, int64_t ny, int64_t nz,
     Geom g = make_geom(nx, ny, nz, ndim);
     size_t N = (size_t)g.n;
     Launch lc = make_launch(c, stream);
-    const float *src = img;
-    if (r > 0) {
-        if ((rc = ensure(c, c->g0, N * 4, "blur buffer")) != WS_OK) return rc;
-        if ((rc = ensure(c, c->g1, N * 4, "blur buffer")) != WS_OK) return rc;
-        wsk::BlurTaps taps;
-        taps.r = r;
-        double w[129], sum = 0.0;
-        for (int k = -r; k <= r; ++k) { w[k + r] = exp(-0.5 * (double)k * (double)k / ((double)sigma * (double)sigma)); sum += w[k + r]; }
-        for (int k = 0; k <= 2 * r; ++k) taps.w[k] = (float)(w[k] / sum);
-        float *bufs[2] = {(float *)c->g0.p, (float *)c->g1.p};
-        for (int ax = 0; ax < ndim; ++ax) {
-            float *dst = bufs[ax & 1];
-            WS_TRY(wsk::launch_grad_blur(lc, g, src, dst, ax, taps));
-            src = dst;
-        }
-    }
+    if ((rc = ensure(c, c->gmax, wsk::MAXSLOTS * 4, "maximum")) != WS_OK) return rc;
+    unsigned int *slots = (unsigned int *)c->gmax.p;
     float *mag = mag_or_null;
     if (!mag) {
         if ((rc = ensure(c, c->mag, N * 4, "magnitude buffer")) != WS_OK) return rc;
         mag = (float *)c->mag.p;
     }
-    if ((rc = ensure(c, c->gmax, 256, "maximum")) != WS_OK) return rc;
-    unsigned int *mx = (unsigned int *)c->gmax.p;
-    WS_TRY(wsk::launch_grad_zero_max(lc, mx));
-    WS_TRY(wsk::launch_grad_sobel(lc, g, ndim, src, mag, mx));
-    WS_TRY(wsk::launch_grad_quant(lc, g.n, dtype == WS_U16, mag, grad, mx));
+    wsk::BlurTaps taps;
+    taps.r = r;
+    {
+        double w[129], sum = 0.0;
+        for (int k = -r; k <= r; ++k) {
+            w[k + r] = r > 0 ? exp(-0.5 * (double)k * (double)k / ((double)sigma * (double)sigma)) : 1.0;
+            sum += w[k + r];
+        }
+        for (int k = 0; k <= 2 * r; ++k) taps.w[k] = (float)(w[k] / sum);
+    }
+    WS_TRY(wsk::launch_grad_zero_slots(lc, slots));
+    if (ndim == 2 && r <= wsk::FUSED_MAX_R) {
+        WS_TRY(wsk::launch_grad_fused2d(lc, g, img, mag, slots, taps));
+    } else {
+        const float *src = img;
+        if (r > 0) {
+            if ((rc = ensure(c, c->g0, N * 4, "blur buffer")) != WS_OK) return rc;
+            if ((rc = ensure(c, c->g1, N * 4, "blur buffer")) != WS_OK) return rc;
+            float *bufs[2] = {(float *)c->g0.p, (float *)c->g1.p};
+            for (int ax = 0; ax < ndim; ++ax) {
+                float *dst = bufs[ax & 1];
+                WS_TRY(wsk::launch_grad_blur(lc, g, src, dst, ax, taps));
+                src = dst;
+            }
+        }
+        WS_TRY(wsk::launch_grad_sobel(lc, g, ndim, src, mag, slots));
+    }
+    WS_TRY(wsk::launch_grad_quant(lc, g.n, dtype == WS_U16, mag, grad, slots));
     return WS_OK;
 }
 
@@ -323,8 +333,11 @@ int ws_watershed(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny,
     c->stats[2] = 0;
     if ((rc = run_distances(c, lc, g, conn, u16, grad)) != WS_OK) return rc;
     const int32_t *D = (const int32_t *)c->D.p;
-    WS_TRY(wsk::launch_ws_label(lc, g, conn, u16, grad, D, labels));
-    WS_TRY(wsk::launch_ws_merge(lc, g, conn, u16, grad, D, labels));
+    size_t nrec = (size_t)g.ntx * g.nty * g.ntz * wsk::border_cells(ndim);
+    if ((rc = ensure(c, c->rec, nrec * 4, "border records")) != WS_OK) return rc;
+    int32_t *rec = (int32_t *)c->rec.p;
+    WS_TRY(wsk::launch_ws_label(lc, g, conn, u16, grad, D, labels, rec));
+    WS_TRY(wsk::launch_ws_merge(lc, g, conn, u16, grad, rec, labels));
     if (c->step3 == 0) {
         WS_TRY(wsk::launch_ws_find(lc, g.n, labels));
     } else {
@@ -376,25 +389,31 @@ int ws_waterfall(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, 
     if ((rc = ensure(c, c->lista, N * 4, "region list")) != WS_OK) return rc;
     if ((rc = ensure(c, c->listb, N * 4, "region list")) != WS_OK) return rc;
     if ((rc = ensure(c, c->wfcnt, (size_t)NL * 4, "region counts")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->chunks, (size_t)wsk::compact_chunks(g.n) * 4, "compaction offsets")) != WS_OK) return rc;
     uint64_t *key = (uint64_t *)c->key.p;
-    int32_t *par = (int32_t *)c->par.p, *cnt = (int32_t *)c->wfcnt.p;
+    int32_t *par = (int32_t *)c->par.p, *cnt = (int32_t *)c->wfcnt.p, *chunks = (int32_t *)c->chunks.p;
     int32_t *lists[2] = {(int32_t *)c->lista.p, (int32_t *)c->listb.p};
     if (labels != out) {
         hipError_t e = hipMemcpyAsync(out, labels, N * 4, hipMemcpyDeviceToDevice, lc.stream);
         if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
     }
     WS_TRY(wsk::launch_fill_i32(lc, cnt, NL, 0));
-    WS_TRY(wsk::launch_wf_init(lc, g.n, out, lists[0], cnt, key, par));
+    WS_TRY(wsk::launch_wf_init(lc, g.n, out, lists[0], cnt, key, par, chunks));
     for (int k = 1; k < NL; ++k) {
-        const int32_t *prev = out + (size_t)(k - 1) * N;
-        int32_t *cur = out + (size_t)k * N;
         int32_t *lin = lists[(k - 1) & 1], *lout = lists[k & 1];
-        WS_TRY(wsk::launch_wf_edge(lc, g, conn, u16, grad, prev, key));
+        if (k == 1) {
+            WS_TRY(wsk::launch_wf_edge(lc, g, conn, u16, grad, out, nullptr, nullptr, key));
+        } else {
+            // relabel layer k-1 from layer k-2 while computing layer k's keys
+            WS_TRY(wsk::launch_wf_edge(lc, g, conn, u16, grad, out + (size_t)(k - 2) * N, par,
+                                       out + (size_t)(k - 1) * N, key));
+        }
         WS_TRY(wsk::launch_wf_union(lc, g.n, lin, cnt + k - 1, key, par));
         WS_TRY(wsk::launch_wf_compress(lc, g.n, lin, cnt + k - 1, par));
-        WS_TRY(wsk::launch_wf_compact(lc, g.n, lin, cnt + k - 1, lout, cnt + k, par, key));
-        WS_TRY(wsk::launch_wf_relabel(lc, g.n, prev, cur, par));
+        WS_TRY(wsk::launch_wf_compact(lc, g.n, lin, cnt + k - 1, lout, cnt + k, par, key, chunks));
     }
+    if (NL >= 2)
+        WS_TRY(wsk::launch_wf_relabel(lc, g.n, out + (size_t)(NL - 2) * N, out + (size_t)(NL - 1) * N, par));
     if (nregions) WS_TRY(wsk::launch_wf_counts(lc, NL, cnt, nregions));
     return WS_OK;
 }

@@ -48,26 +48,14 @@ __device__ __forceinline__ void tile_origin(const Geom &g, int t, int &ox, int &
 template <int NDIM, int R, typename T>
 __device__ __forceinline__ void load_grey(const Geom &g, const T *__restrict__ I, int *sI, int ox, int oy, int oz) {
     using S = Lds<NDIM, R>;
-    for (int c = threadIdx.x; c < S::CELLS; c += NTHREADS) {
-        int cx = c % S::SX, cy = (c / S::SX) % S::SY, cz = c / (S::SX * S::SY);
-        int x = ox + cx - R, y = oy + cy - R, z = oz + cz - S::RZ;
-        int v = SENT;
-        if (in_image(g, x, y, z)) v = (int)I[x + g.nx * (y + g.ny * z)];
-        sI[c] = v;
-    }
+    load_box<S::SX, S::SY, S::SZ, T, int>(g, ox - R, oy - R, oz - S::RZ, I, sI, SENT);
 }
 
 // Loads D of the tile plus a ring of width 1; cells outside the image get INF.
 template <int NDIM>
 __device__ __forceinline__ void load_dist(const Geom &g, const int32_t *__restrict__ D, int *sD, int ox, int oy, int oz) {
     using S = Lds<NDIM, 1>;
-    for (int c = threadIdx.x; c < S::CELLS; c += NTHREADS) {
-        int cx = c % S::SX, cy = (c / S::SX) % S::SY, cz = c / (S::SX * S::SY);
-        int x = ox + cx - 1, y = oy + cy - 1, z = oz + cz - S::RZ;
-        int v = INF;
-        if (in_image(g, x, y, z)) v = D[x + g.nx * (y + g.ny * z)];
-        sD[c] = v;
-    }
+    load_box<S::SX, S::SY, S::SZ, int32_t, int>(g, ox - 1, oy - 1, oz - S::RZ, D, sD, INF);
 }
 
 // Relaxes the plateau distances of the tile's pixels to a local fixpoint
@@ -251,15 +239,77 @@ __device__ __forceinline__ int lds_arrow(const int *sI, const int *sD, int s) {
 }
 
 // ---------------------------------------------------------------------------
-// Tile-local union-find of arrows and minimal-plateau adjacencies; writes the
-// tile-local root (as a global pixel index) of every pixel into L.
+// Border cells of a tile, enumerated face by face: NB(2D) = 2X + 2(Y-2),
+// NB(3D) = 2XY + (Z-2)(2X + 2(Y-2)). border_cell maps b -> (x, y, z) and
+// border_index is its inverse for cells on the border.
+// ---------------------------------------------------------------------------
+template <int NDIM> struct Border {
+    using TS = TileShape<NDIM>;
+    static constexpr int RING = 2 * TS::X + 2 * (TS::Y - 2);
+    static constexpr int FACE = TS::X * TS::Y;
+    static constexpr int NB = NDIM == 2 ? RING : 2 * FACE + (TS::Z - 2) * RING;
+};
+
+template <int NDIM>
+__device__ __forceinline__ void border_cell(int b, int &x, int &y, int &z) {
+    using TS = TileShape<NDIM>;
+    using B = Border<NDIM>;
+    z = 0;
+    if (NDIM == 3) {
+        if (b < 2 * B::FACE) {
+            x = b % TS::X;
+            y = (b / TS::X) % TS::Y;
+            z = b < B::FACE ? 0 : TS::Z - 1;
+            return;
+        }
+        b -= 2 * B::FACE;
+        z = 1 + b / B::RING;
+        b %= B::RING;
+    }
+    if (b < 2 * TS::X) {
+        x = b % TS::X;
+        y = b < TS::X ? 0 : TS::Y - 1;
+        return;
+    }
+    b -= 2 * TS::X;
+    y = 1 + (b >> 1);
+    x = (b & 1) ? TS::X - 1 : 0;
+}
+
+template <int NDIM>
+__device__ __forceinline__ int border_index(int x, int y, int z) {
+    using TS = TileShape<NDIM>;
+    using B = Border<NDIM>;
+    int base = 0;
+    if (NDIM == 3) {
+        if (z == 0) return x + TS::X * y;
+        if (z == TS::Z - 1) return B::FACE + x + TS::X * y;
+        base = 2 * B::FACE + (z - 1) * B::RING;
+    }
+    if (y == 0) return base + x;
+    if (y == TS::Y - 1) return base + TS::X + x;
+    return base + 2 * TS::X + 2 * (y - 1) + (x == TS::X - 1 ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// Tile-local labelling. Every pixel's arrow inside the tile is contracted by
+// pointer jumping (path reduction, Step III) to its terminal: a local minimum,
+// a minimal-plateau pixel, or an exit whose arrow leaves the tile. Minimal-
+// plateau pixels are then joined with their equal neighbours by union-find
+// (Step IV). Each tile-local component is named by its smallest pixel (LDS
+// atomicMin), written into L as a global index. For every border pixel the
+// crossing it needs in the global merge is recorded in rec: the target of an
+// arrow that leaves the tile, -2 for a minimal-plateau pixel with an equal
+// neighbour outside the tile, -1 otherwise.
 // ---------------------------------------------------------------------------
 template <int NDIM, int CONN, typename T>
 __global__ __launch_bounds__(NTHREADS) void k_ws_label(Geom g, const T *__restrict__ I, const int32_t *__restrict__ D,
-                                                       int32_t *__restrict__ L) {
+                                                       int32_t *__restrict__ L, int32_t *__restrict__ rec) {
     using TS = TileShape<NDIM>;
     using S = Lds<NDIM, 1>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
+    constexpr int PER = PIX / NTHREADS;
+    static_assert(PIX % NTHREADS == 0, "tile must be a multiple of the workgroup");
     __shared__ int sI[S::CELLS];
     __shared__ int sD[S::CELLS];
     __shared__ int sP[PIX];
@@ -267,21 +317,64 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Geom g, const T *__restri
     tile_origin<NDIM>(g, blockIdx.x, ox, oy, oz);
     load_grey<NDIM, 1, T>(g, I, sI, ox, oy, oz);
     load_dist<NDIM>(g, D, sD, ox, oy, oz);
-    for (int i = threadIdx.x; i < PIX; i += NTHREADS) sP[i] = i;
     __syncthreads();
-    for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
+    uint32_t minzone = 0, inimg = 0;
+    int32_t *trec = rec + (size_t)blockIdx.x * Border<NDIM>::NB;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int i = threadIdx.x + j * NTHREADS;
         int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-        if (!in_image(g, ox + x, oy + y, oz + z)) continue;
-        int s = S::at(x, y, z);
-        int k = lds_arrow<NDIM, CONN>(sI, sD, s);
-        if (k >= 0) {
-            int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
-            if (xx >= 0 && xx < TS::X && yy >= 0 && yy < TS::Y && zz >= 0 && zz < TS::Z)
-                lunion(sP, i, xx + TS::X * (yy + TS::Y * zz));
-        } else if (k == -2) {
+        int gx = ox + x, gy = oy + y, gz = oz + z;
+        int to = i;
+        if (in_image(g, gx, gy, gz)) {
+            inimg |= 1u << j;
+            int s = S::at(x, y, z);
+            int k = lds_arrow<NDIM, CONN>(sI, sD, s);
+            int code = -1;
+            if (k >= 0) {
+                int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
+                if (xx >= 0 && xx < TS::X && yy >= 0 && yy < TS::Y && zz >= 0 && zz < TS::Z)
+                    to = xx + TS::X * (yy + TS::Y * zz);
+                else
+                    code = (gx + nb_dx<CONN>(k)) + g.nx * ((gy + nb_dy<CONN>(k)) + g.ny * (gz + nb_dz<CONN>(k)));
+            } else if (k == -2) {
+                minzone |= 1u << j;
+                int v = sI[s];
+#pragma unroll
+                for (int k2 = CONN / 2; k2 < CONN; ++k2) {  // neighbours after p
+                    int xx = x + nb_dx<CONN>(k2), yy = y + nb_dy<CONN>(k2), zz = z + nb_dz<CONN>(k2);
+                    bool inside = xx >= 0 && xx < TS::X && yy >= 0 && yy < TS::Y && zz >= 0 && zz < TS::Z;
+                    if (!inside && sI[s + S::template off<CONN>(k2)] == v) code = -2;
+                }
+            }
+            if (on_tile_border<NDIM>(x, y, z)) trec[border_index<NDIM>(x, y, z)] = code;
+        }
+        sP[i] = to;
+    }
+    __syncthreads();
+    // pointer jumping to the in-tile terminals
+    for (;;) {
+        int changed = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            int i = threadIdx.x + j * NTHREADS;
+            int p = sP[i];
+            int pp = sP[p];
+            if (pp != p) { sP[i] = pp; changed = 1; }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+    // minimal plateaux: join equal neighbours after p inside the tile
+    if (minzone) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            if (!(minzone >> j & 1u)) continue;
+            int i = threadIdx.x + j * NTHREADS;
+            int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+            int s = S::at(x, y, z);
             int v = sI[s];
 #pragma unroll
-            for (int k2 = CONN / 2; k2 < CONN; ++k2) {  // neighbours after p only
+            for (int k2 = CONN / 2; k2 < CONN; ++k2) {
                 int xx = x + nb_dx<CONN>(k2), yy = y + nb_dy<CONN>(k2), zz = z + nb_dz<CONN>(k2);
                 if (xx < 0 || xx >= TS::X || yy < 0 || yy >= TS::Y || zz < 0 || zz >= TS::Z) continue;
                 if (sI[s + S::template off<CONN>(k2)] == v) lunion(sP, i, xx + TS::X * (yy + TS::Y * zz));
@@ -289,13 +382,27 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Geom g, const T *__restri
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
+    // smallest pixel of every tile-local component (sD reused)
+    int *cm = sD;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) cm[threadIdx.x + j * NTHREADS] = 0x7fffffff;
+    __syncthreads();
+    int root[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int i = threadIdx.x + j * NTHREADS;
+        root[j] = lfind(sP, i);
+        if (inimg >> j & 1u) atomicMin(&cm[root[j]], i);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        if (!(inimg >> j & 1u)) continue;
+        int i = threadIdx.x + j * NTHREADS;
         int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-        int gx = ox + x, gy = oy + y, gz = oz + z;
-        if (!in_image(g, gx, gy, gz)) continue;
-        int r = lfind(sP, i);
+        int r = cm[root[j]];
         int rx = r % TS::X, ry = (r / TS::X) % TS::Y, rz = r / (TS::X * TS::Y);
-        L[gx + g.nx * (gy + g.ny * gz)] = (ox + rx) + g.nx * ((oy + ry) + g.ny * (oz + rz));
+        L[(ox + x) + g.nx * ((oy + y) + g.ny * (oz + z))] = (ox + rx) + g.nx * ((oy + ry) + g.ny * (oz + rz));
     }
 }
 
@@ -306,64 +413,70 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Geom g, const T *__restri
 template <int CONN, typename T>
 __device__ __forceinline__ int32_t glb_arrow(const Geom &g, const T *__restrict__ I, const int32_t *__restrict__ D,
                                              int x, int y, int z, int32_t p, int32_t *state_out) {
+    // all neighbour loads are issued before any is used (out-of-image
+    // neighbours read pixel p and are masked)
+    int32_t r[CONN];
+    bool ok[CONN];
+#pragma unroll
+    for (int k = 0; k < CONN; ++k) {
+        int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
+        ok[k] = in_image(g, xx, yy, zz);
+        r[k] = ok[k] ? xx + g.nx * (yy + g.ny * zz) : p;
+    }
+    int w[CONN], dq[CONN];
+#pragma unroll
+    for (int k = 0; k < CONN; ++k) w[k] = I[r[k]];
+#pragma unroll
+    for (int k = 0; k < CONN; ++k) dq[k] = D[r[k]];
     int v = I[p], d = D[p];
     int m = SENT;
     int32_t q = -1;
 #pragma unroll
-    for (int k = 0; k < CONN; ++k) {
-        int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
-        if (!in_image(g, xx, yy, zz)) continue;
-        int32_t r = xx + g.nx * (yy + g.ny * zz);
-        int w = I[r];
-        if (w <= m) { m = w; q = r; }
-    }
+    for (int k = 0; k < CONN; ++k)
+        if (ok[k] && w[k] <= m) { m = w[k]; q = r[k]; }
     int state = (m > v) ? 1 : (m < v) ? 0 : (q > p ? 2 : 3);
     if (state_out) *state_out = state;
     if (d == INF) return -2;
     if (d == 0) return state == 0 ? q : -1;
 #pragma unroll
-    for (int k = 0; k < CONN; ++k) {
-        int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
-        if (!in_image(g, xx, yy, zz)) continue;
-        int32_t r = xx + g.nx * (yy + g.ny * zz);
-        if (I[r] == v && D[r] == d - 1) return r;
-    }
+    for (int k = 0; k < CONN; ++k)
+        if (ok[k] && w[k] == v && dq[k] == d - 1) return r[k];
     return -1;
 }
 
 // ---------------------------------------------------------------------------
 // Unions for every arrow / minimal-plateau adjacency that crosses a tile
-// border. One workgroup per tile; only the tile's border pixels work.
+// border, driven by the records of k_ws_label. One workgroup per tile, one
+// thread per border cell.
 // ---------------------------------------------------------------------------
 template <int NDIM, int CONN, typename T>
-__global__ __launch_bounds__(NTHREADS) void k_ws_merge(Geom g, const T *__restrict__ I, const int32_t *__restrict__ D,
+__global__ __launch_bounds__(NTHREADS) void k_ws_merge(Geom g, const T *__restrict__ I, const int32_t *__restrict__ rec,
                                                        int32_t *__restrict__ L) {
     using TS = TileShape<NDIM>;
-    constexpr int PIX = TS::X * TS::Y * TS::Z;
+    constexpr int NB = Border<NDIM>::NB;
     int ox, oy, oz;
     tile_origin<NDIM>(g, blockIdx.x, ox, oy, oz);
-    for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
-        int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-        if (!on_tile_border<NDIM>(x, y, z)) continue;
+    const int32_t *trec = rec + (size_t)blockIdx.x * NB;
+    for (int b = threadIdx.x; b < NB; b += NTHREADS) {
+        int x, y, z;
+        border_cell<NDIM>(b, x, y, z);
         int gx = ox + x, gy = oy + y, gz = oz + z;
         if (!in_image(g, gx, gy, gz)) continue;
+        int32_t code = trec[b];
+        if (code == -1) continue;
         int32_t p = gx + g.nx * (gy + g.ny * gz);
-        int32_t q = glb_arrow<CONN, T>(g, I, D, gx, gy, gz, p, nullptr);
-        if (q >= 0) {
-            int qx, qy, qz;
-            pixel_coords(g, q, qx, qy, qz);
-            if (qx < ox || qx >= ox + TS::X || qy < oy || qy >= oy + TS::Y || qz < oz || qz >= oz + TS::Z)
-                gunion(L, p, q);
-        } else if (q == -2) {
-            int v = I[p];
+        if (code >= 0) {
+            gunion(L, p, code);
+            continue;
+        }
+        int v = I[p];
 #pragma unroll
-            for (int k = CONN / 2; k < CONN; ++k) {
-                int xx = gx + nb_dx<CONN>(k), yy = gy + nb_dy<CONN>(k), zz = gz + nb_dz<CONN>(k);
-                if (!in_image(g, xx, yy, zz)) continue;
-                if (xx >= ox && xx < ox + TS::X && yy >= oy && yy < oy + TS::Y && zz >= oz && zz < oz + TS::Z) continue;
-                int32_t r = xx + g.nx * (yy + g.ny * zz);
-                if ((int)I[r] == v) gunion(L, p, r);
-            }
+        for (int k = CONN / 2; k < CONN; ++k) {
+            int xx = gx + nb_dx<CONN>(k), yy = gy + nb_dy<CONN>(k), zz = gz + nb_dz<CONN>(k);
+            if (!in_image(g, xx, yy, zz)) continue;
+            if (xx >= ox && xx < ox + TS::X && yy >= oy && yy < oy + TS::Y && zz >= oz && zz < oz + TS::Z) continue;
+            int32_t r = xx + g.nx * (yy + g.ny * zz);
+            if ((int)I[r] == v) gunion(L, p, r);
         }
     }
 }
@@ -454,16 +567,16 @@ static int launch_ws_sweep_t(Launch &lc, const Geom &g, const void *I, int32_t *
                   (const T *)I, D, stamp, changed, s);
 }
 template <int CONN, typename T>
-static int launch_ws_label_t(Launch &lc, const Geom &g, const void *I, const int32_t *D, int32_t *L) {
+static int launch_ws_label_t(Launch &lc, const Geom &g, const void *I, const int32_t *D, int32_t *L, int32_t *rec) {
     constexpr int ND = ndim_of<CONN>();
     return lc.run("ws_label", k_ws_label<ND, CONN, T>, dim3(g.ntx * g.nty * g.ntz), dim3(NTHREADS), g,
-                  (const T *)I, D, L);
+                  (const T *)I, D, L, rec);
 }
 template <int CONN, typename T>
-static int launch_ws_merge_t(Launch &lc, const Geom &g, const void *I, const int32_t *D, int32_t *L) {
+static int launch_ws_merge_t(Launch &lc, const Geom &g, const void *I, const int32_t *rec, int32_t *L) {
     constexpr int ND = ndim_of<CONN>();
     return lc.run("ws_merge", k_ws_merge<ND, CONN, T>, dim3(g.ntx * g.nty * g.ntz), dim3(NTHREADS), g,
-                  (const T *)I, D, L);
+                  (const T *)I, rec, L);
 }
 template <int CONN, typename T>
 static int launch_ws_stages_t(Launch &lc, const Geom &g, const void *I, const int32_t *D, int32_t *bal, int32_t *arrow) {
@@ -488,12 +601,14 @@ int launch_ws_sweep(Launch &lc, const Geom &g, int conn, bool u16, const void *I
                     int32_t *changed, int32_t s) {
     WS_DISPATCH(launch_ws_sweep_t, conn, u16, lc, g, I, D, stamp, changed, s)
 }
-int launch_ws_label(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *L) {
-    WS_DISPATCH(launch_ws_label_t, conn, u16, lc, g, I, D, L)
+int launch_ws_label(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *L,
+                    int32_t *rec) {
+    WS_DISPATCH(launch_ws_label_t, conn, u16, lc, g, I, D, L, rec)
 }
-int launch_ws_merge(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *L) {
-    WS_DISPATCH(launch_ws_merge_t, conn, u16, lc, g, I, D, L)
+int launch_ws_merge(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *rec, int32_t *L) {
+    WS_DISPATCH(launch_ws_merge_t, conn, u16, lc, g, I, rec, L)
 }
+int border_cells(int ndim) { return ndim == 3 ? Border<3>::NB : Border<2>::NB; }
 int launch_ws_stages(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *bal,
                      int32_t *arrow) {
     WS_DISPATCH(launch_ws_stages_t, conn, u16, lc, g, I, D, bal, arrow)

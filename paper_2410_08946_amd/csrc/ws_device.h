@@ -13,6 +13,7 @@ namespace wsk {
 constexpr int32_t INF = 0x7fffffff;   // unresolved plateau distance
 constexpr int32_t SENT = 0x10000;     // grey value of out-of-image cells (> any uint16)
 constexpr int NTHREADS = 256;          // threads of every tile kernel (4 waves of 64)
+constexpr int MAXSLOTS = 64;           // words holding partial maxima of the gradient
 
 // Unsigned division by a runtime constant for dividends below 2^31
 // (multiply-high with a rounded-up magic number, shift s = ceil(log2 d)).
@@ -78,6 +79,36 @@ __device__ __forceinline__ void pixel_coords(const Geom &g, int32_t p, int &x, i
 
 __device__ __forceinline__ bool in_image(const Geom &g, int x, int y, int z) {
     return x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+}
+
+// Batched, branch-free load of a box of cells (SX x SY x SZ, first cell at
+// image coordinates (bx, by, bz)) into LDS: every thread first computes all its
+// addresses (cells outside the image read pixel 0 and are replaced by `fill`),
+// then issues all its loads back to back, then writes LDS, so a workgroup
+// waits for one memory latency instead of one per cell.
+template <int SX, int SY, int SZ, typename T, typename V>
+__device__ __forceinline__ void load_box(const Geom &g, int bx, int by, int bz, const T *__restrict__ src, V *dst,
+                                         V fill) {
+    constexpr int CELLS = SX * SY * SZ;
+    constexpr int PER = (CELLS + NTHREADS - 1) / NTHREADS;
+    int32_t idx[PER];
+    bool ok[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int c = threadIdx.x + j * NTHREADS;
+        int cx = c % SX, cy = (c / SX) % SY, cz = c / (SX * SY);
+        int x = bx + cx, y = by + cy, z = bz + cz;
+        ok[j] = c < CELLS && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+        idx[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
+    }
+    T v[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) v[j] = src[idx[j]];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int c = threadIdx.x + j * NTHREADS;
+        if (c < CELLS) dst[c] = ok[j] ? (V)v[j] : fill;
+    }
 }
 
 // Relaxed loads that always go to the coherent level of the memory hierarchy

@@ -33,13 +33,18 @@ struct Launch {
 
     template <typename K, typename... A>
     int run(const char *name, K kernel, dim3 grid, dim3 block, A... args) {
+        return run_shm(name, kernel, grid, block, 0, args...);
+    }
+
+    template <typename K, typename... A>
+    int run_shm(const char *name, K kernel, dim3 grid, dim3 block, size_t shm, A... args) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (timing) {
             e0 = timing->get();
             e1 = timing->get();
             if (e0) (void)hipEventRecord(e0, stream);
         }
-        hipLaunchKernelGGL(kernel, grid, block, 0, stream, args...);
+        hipLaunchKernelGGL(kernel, grid, block, shm, stream, args...);
         hipError_t err = hipGetLastError();
         if (timing && e0 && e1) {
             (void)hipEventRecord(e1, stream);
@@ -63,8 +68,10 @@ int launch_ws_init(Launch &lc, const Geom &g, int conn, bool u16, const void *I,
                    int32_t *changed);
 int launch_ws_sweep(Launch &lc, const Geom &g, int conn, bool u16, const void *I, int32_t *D, int32_t *stamp,
                     int32_t *changed, int32_t s);
-int launch_ws_label(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *L);
-int launch_ws_merge(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *L);
+int border_cells(int ndim);
+int launch_ws_label(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *L,
+                    int32_t *rec);
+int launch_ws_merge(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *rec, int32_t *L);
 int launch_ws_stages(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *bal,
                      int32_t *arrow);
 int launch_ws_find(Launch &lc, int32_t n, int32_t *L);
@@ -72,19 +79,24 @@ int launch_ws_jump(Launch &lc, int32_t n, int32_t *L, int32_t rr, int32_t *chang
 int launch_fill_i32(Launch &lc, int32_t *a, int32_t n, int32_t v);
 
 // waterfall.hip
-int launch_wf_init(Launch &lc, int32_t n, const int32_t *lab, int32_t *list, int32_t *count, uint64_t *key, int32_t *par);
-int launch_wf_edge(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *lab, uint64_t *key);
+int compact_chunks(int32_t bound);
+int launch_wf_init(Launch &lc, int32_t n, const int32_t *lab, int32_t *list, int32_t *count, uint64_t *key, int32_t *par,
+                   int32_t *chunk_tmp);
+int launch_wf_edge(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *prev,
+                   const int32_t *map, int32_t *cur, uint64_t *key);
 int launch_wf_union(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, const uint64_t *key, int32_t *par);
 int launch_wf_compress(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, int32_t *par);
 int launch_wf_compact(Launch &lc, int32_t bound, const int32_t *list_in, const int32_t *count_in, int32_t *list_out,
-                      int32_t *count_out, const int32_t *par, uint64_t *key);
+                      int32_t *count_out, const int32_t *par, uint64_t *key, int32_t *chunk_tmp);
 int launch_wf_relabel(Launch &lc, int32_t n, const int32_t *prev, int32_t *cur, const int32_t *par);
 int launch_wf_counts(Launch &lc, int32_t nl, const int32_t *counts, int64_t *out);
 
 // gradient.hip
+constexpr int FUSED_MAX_R = 16;   // largest blur radius of the fused 2D kernel
+int launch_grad_fused2d(Launch &lc, const Geom &g, const float *img, float *mag, unsigned int *slots, const BlurTaps &taps);
 int launch_grad_blur(Launch &lc, const Geom &g, const float *in, float *out, int axis, const BlurTaps &taps);
-int launch_grad_sobel(Launch &lc, const Geom &g, int ndim, const float *a, float *mag, unsigned int *maxbits);
-int launch_grad_quant(Launch &lc, int32_t n, bool u16, const float *mag, void *out, const unsigned int *maxbits);
-int launch_grad_zero_max(Launch &lc, unsigned int *maxbits);
+int launch_grad_sobel(Launch &lc, const Geom &g, int ndim, const float *a, float *mag, unsigned int *slots);
+int launch_grad_quant(Launch &lc, int32_t n, bool u16, const float *mag, void *out, const unsigned int *slots);
+int launch_grad_zero_slots(Launch &lc, unsigned int *slots);
 
 }  // namespace wsk
