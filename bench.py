@@ -53,9 +53,174 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--workload", choices=("single", "batch", "serve"), default="single",
+                    help="single: the 4096x4096 image (default); batch: 512 uneven 2D images, "
+                         "one batched call vs one call per image; serve: Poisson arrivals of mixed "
+                         "2D/3D jobs through the continuous-batching server")
+    ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="serve workload: request rates (req/s)")
+    ap.add_argument("--requests", type=int, default=200, help="serve workload: requests per rate")
+    ap.add_argument("--slots", type=int, default=4, help="serve workload: execution slots")
+    ap.add_argument("--images", type=int, default=512, help="batch workload: number of images")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (counter calibration)")
     return ap.parse_args()
+
+
+def bench_batch(args):
+    """512 seeded uneven 2D u8 gradient images (sides log-uniform in [128, 2048],
+    content of the 256x256 blob recipe), 8-connectivity, watershed + NL = 4:
+    one ws_batch call per step vs one ws_watershed + ws_waterfall per image."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2410_08946_amd as ws
+
+    dev = torch.device("cuda:0")
+    conn, NL = 8, 4
+    ctx = ws.Context(0)
+    print("bench: generating %d images" % args.images, file=sys.stderr, flush=True)
+    import concurrent.futures as cf
+    grads = []
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(max_workers=workers) as pool:
+        for i, arr in enumerate(pool.map(gen.synth.batch_image, range(args.images), chunksize=8)):
+            img = torch.from_numpy(arr).to(dev)
+            grads.append(ctx.gradient(img, 0.0, "u8"))
+            del img
+            if (i + 1) % 128 == 0:
+                print("bench: %d images ready" % (i + 1), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    N = sum(int(g.numel()) for g in grads)
+    outs_b = [torch.empty((NL,) + tuple(g.shape), dtype=torch.int32, device=dev) for g in grads]
+    nreg_b = [torch.zeros(NL, dtype=torch.int64, device=dev) for _ in grads]
+    outs_s = [torch.empty((NL,) + tuple(g.shape), dtype=torch.int32, device=dev) for g in grads]
+    nreg_s = [torch.zeros(NL, dtype=torch.int64, device=dev) for _ in grads]
+
+    def step_batch():
+        ctx.batch(grads, conn, NL, outs=outs_b, nregions=nreg_b)
+
+    def step_single():
+        for g, o, n in zip(grads, outs_s, nreg_s):
+            ctx.watershed(g, conn, out=o[0])
+            ctx.waterfall(o[0], g, conn, NL, out=o, nregions=n)
+
+    def timed(fn, steps):
+        stream = torch.cuda.current_stream(dev)
+        a = torch.cuda.Event(enable_timing=True)
+        z = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        z.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(z) / steps
+
+    for _ in range(args.warmup):
+        step_batch()
+        step_single()
+    torch.cuda.synchronize()
+    print("bench: timing", file=sys.stderr, flush=True)
+    ms_b = timed(step_batch, args.steps)
+    ms_s = timed(step_single, max(1, args.steps // 4))
+    same = all(torch.equal(a, b) for a, b in zip(outs_b, outs_s)) and \
+        all(torch.equal(a, b) for a, b in zip(nreg_b, nreg_s))
+    line = {
+        "metric": "Mvoxel/s watershed+NL waterfall (batched)",
+        "value": round(N / (ms_b / 1e3) / 1e6, 2),
+        "unit": "Mvoxel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_b, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "%d uneven 2D uint8 gradient images (sides log-uniform in [128,2048], blob recipe), "
+                               "8-connectivity, watershed + NL=4" % args.images, "pixels": N, "NL": NL, "conn": conn,
+                   "parallelism": "single GPU"},
+        "per_image_calls": {"value": round(N / (ms_s / 1e3) / 1e6, 2), "unit": "Mvoxel/s", "ms_per_step": round(ms_s, 3)},
+        "batched_over_per_image": round(ms_s / ms_b, 3),
+        "identical_outputs": bool(same),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """Poisson arrivals (rates swept) of mixed jobs: 70 % square 2D u8 images
+    (sides 512-4096, 8-connectivity), 30 % cubic 3D u8 volumes (sides 128-512,
+    6-connectivity), NL = 4, through the continuous-batching server with
+    device-memory admission. Latency = arrival -> labels ready on the device."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2410_08946_amd as ws
+    from paper_2410_08946_amd import serve
+
+    dev = torch.device("cuda:0")
+    NL = 4
+    ctx = ws.Context(0)
+    pool2, pool3 = [], []
+    for spec in gen.synth.serving_pool_specs():
+        f = gen.synth.blobs_device(spec["shape"], spec["seed"], spec["n_blobs"], spec["sigma"], scale=spec["scale"],
+                                   noise=spec["noise"], salt=spec["salt"], device=dev)
+        g = ctx.gradient(f, 0.0, "u8")
+        (pool2 if len(spec["shape"]) == 2 else pool3).append((g, spec["conn"]))
+        del f
+    torch.cuda.synchronize()
+    print("bench: pool ready (%d 2D, %d 3D)" % (len(pool2), len(pool3)), file=sys.stderr, flush=True)
+    results = []
+    for rate in [float(r) for r in args.rates.split(",")]:
+        rng = np.random.default_rng(4)
+        gaps = rng.exponential(1.0 / rate, size=args.requests)
+        picks = rng.random(args.requests)
+        idx = rng.integers(0, 1 << 30, size=args.requests)
+        srv = serve.Server(slots=args.slots)
+        jobs = []
+        t0 = time.perf_counter()
+        t_next = t0
+        for k in range(args.requests):
+            t_next += gaps[k]
+            while time.perf_counter() < t_next:
+                time.sleep(max(0.0, min(0.001, t_next - time.perf_counter())))
+            g, conn = (pool2[idx[k] % len(pool2)] if picks[k] < 0.7 else pool3[idx[k] % len(pool3)])
+            jobs.append(srv.submit(serve.Job(grad=g, conn=conn, NL=NL, jid=k)))
+        srv.drain()
+        t_end = max(j.t_done for j in jobs)
+        lat = [1e3 * (j.t_done - j.t_arrival) for j in jobs if j.error is None]
+        vox = sum(int(j.grad.numel()) for j in jobs if j.error is None)
+        results.append({"rate": rate, "requests": args.requests, "completed": len(lat),
+                        "p50_ms": round(serve.percentile(lat, 50), 3), "p99_ms": round(serve.percentile(lat, 99), 3),
+                        "throughput_mvox_s": round(vox / (t_end - t0) / 1e6, 2),
+                        "micro_batches": srv.batches, "max_concurrent_slots": srv.max_concurrent})
+        print("bench: rate %g done: %s" % (rate, results[-1]), file=sys.stderr, flush=True)
+        srv.close()
+        del srv, jobs
+        torch.cuda.empty_cache()
+    best = max(r["throughput_mvox_s"] for r in results)
+    line = {
+        "metric": "Mvoxel/s watershed+NL waterfall (served), p50/p99 latency",
+        "value": best,
+        "unit": "Mvoxel/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "Poisson serving: 70%% 2D u8 512^2-4096^2 (8-conn), 30%% 3D u8 128^3-512^3 (6-conn), "
+                               "NL=4, %d slots, device-memory admission" % args.slots,
+                   "parallelism": "single GPU"},
+        "rates": results,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -64,6 +229,12 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr, flush=True)
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
+        return
     import numpy as np
     import torch
 

@@ -188,3 +188,57 @@ def serpentine(ny: int, nx: int, wall: int = 9, corridor: int = 5, exit_value: i
             img[y + 1, gx] = corridor
     img[0, 1] = exit_value
     return img
+
+
+def blobs_device(shape, seed, n_blobs, sigma, amp=(0.2, 1.0), scale=1.0, noise=0.0, salt=0.0, device="cuda:0"):
+    """The blob recipe evaluated on a torch device in float32 (pools of large
+    serving inputs). Parameters are drawn with PCG64 in the order of
+    blobs2d / blobs3d (centres x, y[, z], sigmas, amplitudes, then salt
+    positions or the noise field); each blob covers its 4-sigma box."""
+    import torch
+    rng = _rng(seed)
+    nd = len(shape)
+    dims = list(reversed(shape))  # x, y[, z]
+    cs = [rng.uniform(0.0, dims[a], n_blobs) for a in range(nd)]
+    sg = rng.uniform(sigma[0], sigma[1], n_blobs)
+    am = scale * rng.uniform(amp[0], amp[1], n_blobs)
+    f = torch.zeros(shape, dtype=torch.float32, device=device)
+    for i in range(n_blobs):
+        r = 4.0 * sg[i]
+        lo = [max(0, int(math.floor(cs[a][i] - r))) for a in range(nd)]
+        hi = [min(dims[a], int(math.ceil(cs[a][i] + r)) + 1) for a in range(nd)]
+        if any(l >= h for l, h in zip(lo, hi)):
+            continue
+        k = -1.0 / (2.0 * sg[i] * sg[i])
+        g1 = [torch.exp(k * (torch.arange(lo[a], hi[a], device=device, dtype=torch.float32) - float(cs[a][i])) ** 2)
+              for a in range(nd)]
+        if nd == 2:
+            f[lo[1]:hi[1], lo[0]:hi[0]] += float(am[i]) * g1[1][:, None] * g1[0][None, :]
+        else:
+            f[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] += float(am[i]) * (g1[2][:, None, None] * g1[1][None, :, None]
+                                                                          * g1[0][None, None, :])
+    n = f.numel()
+    if salt > 0:
+        idx = rng.choice(n, size=int(round(salt * n)), replace=False)
+        f.view(-1)[torch.from_numpy(idx).to(device)] = f.max()
+    if noise > 0:
+        f += torch.from_numpy(rng.normal(0.0, noise, size=shape).astype(np.float32)).to(device)
+    return f
+
+
+def serving_pool_specs(n2d: int = 24, n3d: int = 8, seed: int = 4):
+    """Job shapes of the serving mix: square 2D sides log-uniform in
+    [512, 4096] (8-connectivity), cubic 3D sides log-uniform in [128, 512]
+    (6-connectivity); 3D blob count at the 928^3 recipe's density."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(n2d):
+        s = int(round(math.exp(rng.uniform(math.log(512), math.log(4096)))))
+        specs.append(dict(shape=(s, s), conn=8, seed=4_000_000 + i, n_blobs=32, sigma=(8.0, 24.0), salt=0.01,
+                          noise=0.0, scale=1.0))
+    for i in range(n3d):
+        s = int(round(math.exp(rng.uniform(math.log(128), math.log(512)))))
+        nb = max(1, int(round(5000 * (s / 928.0) ** 3)))
+        specs.append(dict(shape=(s, s, s), conn=6, seed=4_100_000 + i, n_blobs=nb, sigma=(4.0, 32.0), salt=0.0,
+                          noise=2.0, scale=255.0))
+    return specs

@@ -134,6 +134,36 @@ int ws_waterfall(ws_ctx *ctx, const int32_t *labels, const void *grad, int dtype
                  void *stream);
 
 /*
+ * One image of a batched call (ws_batch).
+ *   grad      grey values (device, u8/u16 as the batch's dtype), read only.
+ *   nx,ny,nz  its size (same rules as ws_watershed; nz == 1 for conn 4/8 and
+ *             nz > 1 for conn 6/26).
+ *   out       int32[NL*N] (device): layer k at out + k*N, canonical labels
+ *             local to the image (smallest pixel index of the image).
+ *   nregions  optional int64[NL] (device): region count per layer.
+ */
+typedef struct {
+    const void *grad;
+    int64_t nx, ny, nz;
+    int32_t *out;
+    int64_t *nregions;
+} ws_item;
+
+/*
+ * Watershed + NL-layer waterfall of many images of uneven sizes in one set of
+ * launches (every kernel covers the tiles of all images through a tile ->
+ * image table; the Step II convergence loop is shared). The result of every
+ * image is bit-identical to ws_watershed followed by ws_waterfall on it alone.
+ *   items    host array of n_items >= 1 items; the total pixel count must be
+ *            below 2^31.
+ *   dtype    grey type of every item; conn: one connectivity for all items.
+ * Waits on `stream` a few times (Step II convergence, and to reuse the
+ * pinned staging of the previous call's tables). Same errors as ws_watershed;
+ * WS_EINVAL names the first offending item.
+ */
+int ws_batch(ws_ctx *ctx, const ws_item *items, int n_items, int dtype, int conn, int NL, void *stream);
+
+/*
  * Step-level outputs of the watershed for verification (Alg. 1, Steps I-II;
  * balanced encoding of Section 3.4).
  *   bal    int32[N]: -d for a non-minimal plateau pixel resolved at geodesic

@@ -14,6 +14,14 @@ _STATUS = {WS_EINVAL: "WS_EINVAL", WS_ENOMEM: "WS_ENOMEM", WS_EDEVICE: "WS_EDEVI
 
 # Every symbol include/ws.h declares, with its ctypes signature.
 _i64, _int, _ptr, _f32 = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_float
+
+
+class WsItem(ctypes.Structure):
+    """ws_item of include/ws.h."""
+    _fields_ = [("grad", ctypes.c_void_p), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("nz", ctypes.c_int64), ("out", ctypes.c_void_p), ("nregions", ctypes.c_void_p)]
+
+
 SIGNATURES = {
     "ws_create": (_int, [ctypes.POINTER(ctypes.c_void_p), _int]),
     "ws_destroy": (None, [_ptr]),
@@ -24,6 +32,7 @@ SIGNATURES = {
     "ws_watershed": (_int, [_ptr, _ptr, _int, _i64, _i64, _i64, _int, _ptr, _ptr]),
     "ws_waterfall": (_int, [_ptr, _ptr, _ptr, _int, _i64, _i64, _i64, _int, _int, _ptr, _ptr, _ptr]),
     "ws_watershed_stages": (_int, [_ptr, _ptr, _int, _i64, _i64, _i64, _int, _ptr, _ptr, _ptr]),
+    "ws_batch": (_int, [_ptr, ctypes.POINTER(WsItem), _int, _int, _int, _int, _ptr]),
     "ws_set_option": (_int, [_ptr, ctypes.c_char_p, _i64]),
     "ws_get_stats": (_int, [_ptr, ctypes.POINTER(ctypes.c_int64), _int]),
     "ws_timing_read": (_int, [_ptr, ctypes.c_char_p, _int, ctypes.POINTER(ctypes.c_double),
@@ -182,6 +191,31 @@ class Context:
                                                   int(conn), _dev(bal, "bal"), _dev(arrow, "arrow"), _stream(grad)))
         return bal, arrow
 
+    def batch(self, grads, conn: int, NL: int, outs=None, nregions=None):
+        """Watershed + NL-layer waterfall of a list of gradient tensors (same
+        dtype, one connectivity) in one batched call. Returns (outs, nregions):
+        per image an int32 [NL, *shape] tensor and an int64 [NL] tensor."""
+        import torch
+        if not grads:
+            raise ValueError("empty batch")
+        code = _grey_code(grads[0])
+        dev = grads[0].device
+        if outs is None:
+            outs = [torch.empty((int(NL),) + tuple(g.shape), dtype=torch.int32, device=dev) for g in grads]
+        if nregions is None:
+            nregions = [torch.zeros(int(NL), dtype=torch.int64, device=dev) for _ in grads]
+        items = (WsItem * len(grads))()
+        for i, g in enumerate(grads):
+            if _grey_code(g) != code:
+                raise TypeError("all gradients of a batch must share one dtype")
+            nx, ny, nz = _dims(g.shape)
+            items[i].grad = _dev(g, "gradient").value
+            items[i].nx, items[i].ny, items[i].nz = nx, ny, nz
+            items[i].out = _dev(outs[i], "out").value
+            items[i].nregions = _dev(nregions[i], "nregions").value
+        self._check(self._lib.ws_batch(self._h, items, len(grads), code, int(conn), int(NL), _stream(grads[0])))
+        return outs, nregions
+
     def waterfall(self, labels, grad, conn: int, NL: int, out=None, nregions=None):
         import torch
         nx, ny, nz = _dims(grad.shape)
@@ -216,6 +250,10 @@ def ws_watershed(grad, conn, out=None):
 
 def ws_waterfall(labels, grad, conn, NL, out=None, nregions=None):
     return default_context(grad.device.index or 0).waterfall(labels, grad, conn, NL, out=out, nregions=nregions)
+
+
+def ws_batch(grads, conn, NL, outs=None, nregions=None):
+    return default_context(grads[0].device.index or 0).batch(grads, conn, NL, outs=outs, nregions=nregions)
 
 
 def ws_watershed_stages(grad, conn):

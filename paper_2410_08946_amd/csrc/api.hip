@@ -37,8 +37,13 @@ struct ws_ctx {
     Buf D, stamp, cnt, rec;               // watershed scratch
     Buf key, par, lista, listb, wfcnt;    // waterfall scratch
     Buf g0, g1, mag, gmax;                // gradient scratch
-    Buf chunks;                           // compaction offsets
+    Buf chunks, tiletmp, tilecnt;         // compaction offsets, per-tile counts
+    Buf tab;                              // batch descriptor table + tile maps
     int32_t *host_cnt = nullptr;          // pinned readback of counters
+    void *stage = nullptr;                // pinned staging of batch tables
+    size_t stage_n = 0;
+    hipEvent_t stage_ev = nullptr;        // last upload from `stage`
+    bool stage_pending = false;
     int step3 = 0, rr = 6, sweep_batch = 4;
     int64_t max_sweeps = 0x7fffffff;
     bool timing = false;
@@ -129,18 +134,17 @@ Launch make_launch(ws_ctx *c, void *stream) {
     } while (0)
 
 // Step II to convergence: the initial tile pass, then batches of sweeps with
-// one counter read-back per batch. Leaves D converged in c->D.
-int run_distances(ws_ctx *c, Launch &lc, const Geom &g, int conn, bool u16, const void *grad) {
-    int32_t ntiles = g.ntx * g.nty * g.ntz;
-    size_t N = (size_t)g.n;
+// one counter read-back per batch. Leaves D converged in c->D (arena-wide).
+template <class Src>
+int run_distances(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg, int conn, bool u16, size_t arena) {
     int rc;
-    if ((rc = ensure(c, c->D, N * 4, "distances")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->stamp, (size_t)ntiles * 4, "tile stamps")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->D, arena * 4, "distances")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->stamp, (size_t)tg.ntiles * 4, "tile stamps")) != WS_OK) return rc;
     if ((rc = ensure(c, c->cnt, kCounterSlots * 4, "counters")) != WS_OK) return rc;
     int32_t *D = (int32_t *)c->D.p, *stamp = (int32_t *)c->stamp.p, *cnt = (int32_t *)c->cnt.p;
-    WS_TRY(wsk::launch_fill_i32(lc, stamp, ntiles, -1));
+    WS_TRY(wsk::launch_fill_i32(lc, stamp, tg.ntiles, -1));
     WS_TRY(wsk::launch_fill_i32(lc, cnt, kCounterSlots, 0));
-    WS_TRY(wsk::launch_ws_init(lc, g, conn, u16, grad, D, stamp, cnt));
+    WS_TRY(wsk::launch_ws_init(lc, src, tg, conn, u16, D, stamp, cnt));
     int64_t launched = 1, changing = 0;
     int32_t s = 1;
     bool first = true;
@@ -148,7 +152,8 @@ int run_distances(ws_ctx *c, Launch &lc, const Geom &g, int conn, bool u16, cons
     for (;;) {
         if (!first) WS_TRY(wsk::launch_fill_i32(lc, cnt, kCounterSlots, 0));
         int32_t s0 = s;
-        for (int b = 0; b < batch; ++b, ++s) WS_TRY(wsk::launch_ws_sweep(lc, g, conn, u16, grad, D, stamp, cnt + (s % kCounterSlots), s));
+        for (int b = 0; b < batch; ++b, ++s)
+            WS_TRY(wsk::launch_ws_sweep(lc, src, tg, conn, u16, D, stamp, cnt + (s % kCounterSlots), s));
         launched += batch;
         hipError_t e = hipMemcpyAsync(c->host_cnt, cnt, kCounterSlots * 4, hipMemcpyDeviceToHost, lc.stream);
         if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
@@ -173,8 +178,97 @@ int run_distances(ws_ctx *c, Launch &lc, const Geom &g, int conn, bool u16, cons
     }
     c->stats[0] = launched;
     c->stats[1] = changing;
-    c->stats[3] = ntiles;
+    c->stats[3] = tg.ntiles;
     return WS_OK;
+}
+
+// Watershed of every image of `src` into its lab (layer 0).
+template <class Src>
+int run_watershed(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg, int ndim, int conn, bool u16,
+                  size_t arena) {
+    int rc;
+    c->stats[2] = 0;
+    if ((rc = run_distances(c, lc, src, tg, conn, u16, arena)) != WS_OK) return rc;
+    size_t nrec = (size_t)tg.ntiles * wsk::border_cells(ndim);
+    if ((rc = ensure(c, c->rec, nrec * 4, "border records")) != WS_OK) return rc;
+    int32_t *rec = (int32_t *)c->rec.p;
+    const int32_t *D = (const int32_t *)c->D.p;
+    WS_TRY(wsk::launch_ws_label(lc, src, tg, conn, u16, D, rec));
+    WS_TRY(wsk::launch_ws_merge(lc, src, tg, conn, u16, rec));
+    if (c->step3 == 0) {
+        WS_TRY(wsk::launch_ws_find(lc, src, tg, conn));
+    } else {
+        int32_t *cnt = (int32_t *)c->cnt.p;
+        int64_t syncs = 0;
+        for (;;) {
+            WS_TRY(wsk::launch_fill_i32(lc, cnt, 1, 0));
+            WS_TRY(wsk::launch_ws_jump(lc, src, tg, conn, c->rr, cnt));
+            hipError_t e = hipMemcpyAsync(c->host_cnt, cnt, 4, hipMemcpyDeviceToHost, lc.stream);
+            if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+            if ((e = hipStreamSynchronize(lc.stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+            if (c->host_cnt[0] == 0) break;
+            ++syncs;
+        }
+        c->stats[2] = syncs;
+    }
+    return WS_OK;
+}
+
+// NL waterfall layers of every image of `src` (layer 0 already in lab).
+// Region counts go to outs[b] (batch, device array of device pointers) or
+// one_out (single image).
+template <class Src>
+int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg, int ndim, int conn, bool u16,
+                  int NL, size_t arena, const wsk::Img *tab_dev, const wsk::Img &one, int nimg,
+                  int64_t *const *outs_dev, int64_t *one_out) {
+    int rc;
+    int32_t bound = (int32_t)arena;
+    if ((rc = ensure(c, c->key, arena * 8, "region keys")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->par, arena * 4, "region parents")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->lista, arena * 4, "region list")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->listb, arena * 4, "region list")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->wfcnt, (size_t)NL * 4, "region counts")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->chunks, (size_t)wsk::compact_chunks(bound) * 4, "compaction offsets")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->tiletmp, (size_t)(tg.ntiles + 1) * 4, "tile offsets")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->tilecnt, (size_t)NL * tg.ntiles * 4, "tile counts")) != WS_OK) return rc;
+    uint64_t *key = (uint64_t *)c->key.p;
+    int32_t *par = (int32_t *)c->par.p, *cnt = (int32_t *)c->wfcnt.p, *chunks = (int32_t *)c->chunks.p;
+    int32_t *tcnt = (int32_t *)c->tilecnt.p;
+    int32_t *lists[2] = {(int32_t *)c->lista.p, (int32_t *)c->listb.p};
+    WS_TRY(wsk::launch_fill_i32(lc, cnt, NL, 0));
+    WS_TRY(wsk::launch_wf_init(lc, src, tg, ndim, lists[0], cnt, key, par, (int32_t *)c->tiletmp.p, tcnt));
+    for (int k = 1; k < NL; ++k) {
+        int32_t *lin = lists[(k - 1) & 1], *lout = lists[k & 1];
+        if (k == 1)
+            WS_TRY(wsk::launch_wf_edge(lc, src, tg, conn, u16, 0, 0, par, key, tcnt));
+        else  // relabel layer k-1 from layer k-2 while computing layer k-1's keys
+            WS_TRY(wsk::launch_wf_edge(lc, src, tg, conn, u16, k - 2, 1, par, key, tcnt + (size_t)(k - 1) * tg.ntiles));
+        WS_TRY(wsk::launch_wf_union(lc, bound, lin, cnt + k - 1, key, par));
+        WS_TRY(wsk::launch_wf_compress(lc, bound, lin, cnt + k - 1, par));
+        WS_TRY(wsk::launch_wf_compact(lc, bound, lin, cnt + k - 1, lout, cnt + k, par, key, chunks));
+    }
+    if (NL >= 2) WS_TRY(wsk::launch_wf_relabel(lc, src, tg, ndim, NL - 2, par, tcnt + (size_t)(NL - 1) * tg.ntiles));
+    if (outs_dev || one_out)
+        WS_TRY(wsk::launch_img_counts(lc, tab_dev, one, nimg, NL, tg.ntiles, tcnt, outs_dev, one_out));
+    return WS_OK;
+}
+
+wsk::Img single_img(int64_t nx, int64_t ny, int64_t nz, const void *grad, int32_t *lab) {
+    wsk::Img im{};
+    im.g = make_geom(nx, ny, nz, nz > 1 ? 3 : 2);
+    im.pix0 = 0;
+    im.tile0[0] = im.tile0[1] = im.tile0[2] = 0;
+    im.slot0 = 0;
+    im.grey = grad;
+    im.lab = lab;
+    return im;
+}
+
+wsk::TileGrid full_grid(int32_t ntiles) {
+    wsk::TileGrid tg;
+    tg.ntiles = ntiles;
+    tg.grid = ntiles > 0 ? ntiles : 1;
+    return tg;
 }
 
 }  // namespace
@@ -206,12 +300,14 @@ void ws_destroy(ws_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     Buf *bufs[] = {&c->D, &c->stamp, &c->cnt, &c->rec, &c->key, &c->par, &c->lista, &c->listb, &c->wfcnt,
-                   &c->g0, &c->g1, &c->mag, &c->gmax, &c->chunks};
+                   &c->g0, &c->g1, &c->mag, &c->gmax, &c->chunks, &c->tiletmp, &c->tilecnt, &c->tab};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &r : c->sink.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (auto e : c->sink.pool) (void)hipEventDestroy(e);
     if (c->host_cnt) (void)hipHostFree(c->host_cnt);
+    if (c->stage) (void)hipHostFree(c->stage);
+    if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
     delete c;
 }
 
@@ -327,34 +423,10 @@ int ws_watershed(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny,
     if (rc) return rc;
     if ((rc = set_device(c))) return rc;
     int ndim = nz > 1 ? 3 : 2;
-    Geom g = make_geom(nx, ny, nz, ndim);
     Launch lc = make_launch(c, stream);
-    bool u16 = dtype == WS_U16;
-    c->stats[2] = 0;
-    if ((rc = run_distances(c, lc, g, conn, u16, grad)) != WS_OK) return rc;
-    const int32_t *D = (const int32_t *)c->D.p;
-    size_t nrec = (size_t)g.ntx * g.nty * g.ntz * wsk::border_cells(ndim);
-    if ((rc = ensure(c, c->rec, nrec * 4, "border records")) != WS_OK) return rc;
-    int32_t *rec = (int32_t *)c->rec.p;
-    WS_TRY(wsk::launch_ws_label(lc, g, conn, u16, grad, D, labels, rec));
-    WS_TRY(wsk::launch_ws_merge(lc, g, conn, u16, grad, rec, labels));
-    if (c->step3 == 0) {
-        WS_TRY(wsk::launch_ws_find(lc, g.n, labels));
-    } else {
-        int32_t *cnt = (int32_t *)c->cnt.p;
-        int64_t syncs = 0;
-        for (;;) {
-            WS_TRY(wsk::launch_fill_i32(lc, cnt, 1, 0));
-            WS_TRY(wsk::launch_ws_jump(lc, g.n, labels, c->rr, cnt));
-            hipError_t e = hipMemcpyAsync(c->host_cnt, cnt, 4, hipMemcpyDeviceToHost, lc.stream);
-            if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
-            if ((e = hipStreamSynchronize(lc.stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
-            if (c->host_cnt[0] == 0) break;
-            ++syncs;
-        }
-        c->stats[2] = syncs;
-    }
-    return WS_OK;
+    wsk::OneImg src{single_img(nx, ny, nz, grad, labels)};
+    const wsk::Geom &g = src.im.g;
+    return run_watershed(c, lc, src, full_grid(g.ntx * g.nty * g.ntz), ndim, conn, dtype == WS_U16, (size_t)g.n);
 }
 
 int ws_watershed_stages(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz, int conn,
@@ -363,11 +435,11 @@ int ws_watershed_stages(ws_ctx *c, const void *grad, int dtype, int64_t nx, int6
     if (rc) return rc;
     if (!arrow) return fail(c, WS_EINVAL, "ws_watershed_stages: NULL buffer");
     if ((rc = set_device(c))) return rc;
-    int ndim = nz > 1 ? 3 : 2;
-    Geom g = make_geom(nx, ny, nz, ndim);
     Launch lc = make_launch(c, stream);
     bool u16 = dtype == WS_U16;
-    if ((rc = run_distances(c, lc, g, conn, u16, grad)) != WS_OK) return rc;
+    wsk::OneImg src{single_img(nx, ny, nz, grad, nullptr)};
+    const wsk::Geom &g = src.im.g;
+    if ((rc = run_distances(c, lc, src, full_grid(g.ntx * g.nty * g.ntz), conn, u16, (size_t)g.n)) != WS_OK) return rc;
     WS_TRY(wsk::launch_ws_stages(lc, g, conn, u16, grad, (const int32_t *)c->D.p, bal, arrow));
     return WS_OK;
 }
@@ -380,42 +452,106 @@ int ws_waterfall(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, 
     if (NL < 1) return fail(c, WS_EINVAL, "ws_waterfall: NL must be >= 1");
     if ((rc = set_device(c))) return rc;
     int ndim = nz > 1 ? 3 : 2;
-    Geom g = make_geom(nx, ny, nz, ndim);
-    size_t N = (size_t)g.n;
     Launch lc = make_launch(c, stream);
-    bool u16 = dtype == WS_U16;
-    if ((rc = ensure(c, c->key, N * 8, "region keys")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->par, N * 4, "region parents")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->lista, N * 4, "region list")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->listb, N * 4, "region list")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->wfcnt, (size_t)NL * 4, "region counts")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->chunks, (size_t)wsk::compact_chunks(g.n) * 4, "compaction offsets")) != WS_OK) return rc;
-    uint64_t *key = (uint64_t *)c->key.p;
-    int32_t *par = (int32_t *)c->par.p, *cnt = (int32_t *)c->wfcnt.p, *chunks = (int32_t *)c->chunks.p;
-    int32_t *lists[2] = {(int32_t *)c->lista.p, (int32_t *)c->listb.p};
+    wsk::OneImg src{single_img(nx, ny, nz, grad, out)};
+    const wsk::Geom &g = src.im.g;
     if (labels != out) {
-        hipError_t e = hipMemcpyAsync(out, labels, N * 4, hipMemcpyDeviceToDevice, lc.stream);
+        hipError_t e = hipMemcpyAsync(out, labels, (size_t)g.n * 4, hipMemcpyDeviceToDevice, lc.stream);
         if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
     }
-    WS_TRY(wsk::launch_fill_i32(lc, cnt, NL, 0));
-    WS_TRY(wsk::launch_wf_init(lc, g.n, out, lists[0], cnt, key, par, chunks));
-    for (int k = 1; k < NL; ++k) {
-        int32_t *lin = lists[(k - 1) & 1], *lout = lists[k & 1];
-        if (k == 1) {
-            WS_TRY(wsk::launch_wf_edge(lc, g, conn, u16, grad, out, nullptr, nullptr, key));
-        } else {
-            // relabel layer k-1 from layer k-2 while computing layer k's keys
-            WS_TRY(wsk::launch_wf_edge(lc, g, conn, u16, grad, out + (size_t)(k - 2) * N, par,
-                                       out + (size_t)(k - 1) * N, key));
-        }
-        WS_TRY(wsk::launch_wf_union(lc, g.n, lin, cnt + k - 1, key, par));
-        WS_TRY(wsk::launch_wf_compress(lc, g.n, lin, cnt + k - 1, par));
-        WS_TRY(wsk::launch_wf_compact(lc, g.n, lin, cnt + k - 1, lout, cnt + k, par, key, chunks));
+    return run_waterfall(c, lc, src, full_grid(wsk::wf_tiles(g, ndim)), ndim, conn, dtype == WS_U16, NL, (size_t)g.n,
+                         nullptr, src.im, 1, nullptr, nregions);
+}
+
+int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, int NL, void *stream) {
+    if (!c) return fail(c, WS_EINVAL, "ws_batch: ctx is NULL");
+    if (!items || n_items < 1) return fail(c, WS_EINVAL, "ws_batch: no items");
+    if (dtype != WS_U8 && dtype != WS_U16) return fail(c, WS_EINVAL, "ws_batch: dtype must be WS_U8 or WS_U16");
+    if (NL < 1) return fail(c, WS_EINVAL, "ws_batch: NL must be >= 1");
+    int ndim = (conn == 4 || conn == 8) ? 2 : (conn == 6 || conn == 26) ? 3 : 0;
+    if (!ndim) return fail(c, WS_EINVAL, "ws_batch: conn must be 4, 8, 6 or 26");
+    int64_t arena = 0, tws = 0, twf = 0;
+    std::string why;
+    for (int i = 0; i < n_items; ++i) {
+        const ws_item &it = items[i];
+        if (!it.grad || !it.out) return fail(c, WS_EINVAL, "ws_batch: item " + std::to_string(i) + " has a NULL buffer");
+        if (!valid_dims(it.nx, it.ny, it.nz, why)) return fail(c, WS_EINVAL, "ws_batch: item " + std::to_string(i) + ": " + why);
+        if (!valid_conn(it.nz, conn))
+            return fail(c, WS_EINVAL, "ws_batch: item " + std::to_string(i) + " does not match the connectivity");
+        arena += it.nx * it.ny * it.nz;
+        wsk::Geom g = make_geom(it.nx, it.ny, it.nz, ndim);
+        tws += (int64_t)g.ntx * g.nty * g.ntz;
+        twf += wsk::wf_tiles(g, ndim);
     }
-    if (NL >= 2)
-        WS_TRY(wsk::launch_wf_relabel(lc, g.n, out + (size_t)(NL - 2) * N, out + (size_t)(NL - 1) * N, par));
-    if (nregions) WS_TRY(wsk::launch_wf_counts(lc, NL, cnt, nregions));
-    return WS_OK;
+    if (arena >= (1LL << 31)) return fail(c, WS_EINVAL, "ws_batch: total pixels must be < 2^31");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    Launch lc = make_launch(c, stream);
+    // host staging: [Img table][ws tile map][wf tile map][nregions pointers]
+    size_t tab_b = sizeof(wsk::Img) * (size_t)n_items;
+    size_t off_ws = (tab_b + 255) & ~(size_t)255;
+    size_t off_wf = (off_ws + 4 * (size_t)tws + 255) & ~(size_t)255;
+    size_t off_outs = (off_wf + 4 * (size_t)twf + 255) & ~(size_t)255;
+    size_t total = off_outs + sizeof(int64_t *) * (size_t)n_items;
+    if (c->stage_pending) {
+        hipError_t e = hipEventSynchronize(c->stage_ev);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+        c->stage_pending = false;
+    }
+    if (c->stage_n < total) {
+        if (c->stage) (void)hipHostFree(c->stage);
+        c->stage = nullptr;
+        c->stage_n = 0;
+        hipError_t e = hipHostMalloc(&c->stage, total, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc");
+        c->stage_n = total;
+    }
+    if (!c->stage_ev) {
+        hipError_t e = hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+    }
+    if ((rc = ensure(c, c->tab, total, "batch tables")) != WS_OK) return rc;
+    char *h = (char *)c->stage;
+    wsk::Img *tab = (wsk::Img *)h;
+    int32_t *mws = (int32_t *)(h + off_ws), *mwf = (int32_t *)(h + off_wf);
+    int64_t **outs = (int64_t **)(h + off_outs);
+    int32_t pix = 0, t0 = 0, t1 = 0;
+    bool any_counts = false;
+    for (int i = 0; i < n_items; ++i) {
+        const ws_item &it = items[i];
+        wsk::Img im{};
+        im.g = make_geom(it.nx, it.ny, it.nz, ndim);
+        im.pix0 = pix;
+        im.tile0[wsk::TK_WS] = t0;
+        im.tile0[wsk::TK_WF] = t1;
+        im.tile0[wsk::TK_GR] = 0;
+        im.slot0 = 0;
+        im.grey = it.grad;
+        im.lab = it.out;
+        tab[i] = im;
+        int32_t nws = im.g.ntx * im.g.nty * im.g.ntz, nwf = wsk::wf_tiles(im.g, ndim);
+        for (int32_t k = 0; k < nws; ++k) mws[t0 + k] = i;
+        for (int32_t k = 0; k < nwf; ++k) mwf[t1 + k] = i;
+        outs[i] = it.nregions;
+        any_counts = any_counts || it.nregions;
+        pix += im.g.n;
+        t0 += nws;
+        t1 += nwf;
+    }
+    hipError_t e = hipMemcpyAsync(c->tab.p, c->stage, total, hipMemcpyHostToDevice, lc.stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+    if ((e = hipEventRecord(c->stage_ev, lc.stream)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
+    c->stage_pending = true;
+    char *d = (char *)c->tab.p;
+    const wsk::Img *tab_dev = (const wsk::Img *)d;
+    wsk::ImgTable src_ws{tab_dev, (const int32_t *)(d + off_ws)};
+    wsk::ImgTable src_wf{tab_dev, (const int32_t *)(d + off_wf)};
+    wsk::TileGrid tg_ws = full_grid((int32_t)tws), tg_wf = full_grid((int32_t)twf);
+    bool u16 = dtype == WS_U16;
+    if ((rc = run_watershed(c, lc, src_ws, tg_ws, ndim, conn, u16, (size_t)arena)) != WS_OK) return rc;
+    wsk::Img none{};
+    return run_waterfall(c, lc, src_wf, tg_wf, ndim, conn, u16, NL, (size_t)arena, tab_dev, none, n_items,
+                         any_counts ? (int64_t *const *)(d + off_outs) : nullptr, nullptr);
 }
 
 int ws_timing_reset(ws_ctx *c) {

@@ -1,12 +1,12 @@
 // watershed.hip -- gfx950 kernels of the watershed transform (Alg. 1).
 //
-// Data on the device (all int32 unless noted, N pixels each):
+// Data on the device (int32 unless noted, per image):
 //   I  grey values (uint8/uint16), read only
-//   D  Step II distance field: 0 for pixels with a lower neighbour (state 0)
-//      and for strict local minima (state 1); d >= 1 for a non-minimal
-//      plateau pixel at geodesic distance d from its plateau's lower border;
-//      INF for pixels of minimal plateaux (states 2/3 that Step II never
-//      resolves).
+//   D  Step II distance field (arena-wide scratch): 0 for pixels with a lower
+//      neighbour (state 0) and for strict local minima (state 1); d >= 1 for a
+//      non-minimal plateau pixel at geodesic distance d from its plateau's
+//      lower border; INF for pixels of minimal plateaux (states 2/3 that Step
+//      II never resolves).
 //   L  labels / union-find parents (parent <= pixel, roots are self loops).
 //
 // Step II is computed as the unique fixpoint of
@@ -17,31 +17,19 @@
 // neighbouring tile changed one of its border distances (tile "stamps").
 //
 // Arrows (Eq. (1) for pixels with a lower neighbour; the equal neighbour at
-// distance d-1 with the smallest index for resolved plateau pixels) and the
-// adjacency of minimal-plateau pixels (Step IV's union pairs) are then
-// contracted by union-find: inside each tile in LDS, then across tile borders
-// in global memory, then a final Find (path reduction, Step III). Because
-// unions always hook the larger root below the smaller, every basin ends with
-// its smallest pixel index as root: the canonical label.
+// distance d-1 with the smallest index for resolved plateau pixels) are then
+// contracted inside each tile by pointer jumping (Step III), minimal plateaux
+// are joined by union-find (Step IV), and every tile-local component is named
+// by its smallest pixel. Crossings between tiles go through a global
+// union-find that always hooks the larger root below the smaller, so every
+// basin ends with its smallest pixel index as root: the canonical label.
+//
+// Every tile kernel handles one tile per workgroup, of one image or of a batch
+// of images (through a tile -> image table); the same code serves both.
 #include "ws_device.h"
 #include "ws_kernels.h"
 
 namespace wsk {
-
-// ---------------------------------------------------------------------------
-// Tile helpers
-// ---------------------------------------------------------------------------
-template <int NDIM>
-__device__ __forceinline__ void tile_origin(const Geom &g, int t, int &ox, int &oy, int &oz) {
-    using TS = TileShape<NDIM>;
-    int tx = t % g.ntx;
-    int r = t / g.ntx;
-    int ty = r % g.nty;
-    int tz = r / g.nty;
-    ox = tx * TS::X;
-    oy = ty * TS::Y;
-    oz = tz * TS::Z;
-}
 
 // Loads grey values of the tile plus a ring of width R into LDS as int32;
 // cells outside the image get SENT.
@@ -67,7 +55,6 @@ __device__ __forceinline__ void relax_tile(int *sI, int *sD) {
     using TS = TileShape<NDIM>;
     using S = Lds<NDIM, R>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
-    constexpr int NB = CONN;
     for (;;) {
         int changed = 0;
         for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
@@ -79,7 +66,7 @@ __device__ __forceinline__ void relax_tile(int *sI, int *sD) {
             if (v == SENT) continue;
             int best = d;
 #pragma unroll
-            for (int k = 0; k < NB; ++k) {
+            for (int k = 0; k < CONN; ++k) {
                 int o = s + S::template off<CONN>(k);
                 int dq = sD[o];
                 if (sI[o] == v && dq != INF && dq + 1 < best) best = dq + 1;
@@ -98,53 +85,68 @@ __device__ __forceinline__ bool on_tile_border(int x, int y, int z) {
     return b;
 }
 
+template <int NDIM>
+__device__ __forceinline__ void ws_tile(const Geom &g, int lt, int &ox, int &oy, int &oz) {
+    using TS = TileShape<NDIM>;
+    tile_xyz<TS::X, TS::Y, TS::Z>(g, lt, ox, oy, oz);
+}
+
 // ---------------------------------------------------------------------------
 // Step I + first Step II pass: initial distances of the tile and its ring
 // (0 = has a lower neighbour or no equal one, INF = plateau pixel), then a
 // local fixpoint. Stamps the tile with sweep 0 when a border pixel obtained a
 // finite distance its neighbours could not have known.
 // ---------------------------------------------------------------------------
-template <int NDIM, int CONN, typename T>
-__global__ __launch_bounds__(NTHREADS) void k_ws_init(Geom g, const T *__restrict__ I, int32_t *__restrict__ D,
+template <int NDIM, int CONN, typename T, class Src>
+__global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, int32_t *__restrict__ Darena,
                                                       int32_t *__restrict__ stamp, int32_t *__restrict__ changed) {
     using TS = TileShape<NDIM>;
     using S2 = Lds<NDIM, 2>;
+    using S1 = Lds<NDIM, 1>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
     __shared__ int sI[S2::CELLS];
     __shared__ int sD[S2::CELLS];
-    int ox, oy, oz;
-    tile_origin<NDIM>(g, blockIdx.x, ox, oy, oz);
-    load_grey<NDIM, 2, T>(g, I, sI, ox, oy, oz);
-    __syncthreads();
-    // Initial distances on the tile plus a ring of width 1 (Step I state test).
-    using S1 = Lds<NDIM, 1>;
-    for (int c = threadIdx.x; c < S1::CELLS; c += NTHREADS) {
-        int cx = c % S1::SX, cy = (c / S1::SX) % S1::SY, cz = c / (S1::SX * S1::SY);
-        int s = S2::at(cx - 1, cy - 1, cz - S1::RZ);
-        int v = sI[s];
-        int d = INF;
-        if (v != SENT) {
-            int m = SENT;
+    {
+        const int t = blockIdx.x;
+        if (t >= ntiles) return;
+        Img im;
+        int lt;
+        fetch(src, t, TK_WS, im, lt);
+        const Geom &g = im.g;
+        int32_t *D = Darena + im.pix0;
+        int ox, oy, oz;
+        ws_tile<NDIM>(g, lt, ox, oy, oz);
+        load_grey<NDIM, 2, T>(g, (const T *)im.grey, sI, ox, oy, oz);
+        __syncthreads();
+        // Initial distances on the tile plus a ring of width 1 (Step I state test).
+        for (int c = threadIdx.x; c < S1::CELLS; c += NTHREADS) {
+            int cx = c % S1::SX, cy = (c / S1::SX) % S1::SY, cz = c / (S1::SX * S1::SY);
+            int s = S2::at(cx - 1, cy - 1, cz - S1::RZ);
+            int v = sI[s];
+            int d = INF;
+            if (v != SENT) {
+                int m = SENT;
 #pragma unroll
-            for (int k = 0; k < CONN; ++k) m = min(m, sI[s + S2::template off<CONN>(k)]);
-            d = (m == v) ? INF : 0;
+                for (int k = 0; k < CONN; ++k) m = min(m, sI[s + S2::template off<CONN>(k)]);
+                d = (m == v) ? INF : 0;
+            }
+            sD[s] = d;
         }
-        sD[s] = d;
-    }
-    __syncthreads();
-    relax_tile<NDIM, CONN, 2>(sI, sD);
-    int border = 0;
-    for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
-        int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-        int gx = ox + x, gy = oy + y, gz = oz + z;
-        if (!in_image(g, gx, gy, gz)) continue;
-        int d = sD[S2::at(x, y, z)];
-        D[gx + g.nx * (gy + g.ny * gz)] = d;
-        if (d != 0 && d != INF && on_tile_border<NDIM>(x, y, z)) border = 1;
-    }
-    if (__syncthreads_or(border) && threadIdx.x == 0) {
-        stamp[blockIdx.x] = 0;
-        atomicAdd(changed, 1);
+        __syncthreads();
+        relax_tile<NDIM, CONN, 2>(sI, sD);
+        int border = 0;
+        for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
+            int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+            int gx = ox + x, gy = oy + y, gz = oz + z;
+            if (!in_image(g, gx, gy, gz)) continue;
+            int d = sD[S2::at(x, y, z)];
+            D[gx + g.nx * (gy + g.ny * gz)] = d;
+            if (d != 0 && d != INF && on_tile_border<NDIM>(x, y, z)) border = 1;
+        }
+        if (__syncthreads_or(border) && threadIdx.x == 0) {
+            stamp[t] = 0;
+            atomicAdd(changed, 1);
+        }
     }
 }
 
@@ -152,8 +154,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Geom g, const T *__restric
 // Step II sweep s >= 1: tiles next to a tile stamped in sweep s-1 reload their
 // ring from global memory and relax again.
 // ---------------------------------------------------------------------------
-template <int NDIM, int CONN, typename T>
-__global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Geom g, const T *__restrict__ I, int32_t *__restrict__ D,
+template <int NDIM, int CONN, typename T, class Src>
+__global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, int32_t *__restrict__ Darena,
                                                        int32_t *__restrict__ stamp, int32_t *__restrict__ changed,
                                                        int32_t s) {
     using TS = TileShape<NDIM>;
@@ -162,52 +164,60 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Geom g, const T *__restri
     constexpr int PER = (PIX + NTHREADS - 1) / NTHREADS;
     __shared__ int sI[S::CELLS];
     __shared__ int sD[S::CELLS];
-    int t = blockIdx.x;
-    int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
-    int active = 0;
     {
-        int j = threadIdx.x;  // one neighbouring tile per thread
-        if (j < 27) {
-            int dx = j % 3 - 1, dy = (j / 3) % 3 - 1, dz = j / 9 - 1;
-            int ux = tx + dx, uy = ty + dy, uz = tz + dz;
-            bool used = (NDIM == 3 || dz == 0) && (dx != 0 || dy != 0 || dz != 0);
-            if (used && ux >= 0 && ux < g.ntx && uy >= 0 && uy < g.nty && uz >= 0 && uz < g.ntz)
-                active = stamp[ux + g.ntx * (uy + g.nty * uz)] == s - 1;
+        const int t = blockIdx.x;
+        if (t >= ntiles) return;
+        Img im;
+        int lt;
+        fetch(src, t, TK_WS, im, lt);
+        const Geom &g = im.g;
+        int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
+        int active = 0;
+        {
+            int j = threadIdx.x;  // one neighbouring tile per thread
+            if (j < 27) {
+                int dx = j % 3 - 1, dy = (j / 3) % 3 - 1, dz = j / 9 - 1;
+                int ux = tx + dx, uy = ty + dy, uz = tz + dz;
+                bool used = (NDIM == 3 || dz == 0) && (dx != 0 || dy != 0 || dz != 0);
+                if (used && ux >= 0 && ux < g.ntx && uy >= 0 && uy < g.nty && uz >= 0 && uz < g.ntz)
+                    active = stamp[im.tile0[TK_WS] + ux + g.ntx * (uy + g.nty * uz)] == s - 1;
+            }
         }
-    }
-    if (!__syncthreads_or(active)) return;
-    int ox = tx * TS::X, oy = ty * TS::Y, oz = tz * TS::Z;
-    load_grey<NDIM, 1, T>(g, I, sI, ox, oy, oz);
-    load_dist<NDIM>(g, D, sD, ox, oy, oz);
-    __syncthreads();
-    int before[PER];
+        if (!__syncthreads_or(active)) return;
+        int32_t *D = Darena + im.pix0;
+        int ox = tx * TS::X, oy = ty * TS::Y, oz = tz * TS::Z;
+        load_grey<NDIM, 1, T>(g, (const T *)im.grey, sI, ox, oy, oz);
+        load_dist<NDIM>(g, D, sD, ox, oy, oz);
+        __syncthreads();
+        int before[PER];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        int i = threadIdx.x + j * NTHREADS;
-        before[j] = INF;
-        if (i < PIX) {
+        for (int j = 0; j < PER; ++j) {
+            int i = threadIdx.x + j * NTHREADS;
+            before[j] = INF;
+            if (i < PIX) {
+                int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+                before[j] = sD[S::at(x, y, z)];
+            }
+        }
+        relax_tile<NDIM, CONN, 1>(sI, sD);
+        int border = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            int i = threadIdx.x + j * NTHREADS;
+            if (i >= PIX) continue;
             int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-            before[j] = sD[S::at(x, y, z)];
+            int gx = ox + x, gy = oy + y, gz = oz + z;
+            if (!in_image(g, gx, gy, gz)) continue;
+            int d = sD[S::at(x, y, z)];
+            if (d != before[j]) {
+                D[gx + g.nx * (gy + g.ny * gz)] = d;
+                if (on_tile_border<NDIM>(x, y, z)) border = 1;
+            }
         }
-    }
-    relax_tile<NDIM, CONN, 1>(sI, sD);
-    int border = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        int i = threadIdx.x + j * NTHREADS;
-        if (i >= PIX) continue;
-        int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-        int gx = ox + x, gy = oy + y, gz = oz + z;
-        if (!in_image(g, gx, gy, gz)) continue;
-        int d = sD[S::at(x, y, z)];
-        if (d != before[j]) {
-            D[gx + g.nx * (gy + g.ny * gz)] = d;
-            if (on_tile_border<NDIM>(x, y, z)) border = 1;
+        if (__syncthreads_or(border) && threadIdx.x == 0) {
+            stamp[t] = s;
+            atomicAdd(changed, 1);
         }
-    }
-    if (__syncthreads_or(border) && threadIdx.x == 0) {
-        stamp[t] = s;
-        atomicAdd(changed, 1);
     }
 }
 
@@ -297,14 +307,14 @@ __device__ __forceinline__ int border_index(int x, int y, int z) {
 // a minimal-plateau pixel, or an exit whose arrow leaves the tile. Minimal-
 // plateau pixels are then joined with their equal neighbours by union-find
 // (Step IV). Each tile-local component is named by its smallest pixel (LDS
-// atomicMin), written into L as a global index. For every border pixel the
-// crossing it needs in the global merge is recorded in rec: the target of an
-// arrow that leaves the tile, -2 for a minimal-plateau pixel with an equal
-// neighbour outside the tile, -1 otherwise.
+// atomicMin), written into L. For every border pixel the crossing it needs in
+// the global merge is recorded in rec: the target of an arrow that leaves the
+// tile, -2 for a minimal-plateau pixel with an equal neighbour outside the
+// tile, -1 otherwise.
 // ---------------------------------------------------------------------------
-template <int NDIM, int CONN, typename T>
-__global__ __launch_bounds__(NTHREADS) void k_ws_label(Geom g, const T *__restrict__ I, const int32_t *__restrict__ D,
-                                                       int32_t *__restrict__ L, int32_t *__restrict__ rec) {
+template <int NDIM, int CONN, typename T, class Src>
+__global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, const int32_t *__restrict__ Darena,
+                                                       int32_t *__restrict__ rec) {
     using TS = TileShape<NDIM>;
     using S = Lds<NDIM, 1>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
@@ -313,108 +323,252 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Geom g, const T *__restri
     __shared__ int sI[S::CELLS];
     __shared__ int sD[S::CELLS];
     __shared__ int sP[PIX];
-    int ox, oy, oz;
-    tile_origin<NDIM>(g, blockIdx.x, ox, oy, oz);
-    load_grey<NDIM, 1, T>(g, I, sI, ox, oy, oz);
-    load_dist<NDIM>(g, D, sD, ox, oy, oz);
-    __syncthreads();
-    uint32_t minzone = 0, inimg = 0;
-    int32_t *trec = rec + (size_t)blockIdx.x * Border<NDIM>::NB;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        int i = threadIdx.x + j * NTHREADS;
-        int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-        int gx = ox + x, gy = oy + y, gz = oz + z;
-        int to = i;
-        if (in_image(g, gx, gy, gz)) {
-            inimg |= 1u << j;
-            int s = S::at(x, y, z);
-            int k = lds_arrow<NDIM, CONN>(sI, sD, s);
-            int code = -1;
-            if (k >= 0) {
-                int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
-                if (xx >= 0 && xx < TS::X && yy >= 0 && yy < TS::Y && zz >= 0 && zz < TS::Z)
-                    to = xx + TS::X * (yy + TS::Y * zz);
-                else
-                    code = (gx + nb_dx<CONN>(k)) + g.nx * ((gy + nb_dy<CONN>(k)) + g.ny * (gz + nb_dz<CONN>(k)));
-            } else if (k == -2) {
-                minzone |= 1u << j;
-                int v = sI[s];
-#pragma unroll
-                for (int k2 = CONN / 2; k2 < CONN; ++k2) {  // neighbours after p
-                    int xx = x + nb_dx<CONN>(k2), yy = y + nb_dy<CONN>(k2), zz = z + nb_dz<CONN>(k2);
-                    bool inside = xx >= 0 && xx < TS::X && yy >= 0 && yy < TS::Y && zz >= 0 && zz < TS::Z;
-                    if (!inside && sI[s + S::template off<CONN>(k2)] == v) code = -2;
-                }
-            }
-            if (on_tile_border<NDIM>(x, y, z)) trec[border_index<NDIM>(x, y, z)] = code;
-        }
-        sP[i] = to;
-    }
-    __syncthreads();
-    // pointer jumping to the in-tile terminals
-    for (;;) {
-        int changed = 0;
+    {
+        const int t = blockIdx.x;
+        if (t >= ntiles) return;
+        Img im;
+        int lt;
+        fetch(src, t, TK_WS, im, lt);
+        const Geom &g = im.g;
+        int32_t *L = im.lab;
+        int ox, oy, oz;
+        ws_tile<NDIM>(g, lt, ox, oy, oz);
+        load_grey<NDIM, 1, T>(g, (const T *)im.grey, sI, ox, oy, oz);
+        load_dist<NDIM>(g, Darena + im.pix0, sD, ox, oy, oz);
+        __syncthreads();
+        uint32_t minzone = 0, inimg = 0;
+        int32_t *trec = rec + (size_t)t * Border<NDIM>::NB;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            int i = threadIdx.x + j * NTHREADS;
-            int p = sP[i];
-            int pp = sP[p];
-            if (pp != p) { sP[i] = pp; changed = 1; }
-        }
-        if (!__syncthreads_or(changed)) break;
-    }
-    // minimal plateaux: join equal neighbours after p inside the tile
-    if (minzone) {
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            if (!(minzone >> j & 1u)) continue;
             int i = threadIdx.x + j * NTHREADS;
             int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-            int s = S::at(x, y, z);
-            int v = sI[s];
+            int gx = ox + x, gy = oy + y, gz = oz + z;
+            int to = i;
+            if (in_image(g, gx, gy, gz)) {
+                inimg |= 1u << j;
+                int s = S::at(x, y, z);
+                int k = lds_arrow<NDIM, CONN>(sI, sD, s);
+                int code = -1;
+                if (k >= 0) {
+                    int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
+                    if (xx >= 0 && xx < TS::X && yy >= 0 && yy < TS::Y && zz >= 0 && zz < TS::Z)
+                        to = xx + TS::X * (yy + TS::Y * zz);
+                    else
+                        code = (gx + nb_dx<CONN>(k)) + g.nx * ((gy + nb_dy<CONN>(k)) + g.ny * (gz + nb_dz<CONN>(k)));
+                } else if (k == -2) {
+                    minzone |= 1u << j;
+                    int v = sI[s];
 #pragma unroll
-            for (int k2 = CONN / 2; k2 < CONN; ++k2) {
-                int xx = x + nb_dx<CONN>(k2), yy = y + nb_dy<CONN>(k2), zz = z + nb_dz<CONN>(k2);
-                if (xx < 0 || xx >= TS::X || yy < 0 || yy >= TS::Y || zz < 0 || zz >= TS::Z) continue;
-                if (sI[s + S::template off<CONN>(k2)] == v) lunion(sP, i, xx + TS::X * (yy + TS::Y * zz));
+                    for (int k2 = CONN / 2; k2 < CONN; ++k2) {  // neighbours after p
+                        int xx = x + nb_dx<CONN>(k2), yy = y + nb_dy<CONN>(k2), zz = z + nb_dz<CONN>(k2);
+                        bool inside = xx >= 0 && xx < TS::X && yy >= 0 && yy < TS::Y && zz >= 0 && zz < TS::Z;
+                        if (!inside && sI[s + S::template off<CONN>(k2)] == v) code = -2;
+                    }
+                }
+                if (on_tile_border<NDIM>(x, y, z)) trec[border_index<NDIM>(x, y, z)] = code;
+            }
+            sP[i] = to;
+        }
+        __syncthreads();
+        // pointer jumping to the in-tile terminals
+        for (;;) {
+            int changed = 0;
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                int i = threadIdx.x + j * NTHREADS;
+                int p = sP[i];
+                int pp = sP[p];
+                if (pp != p) { sP[i] = pp; changed = 1; }
+            }
+            if (!__syncthreads_or(changed)) break;
+        }
+        // minimal plateaux: join equal neighbours after p inside the tile
+        if (minzone) {
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                if (!(minzone >> j & 1u)) continue;
+                int i = threadIdx.x + j * NTHREADS;
+                int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+                int s = S::at(x, y, z);
+                int v = sI[s];
+#pragma unroll
+                for (int k2 = CONN / 2; k2 < CONN; ++k2) {
+                    int xx = x + nb_dx<CONN>(k2), yy = y + nb_dy<CONN>(k2), zz = z + nb_dz<CONN>(k2);
+                    if (xx < 0 || xx >= TS::X || yy < 0 || yy >= TS::Y || zz < 0 || zz >= TS::Z) continue;
+                    if (sI[s + S::template off<CONN>(k2)] == v) lunion(sP, i, xx + TS::X * (yy + TS::Y * zz));
+                }
             }
         }
-    }
-    __syncthreads();
-    // smallest pixel of every tile-local component (sD reused)
-    int *cm = sD;
+        __syncthreads();
+        // smallest pixel of every tile-local component (sD reused)
+        int *cm = sD;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) cm[threadIdx.x + j * NTHREADS] = 0x7fffffff;
-    __syncthreads();
-    int root[PER];
+        for (int j = 0; j < PER; ++j) cm[threadIdx.x + j * NTHREADS] = 0x7fffffff;
+        __syncthreads();
+        int root[PER];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        int i = threadIdx.x + j * NTHREADS;
-        root[j] = lfind(sP, i);
-        if (inimg >> j & 1u) atomicMin(&cm[root[j]], i);
-    }
-    __syncthreads();
+        for (int j = 0; j < PER; ++j) {
+            int i = threadIdx.x + j * NTHREADS;
+            root[j] = lfind(sP, i);
+            if (inimg >> j & 1u) atomicMin(&cm[root[j]], i);
+        }
+        __syncthreads();
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        if (!(inimg >> j & 1u)) continue;
-        int i = threadIdx.x + j * NTHREADS;
-        int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-        int r = cm[root[j]];
-        int rx = r % TS::X, ry = (r / TS::X) % TS::Y, rz = r / (TS::X * TS::Y);
-        L[(ox + x) + g.nx * ((oy + y) + g.ny * (oz + z))] = (ox + rx) + g.nx * ((oy + ry) + g.ny * (oz + rz));
+        for (int j = 0; j < PER; ++j) {
+            if (!(inimg >> j & 1u)) continue;
+            int i = threadIdx.x + j * NTHREADS;
+            int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+            int r = cm[root[j]];
+            int rx = r % TS::X, ry = (r / TS::X) % TS::Y, rz = r / (TS::X * TS::Y);
+            L[(ox + x) + g.nx * ((oy + y) + g.ny * (oz + z))] = (ox + rx) + g.nx * ((oy + ry) + g.ny * (oz + rz));
+        }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// Arrow of one pixel from global memory (same rules as lds_arrow).
-// Returns the target pixel, -1 for a root, -2 for a minimal plateau pixel.
+// Unions for every arrow / minimal-plateau adjacency that crosses a tile
+// border, driven by the records of k_ws_label. One thread per border cell.
+// ---------------------------------------------------------------------------
+template <int NDIM, int CONN, typename T, class Src>
+__global__ __launch_bounds__(NTHREADS) void k_ws_merge(Src src, int32_t ntiles, const int32_t *__restrict__ rec) {
+    using TS = TileShape<NDIM>;
+    constexpr int NB = Border<NDIM>::NB;
+    {
+        const int t = blockIdx.x;
+        if (t >= ntiles) return;
+        Img im;
+        int lt;
+        fetch(src, t, TK_WS, im, lt);
+        const Geom &g = im.g;
+        const T *I = (const T *)im.grey;
+        int32_t *L = im.lab;
+        int ox, oy, oz;
+        ws_tile<NDIM>(g, lt, ox, oy, oz);
+        const int32_t *trec = rec + (size_t)t * NB;
+        for (int b = threadIdx.x; b < NB; b += NTHREADS) {
+            int x, y, z;
+            border_cell<NDIM>(b, x, y, z);
+            int gx = ox + x, gy = oy + y, gz = oz + z;
+            if (!in_image(g, gx, gy, gz)) continue;
+            int32_t code = trec[b];
+            if (code == -1) continue;
+            int32_t p = gx + g.nx * (gy + g.ny * gz);
+            if (code >= 0) {
+                gunion(L, p, code);
+                continue;
+            }
+            int v = I[p];
+#pragma unroll
+            for (int k = CONN / 2; k < CONN; ++k) {
+                int xx = gx + nb_dx<CONN>(k), yy = gy + nb_dy<CONN>(k), zz = gz + nb_dz<CONN>(k);
+                if (!in_image(g, xx, yy, zz)) continue;
+                if (xx >= ox && xx < ox + TS::X && yy >= oy && yy < oy + TS::Y && zz >= oz && zz < oz + TS::Z) continue;
+                int32_t r = xx + g.nx * (yy + g.ny * zz);
+                if ((int)I[r] == v) gunion(L, p, r);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Final Find of every pixel (APRUF form: each pixel follows its own path), per
+// watershed tile.
+// ---------------------------------------------------------------------------
+template <int NDIM, class Src>
+__global__ __launch_bounds__(NTHREADS) void k_ws_find(Src src, int32_t ntiles) {
+    using TS = TileShape<NDIM>;
+    constexpr int PIX = TS::X * TS::Y * TS::Z;
+    constexpr int PER = PIX / NTHREADS;
+    {
+        const int t = blockIdx.x;
+        if (t >= ntiles) return;
+        Img im;
+        int lt;
+        fetch(src, t, TK_WS, im, lt);
+        const Geom &g = im.g;
+        int32_t *L = im.lab;
+        int ox, oy, oz;
+        ws_tile<NDIM>(g, lt, ox, oy, oz);
+        int32_t p[PER], r[PER];
+        bool ok[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            int i = threadIdx.x + j * NTHREADS;
+            int x = ox + i % TS::X, y = oy + (i / TS::X) % TS::Y, z = oz + i / (TS::X * TS::Y);
+            ok[j] = in_image(g, x, y, z);
+            p[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) r[j] = L[p[j]];
+        // chase all PER paths together so their loads overlap
+        uint32_t live = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (ok[j]) live |= 1u << j;
+        while (live) {
+            int32_t nxt[PER];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) nxt[j] = (live >> j & 1u) ? L[r[j]] : r[j];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                if (!(live >> j & 1u)) continue;
+                if (nxt[j] == r[j]) live &= ~(1u << j);
+                else r[j] = nxt[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (ok[j]) L[p[j]] = r[j];
+    }
+}
+
+// RR pointer jumps per synchronisation (PRUF form of Step III), per tile.
+template <int NDIM, class Src>
+__global__ __launch_bounds__(NTHREADS) void k_ws_jump(Src src, int32_t ntiles, int32_t rr,
+                                                      int32_t *__restrict__ changed) {
+    using TS = TileShape<NDIM>;
+    constexpr int PIX = TS::X * TS::Y * TS::Z;
+    {
+        const int t = blockIdx.x;
+        if (t >= ntiles) return;
+        Img im;
+        int lt;
+        fetch(src, t, TK_WS, im, lt);
+        const Geom &g = im.g;
+        int32_t *L = im.lab;
+        int ox, oy, oz;
+        ws_tile<NDIM>(g, lt, ox, oy, oz);
+        int ch = 0;
+        for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
+            int x = ox + i % TS::X, y = oy + (i / TS::X) % TS::Y, z = oz + i / (TS::X * TS::Y);
+            if (!in_image(g, x, y, z)) continue;
+            int32_t p = x + g.nx * (y + g.ny * z);
+            int32_t l = L[p];
+            bool moved = false;
+            for (int k = 0; k < rr; ++k) {
+                int32_t ll = ld_relaxed(L + l);
+                if (ll == l) break;
+                l = ll;
+                moved = true;
+            }
+            if (moved) {
+                L[p] = l;
+                ch = 1;
+            }
+        }
+        if (__syncthreads_or(ch) && threadIdx.x == 0) atomicAdd(changed, 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Arrow of one pixel from global memory (same rules as lds_arrow), used by
+// the step-level output kernel. Returns the target pixel, -1 for a root, -2
+// for a minimal plateau pixel.
 // ---------------------------------------------------------------------------
 template <int CONN, typename T>
 __device__ __forceinline__ int32_t glb_arrow(const Geom &g, const T *__restrict__ I, const int32_t *__restrict__ D,
-                                             int x, int y, int z, int32_t p, int32_t *state_out) {
-    // all neighbour loads are issued before any is used (out-of-image
-    // neighbours read pixel p and are masked)
+                                             int x, int y, int z, int32_t p, int32_t *state_out, int32_t *eq1_out) {
     int32_t r[CONN];
     bool ok[CONN];
 #pragma unroll
@@ -430,86 +584,19 @@ __device__ __forceinline__ int32_t glb_arrow(const Geom &g, const T *__restrict_
     for (int k = 0; k < CONN; ++k) dq[k] = D[r[k]];
     int v = I[p], d = D[p];
     int m = SENT;
-    int32_t q = -1;
+    int32_t q = p;
 #pragma unroll
     for (int k = 0; k < CONN; ++k)
         if (ok[k] && w[k] <= m) { m = w[k]; q = r[k]; }
     int state = (m > v) ? 1 : (m < v) ? 0 : (q > p ? 2 : 3);
-    if (state_out) *state_out = state;
+    *state_out = state;
+    *eq1_out = q;
     if (d == INF) return -2;
     if (d == 0) return state == 0 ? q : -1;
 #pragma unroll
     for (int k = 0; k < CONN; ++k)
         if (ok[k] && w[k] == v && dq[k] == d - 1) return r[k];
     return -1;
-}
-
-// ---------------------------------------------------------------------------
-// Unions for every arrow / minimal-plateau adjacency that crosses a tile
-// border, driven by the records of k_ws_label. One workgroup per tile, one
-// thread per border cell.
-// ---------------------------------------------------------------------------
-template <int NDIM, int CONN, typename T>
-__global__ __launch_bounds__(NTHREADS) void k_ws_merge(Geom g, const T *__restrict__ I, const int32_t *__restrict__ rec,
-                                                       int32_t *__restrict__ L) {
-    using TS = TileShape<NDIM>;
-    constexpr int NB = Border<NDIM>::NB;
-    int ox, oy, oz;
-    tile_origin<NDIM>(g, blockIdx.x, ox, oy, oz);
-    const int32_t *trec = rec + (size_t)blockIdx.x * NB;
-    for (int b = threadIdx.x; b < NB; b += NTHREADS) {
-        int x, y, z;
-        border_cell<NDIM>(b, x, y, z);
-        int gx = ox + x, gy = oy + y, gz = oz + z;
-        if (!in_image(g, gx, gy, gz)) continue;
-        int32_t code = trec[b];
-        if (code == -1) continue;
-        int32_t p = gx + g.nx * (gy + g.ny * gz);
-        if (code >= 0) {
-            gunion(L, p, code);
-            continue;
-        }
-        int v = I[p];
-#pragma unroll
-        for (int k = CONN / 2; k < CONN; ++k) {
-            int xx = gx + nb_dx<CONN>(k), yy = gy + nb_dy<CONN>(k), zz = gz + nb_dz<CONN>(k);
-            if (!in_image(g, xx, yy, zz)) continue;
-            if (xx >= ox && xx < ox + TS::X && yy >= oy && yy < oy + TS::Y && zz >= oz && zz < oz + TS::Z) continue;
-            int32_t r = xx + g.nx * (yy + g.ny * zz);
-            if ((int)I[r] == v) gunion(L, p, r);
-        }
-    }
-}
-
-// Final Find of every pixel (per-pixel path reduction, APRUF form).
-__global__ __launch_bounds__(NTHREADS) void k_ws_find(int32_t n, int32_t *__restrict__ L) {
-    int32_t p = blockIdx.x * NTHREADS + threadIdx.x;
-    if (p >= n) return;
-    int32_t r = L[p];
-    for (;;) {
-        int32_t rr = L[r];
-        if (rr == r) break;
-        r = rr;
-    }
-    L[p] = r;
-}
-
-// RR pointer jumps per synchronisation (PRUF form of Step III).
-__global__ __launch_bounds__(NTHREADS) void k_ws_jump(int32_t n, int32_t *__restrict__ L, int32_t rr,
-                                                      int32_t *__restrict__ changed) {
-    int32_t p = blockIdx.x * NTHREADS + threadIdx.x;
-    int ch = 0;
-    if (p < n) {
-        int32_t l = L[p];
-        for (int i = 0; i < rr; ++i) {
-            int32_t ll = ld_relaxed(L + l);
-            if (ll == l) break;
-            l = ll;
-            ch = 1;
-        }
-        if (ch) L[p] = l;
-    }
-    if (__syncthreads_or(ch) && threadIdx.x == 0) atomicAdd(changed, 1);
 }
 
 // Step-level outputs (balanced state encoding and arrows) for verification.
@@ -521,7 +608,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_stages(Geom g, const T *__restr
     int x, y, z;
     pixel_coords(g, p, x, y, z);
     int state = 1;
-    int32_t q = glb_arrow<CONN, T>(g, I, D, x, y, z, p, &state);
+    int32_t eq1 = p;
+    int32_t q = glb_arrow<CONN, T>(g, I, D, x, y, z, p, &state, &eq1);
     int d = D[p];
     if (d != 0 && d != INF) {
         bal[p] = -d;
@@ -529,20 +617,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_stages(Geom g, const T *__restr
         return;
     }
     bal[p] = state;
-    if (state == 0) arrow[p] = q;
-    else if (state == 2) {  // minimal plateau pixel: Eq. (1) target
-        int m = SENT;
-        int32_t qq = p;
-#pragma unroll
-        for (int k = 0; k < CONN; ++k) {
-            int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
-            if (!in_image(g, xx, yy, zz)) continue;
-            int32_t r = xx + g.nx * (yy + g.ny * zz);
-            int w = I[r];
-            if (w <= m) { m = w; qq = r; }
-        }
-        arrow[p] = qq;
-    } else arrow[p] = p;
+    arrow[p] = (state == 0 || state == 2) ? eq1 : p;  // Eq. (1) target, or a self loop
 }
 
 __global__ void k_fill_i32(int32_t *a, int32_t n, int32_t v) {
@@ -551,32 +626,41 @@ __global__ void k_fill_i32(int32_t *a, int32_t n, int32_t v) {
 }
 
 // ---------------------------------------------------------------------------
-// Host-side launchers (instantiated per connectivity and grey type).
+// Host-side launchers (instantiated per connectivity, grey type and source).
 // ---------------------------------------------------------------------------
-template <int CONN, typename T>
-static int launch_ws_init_t(Launch &lc, const Geom &g, const void *I, int32_t *D, int32_t *stamp, int32_t *changed) {
+template <int CONN, typename T, class Src>
+static int launch_ws_init_t(Launch &lc, const Src &src, const TileGrid &tg, int32_t *D, int32_t *stamp,
+                            int32_t *changed) {
     constexpr int ND = ndim_of<CONN>();
-    return lc.run("ws_init", k_ws_init<ND, CONN, T>, dim3(g.ntx * g.nty * g.ntz), dim3(NTHREADS), g,
-                  (const T *)I, D, stamp, changed);
+    return lc.run("ws_init", k_ws_init<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, D, stamp,
+                  changed);
 }
-template <int CONN, typename T>
-static int launch_ws_sweep_t(Launch &lc, const Geom &g, const void *I, int32_t *D, int32_t *stamp, int32_t *changed,
-                             int32_t s) {
+template <int CONN, typename T, class Src>
+static int launch_ws_sweep_t(Launch &lc, const Src &src, const TileGrid &tg, int32_t *D, int32_t *stamp,
+                             int32_t *changed, int32_t s) {
     constexpr int ND = ndim_of<CONN>();
-    return lc.run("ws_sweep", k_ws_sweep<ND, CONN, T>, dim3(g.ntx * g.nty * g.ntz), dim3(NTHREADS), g,
-                  (const T *)I, D, stamp, changed, s);
+    return lc.run("ws_sweep", k_ws_sweep<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, D, stamp,
+                  changed, s);
 }
-template <int CONN, typename T>
-static int launch_ws_label_t(Launch &lc, const Geom &g, const void *I, const int32_t *D, int32_t *L, int32_t *rec) {
+template <int CONN, typename T, class Src>
+static int launch_ws_label_t(Launch &lc, const Src &src, const TileGrid &tg, const int32_t *D, int32_t *rec) {
     constexpr int ND = ndim_of<CONN>();
-    return lc.run("ws_label", k_ws_label<ND, CONN, T>, dim3(g.ntx * g.nty * g.ntz), dim3(NTHREADS), g,
-                  (const T *)I, D, L, rec);
+    return lc.run("ws_label", k_ws_label<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, D, rec);
 }
-template <int CONN, typename T>
-static int launch_ws_merge_t(Launch &lc, const Geom &g, const void *I, const int32_t *rec, int32_t *L) {
+template <int CONN, typename T, class Src>
+static int launch_ws_merge_t(Launch &lc, const Src &src, const TileGrid &tg, const int32_t *rec) {
     constexpr int ND = ndim_of<CONN>();
-    return lc.run("ws_merge", k_ws_merge<ND, CONN, T>, dim3(g.ntx * g.nty * g.ntz), dim3(NTHREADS), g,
-                  (const T *)I, rec, L);
+    return lc.run("ws_merge", k_ws_merge<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, rec);
+}
+template <int CONN, typename T, class Src>
+static int launch_ws_find_t(Launch &lc, const Src &src, const TileGrid &tg) {
+    constexpr int ND = ndim_of<CONN>();
+    return lc.run("ws_find", k_ws_find<ND, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles);
+}
+template <int CONN, typename T, class Src>
+static int launch_ws_jump_t(Launch &lc, const Src &src, const TileGrid &tg, int32_t rr, int32_t *changed) {
+    constexpr int ND = ndim_of<CONN>();
+    return lc.run("ws_jump", k_ws_jump<ND, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, rr, changed);
 }
 template <int CONN, typename T>
 static int launch_ws_stages_t(Launch &lc, const Geom &g, const void *I, const int32_t *D, int32_t *bal, int32_t *arrow) {
@@ -584,44 +668,49 @@ static int launch_ws_stages_t(Launch &lc, const Geom &g, const void *I, const in
                   (const T *)I, D, bal, arrow);
 }
 
-#define WS_DISPATCH(FN, conn, u16, ...)                                        \
-    switch (conn) {                                                            \
+#define WS_DISPATCH(FN, conn, u16, ...)                                                  \
+    switch (conn) {                                                                      \
     case 4: return u16 ? FN<4, uint16_t>(__VA_ARGS__) : FN<4, uint8_t>(__VA_ARGS__);     \
     case 8: return u16 ? FN<8, uint16_t>(__VA_ARGS__) : FN<8, uint8_t>(__VA_ARGS__);     \
     case 6: return u16 ? FN<6, uint16_t>(__VA_ARGS__) : FN<6, uint8_t>(__VA_ARGS__);     \
     case 26: return u16 ? FN<26, uint16_t>(__VA_ARGS__) : FN<26, uint8_t>(__VA_ARGS__);  \
-    default: return -1;                                                        \
+    default: return -1;                                                                  \
     }
 
-int launch_ws_init(Launch &lc, const Geom &g, int conn, bool u16, const void *I, int32_t *D, int32_t *stamp,
-                   int32_t *changed) {
-    WS_DISPATCH(launch_ws_init_t, conn, u16, lc, g, I, D, stamp, changed)
-}
-int launch_ws_sweep(Launch &lc, const Geom &g, int conn, bool u16, const void *I, int32_t *D, int32_t *stamp,
-                    int32_t *changed, int32_t s) {
-    WS_DISPATCH(launch_ws_sweep_t, conn, u16, lc, g, I, D, stamp, changed, s)
-}
-int launch_ws_label(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *L,
-                    int32_t *rec) {
-    WS_DISPATCH(launch_ws_label_t, conn, u16, lc, g, I, D, L, rec)
-}
-int launch_ws_merge(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *rec, int32_t *L) {
-    WS_DISPATCH(launch_ws_merge_t, conn, u16, lc, g, I, rec, L)
-}
-int border_cells(int ndim) { return ndim == 3 ? Border<3>::NB : Border<2>::NB; }
+#define WS_SRC_FUNCS(Src)                                                                                          \
+    int launch_ws_init(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,            \
+                       int32_t *stamp, int32_t *changed) {                                                         \
+        WS_DISPATCH(launch_ws_init_t, conn, u16, lc, src, tg, D, stamp, changed)                                   \
+    }                                                                                                              \
+    int launch_ws_sweep(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,           \
+                        int32_t *stamp, int32_t *changed, int32_t s) {                                             \
+        WS_DISPATCH(launch_ws_sweep_t, conn, u16, lc, src, tg, D, stamp, changed, s)                               \
+    }                                                                                                              \
+    int launch_ws_label(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *D,     \
+                        int32_t *rec) {                                                                            \
+        WS_DISPATCH(launch_ws_label_t, conn, u16, lc, src, tg, D, rec)                                             \
+    }                                                                                                              \
+    int launch_ws_merge(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *rec) { \
+        WS_DISPATCH(launch_ws_merge_t, conn, u16, lc, src, tg, rec)                                                \
+    }                                                                                                              \
+    int launch_ws_find(Launch &lc, const Src &src, const TileGrid &tg, int conn) {                                \
+        WS_DISPATCH(launch_ws_find_t, conn, false, lc, src, tg)                                                    \
+    }                                                                                                              \
+    int launch_ws_jump(Launch &lc, const Src &src, const TileGrid &tg, int conn, int32_t rr, int32_t *changed) {  \
+        WS_DISPATCH(launch_ws_jump_t, conn, false, lc, src, tg, rr, changed)                                       \
+    }
+
+WS_SRC_FUNCS(OneImg)
+WS_SRC_FUNCS(ImgTable)
+
 int launch_ws_stages(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *bal,
                      int32_t *arrow) {
     WS_DISPATCH(launch_ws_stages_t, conn, u16, lc, g, I, D, bal, arrow)
-}
-int launch_ws_find(Launch &lc, int32_t n, int32_t *L) {
-    return lc.run("ws_find", k_ws_find, dim3((n + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), n, L);
-}
-int launch_ws_jump(Launch &lc, int32_t n, int32_t *L, int32_t rr, int32_t *changed) {
-    return lc.run("ws_jump", k_ws_jump, dim3((n + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), n, L, rr, changed);
 }
 int launch_fill_i32(Launch &lc, int32_t *a, int32_t n, int32_t v) {
     if (n <= 0) return 0;
     return lc.run("fill", k_fill_i32, dim3((n + 255) / 256), dim3(256), a, n, v);
 }
+int border_cells(int ndim) { return ndim == 3 ? Border<3>::NB : Border<2>::NB; }
 
 }  // namespace wsk

@@ -35,6 +35,52 @@ struct Geom {
     FastDiv dnx, dny;          // division by nx and ny
 };
 
+// One image of a call. A single-image call passes one Img by value; a batched
+// call passes a device table of them plus, per tiling, a tile -> image map.
+// Scratch that spans the whole call (distances, region keys and parents) is
+// addressed with pix0 + local pixel index ("arena" index).
+enum TileKind { TK_WS = 0, TK_WF = 1, TK_GR = 2 };
+
+struct Img {
+    Geom g;               // sizes (the ntx/nty/ntz fields hold the watershed tiling)
+    int32_t pix0;         // arena offset of the image's pixel 0
+    int32_t tile0[3];     // first tile of the image in each tiling (global tile index)
+    int32_t slot0;        // first partial-maximum word (gradient)
+    const void *grey;     // quantised gradient (u8/u16)
+    int32_t *lab;         // label layers: layer k at lab + k * g.n
+    const float *fimg;    // gradient input
+    void *gout;           // gradient output
+    float *mag;           // gradient magnitude
+};
+
+struct OneImg {
+    Img im;
+};
+struct ImgTable {
+    const Img *tab;       // device table of images
+    const int32_t *map;   // global tile -> image, for the kernel's tiling
+};
+
+__device__ __forceinline__ void fetch(const OneImg &s, int t, int, Img &im, int &lt) {
+    im = s.im;
+    lt = t;
+}
+__device__ __forceinline__ void fetch(const ImgTable &s, int t, int kind, Img &im, int &lt) {
+    int b = s.map[t];
+    im = s.tab[b];
+    lt = t - im.tile0[kind];
+}
+
+// Origin of local tile lt of a tiling with tile shape (X, Y, Z).
+template <int X, int Y, int Z>
+__device__ __forceinline__ void tile_xyz(const Geom &g, int lt, int &ox, int &oy, int &oz) {
+    int ntx = (g.nx + X - 1) / X, nty = (g.ny + Y - 1) / Y;
+    int tx = lt % ntx, r = lt / ntx;
+    ox = tx * X;
+    oy = (r % nty) * Y;
+    oz = (r / nty) * Z;
+}
+
 // Neighbour k of a connectivity, as an index j into the 3x3x3 cube
 // (j = 9*(dz+1) + 3*(dy+1) + (dx+1)); increasing k gives increasing j, hence
 // increasing linear pixel index.

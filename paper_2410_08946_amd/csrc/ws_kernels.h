@@ -63,33 +63,48 @@ struct BlurTaps {
     float w[129];
 };
 
+// Tiles of one tiling and the launch grid that covers them (one workgroup per
+// tile).
+struct TileGrid {
+    int32_t ntiles = 0;
+    int32_t grid = 0;
+};
+
 // watershed.hip
-int launch_ws_init(Launch &lc, const Geom &g, int conn, bool u16, const void *I, int32_t *D, int32_t *stamp,
-                   int32_t *changed);
-int launch_ws_sweep(Launch &lc, const Geom &g, int conn, bool u16, const void *I, int32_t *D, int32_t *stamp,
-                    int32_t *changed, int32_t s);
+#define WS_DECL_SRC(Src)                                                                                          \
+    int launch_ws_init(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,           \
+                       int32_t *stamp, int32_t *changed);                                                         \
+    int launch_ws_sweep(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,          \
+                        int32_t *stamp, int32_t *changed, int32_t s);                                             \
+    int launch_ws_label(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *D,    \
+                        int32_t *rec);                                                                            \
+    int launch_ws_merge(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *rec); \
+    int launch_ws_find(Launch &lc, const Src &src, const TileGrid &tg, int conn);                                \
+    int launch_ws_jump(Launch &lc, const Src &src, const TileGrid &tg, int conn, int32_t rr, int32_t *changed);  \
+    int launch_wf_init(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t *list, int32_t *count,  \
+                       uint64_t *key, int32_t *par, int32_t *tile_tmp, int32_t *tile_cnt0);                       \
+    int launch_wf_edge(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t layer,        \
+                       int32_t relabel, const int32_t *par, uint64_t *key, int32_t *tile_cnt);                    \
+    int launch_wf_relabel(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t layer,               \
+                          const int32_t *par, int32_t *tile_cnt);
+WS_DECL_SRC(OneImg)
+WS_DECL_SRC(ImgTable)
+#undef WS_DECL_SRC
+
 int border_cells(int ndim);
-int launch_ws_label(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *L,
-                    int32_t *rec);
-int launch_ws_merge(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *rec, int32_t *L);
 int launch_ws_stages(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *bal,
                      int32_t *arrow);
-int launch_ws_find(Launch &lc, int32_t n, int32_t *L);
-int launch_ws_jump(Launch &lc, int32_t n, int32_t *L, int32_t rr, int32_t *changed);
 int launch_fill_i32(Launch &lc, int32_t *a, int32_t n, int32_t v);
 
 // waterfall.hip
 int compact_chunks(int32_t bound);
-int launch_wf_init(Launch &lc, int32_t n, const int32_t *lab, int32_t *list, int32_t *count, uint64_t *key, int32_t *par,
-                   int32_t *chunk_tmp);
-int launch_wf_edge(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *prev,
-                   const int32_t *map, int32_t *cur, uint64_t *key);
+int wf_tiles(const Geom &g, int ndim);
 int launch_wf_union(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, const uint64_t *key, int32_t *par);
 int launch_wf_compress(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, int32_t *par);
 int launch_wf_compact(Launch &lc, int32_t bound, const int32_t *list_in, const int32_t *count_in, int32_t *list_out,
                       int32_t *count_out, const int32_t *par, uint64_t *key, int32_t *chunk_tmp);
-int launch_wf_relabel(Launch &lc, int32_t n, const int32_t *prev, int32_t *cur, const int32_t *par);
-int launch_wf_counts(Launch &lc, int32_t nl, const int32_t *counts, int64_t *out);
+int launch_img_counts(Launch &lc, const Img *tab, const Img &one, int32_t nimg, int32_t nl, int32_t ntiles_total,
+                      const int32_t *tile_cnt, int64_t *const *outs, int64_t *one_out);
 
 // gradient.hip
 constexpr int FUSED_MAX_R = 16;   // largest blur radius of the fused 2D kernel

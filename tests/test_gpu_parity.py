@@ -264,3 +264,117 @@ def test_c1_full_size(ctx):
     lab2 = ctx.watershed(g2, 8)
     assert np.array_equal(to_host(lab2), oracle.watershed(q, 8))
     torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------
+# Batched path: every image of an uneven batch equals the oracle (and the
+# single-image calls) bit for bit.
+# --------------------------------------------------------------------------
+
+def _batch_case(ctx, grads, conn, NL):
+    say("  batch", len(grads), "images conn", conn, "NL", NL)
+    outs, nregs = ctx.batch([to_dev(g) for g in grads], conn, NL)
+    for g, o, n in zip(grads, outs, nregs):
+        ref0 = oracle.watershed(g, conn)
+        ref, refn = oracle.waterfall_g1(ref0, g, conn, NL)
+        assert np.array_equal(to_host(o), ref)
+        assert to_host(n).tolist() == refn.tolist()
+    return outs
+
+
+def test_batch_2d_uneven(ctx):
+    rng = np.random.default_rng(77)
+    grads = []
+    for i in range(24):
+        ny, nx = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+        if i % 3 == 0:
+            img = gen.blobs2d(max(ny, 8), max(nx, 8), seed=100 + i)
+            grads.append(oracle.gradient(img, 0.0, "u8"))
+        else:
+            grads.append(rng.integers(0, 1 + i % 7, size=(ny, nx)).astype(np.uint8))
+    _batch_case(ctx, grads, 8, 4)
+    _batch_case(ctx, grads, 4, 3)
+
+
+def test_batch_matches_single_calls(ctx):
+    rng = np.random.default_rng(5)
+    grads = [rng.integers(0, 30, size=(int(rng.integers(20, 200)), int(rng.integers(20, 200)))).astype(np.uint16)
+             for _ in range(9)]
+    outs = _batch_case(ctx, grads, 8, 5)
+    for g, o in zip(grads, outs):
+        d = to_dev(g)
+        lab = ctx.watershed(d, 8)
+        single, _ = ctx.waterfall(lab, d, 8, 5)
+        assert np.array_equal(to_host(single), to_host(o))
+
+
+def test_batch_3d_and_plateaux(ctx):
+    rng = np.random.default_rng(9)
+    grads = [rng.integers(0, 4, size=(int(rng.integers(2, 20)), int(rng.integers(2, 20)), int(rng.integers(2, 40))))
+             .astype(np.uint8) for _ in range(7)]
+    grads.append(np.full((9, 10, 70), 3, np.uint8))
+    _batch_case(ctx, grads, 6, 4)
+    _batch_case(ctx, grads, 26, 3)
+    serp = [gen.serpentine(66, 130), gen.serpentine(9, 12), np.full((40, 70), 2, np.uint16)]
+    _batch_case(ctx, serp, 4, 3)
+
+
+def test_batch_errors(ctx):
+    import torch
+    import paper_2410_08946_amd as ws
+    g = torch.zeros((16, 16), dtype=torch.uint8, device="cuda:0")
+    g3 = torch.zeros((4, 16, 16), dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(ws.WSError):
+        ctx.batch([g, g3], 8, 3)
+    with pytest.raises(ws.WSError):
+        ctx.batch([g], 8, 0)
+    with pytest.raises(ValueError):
+        ctx.batch([], 8, 3)
+
+
+# --------------------------------------------------------------------------
+# Serving: jobs admitted while others run, micro-batched across slots; every
+# result equals the job run alone.
+# --------------------------------------------------------------------------
+
+def test_serving_mix_identity(ctx):
+    import torch
+    from paper_2410_08946_amd import serve
+    rng = np.random.default_rng(21)
+    jobs_in = []
+    for i in range(40):
+        if i % 3 == 2:
+            s = int(rng.integers(8, 40))
+            g = rng.integers(0, 5, size=(int(rng.integers(2, 12)), s, s + 3)).astype(np.uint8)
+            jobs_in.append((g, 6))
+        else:
+            ny, nx = int(rng.integers(16, 300)), int(rng.integers(16, 300))
+            g = oracle.gradient(gen.blobs2d(ny, nx, seed=500 + i), 0.0, "u8")
+            jobs_in.append((g, 8))
+    devs = [(to_dev(g), c) for g, c in jobs_in]
+    solo = []
+    for d, c in devs:
+        lab = ctx.watershed(d, c)
+        out, n = ctx.waterfall(lab, d, c, 4)
+        solo.append((to_host(out), to_host(n)))
+    srv = serve.Server(slots=3, budget_bytes=64 << 20, max_batch_jobs=6)
+    try:
+        jobs = [srv.submit(serve.Job(grad=d, conn=c, NL=4, jid=k)) for k, (d, c) in enumerate(devs)]
+        assert srv.drain(timeout=120)
+    finally:
+        srv.close()
+    for j, (o, n) in zip(jobs, solo):
+        assert j.error is None, j.error
+        assert np.array_equal(to_host(j.out), o)
+        assert to_host(j.nregions).tolist() == n.tolist()
+    assert srv.batches >= 2
+    # a job larger than the whole budget is rejected without harming the rest
+    srv2 = serve.Server(slots=2, budget_bytes=8 << 20)
+    try:
+        big = srv2.submit(serve.Job(grad=to_dev(np.zeros((1000, 1000), np.uint8)), conn=8))
+        small = srv2.submit(serve.Job(grad=devs[0][0], conn=devs[0][1]))
+        assert srv2.drain(timeout=60)
+    finally:
+        srv2.close()
+    assert big.error is not None and small.error is None
+    assert np.array_equal(to_host(small.out), solo[0][0])
