@@ -179,7 +179,7 @@ int ws_watershed_stages(ws_ctx *ctx, const void *grad, int dtype, int64_t nx, in
                         int64_t nz, int conn, int32_t *bal, int32_t *arrow, void *stream);
 
 /*
- * Schedule options. None of them changes any result, only time.
+ * Options. None of them changes any result, only time.
  *   "step3"        0 = per-pixel Find (APRUF, Section 3.2), 1 = RR pointer
  *                  jumps per synchronisation (PRUF, Alg. 1 Step III).
  *   "rr"           reduction rate for step3 = 1 (default 6, Section 5).
@@ -187,6 +187,10 @@ int ws_watershed_stages(ws_ctx *ctx, const void *grad, int dtype, int64_t nx, in
  *   "max_sweeps"   cap on Step II sweeps; reaching it returns WS_ENOCONV
  *                  (default 2^31-1).
  *   "timing"       1 = record a HIP event pair around every kernel launch.
+ *   "reserve_pixels"  allocate now the scratch of calls covering up to this
+ *                  many pixels (any 2D/3D mix, NL <= 16), so later calls do
+ *                  not allocate (allocation waits for the whole device);
+ *                  may return WS_ENOMEM.
  * Returns WS_EINVAL for an unknown name or out-of-range value.
  */
 int ws_set_option(ws_ctx *ctx, const char *name, int64_t value);

@@ -66,6 +66,9 @@ int hip_fail(ws_ctx *c, hipError_t e, const char *where) {
 int ensure(ws_ctx *c, Buf &b, size_t bytes, const char *what) {
     if (bytes == 0) bytes = 256;
     if (b.n >= bytes) return WS_OK;
+    // grow geometrically: hipFree waits for the whole device, so a context
+    // that serves growing batches should reallocate rarely
+    if (b.n > 0 && bytes < b.n + b.n / 2) bytes = b.n + b.n / 2;
     if (b.p) {
         hipError_t e = hipFree(b.p);
         b.p = nullptr;
@@ -232,24 +235,55 @@ int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg
     if ((rc = ensure(c, c->tiletmp, (size_t)(tg.ntiles + 1) * 4, "tile offsets")) != WS_OK) return rc;
     if ((rc = ensure(c, c->tilecnt, (size_t)NL * tg.ntiles * 4, "tile counts")) != WS_OK) return rc;
     uint64_t *key = (uint64_t *)c->key.p;
-    int32_t *par = (int32_t *)c->par.p, *cnt = (int32_t *)c->wfcnt.p, *chunks = (int32_t *)c->chunks.p;
+    int32_t *par = (int32_t *)c->par.p, *cnt = (int32_t *)c->wfcnt.p;
     int32_t *tcnt = (int32_t *)c->tilecnt.p;
     int32_t *lists[2] = {(int32_t *)c->lista.p, (int32_t *)c->listb.p};
     WS_TRY(wsk::launch_fill_i32(lc, cnt, NL, 0));
     WS_TRY(wsk::launch_wf_init(lc, src, tg, ndim, lists[0], cnt, key, par, (int32_t *)c->tiletmp.p, tcnt));
+    // Levels walk a region list that holds every region still alive (live
+    // regions carry a key, see k_wf_union; compression covers all entries).
+    // The layer-0 list is compacted once, after the first level, where the
+    // count drops the most.
+    int32_t *list = lists[0], *count = cnt;
     for (int k = 1; k < NL; ++k) {
-        int32_t *lin = lists[(k - 1) & 1], *lout = lists[k & 1];
         if (k == 1)
             WS_TRY(wsk::launch_wf_edge(lc, src, tg, conn, u16, 0, 0, par, key, tcnt));
         else  // relabel layer k-1 from layer k-2 while computing layer k-1's keys
             WS_TRY(wsk::launch_wf_edge(lc, src, tg, conn, u16, k - 2, 1, par, key, tcnt + (size_t)(k - 1) * tg.ntiles));
-        WS_TRY(wsk::launch_wf_union(lc, bound, lin, cnt + k - 1, key, par));
-        WS_TRY(wsk::launch_wf_compress(lc, bound, lin, cnt + k - 1, par));
-        WS_TRY(wsk::launch_wf_compact(lc, bound, lin, cnt + k - 1, lout, cnt + k, par, key, chunks));
+        WS_TRY(wsk::launch_wf_union(lc, bound, list, count, key, par));
+        WS_TRY(wsk::launch_wf_compress(lc, bound, list, count, par));
+        if (k == 1 && NL > 2) {
+            WS_TRY(wsk::launch_wf_compact(lc, bound, lists[0], cnt, lists[1], cnt + 1, par, key,
+                                          (int32_t *)c->chunks.p));
+            list = lists[1];
+            count = cnt + 1;
+        }
     }
     if (NL >= 2) WS_TRY(wsk::launch_wf_relabel(lc, src, tg, ndim, NL - 2, par, tcnt + (size_t)(NL - 1) * tg.ntiles));
     if (outs_dev || one_out)
         WS_TRY(wsk::launch_img_counts(lc, tab_dev, one, nimg, NL, tg.ntiles, tcnt, outs_dev, one_out));
+    return WS_OK;
+}
+
+// Pre-allocates the scratch of calls covering up to n pixels (any mix of 2D
+// and 3D images, NL <= 16), so that later calls allocate nothing.
+int reserve(ws_ctx *c, int64_t n) {
+    size_t N = (size_t)n;
+    size_t tiles = N / 256 + 1024;  // partial tiles of many small images
+    int rc;
+    Buf *four[] = {&c->D, &c->par, &c->lista, &c->listb};
+    for (Buf *b : four)
+        if ((rc = ensure(c, *b, N * 4, "reserved scratch")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->key, N * 8, "reserved keys")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->stamp, tiles * 4, "reserved stamps")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->rec, tiles * (size_t)wsk::border_cells(3) * 4, "reserved records")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->tiletmp, (tiles + 1) * 4, "reserved tile offsets")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->tilecnt, tiles * 16 * 4, "reserved tile counts")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->chunks, (size_t)wsk::compact_chunks((int32_t)std::min<int64_t>(n, 0x7fffffff)) * 4,
+                     "reserved offsets")) != WS_OK)
+        return rc;
+    if ((rc = ensure(c, c->wfcnt, 16 * 4, "reserved counts")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->cnt, kCounterSlots * 4, "counters")) != WS_OK) return rc;
     return WS_OK;
 }
 
@@ -340,6 +374,11 @@ int ws_set_option(ws_ctx *c, const char *name, int64_t v) {
     else if (k == "sweep_batch" && v >= 1 && v <= kMaxSweepBatch) c->sweep_batch = (int)v;
     else if (k == "max_sweeps" && v >= 1) c->max_sweeps = v;
     else if (k == "timing" && (v == 0 || v == 1)) c->timing = v != 0;
+    else if (k == "reserve_pixels" && v >= 0 && v < (1LL << 31)) {
+        int rc = set_device(c);
+        if (rc) return rc;
+        return reserve(c, v);
+    }
     else return fail(c, WS_EINVAL, "ws_set_option: unknown option or value out of range: " + k);
     return WS_OK;
 }

@@ -50,6 +50,9 @@ __device__ __forceinline__ void block_max_to_slot(float m, unsigned int *slots) 
 // ---------------------------------------------------------------------------
 constexpr int GX = 64, GY = 16;
 
+// RB bounds the blur radius of the instantiation (the loads of the raw tile
+// are unrolled for it); the taps' runtime radius r <= RB sizes the LDS tile.
+template <int RB>
 __global__ __launch_bounds__(NTHREADS) void k_grad_fused2d(Geom g, const float *__restrict__ img,
                                                            float *__restrict__ mag, unsigned int *__restrict__ slots,
                                                            BlurTaps taps) {
@@ -62,10 +65,26 @@ __global__ __launch_bounds__(NTHREADS) void k_grad_fused2d(Geom g, const float *
     float *bb = bx + BW * RH;
     int tiles_x = (g.nx + GX - 1) / GX;
     int x0 = (blockIdx.x % tiles_x) * GX, y0 = (blockIdx.x / tiles_x) * GY;
-    for (int c = threadIdx.x; c < RW * RH; c += NTHREADS) {
-        int i = c % RW, j = c / RW;
-        int gx = reflect_idx(x0 - 1 - r + i, g.nx), gy = reflect_idx(y0 - 1 - r + j, g.ny);
-        raw[c] = img[gx + (int32_t)gy * g.nx];
+    {
+        // batched raw loads: mirrored addresses first, then all loads
+        constexpr int PER = ((GX + 2 + 2 * RB) * (GY + 2 + 2 * RB) + NTHREADS - 1) / NTHREADS;
+        int32_t idx[PER];
+        float v[PER];
+        const int cells = RW * RH;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            int c = threadIdx.x + j * NTHREADS;
+            int i = c % RW, jj = c / RW;
+            int gx = reflect_idx(x0 - 1 - r + i, g.nx), gy = reflect_idx(y0 - 1 - r + jj, g.ny);
+            idx[j] = c < cells ? gx + (int32_t)gy * g.nx : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) v[j] = img[idx[j]];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            int c = threadIdx.x + j * NTHREADS;
+            if (c < cells) raw[c] = v[j];
+        }
     }
     __syncthreads();
     for (int c = threadIdx.x; c < BW * RH; c += NTHREADS) {
@@ -95,9 +114,9 @@ __global__ __launch_bounds__(NTHREADS) void k_grad_fused2d(Geom g, const float *
         const float *r0 = bb + ym * BW, *r1 = bb + yc * BW, *r2 = bb + yp * BW;
         float gxv = (r0[xp] - r0[xm]) + 2.f * (r1[xp] - r1[xm]) + (r2[xp] - r2[xm]);
         float gyv = (r2[xm] - r0[xm]) + 2.f * (r2[xc] - r0[xc]) + (r2[xp] - r0[xp]);
-        float v = sqrtf(gxv * gxv + gyv * gyv);
-        mag[gx + (int32_t)gy * g.nx] = v;
-        m = fmaxf(m, v);
+        float vv = sqrtf(gxv * gxv + gyv * gyv);
+        mag[gx + (int32_t)gy * g.nx] = vv;
+        m = fmaxf(m, vv);
     }
     block_max_to_slot(m, slots);
 }
@@ -200,8 +219,14 @@ size_t grad_fused2d_lds(int r) {
 
 int launch_grad_fused2d(Launch &lc, const Geom &g, const float *img, float *mag, unsigned int *slots, const BlurTaps &taps) {
     int tiles = ((g.nx + GX - 1) / GX) * ((g.ny + GY - 1) / GY);
-    return lc.run_shm("grad_fused", k_grad_fused2d, dim3(tiles), dim3(NTHREADS), grad_fused2d_lds(taps.r), g, img, mag,
-                      slots, taps);
+    size_t shm = grad_fused2d_lds(taps.r);
+    if (taps.r == 0)
+        return lc.run_shm("grad_fused", k_grad_fused2d<0>, dim3(tiles), dim3(NTHREADS), shm, g, img, mag, slots, taps);
+    if (taps.r <= 4)
+        return lc.run_shm("grad_fused", k_grad_fused2d<4>, dim3(tiles), dim3(NTHREADS), shm, g, img, mag, slots, taps);
+    if (taps.r <= 8)
+        return lc.run_shm("grad_fused", k_grad_fused2d<8>, dim3(tiles), dim3(NTHREADS), shm, g, img, mag, slots, taps);
+    return lc.run_shm("grad_fused", k_grad_fused2d<16>, dim3(tiles), dim3(NTHREADS), shm, g, img, mag, slots, taps);
 }
 int launch_grad_blur(Launch &lc, const Geom &g, const float *in, float *out, int axis, const BlurTaps &taps) {
     return lc.run("grad_blur", k_grad_blur, dim3((g.n + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), g, in, out, axis, taps);

@@ -185,20 +185,38 @@ __global__ __launch_bounds__(NTHREADS) void k_compact_count(const int32_t *__res
 }
 
 // Exclusive scan of n counts in place (one workgroup); total into *total_out.
-// n is derived from *n_dev when given (chunks of a device-sized list).
+// n is derived from *n_dev when given (chunks of a device-sized list). Each
+// thread owns a contiguous run of the counts (loads issued together), the
+// runs' sums are scanned across the workgroup, then each run is rewritten.
 __global__ __launch_bounds__(NTHREADS) void k_scan(int32_t n_host, const int32_t *__restrict__ n_dev, int32_t chunk,
                                                    int32_t *__restrict__ cnt, int32_t *__restrict__ total_out) {
+    constexpr int U = 16;
     int32_t n = n_dev ? (*n_dev + chunk - 1) / chunk : n_host;
-    int32_t carry = 0;
-    for (int32_t base = 0; base < n; base += NTHREADS) {
-        int32_t i = base + threadIdx.x;
-        int v = i < n ? cnt[i] : 0;
-        int excl;
-        int total = block_scan_excl(v, excl);
-        if (i < n) cnt[i] = carry + excl;
-        carry += total;
+    int32_t per = (n + NTHREADS - 1) / NTHREADS;
+    int32_t lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
+    int32_t sum = 0;
+    for (int32_t b = lo; b < hi; b += U) {
+        int32_t v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = b + j < hi ? cnt[b + j] : 0;
+#pragma unroll
+        for (int j = 0; j < U; ++j) sum += v[j];
     }
-    if (threadIdx.x == 0 && total_out) *total_out = carry;
+    int excl;
+    int total = block_scan_excl(sum, excl);
+    int32_t run = excl;
+    for (int32_t b = lo; b < hi; b += U) {
+        int32_t v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = b + j < hi ? cnt[b + j] : 0;
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (b + j < hi) {
+                cnt[b + j] = run;
+                run += v[j];
+            }
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = total;
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_compact_write(const int32_t *__restrict__ list,
@@ -304,27 +322,30 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_edge(Src src, int32_t ntiles, i
             hv[h] = NOKEY;
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
+        static_assert(PIX % NTHREADS == 0, "whole waves per tile");
+        for (int i = threadIdx.x; i < PIX; i += NTHREADS) {  // uniform trip count
             int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
             int s = ((z + RZ) * SY + (y + 1)) * SX + (x + 1);
             int l = sL[s];
-            if (l < 0) continue;
-            uint32_t v = (uint32_t)sI[s];
             uint64_t best = NOKEY;
+            if (l >= 0) {
+                uint32_t v = (uint32_t)sI[s];
 #pragma unroll
-            for (int k = 0; k < CONN; ++k) {
-                int o = s + nb_dx<CONN>(k) + SX * (nb_dy<CONN>(k) + SY * nb_dz<CONN>(k));
-                int lq = sL[o];
-                if (lq < 0 || lq == l) continue;
-                uint32_t w = (uint32_t)sI[o];
-                uint64_t c = ((uint64_t)(v > w ? v : w) << 32) | (uint32_t)(im.pix0 + lq);
-                best = c < best ? c : best;
+                for (int k = 0; k < CONN; ++k) {
+                    int o = s + nb_dx<CONN>(k) + SX * (nb_dy<CONN>(k) + SY * nb_dz<CONN>(k));
+                    int lq = sL[o];
+                    if (lq < 0 || lq == l) continue;
+                    uint32_t w = (uint32_t)sI[o];
+                    uint64_t c = ((uint64_t)(v > w ? v : w) << 32) | (uint32_t)(im.pix0 + lq);
+                    best = c < best ? c : best;
+                }
             }
             if (best == NOKEY) continue;
             uint32_t h = ((uint32_t)l * 2654435761u) >> (32 - HBITS);
             for (;;) {
-                int old = atomicCAS(&hk[h], -1, l);
-                if (old == -1 || old == l) {
+                int cur = hk[h];
+                if (cur == -1) cur = atomicCAS(&hk[h], -1, l);
+                if (cur == -1 || cur == l) {
                     atomicMin(&hv[h], (unsigned long long)best);
                     break;
                 }
@@ -345,15 +366,20 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_edge(Src src, int32_t ntiles, i
     }
 }
 
-// Join every region with the region across its lowest pass.
+// Join every region with the region across its lowest pass. The list holds
+// every layer-0 region; exactly the regions of the current layer that have a
+// boundary carry a key (dead regions had theirs reset when they merged), and
+// each key is reset here for the next layer.
 __global__ __launch_bounds__(NTHREADS) void k_wf_union(const int32_t *__restrict__ list,
                                                        const int32_t *__restrict__ count,
-                                                       const uint64_t *__restrict__ key, int32_t *__restrict__ par) {
+                                                       uint64_t *__restrict__ key, int32_t *__restrict__ par) {
     int32_t c = *count;
     for (int32_t i = blockIdx.x * NTHREADS + threadIdx.x; i < c; i += gridDim.x * NTHREADS) {
         int32_t r = list[i];
         uint64_t kk = key[r];
-        if (kk != NOKEY) gunion(par, r, (int32_t)(uint32_t)(kk & 0xffffffffull));
+        if (kk == NOKEY) continue;
+        key[r] = NOKEY;
+        gunion(par, r, (int32_t)(uint32_t)(kk & 0xffffffffull));
     }
 }
 
@@ -415,13 +441,20 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_relabel(Src src, int32_t ntiles
 __global__ __launch_bounds__(NTHREADS) void k_img_counts(const Img *__restrict__ tab, Img one, int32_t nimg, int32_t nl,
                                                          int32_t ntiles_total, const int32_t *__restrict__ tile_cnt,
                                                          int64_t *const *__restrict__ outs, int64_t *one_out) {
+    constexpr int U = 8;
     int b = blockIdx.x, k = blockIdx.y;
     if (b >= nimg || k >= nl) return;
     int32_t t0 = tab ? tab[b].tile0[TK_WF] : one.tile0[TK_WF];
     int32_t t1 = b + 1 < nimg ? tab[b + 1].tile0[TK_WF] : ntiles_total;
     const int32_t *c = tile_cnt + (size_t)k * ntiles_total;
     int s = 0;
-    for (int32_t t = t0 + threadIdx.x; t < t1; t += NTHREADS) s += c[t];
+    for (int32_t t = t0 + threadIdx.x; t < t1; t += NTHREADS * U) {
+        int v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = t + j * NTHREADS < t1 ? c[t + j * NTHREADS] : 0;
+#pragma unroll
+        for (int j = 0; j < U; ++j) s += v[j];
+    }
     int excl;
     int total = block_scan_excl(s, excl);
     int64_t *dst = tab ? outs[b] : one_out;
@@ -528,7 +561,7 @@ int launch_wf_compact(Launch &lc, int32_t bound, const int32_t *list_in, const i
                   (const int32_t *)chunk_tmp, list_out, key);
 }
 
-int launch_wf_union(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, const uint64_t *key, int32_t *par) {
+int launch_wf_union(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, uint64_t *key, int32_t *par) {
     return lc.run("wf_union", k_wf_union, list_grid(bound), dim3(NTHREADS), list, count, key, par);
 }
 int launch_wf_compress(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, int32_t *par) {

@@ -99,7 +99,7 @@ int launch_fill_i32(Launch &lc, int32_t *a, int32_t n, int32_t v);
 // waterfall.hip
 int compact_chunks(int32_t bound);
 int wf_tiles(const Geom &g, int ndim);
-int launch_wf_union(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, const uint64_t *key, int32_t *par);
+int launch_wf_union(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, uint64_t *key, int32_t *par);
 int launch_wf_compress(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, int32_t *par);
 int launch_wf_compact(Launch &lc, int32_t bound, const int32_t *list_in, const int32_t *count_in, int32_t *list_out,
                       int32_t *count_out, const int32_t *par, uint64_t *key, int32_t *chunk_tmp);

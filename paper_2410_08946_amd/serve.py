@@ -53,7 +53,7 @@ class Server:
     """K execution slots, micro-batches of queued jobs, footprint admission."""
 
     def __init__(self, slots: int = 4, budget_bytes: Optional[int] = None, max_batch_jobs: int = 64,
-                 max_batch_pixels: int = 1 << 27, device: int = 0):
+                 max_batch_pixels: int = 1 << 26, device: int = 0):
         import torch
         self.device = torch.device("cuda", device)
         if budget_bytes is None:
@@ -73,6 +73,7 @@ class Server:
         self.slots = []
         for k in range(slots):
             ctx = Context(device)
+            ctx.set_option("reserve_pixels", self.max_batch_pixels)
             stream = torch.cuda.Stream(device=self.device)  # default priority
             slot = {"k": k, "ctx": ctx, "stream": stream, "work": None, "cv": threading.Condition()}
             slot["thread"] = threading.Thread(target=self._worker, args=(slot,), daemon=True)
