@@ -29,20 +29,21 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per pixel each kernel must move (compulsory reads and
-# writes of its inputs/outputs; b = bytes per grey value). Region-level
-# kernels (wf_union, wf_compress, wf_compact, ws_merge) touch a vanishing
-# share of the pixels and are not priced.
-def kernel_bytes_per_pixel(b):
+# writes of its inputs/outputs; b = bytes per grey value, NL = layers).
+# Region- and edge-level kernels (ws_merge, wf_union, wf_compress, wf_level)
+# touch a small, data-dependent share of the pixels' worth of bytes, and
+# wf_ids names three launches of different kinds: none of them is priced.
+def kernel_bytes_per_pixel(b, NL):
     return {
+        "grad_fused": 8.0,         # read f32 image, write f32 magnitude
         "grad_blur": 8.0,          # read f32, write f32
         "grad_sobel": 8.0,         # read f32, write f32 magnitude
         "grad_quant": 4.0 + b,     # read f32, write grey
         "ws_init": b + 4.0,        # read grey, write distance
         "ws_label": b + 8.0,       # read grey + distance, write label
         "ws_find": 8.0,            # read label, write label
-        "wf_init": 4.0,            # read label
-        "wf_edge": 4.0 + b,        # read label + grey
-        "wf_relabel": 8.0,         # read label, write label
+        "wf_pix": 4.0 + b,         # read layer-0 label + grey
+        "wf_out": 4.0 * NL,        # read layer 0, write layers 1 .. NL-1
     }
 
 
@@ -317,7 +318,7 @@ def main():
         torch.cuda.synchronize()
         kt = ctx.timing_read()
         ctx.set_option("timing", 0)
-        per = kernel_bytes_per_pixel(b)
+        per = kernel_bytes_per_pixel(b, NL)
         for name, (ms, cnt) in kt.items():
             kernels[name] = {"launches_per_step": cnt / args.steps, "avg_us": round(ms * 1e3 / cnt, 2),
                              "ms_per_step": round(ms / args.steps, 4)}

@@ -70,11 +70,14 @@ const char *ws_last_error(const ws_ctx *ctx);
 int ws_sync(ws_ctx *ctx, void *stream);
 
 /*
- * Device bytes one watershed + waterfall job of this size needs beyond its
- * inputs and outputs (the context's scratch), plus the job's own buffers
- * (gradient, NL label layers). Pure host arithmetic; 0 on invalid sizes.
+ * Device bytes one watershed + waterfall job of this size needs: the job's own
+ * buffers (gradient, NL label layers) plus the context scratch it uses
+ * (distances and border records of the watershed; for NL >= 2 the dense
+ * region tables and the per-tile edge slabs of the waterfall, whose size
+ * grows with conn). Pure host arithmetic; 0 on invalid sizes, dtype, NL or a
+ * conn that does not match the dimensionality.
  */
-size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int dtype, int NL);
+size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int conn, int dtype, int NL);
 
 /*
  * Gradient magnitude pre-processing (Introduction: smooth, then gradient
@@ -188,7 +191,7 @@ int ws_watershed_stages(ws_ctx *ctx, const void *grad, int dtype, int64_t nx, in
  *                  (default 2^31-1).
  *   "timing"       1 = record a HIP event pair around every kernel launch.
  *   "reserve_pixels"  allocate now the scratch of calls covering up to this
- *                  many pixels (any 2D/3D mix, NL <= 16), so later calls do
+ *                  many pixels (any 2D/3D mix, conn 4/6/8, NL <= 8), so later calls do
  *                  not allocate (allocation waits for the whole device);
  *                  may return WS_ENOMEM.
  * Returns WS_EINVAL for an unknown name or out-of-range value.

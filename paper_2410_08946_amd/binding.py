@@ -27,7 +27,7 @@ SIGNATURES = {
     "ws_destroy": (None, [_ptr]),
     "ws_last_error": (ctypes.c_char_p, [_ptr]),
     "ws_sync": (_int, [_ptr, _ptr]),
-    "ws_footprint_bytes": (ctypes.c_size_t, [_i64, _i64, _i64, _int, _int]),
+    "ws_footprint_bytes": (ctypes.c_size_t, [_i64, _i64, _i64, _int, _int, _int]),
     "ws_gradient": (_int, [_ptr, _ptr, _i64, _i64, _i64, _f32, _int, _ptr, _ptr, _ptr]),
     "ws_watershed": (_int, [_ptr, _ptr, _int, _i64, _i64, _i64, _int, _ptr, _ptr]),
     "ws_waterfall": (_int, [_ptr, _ptr, _ptr, _int, _i64, _i64, _i64, _int, _int, _ptr, _ptr, _ptr]),

@@ -35,9 +35,10 @@ struct ws_ctx {
     int device = 0;
     std::string err;
     Buf D, stamp, cnt, rec;               // watershed scratch
-    Buf key, par, lista, listb, wfcnt;    // waterfall scratch
+    Buf key, par, cimg, rlist, mlab;      // waterfall: region tables (dense by id), per-pixel region ids
+    Buf edges, ecnt, wfcnt;               // edge slabs, their counts, region count
     Buf g0, g1, mag, gmax;                // gradient scratch
-    Buf chunks, tiletmp, tilecnt;         // compaction offsets, per-tile counts
+    Buf chunks, tilecnt;                  // region-id rank tables + scan scratch, per-tile counts
     Buf tab;                              // batch descriptor table + tile maps
     int32_t *host_cnt = nullptr;          // pinned readback of counters
     void *stage = nullptr;                // pinned staging of batch tables
@@ -217,49 +218,56 @@ int run_watershed(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg
     return WS_OK;
 }
 
-// NL waterfall layers of every image of `src` (layer 0 already in lab).
-// Region counts go to outs[b] (batch, device array of device pointers) or
-// one_out (single image).
+// NL waterfall layers of every image of `src` (layer 0 already in lab):
+// region ids, the layer-0 pixel pass, then per layer union + compression and
+// (from layer 2) an edge pass over tile groups growing fourfold, and one pass
+// writing every layer. Region counts go to outs[b] (batch, device array of
+// device pointers) or one_out (single image).
 template <class Src>
-int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg, int ndim, int conn, bool u16,
-                  int NL, size_t arena, const wsk::Img *tab_dev, const wsk::Img &one, int nimg,
-                  int64_t *const *outs_dev, int64_t *one_out) {
+int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const Src &src_ch, int32_t nchunks, const wsk::TileGrid &tg,
+                  int ndim, int conn, bool u16, int NL, size_t arena, const wsk::Img *tab_dev, const wsk::Img &one,
+                  int nimg, int64_t *const *outs_dev, int64_t *one_out) {
     int rc;
     int32_t bound = (int32_t)arena;
-    if ((rc = ensure(c, c->key, arena * 8, "region keys")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->par, arena * 4, "region parents")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->lista, arena * 4, "region list")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->listb, arena * 4, "region list")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->wfcnt, (size_t)NL * 4, "region counts")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->chunks, (size_t)wsk::compact_chunks(bound) * 4, "compaction offsets")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->tiletmp, (size_t)(tg.ntiles + 1) * 4, "tile offsets")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->wfcnt, 4, "region count")) != WS_OK) return rc;
     if ((rc = ensure(c, c->tilecnt, (size_t)NL * tg.ntiles * 4, "tile counts")) != WS_OK) return rc;
-    uint64_t *key = (uint64_t *)c->key.p;
-    int32_t *par = (int32_t *)c->par.p, *cnt = (int32_t *)c->wfcnt.p;
-    int32_t *tcnt = (int32_t *)c->tilecnt.p;
-    int32_t *lists[2] = {(int32_t *)c->lista.p, (int32_t *)c->listb.p};
-    WS_TRY(wsk::launch_fill_i32(lc, cnt, NL, 0));
-    WS_TRY(wsk::launch_wf_init(lc, src, tg, ndim, lists[0], cnt, key, par, (int32_t *)c->tiletmp.p, tcnt));
-    // Levels walk a region list that holds every region still alive (live
-    // regions carry a key, see k_wf_union; compression covers all entries).
-    // The layer-0 list is compacted once, after the first level, where the
-    // count drops the most.
-    int32_t *list = lists[0], *count = cnt;
-    for (int k = 1; k < NL; ++k) {
-        if (k == 1)
-            WS_TRY(wsk::launch_wf_edge(lc, src, tg, conn, u16, 0, 0, par, key, tcnt));
-        else  // relabel layer k-1 from layer k-2 while computing layer k-1's keys
-            WS_TRY(wsk::launch_wf_edge(lc, src, tg, conn, u16, k - 2, 1, par, key, tcnt + (size_t)(k - 1) * tg.ntiles));
-        WS_TRY(wsk::launch_wf_union(lc, bound, list, count, key, par));
-        WS_TRY(wsk::launch_wf_compress(lc, bound, list, count, par));
-        if (k == 1 && NL > 2) {
-            WS_TRY(wsk::launch_wf_compact(lc, bound, lists[0], cnt, lists[1], cnt + 1, par, key,
-                                          (int32_t *)c->chunks.p));
-            list = lists[1];
-            count = cnt + 1;
+    int32_t *nreg0 = (int32_t *)c->wfcnt.p, *tcnt = (int32_t *)c->tilecnt.p;
+    const int32_t *cimg = nullptr, *mlab = nullptr;
+    if (NL >= 2) {
+        const int32_t cap = wsk::wf_slab_cap(conn);
+        const size_t E = (size_t)tg.ntiles * (size_t)cap;
+        if ((rc = ensure(c, c->key, arena * 8, "region keys")) != WS_OK) return rc;
+        if ((rc = ensure(c, c->par, arena * 4, "region parents")) != WS_OK) return rc;
+        if ((rc = ensure(c, c->cimg, arena * 4, "pixel region ids")) != WS_OK) return rc;
+        if ((rc = ensure(c, c->rlist, arena * 4, "region labels")) != WS_OK) return rc;
+        if ((rc = ensure(c, c->mlab, (size_t)(NL - 1) * arena * 4, "layer labels")) != WS_OK) return rc;
+        if ((rc = ensure(c, c->edges, 3 * E * 4, "edge slabs")) != WS_OK) return rc;
+        if ((rc = ensure(c, c->ecnt, (size_t)tg.ntiles * 4, "edge counts")) != WS_OK) return rc;
+        // rank tables: [chunk offsets | scan scratch | bitmap words (8 B) | word prefixes (2 B)]
+        size_t off_bits = (((size_t)nchunks + wsk::scan_tmp_len(nchunks)) * 4 + 7) & ~(size_t)7;
+        size_t off_pre = off_bits + (size_t)nchunks * 64 * 8;
+        if ((rc = ensure(c, c->chunks, off_pre + (size_t)nchunks * 64 * 2, "region-id tables")) != WS_OK) return rc;
+        uint64_t *key = (uint64_t *)c->key.p;
+        int32_t *par = (int32_t *)c->par.p, *ci = (int32_t *)c->cimg.p, *rl = (int32_t *)c->rlist.p;
+        int32_t *ml = (int32_t *)c->mlab.p, *edges = (int32_t *)c->edges.p, *ecnt = (int32_t *)c->ecnt.p;
+        char *tb = (char *)c->chunks.p;
+        wsk::WfIds ids{(unsigned long long *)(tb + off_bits), (uint16_t *)(tb + off_pre), (int32_t *)tb};
+        WS_TRY(wsk::launch_wf_ids(lc, src_ch, nchunks, bound, ids, (int32_t *)tb + nchunks, nreg0, key, par));
+        WS_TRY(wsk::launch_wf_pix(lc, src, tg, conn, u16, ids, nreg0, ci, rl, tcnt, key, edges, ecnt));
+        WS_TRY(wsk::launch_wf_union(lc, bound, nreg0, key, par));
+        WS_TRY(wsk::launch_wf_compress(lc, bound, nreg0, par, rl, ml));
+        int32_t gin = 1;
+        for (int k = 2; k < NL; ++k) {
+            int32_t f = (k == 2 || gin >= tg.ntiles) ? 1 : 4;
+            WS_TRY(wsk::launch_wf_level(lc, tg.ntiles, gin, f, cap, par, key, edges, ecnt));
+            gin *= f;
+            WS_TRY(wsk::launch_wf_union(lc, bound, nreg0, key, par));
+            WS_TRY(wsk::launch_wf_compress(lc, bound, nreg0, par, rl, ml + (size_t)(k - 1) * arena));
         }
+        cimg = ci;
+        mlab = ml;
     }
-    if (NL >= 2) WS_TRY(wsk::launch_wf_relabel(lc, src, tg, ndim, NL - 2, par, tcnt + (size_t)(NL - 1) * tg.ntiles));
+    WS_TRY(wsk::launch_wf_out(lc, src, tg, ndim, NL, cimg, nreg0, mlab, (int64_t)arena, tcnt));
     if (outs_dev || one_out)
         WS_TRY(wsk::launch_img_counts(lc, tab_dev, one, nimg, NL, tg.ntiles, tcnt, outs_dev, one_out));
     return WS_OK;
@@ -269,19 +277,23 @@ int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg
 // and 3D images, NL <= 16), so that later calls allocate nothing.
 int reserve(ws_ctx *c, int64_t n) {
     size_t N = (size_t)n;
-    size_t tiles = N / 256 + 1024;  // partial tiles of many small images
+    size_t tiles = N / 256 + 1024;         // partial tiles of many small images
+    size_t wft = N / 1024 + N / 4096 + 1024;  // waterfall tiles of such a mix
+    constexpr int kLayers = 8;             // layer tables for NL <= 8
     int rc;
-    Buf *four[] = {&c->D, &c->par, &c->lista, &c->listb};
+    Buf *four[] = {&c->D, &c->par, &c->cimg, &c->rlist};
     for (Buf *b : four)
         if ((rc = ensure(c, *b, N * 4, "reserved scratch")) != WS_OK) return rc;
     if ((rc = ensure(c, c->key, N * 8, "reserved keys")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->mlab, N * 4 * (kLayers - 1), "reserved layer labels")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->edges, wft * (size_t)wsk::wf_slab_cap(8) * 12, "reserved edge slabs")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->ecnt, wft * 4, "reserved edge counts")) != WS_OK) return rc;
     if ((rc = ensure(c, c->stamp, tiles * 4, "reserved stamps")) != WS_OK) return rc;
     if ((rc = ensure(c, c->rec, tiles * (size_t)wsk::border_cells(3) * 4, "reserved records")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->tiletmp, (tiles + 1) * 4, "reserved tile offsets")) != WS_OK) return rc;
     if ((rc = ensure(c, c->tilecnt, tiles * 16 * 4, "reserved tile counts")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->chunks, (size_t)wsk::compact_chunks((int32_t)std::min<int64_t>(n, 0x7fffffff)) * 4,
-                     "reserved offsets")) != WS_OK)
-        return rc;
+    int32_t nch = (int32_t)std::min<int64_t>(n / 4096 + 4096, 0x7fffffff / 2);
+    size_t tbl = (((size_t)nch + wsk::scan_tmp_len(nch)) * 4 + 7) / 8 * 8 + (size_t)nch * 64 * 10;
+    if ((rc = ensure(c, c->chunks, tbl, "reserved region-id tables")) != WS_OK) return rc;
     if ((rc = ensure(c, c->wfcnt, 16 * 4, "reserved counts")) != WS_OK) return rc;
     if ((rc = ensure(c, c->cnt, kCounterSlots * 4, "counters")) != WS_OK) return rc;
     return WS_OK;
@@ -291,7 +303,7 @@ wsk::Img single_img(int64_t nx, int64_t ny, int64_t nz, const void *grad, int32_
     wsk::Img im{};
     im.g = make_geom(nx, ny, nz, nz > 1 ? 3 : 2);
     im.pix0 = 0;
-    im.tile0[0] = im.tile0[1] = im.tile0[2] = 0;
+    im.tile0[0] = im.tile0[1] = im.tile0[2] = im.tile0[3] = 0;
     im.slot0 = 0;
     im.grey = grad;
     im.lab = lab;
@@ -333,8 +345,9 @@ int ws_create(ws_ctx **out, int device) {
 void ws_destroy(ws_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    Buf *bufs[] = {&c->D, &c->stamp, &c->cnt, &c->rec, &c->key, &c->par, &c->lista, &c->listb, &c->wfcnt,
-                   &c->g0, &c->g1, &c->mag, &c->gmax, &c->chunks, &c->tiletmp, &c->tilecnt, &c->tab};
+    Buf *bufs[] = {&c->D,     &c->stamp, &c->cnt,  &c->rec, &c->key, &c->par,    &c->cimg,    &c->rlist, &c->mlab,
+                   &c->edges, &c->ecnt,  &c->wfcnt, &c->g0, &c->g1,  &c->mag,    &c->gmax,    &c->chunks,
+                   &c->tilecnt, &c->tab};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &r : c->sink.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
@@ -356,14 +369,24 @@ int ws_sync(ws_ctx *c, void *stream) {
     return WS_OK;
 }
 
-size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int dtype, int NL) {
+size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int conn, int dtype, int NL) {
     std::string why;
-    if (!valid_dims(nx, ny, nz, why) || (dtype != WS_U8 && dtype != WS_U16) || NL < 1) return 0;
+    if (!valid_dims(nx, ny, nz, why) || !valid_conn(nz, conn) || (dtype != WS_U8 && dtype != WS_U16) || NL < 1)
+        return 0;
+    int ndim = nz > 1 ? 3 : 2;
     size_t N = (size_t)(nx * ny * nz);
     size_t b = dtype == WS_U8 ? 1 : 2;
     size_t job = N * (b + 4 * (size_t)NL);
-    size_t scratch = N * 4 /* D */ + N * 8 /* keys */ + N * 4 /* parents */ + N * 8 /* region lists */;
-    return job + scratch + (1 << 20);
+    size_t ws = N * 4 /* D */ + (size_t)make_geom(nx, ny, nz, ndim).ntx * make_geom(nx, ny, nz, ndim).nty *
+                                    make_geom(nx, ny, nz, ndim).ntz * (4 + 4 * (size_t)wsk::border_cells(ndim));
+    size_t wf = 0;
+    if (NL >= 2) {
+        size_t tiles = (size_t)wsk::wf_tiles(make_geom(nx, ny, nz, ndim), ndim);
+        wf = N * (8 /* keys */ + 4 /* parents */ + 4 /* ids */ + 4 /* labels */ + 4 * (size_t)(NL - 1) /* layers */) +
+             tiles * (12 * (size_t)wsk::wf_slab_cap(conn) + 4 + 4 * (size_t)NL) +
+             ((size_t)wsk::wf_chunks((int32_t)N) + 2) * (64 * 10 + 8) /* region-id rank tables */;
+    }
+    return job + ws + wf + (1 <<20);
 }
 
 int ws_set_option(ws_ctx *c, const char *name, int64_t v) {
@@ -406,8 +429,9 @@ int ws_gradient(ws_ctx *c, const float *img, int64_t nx, int64_t ny, int64_t nz,
     Geom g = make_geom(nx, ny, nz, ndim);
     size_t N = (size_t)g.n;
     Launch lc = make_launch(c, stream);
-    if ((rc = ensure(c, c->gmax, wsk::MAXSLOTS * 4, "maximum")) != WS_OK) return rc;
-    unsigned int *slots = (unsigned int *)c->gmax.p;
+    const int32_t nparts = wsk::grad_parts(g, ndim, r);
+    if ((rc = ensure(c, c->gmax, ((size_t)nparts + 257) * 4, "partial maxima")) != WS_OK) return rc;
+    float *part = (float *)c->gmax.p, *part_tmp = part + nparts, *gmax = part_tmp + 256;
     float *mag = mag_or_null;
     if (!mag) {
         if ((rc = ensure(c, c->mag, N * 4, "magnitude buffer")) != WS_OK) return rc;
@@ -423,9 +447,8 @@ int ws_gradient(ws_ctx *c, const float *img, int64_t nx, int64_t ny, int64_t nz,
         }
         for (int k = 0; k <= 2 * r; ++k) taps.w[k] = (float)(w[k] / sum);
     }
-    WS_TRY(wsk::launch_grad_zero_slots(lc, slots));
     if (ndim == 2 && r <= wsk::FUSED_MAX_R) {
-        WS_TRY(wsk::launch_grad_fused2d(lc, g, img, mag, slots, taps));
+        WS_TRY(wsk::launch_grad_fused2d(lc, g, img, mag, part, taps));
     } else {
         const float *src = img;
         if (r > 0) {
@@ -438,9 +461,10 @@ int ws_gradient(ws_ctx *c, const float *img, int64_t nx, int64_t ny, int64_t nz,
                 src = dst;
             }
         }
-        WS_TRY(wsk::launch_grad_sobel(lc, g, ndim, src, mag, slots));
+        WS_TRY(wsk::launch_grad_sobel(lc, g, ndim, src, mag, part));
     }
-    WS_TRY(wsk::launch_grad_quant(lc, g.n, dtype == WS_U16, mag, grad, slots));
+    WS_TRY(wsk::launch_grad_max(lc, nparts, part, part_tmp, gmax));
+    WS_TRY(wsk::launch_grad_quant(lc, g.n, dtype == WS_U16, mag, grad, gmax));
     return WS_OK;
 }
 
@@ -498,8 +522,8 @@ int ws_waterfall(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, 
         hipError_t e = hipMemcpyAsync(out, labels, (size_t)g.n * 4, hipMemcpyDeviceToDevice, lc.stream);
         if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
     }
-    return run_waterfall(c, lc, src, full_grid(wsk::wf_tiles(g, ndim)), ndim, conn, dtype == WS_U16, NL, (size_t)g.n,
-                         nullptr, src.im, 1, nullptr, nregions);
+    return run_waterfall(c, lc, src, src, wsk::wf_chunks(g.n), full_grid(wsk::wf_tiles(g, ndim)), ndim, conn,
+                         dtype == WS_U16, NL, (size_t)g.n, nullptr, src.im, 1, nullptr, nregions);
 }
 
 int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, int NL, void *stream) {
@@ -509,7 +533,7 @@ int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, 
     if (NL < 1) return fail(c, WS_EINVAL, "ws_batch: NL must be >= 1");
     int ndim = (conn == 4 || conn == 8) ? 2 : (conn == 6 || conn == 26) ? 3 : 0;
     if (!ndim) return fail(c, WS_EINVAL, "ws_batch: conn must be 4, 8, 6 or 26");
-    int64_t arena = 0, tws = 0, twf = 0;
+    int64_t arena = 0, tws = 0, twf = 0, tch = 0;
     std::string why;
     for (int i = 0; i < n_items; ++i) {
         const ws_item &it = items[i];
@@ -521,16 +545,18 @@ int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, 
         wsk::Geom g = make_geom(it.nx, it.ny, it.nz, ndim);
         tws += (int64_t)g.ntx * g.nty * g.ntz;
         twf += wsk::wf_tiles(g, ndim);
+        tch += wsk::wf_chunks(g.n);
     }
     if (arena >= (1LL << 31)) return fail(c, WS_EINVAL, "ws_batch: total pixels must be < 2^31");
     int rc;
     if ((rc = set_device(c))) return rc;
     Launch lc = make_launch(c, stream);
-    // host staging: [Img table][ws tile map][wf tile map][nregions pointers]
+    // host staging: [Img table][ws tile map][wf tile map][chunk map][nregions pointers]
     size_t tab_b = sizeof(wsk::Img) * (size_t)n_items;
     size_t off_ws = (tab_b + 255) & ~(size_t)255;
     size_t off_wf = (off_ws + 4 * (size_t)tws + 255) & ~(size_t)255;
-    size_t off_outs = (off_wf + 4 * (size_t)twf + 255) & ~(size_t)255;
+    size_t off_ch = (off_wf + 4 * (size_t)twf + 255) & ~(size_t)255;
+    size_t off_outs = (off_ch + 4 * (size_t)tch + 255) & ~(size_t)255;
     size_t total = off_outs + sizeof(int64_t *) * (size_t)n_items;
     if (c->stage_pending) {
         hipError_t e = hipEventSynchronize(c->stage_ev);
@@ -552,9 +578,9 @@ int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, 
     if ((rc = ensure(c, c->tab, total, "batch tables")) != WS_OK) return rc;
     char *h = (char *)c->stage;
     wsk::Img *tab = (wsk::Img *)h;
-    int32_t *mws = (int32_t *)(h + off_ws), *mwf = (int32_t *)(h + off_wf);
+    int32_t *mws = (int32_t *)(h + off_ws), *mwf = (int32_t *)(h + off_wf), *mch = (int32_t *)(h + off_ch);
     int64_t **outs = (int64_t **)(h + off_outs);
-    int32_t pix = 0, t0 = 0, t1 = 0;
+    int32_t pix = 0, t0 = 0, t1 = 0, t2 = 0;
     bool any_counts = false;
     for (int i = 0; i < n_items; ++i) {
         const ws_item &it = items[i];
@@ -564,18 +590,21 @@ int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, 
         im.tile0[wsk::TK_WS] = t0;
         im.tile0[wsk::TK_WF] = t1;
         im.tile0[wsk::TK_GR] = 0;
+        im.tile0[wsk::TK_CH] = t2;
         im.slot0 = 0;
         im.grey = it.grad;
         im.lab = it.out;
         tab[i] = im;
-        int32_t nws = im.g.ntx * im.g.nty * im.g.ntz, nwf = wsk::wf_tiles(im.g, ndim);
+        int32_t nws = im.g.ntx * im.g.nty * im.g.ntz, nwf = wsk::wf_tiles(im.g, ndim), nch = wsk::wf_chunks(im.g.n);
         for (int32_t k = 0; k < nws; ++k) mws[t0 + k] = i;
         for (int32_t k = 0; k < nwf; ++k) mwf[t1 + k] = i;
+        for (int32_t k = 0; k < nch; ++k) mch[t2 + k] = i;
         outs[i] = it.nregions;
         any_counts = any_counts || it.nregions;
         pix += im.g.n;
         t0 += nws;
         t1 += nwf;
+        t2 += nch;
     }
     hipError_t e = hipMemcpyAsync(c->tab.p, c->stage, total, hipMemcpyHostToDevice, lc.stream);
     if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
@@ -585,12 +614,13 @@ int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, 
     const wsk::Img *tab_dev = (const wsk::Img *)d;
     wsk::ImgTable src_ws{tab_dev, (const int32_t *)(d + off_ws)};
     wsk::ImgTable src_wf{tab_dev, (const int32_t *)(d + off_wf)};
+    wsk::ImgTable src_ch{tab_dev, (const int32_t *)(d + off_ch)};
     wsk::TileGrid tg_ws = full_grid((int32_t)tws), tg_wf = full_grid((int32_t)twf);
     bool u16 = dtype == WS_U16;
     if ((rc = run_watershed(c, lc, src_ws, tg_ws, ndim, conn, u16, (size_t)arena)) != WS_OK) return rc;
     wsk::Img none{};
-    return run_waterfall(c, lc, src_wf, tg_wf, ndim, conn, u16, NL, (size_t)arena, tab_dev, none, n_items,
-                         any_counts ? (int64_t *const *)(d + off_outs) : nullptr, nullptr);
+    return run_waterfall(c, lc, src_wf, src_ch, (int32_t)tch, tg_wf, ndim, conn, u16, NL, (size_t)arena, tab_dev, none,
+                         n_items, any_counts ? (int64_t *const *)(d + off_outs) : nullptr, nullptr);
 }
 
 int ws_timing_reset(ws_ctx *c) {

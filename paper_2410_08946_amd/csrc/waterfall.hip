@@ -1,35 +1,64 @@
 // waterfall.hip -- gfx950 kernels of the hierarchical waterfall (Section 4).
 //
-// One layer step (layer k-1 -> layer k), all on the device:
-//   1. key[R] = min over boundary pairs (p in R, q in N(p), q outside R) of
-//      (max(I(p), I(q)) << 32) | label(q)         (Alg. 4 Step V + tie label)
-//      computed per tile: per-pixel candidates are reduced per label in an LDS
-//      hash table (64-bit LDS atomic min), then one global atomicMin per
-//      (tile, label).
-//   2. union(R, target(key[R])) for every region of layer k-1 (CAS hooking of
-//      the larger root below the smaller, so a group's root is its smallest
-//      label), then compression to the root.
-//   3. compaction of the surviving roots into the region list of layer k.
-// The relabel out_k[p] = root(out_{k-1}[p]) is done by the next layer's key
-// kernel while it loads its labels (and by a last pass for the final layer),
-// which also counts each tile's regions (pixels carrying their own label).
+// Layer k joins every region R of layer k-1 with the region across its lowest
+// boundary pass, key(R) = min over pixel pairs (p in R, q in N(p) outside R)
+// of (max(I(p), I(q)), label(q)). Only the first layer looks at pixels; the
+// later ones work on the region adjacency graph that pass leaves behind:
 //
-// Region tables (keys, parents, lists) use arena labels: the image's arena
-// offset plus its local canonical label, so the region-level kernels need no
-// image lookup and images of a batch never interact. The tables are indexed by
-// label, so they are arena-long but only the entries of live labels are used.
+//   0. Region ids. Layer-0 regions (pixels carrying their own label) get dense
+//      ids in pixel order, so id order is label order and every region table
+//      is dense (rlist[id] = local label, par, key, mlab). The id of label l
+//      is a rank: a bitmap of the roots (one word per 64 pixels) with, per
+//      word, the count of roots before it in its chunk of RCH pixels, and the
+//      chunks' exclusive prefix: id(l) = coff[chunk] + rpre[word] + popcount
+//      of the bits below l. These tables hold 10 bytes per 64 pixels, so the
+//      lookups stay in L2, unlike a pixel-indexed table whose few live
+//      entries each cost a cache line.
+//   1. Pixel pass, one workgroup per tile (it also writes every pixel's
+//      region id, cimg, for step 4): every pixel pair (p, q), q in the
+//      forward half of N(p), whose regions a != b differ is an edge
+//      (a, b, max(I(p), I(q))). A tile's duplicates are merged in an LDS hash
+//      (lowest height kept) and its edges go to the tile's slab. Each edge
+//      lowers key[a] to (w, b) and key[b] to (w, a), first per region in LDS,
+//      then with one 64-bit global atomicMin per (tile, region). Every pixel
+//      pair lies in exactly one tile's forward half, so both directions of
+//      all pairs are seen: the keys equal the definition above.
+//   2. Union of every region with the target of its key (CAS hooking of the
+//      larger id below the smaller, so a group's root is its smallest id =
+//      smallest label), then compression: par[id] = root for every layer-0
+//      id, and the layer's label of every layer-0 region, mlab[k][id].
+//   3. Later layers, one workgroup per group of tiles: the slabs' edges are
+//      mapped to the current roots, edges inside one region dropped,
+//      duplicates merged, keys lowered as in 1; the survivors are written
+//      back compacted at the group's start. Then 2 again.
+//   4. One pass over the pixels writes every layer, out_k[p] =
+//      mlab[k][cimg[p]], and counts each tile's pixels that carry their own
+//      label (the regions of each layer).
+//
+// Hash tables that fill up fall back to direct global writes and atomics, so
+// results never depend on table sizes. Images of a batch have their own
+// chunks, hence disjoint id ranges, and edges only join pixels of one image.
 #include "ws_device.h"
 #include "ws_kernels.h"
 
 namespace wsk {
 
 constexpr uint64_t NOKEY = ~0ull;
+constexpr uint64_t NOPAIR = ~0ull;
 
 template <int NDIM> struct WfTile;
 template <> struct WfTile<2> { static constexpr int X = 64, Y = 16, Z = 1; };
 template <> struct WfTile<3> { static constexpr int X = 16, Y = 8, Z = 8; };
-constexpr int HSLOTS = 1024;  // LDS hash slots (>= pixels per tile, so probing ends)
-constexpr int HBITS = 10;
+constexpr int WF_PIX = 1024;        // pixels per tile (both shapes)
+constexpr int EBITS = 10;           // edge hash: 1024 slots
+constexpr int ESLOTS = 1 << EBITS;
+constexpr int MAXPROBE = 64;        // probes before a hash insert falls back
+constexpr int RCH = 4096;           // pixels per region-id chunk (16 per thread)
+constexpr int SCAN_B = NTHREADS * 16;  // elements per workgroup of the scans
+constexpr int MAX_F = NTHREADS;     // tile groups merged per workgroup (one count per thread)
+
+// Forward half of a neighbourhood: the neighbours with a larger linear index.
+template <int CONN> __host__ __device__ constexpr bool forward(int k) { return nb_j<CONN>(k) > 13; }
 
 // Block-wide exclusive scan of one int per thread; returns the block total.
 __device__ __forceinline__ int block_scan_excl(int v, int &excl) {
@@ -52,146 +81,106 @@ __device__ __forceinline__ int block_scan_excl(int v, int &excl) {
     return total;
 }
 
+__device__ __forceinline__ uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
+
 // ---------------------------------------------------------------------------
-// Layer-0 region lists: per tile, the pixels that carry their own label, in
-// tile order then pixel order; written as arena labels. Also initialises
-// their keys and parents. Per-tile counts are kept for per-image counts.
+// LDS hash tables. Inserts return false when MAXPROBE slots were taken by
+// other keys; the caller then applies the update directly in global memory.
 // ---------------------------------------------------------------------------
-template <int NDIM, class Src>
-__global__ __launch_bounds__(NTHREADS) void k_root_count(Src src, int32_t ntiles, int32_t *__restrict__ tile_cnt,
-                                                         int32_t *__restrict__ tile_cnt_keep) {
-    using TS = WfTile<NDIM>;
-    constexpr int PER = TS::X * TS::Y * TS::Z / NTHREADS;
-    {
-        const int t = blockIdx.x;
-        if (t >= ntiles) return;
-        Img im;
-        int lt;
-        fetch(src, t, TK_WF, im, lt);
-        const Geom &g = im.g;
-        int ox, oy, oz;
-        tile_xyz<TS::X, TS::Y, TS::Z>(g, lt, ox, oy, oz);
-        int32_t p[PER], l[PER];
-        bool ok[PER];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            int i = threadIdx.x * PER + j;
-            int x = ox + i % TS::X, y = oy + (i / TS::X) % TS::Y, z = oz + i / (TS::X * TS::Y);
-            ok[j] = in_image(g, x, y, z);
-            p[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
+__device__ __forceinline__ bool edge_insert(unsigned long long *ek, unsigned int *ew, uint64_t pair, uint32_t w) {
+    uint32_t h = (uint32_t)((pair * 0x9E3779B97F4A7C15ull) >> (64 - EBITS));
+    for (int probe = 0; probe < MAXPROBE; ++probe) {
+        unsigned long long cur = ek[h];
+        if (cur == NOPAIR) cur = atomicCAS(&ek[h], (unsigned long long)NOPAIR, (unsigned long long)pair);
+        if (cur == NOPAIR || cur == pair) {
+            atomicMin(&ew[h], w);
+            return true;
         }
-#pragma unroll
-        for (int j = 0; j < PER; ++j) l[j] = im.lab[p[j]];
-        int cnt = 0;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) cnt += (ok[j] && l[j] == p[j]) ? 1 : 0;
-        int excl;
-        int total = block_scan_excl(cnt, excl);
-        if (threadIdx.x == 0) {
-            tile_cnt[t] = total;
-            tile_cnt_keep[t] = total;
+        h = (h + 1) & (ESLOTS - 1);
+    }
+    return false;
+}
+
+template <int BITS>
+__device__ __forceinline__ bool region_insert(int *hk, unsigned long long *hv, int l, uint64_t v) {
+    uint32_t h = ((uint32_t)l * 2654435761u) >> (32 - BITS);
+    for (int probe = 0; probe < MAXPROBE; ++probe) {
+        int cur = hk[h];
+        if (cur == -1) cur = atomicCAS(&hk[h], -1, l);
+        if (cur == -1 || cur == l) {
+            atomicMin(&hv[h], (unsigned long long)v);
+            return true;
         }
+        h = (h + 1) & ((1 << BITS) - 1);
+    }
+    return false;
+}
+
+// Both directions of edge (lo, hi, w) into the per-region minima.
+template <int BITS>
+__device__ __forceinline__ void edge_keys(int *hk, unsigned long long *hv, uint64_t *__restrict__ key, int32_t lo,
+                                          int32_t hi, uint32_t w) {
+    uint64_t vlo = ((uint64_t)w << 32) | (uint32_t)hi, vhi = ((uint64_t)w << 32) | (uint32_t)lo;
+    if (!region_insert<BITS>(hk, hv, lo, vlo)) atomicMin((unsigned long long *)(key + lo), (unsigned long long)vlo);
+    if (!region_insert<BITS>(hk, hv, hi, vhi)) atomicMin((unsigned long long *)(key + hi), (unsigned long long)vhi);
+}
+
+// An edge that found no hash slot: straight to the slab and the global keys.
+__device__ __forceinline__ void edge_direct(int *ectr, uint64_t *__restrict__ key, int32_t *__restrict__ ea,
+                                            int32_t *__restrict__ eb, int32_t *__restrict__ eww, size_t base,
+                                            int32_t lo, int32_t hi, uint32_t w) {
+    size_t pos = base + atomicAdd(ectr, 1);
+    ea[pos] = lo;
+    eb[pos] = hi;
+    eww[pos] = (int32_t)w;
+    atomicMin((unsigned long long *)(key + lo), (unsigned long long)(((uint64_t)w << 32) | (uint32_t)hi));
+    atomicMin((unsigned long long *)(key + hi), (unsigned long long)(((uint64_t)w << 32) | (uint32_t)lo));
+}
+
+// Writes the edge hash's entries to the slab at base + ectr.., feeding their
+// keys into the region hash. Wave-aggregated slot reservation.
+template <int BITS>
+__device__ __forceinline__ void emit_edges(const unsigned long long *ek, const unsigned int *ew, int *hk,
+                                           unsigned long long *hv, int *ectr, uint64_t *__restrict__ key,
+                                           int32_t *__restrict__ ea, int32_t *__restrict__ eb,
+                                           int32_t *__restrict__ eww, size_t base) {
+    for (int h0 = 0; h0 < ESLOTS; h0 += NTHREADS) {
+        int h = h0 + threadIdx.x;
+        unsigned long long pk = ek[h];
+        bool v = pk != NOPAIR;
+        uint64_t m = __ballot(v);
+        if (m == 0) continue;  // wave-uniform
+        int wbase = 0;
+        if (__lane_id() == 0) wbase = atomicAdd(ectr, __popcll(m));
+        wbase = __shfl(wbase, 0);
+        if (!v) continue;
+        size_t pos = base + wbase + __popcll(m & lanes_below());
+        int32_t lo = (int32_t)(pk >> 32), hi = (int32_t)(uint32_t)pk;
+        uint32_t w = ew[h];
+        ea[pos] = lo;
+        eb[pos] = hi;
+        eww[pos] = (int32_t)w;
+        edge_keys<BITS>(hk, hv, key, lo, hi, w);
     }
 }
 
-template <int NDIM, class Src>
-__global__ __launch_bounds__(NTHREADS) void k_root_write(Src src, int32_t ntiles, const int32_t *__restrict__ tile_off,
-                                                         int32_t *__restrict__ list, uint64_t *__restrict__ key,
-                                                         int32_t *__restrict__ par) {
-    using TS = WfTile<NDIM>;
-    constexpr int PER = TS::X * TS::Y * TS::Z / NTHREADS;
-    {
-        const int t = blockIdx.x;
-        if (t >= ntiles) return;
-        Img im;
-        int lt;
-        fetch(src, t, TK_WF, im, lt);
-        const Geom &g = im.g;
-        int ox, oy, oz;
-        tile_xyz<TS::X, TS::Y, TS::Z>(g, lt, ox, oy, oz);
-        int32_t p[PER], l[PER];
-        bool ok[PER];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            int i = threadIdx.x * PER + j;
-            int x = ox + i % TS::X, y = oy + (i / TS::X) % TS::Y, z = oz + i / (TS::X * TS::Y);
-            ok[j] = in_image(g, x, y, z);
-            p[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
-        }
-#pragma unroll
-        for (int j = 0; j < PER; ++j) l[j] = im.lab[p[j]];
-        uint32_t mask = 0;
-#pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (ok[j] && l[j] == p[j]) mask |= 1u << j;
-        int excl;
-        block_scan_excl(__popc(mask), excl);
-        int32_t o = tile_off[t] + excl;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            if (!(mask >> j & 1u)) continue;
-            int32_t G = im.pix0 + p[j];
-            list[o++] = G;
-            key[G] = NOKEY;
-            par[G] = G;
-        }
+// Per-region minima of the LDS hash into the global keys.
+template <int BITS>
+__device__ __forceinline__ void flush_keys(const int *hk, const unsigned long long *hv, uint64_t *__restrict__ key) {
+    for (int h = threadIdx.x; h < (1 << BITS); h += NTHREADS) {
+        int l = hk[h];
+        if (l >= 0) atomicMin((unsigned long long *)(key + l), hv[h]);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Order-preserving compaction of a region list (survivors: par[r] == r) in
-// three kernels without contended atomics: per-chunk counts, a one-workgroup
-// exclusive scan, per-chunk ordered writes (which also reset the keys).
+// Scans. k_scan: one workgroup, exclusive scan of n counts in place, total to
+// *total_out (n <= SCAN_B * 16 keeps it short). For longer arrays the counts
+// are first summed per SCAN_B block (k_scan_part), the block sums scanned by
+// k_scan, then every block rescanned with its offset (k_scan_apply).
 // ---------------------------------------------------------------------------
-constexpr int CITEMS = 16;                      // elements per thread per chunk
-constexpr int CCHUNK = NTHREADS * CITEMS;       // elements per chunk
-
-// Predicates and values of CITEMS list elements (element j at first + j*step),
-// with all loads of a phase issued before any is used.
-__device__ __forceinline__ uint32_t list_batch(const int32_t *__restrict__ list, const int32_t *__restrict__ par,
-                                               int32_t n, int32_t first, int32_t step, int32_t *vals) {
-    int32_t a[CITEMS], b[CITEMS];
-    uint32_t in = 0;
-#pragma unroll
-    for (int j = 0; j < CITEMS; ++j) {
-        int32_t i = first + j * step;
-        if (i < n) in |= 1u << j;
-        a[j] = list[i < n ? i : 0];
-    }
-#pragma unroll
-    for (int j = 0; j < CITEMS; ++j) b[j] = par[a[j]];
-    uint32_t mask = 0;
-#pragma unroll
-    for (int j = 0; j < CITEMS; ++j) {
-        vals[j] = a[j];
-        if ((in >> j & 1u) && b[j] == a[j]) mask |= 1u << j;
-    }
-    return mask;
-}
-
-__global__ __launch_bounds__(NTHREADS) void k_compact_count(const int32_t *__restrict__ list,
-                                                            const int32_t *__restrict__ count,
-                                                            const int32_t *__restrict__ par,
-                                                            int32_t *__restrict__ chunk_count) {
-    int32_t n = *count;
-    int32_t nchunks = (n + CCHUNK - 1) / CCHUNK;
-    for (int32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        int32_t vals[CITEMS];
-        int cnt = __popc(list_batch(list, par, n, c * CCHUNK + threadIdx.x, NTHREADS, vals));
-        int excl;
-        int total = block_scan_excl(cnt, excl);
-        if (threadIdx.x == 0) chunk_count[c] = total;
-    }
-}
-
-// Exclusive scan of n counts in place (one workgroup); total into *total_out.
-// n is derived from *n_dev when given (chunks of a device-sized list). Each
-// thread owns a contiguous run of the counts (loads issued together), the
-// runs' sums are scanned across the workgroup, then each run is rewritten.
-__global__ __launch_bounds__(NTHREADS) void k_scan(int32_t n_host, const int32_t *__restrict__ n_dev, int32_t chunk,
-                                                   int32_t *__restrict__ cnt, int32_t *__restrict__ total_out) {
+__global__ __launch_bounds__(NTHREADS) void k_scan(int32_t n, int32_t *__restrict__ cnt, int32_t *__restrict__ total_out) {
     constexpr int U = 16;
-    int32_t n = n_dev ? (*n_dev + chunk - 1) / chunk : n_host;
     int32_t per = (n + NTHREADS - 1) / NTHREADS;
     int32_t lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
     int32_t sum = 0;
@@ -219,221 +208,419 @@ __global__ __launch_bounds__(NTHREADS) void k_scan(int32_t n_host, const int32_t
     if (threadIdx.x == 0 && total_out) *total_out = total;
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_compact_write(const int32_t *__restrict__ list,
-                                                            const int32_t *__restrict__ count,
-                                                            const int32_t *__restrict__ par,
-                                                            const int32_t *__restrict__ chunk_off,
-                                                            int32_t *__restrict__ list_out,
-                                                            uint64_t *__restrict__ key) {
-    int32_t n = *count;
-    int32_t nchunks = (n + CCHUNK - 1) / CCHUNK;
-    for (int32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        // per thread: a contiguous run of CITEMS elements, so the written
-        // order equals the source order
-        int32_t vals[CITEMS];
-        uint32_t mask = list_batch(list, par, n, c * CCHUNK + threadIdx.x * CITEMS, 1, vals);
-        int excl;
-        block_scan_excl(__popc(mask), excl);
-        int32_t o = chunk_off[c] + excl;
+__global__ __launch_bounds__(NTHREADS) void k_scan_part(int32_t n, const int32_t *__restrict__ cnt,
+                                                        int32_t *__restrict__ part) {
+    constexpr int U = SCAN_B / NTHREADS;
+    int32_t b0 = blockIdx.x * SCAN_B;
+    int32_t v[U];
 #pragma unroll
-        for (int j = 0; j < CITEMS; ++j) {
-            if (!(mask >> j & 1u)) continue;
-            int32_t r = vals[j];
-            list_out[o++] = r;
-            key[r] = NOKEY;
+    for (int j = 0; j < U; ++j) {
+        int32_t i = b0 + j * NTHREADS + threadIdx.x;
+        v[j] = i < n ? cnt[i] : 0;
+    }
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < U; ++j) s += v[j];
+    int excl;
+    int total = block_scan_excl(s, excl);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_scan_apply(int32_t n, int32_t *__restrict__ cnt,
+                                                         const int32_t *__restrict__ part) {
+    constexpr int U = SCAN_B / NTHREADS;
+    int32_t b0 = blockIdx.x * SCAN_B + threadIdx.x * U;  // a contiguous run per thread
+    int32_t v[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) v[j] = b0 + j < n ? cnt[b0 + j] : 0;
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < U; ++j) s += v[j];
+    int excl;
+    block_scan_excl(s, excl);
+    int32_t run = part[blockIdx.x] + excl;
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        if (b0 + j < n) {
+            cnt[b0 + j] = run;
+            run += v[j];
         }
+}
+
+// ---------------------------------------------------------------------------
+// 0. Region ids. Chunk t covers pixels [lc*RCH, lc*RCH + RCH) of its image;
+// element j of thread i is pixel lc*RCH + j*NTHREADS + i, so the ballot of
+// wave w over element j is bitmap word j*NW + w of the chunk.
+// ---------------------------------------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(NTHREADS) void k_root_bits(Src src, int32_t nchunks, int32_t *__restrict__ ccnt,
+                                                        unsigned long long *__restrict__ rbits,
+                                                        uint16_t *__restrict__ rpre) {
+    constexpr int PER = RCH / NTHREADS;
+    constexpr int NW = NTHREADS / 64;
+    static_assert(PER * NW == 64, "one wave scans the chunk's words");
+    __shared__ int wc[64];
+    const int t = blockIdx.x;
+    if (t >= nchunks) return;
+    Img im;
+    int lc;
+    fetch(src, t, TK_CH, im, lc);
+    const int32_t base = lc * RCH, end = im.g.n;
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    int32_t l[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int32_t p = base + j * NTHREADS + threadIdx.x;
+        l[j] = p < end ? im.lab[p] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        uint64_t m = __ballot(l[j] == base + j * NTHREADS + (int)threadIdx.x);
+        if (lane == 0) {
+            rbits[(size_t)t * 64 + j * NW + w] = m;
+            wc[j * NW + w] = __popcll(m);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        int v = wc[lane], x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            int y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        rpre[(size_t)t * 64 + lane] = (uint16_t)(x - v);
+        if (lane == 63) ccnt[t] = x;
+    }
+}
+
+// Keys and parents of the nreg0 regions.
+__global__ __launch_bounds__(NTHREADS) void k_wf_tables(const int32_t *__restrict__ nreg0, uint64_t *__restrict__ key,
+                                                        int32_t *__restrict__ par) {
+    const int32_t n = *nreg0;
+    for (int32_t c = blockIdx.x * NTHREADS + threadIdx.x; c < n; c += gridDim.x * NTHREADS) {
+        key[c] = NOKEY;
+        par[c] = c;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Step V per tile with LDS aggregation. Layer `layer` is loaded; with
-// `relabel` set its labels are first mapped through the roots in `par` (the
-// merge that produced layer+1), layer+1 is written for the tile's own pixels
-// and its regions are counted into tile_cnt; the keys are then those of
-// layer+1 (else of `layer`).
+// 1. Pixel pass of layer 0 (keys of layer 1 and the tiles' edge slabs; the
+// region id of every own pixel into cimg, the labels of the own roots into
+// rlist, the tile's layer-0 region count). Labels are clamped to the image
+// and ids to [0, nreg0) so that labels that are not canonical cannot address
+// outside the tables.
 // ---------------------------------------------------------------------------
 template <int CONN, typename T, class Src>
-__global__ __launch_bounds__(NTHREADS) void k_wf_edge(Src src, int32_t ntiles, int32_t layer, int32_t relabel,
-                                                      const int32_t *__restrict__ par, uint64_t *__restrict__ key,
-                                                      int32_t *__restrict__ tile_cnt) {
+__global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, const unsigned long long *__restrict__ rbits,
+                                                     const uint16_t *__restrict__ rpre, const int32_t *__restrict__ coff,
+                                                     const int32_t *__restrict__ nreg0, int32_t *__restrict__ cimg,
+                                                     int32_t *__restrict__ rlist, int32_t *__restrict__ tile_cnt0,
+                                                     uint64_t *__restrict__ key, int32_t *__restrict__ ea,
+                                                     int32_t *__restrict__ eb, int32_t *__restrict__ eww,
+                                                     int32_t *__restrict__ ecnt, int32_t cap) {
     constexpr int NDIM = ndim_of<CONN>();
     using TS = WfTile<NDIM>;
     constexpr int SX = TS::X + 2, SY = TS::Y + 2, SZ = NDIM == 3 ? TS::Z + 2 : 1, RZ = NDIM == 3 ? 1 : 0;
     constexpr int CELLS = SX * SY * SZ;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
-    __shared__ int sL[CELLS];
-    __shared__ int sI[CELLS];
-    __shared__ int hk[HSLOTS];
-    __shared__ unsigned long long hv[HSLOTS];
+    static_assert(PIX == WF_PIX && PIX % NTHREADS == 0, "whole waves per tile");
+    // sL/sI hold the tile's ids and grey values; once the edges are collected
+    // the same words hold the region hash (keys, then 64-bit minima)
+    constexpr int RBITS = 9;
+    static_assert((1 << RBITS) * 12 <= CELLS * 8, "region hash fits the id/grey arrays");
+    __shared__ unsigned long long sbuf[CELLS];
+    __shared__ unsigned long long ek[ESLOTS];
+    __shared__ unsigned int ew[ESLOTS];
+    __shared__ int ectr;
+    int *sL = (int *)sbuf, *sI = sL + CELLS;
+    int *hk = (int *)sbuf;
+    unsigned long long *hv = sbuf + (1 << RBITS) / 2;
+    if ((int)blockIdx.x >= ntiles) return;
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    Img im;
+    int lt;
+    fetch(src, t, TK_WF, im, lt);
+    const Geom &g = im.g;
+    const T *I = (const T *)im.grey;
+    const int32_t *L0 = im.lab;
+    int ox, oy, oz;
+    tile_xyz<TS::X, TS::Y, TS::Z>(g, lt, ox, oy, oz);
+    const int32_t nr = *nreg0;
+    const uint32_t cmax = nr > 0 ? (uint32_t)(nr - 1) : 0u;
+    int nroots = 0;
     {
-        const int t = blockIdx.x;
-        if (t >= ntiles) return;
-        Img im;
-        int lt;
-        fetch(src, t, TK_WF, im, lt);
-        const Geom &g = im.g;
-        const T *I = (const T *)im.grey;
-        const int32_t *prev = im.lab + (size_t)layer * g.n;
-        int32_t *cur = im.lab + (size_t)(layer + 1) * g.n;
-        int ox, oy, oz;
-        tile_xyz<TS::X, TS::Y, TS::Z>(g, lt, ox, oy, oz);
-        int nroots = 0;
-        {
-            // batched loads: labels and grey values first, then the root map
-            constexpr int PER = (CELLS + NTHREADS - 1) / NTHREADS;
-            int32_t idx[PER];
-            bool ok[PER], inner[PER];
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                int c = threadIdx.x + j * NTHREADS;
-                int cx = c % SX, cy = (c / SX) % SY, cz = c / (SX * SY);
-                int x = ox + cx - 1, y = oy + cy - 1, z = oz + cz - RZ;
-                ok[j] = c < CELLS && in_image(g, x, y, z);
-                inner[j] = cx >= 1 && cx <= TS::X && cy >= 1 && cy <= TS::Y && (NDIM == 2 || (cz >= 1 && cz <= TS::Z));
-                idx[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
-            }
-            int32_t lv[PER];
-            T gv[PER];
-#pragma unroll
-            for (int j = 0; j < PER; ++j) lv[j] = prev[idx[j]];
-#pragma unroll
-            for (int j = 0; j < PER; ++j) gv[j] = I[idx[j]];
-            if (relabel) {
-#pragma unroll
-                for (int j = 0; j < PER; ++j) lv[j] = par[im.pix0 + lv[j]] - im.pix0;
-#pragma unroll
-                for (int j = 0; j < PER; ++j)
-                    if (ok[j] && inner[j]) {
-                        cur[idx[j]] = lv[j];
-                        nroots += lv[j] == idx[j] ? 1 : 0;
-                    }
-            }
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                int c = threadIdx.x + j * NTHREADS;
-                if (c < CELLS) {
-                    sL[c] = ok[j] ? lv[j] : -1;
-                    sI[c] = ok[j] ? (int)gv[j] : SENT;
-                }
-            }
-        }
-        for (int h = threadIdx.x; h < HSLOTS; h += NTHREADS) {
-            hk[h] = -1;
-            hv[h] = NOKEY;
-        }
-        __syncthreads();
-        static_assert(PIX % NTHREADS == 0, "whole waves per tile");
-        for (int i = threadIdx.x; i < PIX; i += NTHREADS) {  // uniform trip count
-            int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-            int s = ((z + RZ) * SY + (y + 1)) * SX + (x + 1);
-            int l = sL[s];
-            uint64_t best = NOKEY;
-            if (l >= 0) {
-                uint32_t v = (uint32_t)sI[s];
-#pragma unroll
-                for (int k = 0; k < CONN; ++k) {
-                    int o = s + nb_dx<CONN>(k) + SX * (nb_dy<CONN>(k) + SY * nb_dz<CONN>(k));
-                    int lq = sL[o];
-                    if (lq < 0 || lq == l) continue;
-                    uint32_t w = (uint32_t)sI[o];
-                    uint64_t c = ((uint64_t)(v > w ? v : w) << 32) | (uint32_t)(im.pix0 + lq);
-                    best = c < best ? c : best;
-                }
-            }
-            if (best == NOKEY) continue;
-            uint32_t h = ((uint32_t)l * 2654435761u) >> (32 - HBITS);
-            for (;;) {
-                int cur = hk[h];
-                if (cur == -1) cur = atomicCAS(&hk[h], -1, l);
-                if (cur == -1 || cur == l) {
-                    atomicMin(&hv[h], (unsigned long long)best);
-                    break;
-                }
-                h = (h + 1) & (HSLOTS - 1);
-            }
-        }
-        __syncthreads();
-        for (int h = threadIdx.x; h < HSLOTS; h += NTHREADS) {
-            int l = hk[h];
-            if (l >= 0) atomicMin((unsigned long long *)(key + im.pix0 + l), hv[h]);
-        }
-        if (relabel) {
-            int excl;
-            int total = block_scan_excl(nroots, excl);
-            if (threadIdx.x == 0) tile_cnt[t] = total;
-        }
-        __syncthreads();
-    }
-}
-
-// Join every region with the region across its lowest pass. The list holds
-// every layer-0 region; exactly the regions of the current layer that have a
-// boundary carry a key (dead regions had theirs reset when they merged), and
-// each key is reset here for the next layer.
-__global__ __launch_bounds__(NTHREADS) void k_wf_union(const int32_t *__restrict__ list,
-                                                       const int32_t *__restrict__ count,
-                                                       uint64_t *__restrict__ key, int32_t *__restrict__ par) {
-    int32_t c = *count;
-    for (int32_t i = blockIdx.x * NTHREADS + threadIdx.x; i < c; i += gridDim.x * NTHREADS) {
-        int32_t r = list[i];
-        uint64_t kk = key[r];
-        if (kk == NOKEY) continue;
-        key[r] = NOKEY;
-        gunion(par, r, (int32_t)(uint32_t)(kk & 0xffffffffull));
-    }
-}
-
-__global__ __launch_bounds__(NTHREADS) void k_wf_compress(const int32_t *__restrict__ list,
-                                                          const int32_t *__restrict__ count,
-                                                          int32_t *__restrict__ par) {
-    int32_t c = *count;
-    for (int32_t i = blockIdx.x * NTHREADS + threadIdx.x; i < c; i += gridDim.x * NTHREADS) {
-        int32_t r = list[i];
-        par[r] = gfind_ro(par, r);
-    }
-}
-
-// Last layer: out_{layer+1} = root(out_layer), with per-tile region counts.
-template <int NDIM, class Src>
-__global__ __launch_bounds__(NTHREADS) void k_wf_relabel(Src src, int32_t ntiles, int32_t layer,
-                                                         const int32_t *__restrict__ par,
-                                                         int32_t *__restrict__ tile_cnt) {
-    using TS = WfTile<NDIM>;
-    constexpr int PER = TS::X * TS::Y * TS::Z / NTHREADS;
-    {
-        const int t = blockIdx.x;
-        if (t >= ntiles) return;
-        Img im;
-        int lt;
-        fetch(src, t, TK_WF, im, lt);
-        const Geom &g = im.g;
-        const int32_t *prev = im.lab + (size_t)layer * g.n;
-        int32_t *cur = im.lab + (size_t)(layer + 1) * g.n;
-        int ox, oy, oz;
-        tile_xyz<TS::X, TS::Y, TS::Z>(g, lt, ox, oy, oz);
-        int32_t p[PER], l[PER];
-        bool ok[PER];
+        constexpr int PER = (CELLS + NTHREADS - 1) / NTHREADS;
+        int32_t idx[PER];
+        bool ok[PER], own[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            int i = threadIdx.x + j * NTHREADS;
-            int x = ox + i % TS::X, y = oy + (i / TS::X) % TS::Y, z = oz + i / (TS::X * TS::Y);
-            ok[j] = in_image(g, x, y, z);
-            p[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
+            int c = threadIdx.x + j * NTHREADS;
+            int cx = c % SX, cy = (c / SX) % SY, cz = c / (SX * SY);
+            int x = ox + cx - 1, y = oy + cy - 1, z = oz + cz - RZ;
+            ok[j] = c < CELLS && in_image(g, x, y, z);
+            own[j] = ok[j] && cx >= 1 && cx <= TS::X && cy >= 1 && cy <= TS::Y &&
+                     (NDIM == 2 || (cz >= 1 && cz <= TS::Z));
+            idx[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
+        }
+        int32_t lv[PER];
+        T gv[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) lv[j] = L0[idx[j]];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) gv[j] = I[idx[j]];
+        // rank lookups, all loads issued together
+        const int32_t ch0 = im.tile0[TK_CH];
+        unsigned long long bw[PER];
+        int32_t pw[PER], cw[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            int32_t l = (uint32_t)lv[j] < (uint32_t)g.n ? lv[j] : 0;
+            int32_t ch = ch0 + l / RCH;
+            size_t wi = (size_t)ch * 64 + (size_t)((l % RCH) >> 6);
+            bw[j] = rbits[wi] & ((1ull << (l & 63)) - 1ull);
+            pw[j] = rpre[wi];
+            cw[j] = coff[ch];
         }
 #pragma unroll
-        for (int j = 0; j < PER; ++j) l[j] = prev[p[j]];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) l[j] = par[im.pix0 + l[j]] - im.pix0;
-        int nroots = 0;
-#pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (ok[j]) {
-                cur[p[j]] = l[j];
-                nroots += l[j] == p[j] ? 1 : 0;
+        for (int j = 0; j < PER; ++j) {
+            int c = threadIdx.x + j * NTHREADS;
+            uint32_t cv = (uint32_t)(cw[j] + pw[j] + __popcll(bw[j]));
+            cv = cv <= cmax ? cv : cmax;
+            if (c < CELLS) {
+                sL[c] = ok[j] ? (int)cv : -1;
+                sI[c] = ok[j] ? (int)gv[j] : 0;
             }
+            if (own[j]) {
+                cimg[(size_t)im.pix0 + idx[j]] = (int32_t)cv;
+                if (lv[j] == idx[j]) {
+                    rlist[cv] = idx[j];
+                    ++nroots;
+                }
+            }
+        }
+    }
+    for (int h = threadIdx.x; h < ESLOTS; h += NTHREADS) {
+        ek[h] = NOPAIR;
+        ew[h] = 0xffffffffu;
+    }
+    if (threadIdx.x == 0) ectr = 0;
+    __syncthreads();
+    const size_t base = (size_t)t * (size_t)cap;
+    for (int i = threadIdx.x; i < PIX; i += NTHREADS) {  // uniform trip count
+        int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+        int s = ((z + RZ) * SY + (y + 1)) * SX + (x + 1);
+        int a = sL[s];
+        if (a < 0) continue;
+        uint32_t v = (uint32_t)sI[s];
+#pragma unroll
+        for (int k = 0; k < CONN; ++k) {
+            if (!forward<CONN>(k)) continue;
+            int o = s + nb_dx<CONN>(k) + SX * (nb_dy<CONN>(k) + SY * nb_dz<CONN>(k));
+            int b = sL[o];
+            if (b < 0 || b == a) continue;
+            uint32_t wq = (uint32_t)sI[o];
+            uint32_t w = v > wq ? v : wq;
+            int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+            uint64_t pair = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi;
+            if (!edge_insert(ek, ew, pair, w)) edge_direct(&ectr, key, ea, eb, eww, base, lo, hi, w);
+        }
+    }
+    __syncthreads();
+    for (int h = threadIdx.x; h < (1 << RBITS); h += NTHREADS) {
+        hk[h] = -1;
+        hv[h] = NOKEY;
+    }
+    __syncthreads();
+    emit_edges<RBITS>(ek, ew, hk, hv, &ectr, key, ea, eb, eww, base);
+    __syncthreads();
+    flush_keys<RBITS>(hk, hv, key);
+    int excl;
+    int roots = block_scan_excl(nroots, excl);
+    if (threadIdx.x == 0) {
+        ecnt[t] = ectr;
+        tile_cnt0[t] = roots;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. Edge pass of a later layer. Workgroup g merges the f groups of gin tiles
+// starting at tile g*gin*f (their edges sit at the start of each group's
+// slab range, counts at ecnt[first tile of the group]) into one group of
+// gin*f tiles. par maps every layer-0 id to its current root.
+//
+// In-place safety: outputs are written at increasing offsets from the merged
+// group's start, never more of them than inputs consumed so far, and input e
+// (in concatenated order) lies at an offset >= e because every group holds at
+// most its capacity; a barrier after each batch's loads ends its reads first.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NTHREADS) void k_wf_level(int32_t ntiles, int32_t gin, int32_t f, int32_t cap,
+                                                       const int32_t *__restrict__ par, uint64_t *__restrict__ key,
+                                                       int32_t *__restrict__ ea, int32_t *__restrict__ eb,
+                                                       int32_t *__restrict__ eww, int32_t *__restrict__ ecnt) {
+    constexpr int RBITS = 10;
+    __shared__ unsigned long long ek[ESLOTS];
+    __shared__ unsigned int ew[ESLOTS];
+    __shared__ int hk[1 << RBITS];
+    __shared__ unsigned long long hv[1 << RBITS];
+    __shared__ int soff[MAX_F];
+    __shared__ int stotal, ectr;
+    const int32_t t0 = blockIdx.x * gin * f;
+    if (t0 >= ntiles) return;
+    const int32_t nsub = min(f, (ntiles - t0 + gin - 1) / gin);
+    {
+        int c = (int)threadIdx.x < nsub ? ecnt[t0 + threadIdx.x * gin] : 0;
         int excl;
-        int total = block_scan_excl(nroots, excl);
-        if (threadIdx.x == 0) tile_cnt[t] = total;
+        int total = block_scan_excl(c, excl);
+        soff[threadIdx.x] = excl;
+        if (threadIdx.x == 0) {
+            stotal = total;
+            ectr = 0;
+        }
+    }
+    for (int h = threadIdx.x; h < ESLOTS; h += NTHREADS) {
+        ek[h] = NOPAIR;
+        ew[h] = 0xffffffffu;
+    }
+    for (int h = threadIdx.x; h < (1 << RBITS); h += NTHREADS) {
+        hk[h] = -1;
+        hv[h] = NOKEY;
+    }
+    __syncthreads();
+    const int32_t total = stotal;
+    const size_t base = (size_t)t0 * (size_t)cap;
+    for (int32_t e0 = 0; e0 < total; e0 += NTHREADS) {  // uniform trip count
+        int32_t e = e0 + threadIdx.x;
+        int32_t ra = 0, rb = 0;
+        uint32_t w = 0;
+        if (e < total) {
+            int lo = 0, hi = nsub - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (soff[mid] <= e) lo = mid;
+                else hi = mid - 1;
+            }
+            size_t at = (size_t)(t0 + lo * gin) * (size_t)cap + (size_t)(e - soff[lo]);
+            int32_t a = ea[at], b = eb[at];
+            w = (uint32_t)eww[at];
+            ra = par[a];
+            rb = par[b];
+        }
+        __syncthreads();
+        if (e < total && ra != rb) {
+            int32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+            uint64_t pair = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi;
+            if (!edge_insert(ek, ew, pair, w)) edge_direct(&ectr, key, ea, eb, eww, base, lo, hi, w);
+        }
+    }
+    __syncthreads();
+    emit_edges<RBITS>(ek, ew, hk, hv, &ectr, key, ea, eb, eww, base);
+    __syncthreads();
+    flush_keys<RBITS>(hk, hv, key);
+    if (threadIdx.x == 0) ecnt[t0] = ectr;
+}
+
+// ---------------------------------------------------------------------------
+// 2. Union of every live region with the target of its key, then compression.
+// Keys are reset to NOKEY as they are consumed; only roots ever get new ones.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NTHREADS) void k_wf_union(const int32_t *__restrict__ nreg0, uint64_t *__restrict__ key,
+                                                       int32_t *__restrict__ par) {
+    const int32_t n = *nreg0;
+    for (int32_t c = blockIdx.x * NTHREADS + threadIdx.x; c < n; c += gridDim.x * NTHREADS) {
+        uint64_t kk = key[c];
+        if (kk == NOKEY) continue;
+        key[c] = NOKEY;
+        gunion(par, c, (int32_t)(uint32_t)(kk & 0xffffffffull));
+    }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_wf_compress(const int32_t *__restrict__ nreg0, int32_t *__restrict__ par,
+                                                          const int32_t *__restrict__ rlist,
+                                                          int32_t *__restrict__ mlab_k) {
+    const int32_t n = *nreg0;
+    for (int32_t c = blockIdx.x * NTHREADS + threadIdx.x; c < n; c += gridDim.x * NTHREADS) {
+        int32_t r = gfind_ro(par, c);
+        par[c] = r;
+        mlab_k[c] = rlist[r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. Layers 1 .. nl-1 of every pixel from its region id, and per tile the
+// number of pixels carrying their own label in each of them (layer k at
+// tile_cnt[k * ntiles + t]; layer 0's count comes from the pixel pass). With
+// nl == 1 only layer 0 is counted, from the labels.
+// ---------------------------------------------------------------------------
+template <int NDIM, class Src>
+__global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src, int32_t ntiles, int32_t nl,
+                                                     const int32_t *__restrict__ cimg,
+                                                     const int32_t *__restrict__ nreg0,
+                                                     const int32_t *__restrict__ mlab, int64_t mstride,
+                                                     int32_t *__restrict__ tile_cnt) {
+    using TS = WfTile<NDIM>;
+    constexpr int PER = WF_PIX / NTHREADS;
+    constexpr int KB = 8;  // layers counted per LDS round
+    __shared__ int kc[KB];
+    if ((int)blockIdx.x >= ntiles) return;
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    Img im;
+    int lt;
+    fetch(src, t, TK_WF, im, lt);
+    const Geom &g = im.g;
+    int ox, oy, oz;
+    tile_xyz<TS::X, TS::Y, TS::Z>(g, lt, ox, oy, oz);
+    int32_t p[PER], c[PER];
+    bool ok[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int i = threadIdx.x + j * NTHREADS;
+        int x = ox + i % TS::X, y = oy + (i / TS::X) % TS::Y, z = oz + i / (TS::X * TS::Y);
+        ok[j] = in_image(g, x, y, z);
+        p[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
+    }
+    if (threadIdx.x < KB) kc[threadIdx.x] = 0;
+    if (nl == 1) {
+        int own = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) c[j] = im.lab[p[j]];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) own += __popcll(__ballot(ok[j] && c[j] == p[j]));
+        __syncthreads();
+        if (__lane_id() == 0 && own) atomicAdd(&kc[0], own);
+        __syncthreads();
+        if (threadIdx.x == 0) tile_cnt[t] = kc[0];
+        return;
+    }
+    const int32_t nr = *nreg0;
+    const uint32_t cmax = nr > 0 ? (uint32_t)(nr - 1) : 0u;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) c[j] = cimg[(size_t)im.pix0 + p[j]];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) c[j] = (uint32_t)c[j] <= cmax ? c[j] : (int32_t)cmax;
+    __syncthreads();
+    for (int k0 = 1; k0 < nl; k0 += KB) {
+        // one layer per round keeps the kernel at full occupancy
+#pragma unroll 1
+        for (int kk = 0; kk < KB && k0 + kk < nl; ++kk) {
+            const int32_t *m = mlab + (size_t)(k0 + kk - 1) * (size_t)mstride;
+            int32_t *out = im.lab + (size_t)(k0 + kk) * (size_t)g.n;
+            int32_t v[PER];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) v[j] = m[c[j]];
+            int own = 0;
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                if (ok[j]) out[p[j]] = v[j];
+                own += __popcll(__ballot(ok[j] && v[j] == p[j]));
+            }
+            if (__lane_id() == 0 && own) atomicAdd(&kc[kk], own);
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < KB && k0 + (int)threadIdx.x < nl) {
+            tile_cnt[(size_t)(k0 + threadIdx.x) * ntiles + t] = kc[threadIdx.x];
+            kc[threadIdx.x] = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -462,29 +649,8 @@ __global__ __launch_bounds__(NTHREADS) void k_img_counts(const Img *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-template <int CONN, typename T, class Src>
-static int launch_wf_edge_t(Launch &lc, const Src &src, const TileGrid &tg, int32_t layer, int32_t relabel,
-                            const int32_t *par, uint64_t *key, int32_t *tile_cnt) {
-    return lc.run("wf_edge", k_wf_edge<CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, layer, relabel,
-                  par, key, tile_cnt);
-}
-
-template <class Src>
-static int wf_edge_dispatch(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t layer,
-                            int32_t relabel, const int32_t *par, uint64_t *key, int32_t *tile_cnt) {
-    switch (conn) {
-    case 4: return u16 ? launch_wf_edge_t<4, uint16_t>(lc, src, tg, layer, relabel, par, key, tile_cnt)
-                       : launch_wf_edge_t<4, uint8_t>(lc, src, tg, layer, relabel, par, key, tile_cnt);
-    case 8: return u16 ? launch_wf_edge_t<8, uint16_t>(lc, src, tg, layer, relabel, par, key, tile_cnt)
-                       : launch_wf_edge_t<8, uint8_t>(lc, src, tg, layer, relabel, par, key, tile_cnt);
-    case 6: return u16 ? launch_wf_edge_t<6, uint16_t>(lc, src, tg, layer, relabel, par, key, tile_cnt)
-                       : launch_wf_edge_t<6, uint8_t>(lc, src, tg, layer, relabel, par, key, tile_cnt);
-    case 26: return u16 ? launch_wf_edge_t<26, uint16_t>(lc, src, tg, layer, relabel, par, key, tile_cnt)
-                        : launch_wf_edge_t<26, uint8_t>(lc, src, tg, layer, relabel, par, key, tile_cnt);
-    default: return -1;
-    }
-}
-
+// Host side
+// ---------------------------------------------------------------------------
 static inline dim3 list_grid(int32_t n) {
     int32_t b = (n + NTHREADS - 1) / NTHREADS;
     if (b > 8192) b = 8192;
@@ -492,85 +658,111 @@ static inline dim3 list_grid(int32_t n) {
     return dim3(b);
 }
 
-static inline dim3 chunk_grid(int32_t bound) {
-    int32_t c = (bound + CCHUNK - 1) / CCHUNK;
-    if (c > 4096) c = 4096;
-    if (c < 1) c = 1;
-    return dim3(c);
-}
-
-int compact_chunks(int32_t bound) { return (bound + CCHUNK - 1) / CCHUNK + 1; }
-
 int wf_tiles(const Geom &g, int ndim) {
     if (ndim == 3)
         return ((g.nx + WfTile<3>::X - 1) / WfTile<3>::X) * ((g.ny + WfTile<3>::Y - 1) / WfTile<3>::Y) *
                ((g.nz + WfTile<3>::Z - 1) / WfTile<3>::Z);
     return ((g.nx + WfTile<2>::X - 1) / WfTile<2>::X) * ((g.ny + WfTile<2>::Y - 1) / WfTile<2>::Y) * g.nz;
 }
+int wf_chunks(int32_t n) { return (n + RCH - 1) / RCH; }
+int wf_slab_cap(int conn) { return conn / 2 * WF_PIX; }
+int wf_max_merge() { return MAX_F; }
+int scan_tmp_len(int32_t n) { return n <= SCAN_B * 16 ? 1 : (n + SCAN_B - 1) / SCAN_B + 1; }
 
-template <class Src>
-static int wf_init_impl(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t *list, int32_t *count,
-                        uint64_t *key, int32_t *par, int32_t *tile_tmp, int32_t *tile_cnt0) {
-    int rc = ndim == 3 ? lc.run("wf_init", k_root_count<3, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles,
-                                tile_tmp, tile_cnt0)
-                       : lc.run("wf_init", k_root_count<2, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles,
-                                tile_tmp, tile_cnt0);
+// Exclusive scan of n ints in place, total to *total_out; tmp holds
+// scan_tmp_len(n) ints.
+int launch_scan(Launch &lc, int32_t n, int32_t *data, int32_t *tmp, int32_t *total_out) {
+    if (n <= SCAN_B * 16) return lc.run("wf_ids", k_scan, dim3(1), dim3(NTHREADS), n, data, total_out);
+    int32_t nb = (n + SCAN_B - 1) / SCAN_B;
+    int rc = lc.run("wf_ids", k_scan_part, dim3(nb), dim3(NTHREADS), n, (const int32_t *)data, tmp);
     if (rc) return rc;
-    rc = lc.run("wf_init", k_scan, dim3(1), dim3(NTHREADS), tg.ntiles, (const int32_t *)nullptr, 1, tile_tmp, count);
-    if (rc) return rc;
-    return ndim == 3 ? lc.run("wf_init", k_root_write<3, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles,
-                              (const int32_t *)tile_tmp, list, key, par)
-                     : lc.run("wf_init", k_root_write<2, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles,
-                              (const int32_t *)tile_tmp, list, key, par);
+    if ((rc = lc.run("wf_ids", k_scan, dim3(1), dim3(NTHREADS), nb, tmp, total_out))) return rc;
+    return lc.run("wf_ids", k_scan_apply, dim3(nb), dim3(NTHREADS), n, data, (const int32_t *)tmp);
 }
 
-template <class Src>
-static int wf_relabel_impl(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t layer, const int32_t *par,
-                           int32_t *tile_cnt) {
-    return ndim == 3 ? lc.run("wf_relabel", k_wf_relabel<3, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, layer,
-                              par, tile_cnt)
-                     : lc.run("wf_relabel", k_wf_relabel<2, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, layer,
-                              par, tile_cnt);
+int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, int32_t cap, const int32_t *par, uint64_t *key,
+                    int32_t *edges, int32_t *ecnt) {
+    if (f < 1 || f > MAX_F || gin < 1) return -1;
+    int64_t gout = (int64_t)gin * f;
+    int64_t ng = ((int64_t)ntiles + gout - 1) / gout;
+    size_t E = (size_t)ntiles * (size_t)cap;
+    return lc.run("wf_level", k_wf_level, dim3((uint32_t)(ng > 0 ? ng : 1)), dim3(NTHREADS), ntiles, gin, f, cap, par,
+                  key, edges, edges + E, edges + 2 * E, ecnt);
 }
 
-#define WF_SRC_FUNCS(Src)                                                                                         \
-    int launch_wf_init(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t *list, int32_t *count,  \
-                       uint64_t *key, int32_t *par, int32_t *tile_tmp, int32_t *tile_cnt0) {                      \
-        return wf_init_impl(lc, src, tg, ndim, list, count, key, par, tile_tmp, tile_cnt0);                       \
-    }                                                                                                             \
-    int launch_wf_edge(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t layer,        \
-                       int32_t relabel, const int32_t *par, uint64_t *key, int32_t *tile_cnt) {                   \
-        return wf_edge_dispatch(lc, src, tg, conn, u16, layer, relabel, par, key, tile_cnt);                     \
-    }                                                                                                             \
-    int launch_wf_relabel(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t layer,               \
-                          const int32_t *par, int32_t *tile_cnt) {                                                \
-        return wf_relabel_impl(lc, src, tg, ndim, layer, par, tile_cnt);                                          \
-    }
-
-WF_SRC_FUNCS(OneImg)
-WF_SRC_FUNCS(ImgTable)
-
-// Compaction of the survivors of a region list.
-int launch_wf_compact(Launch &lc, int32_t bound, const int32_t *list_in, const int32_t *count_in, int32_t *list_out,
-                      int32_t *count_out, const int32_t *par, uint64_t *key, int32_t *chunk_tmp) {
-    int rc = lc.run("wf_compact", k_compact_count, chunk_grid(bound), dim3(NTHREADS), list_in, count_in, par, chunk_tmp);
-    if (rc) return rc;
-    rc = lc.run("wf_compact", k_scan, dim3(1), dim3(NTHREADS), 0, count_in, CCHUNK, chunk_tmp, count_out);
-    if (rc) return rc;
-    return lc.run("wf_compact", k_compact_write, chunk_grid(bound), dim3(NTHREADS), list_in, count_in, par,
-                  (const int32_t *)chunk_tmp, list_out, key);
+int launch_wf_union(Launch &lc, int32_t bound, const int32_t *nreg0, uint64_t *key, int32_t *par) {
+    return lc.run("wf_union", k_wf_union, list_grid(bound), dim3(NTHREADS), nreg0, key, par);
 }
-
-int launch_wf_union(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, uint64_t *key, int32_t *par) {
-    return lc.run("wf_union", k_wf_union, list_grid(bound), dim3(NTHREADS), list, count, key, par);
-}
-int launch_wf_compress(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, int32_t *par) {
-    return lc.run("wf_compress", k_wf_compress, list_grid(bound), dim3(NTHREADS), list, count, par);
+int launch_wf_compress(Launch &lc, int32_t bound, const int32_t *nreg0, int32_t *par, const int32_t *rlist,
+                       int32_t *mlab_k) {
+    return lc.run("wf_compress", k_wf_compress, list_grid(bound), dim3(NTHREADS), nreg0, par, rlist, mlab_k);
 }
 int launch_img_counts(Launch &lc, const Img *tab, const Img &one, int32_t nimg, int32_t nl, int32_t ntiles_total,
                       const int32_t *tile_cnt, int64_t *const *outs, int64_t *one_out) {
     return lc.run("wf_counts", k_img_counts, dim3(nimg, nl), dim3(NTHREADS), tab, one, nimg, nl, ntiles_total, tile_cnt,
                   outs, one_out);
 }
+
+template <class Src>
+static int wf_ids_impl(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t bound, const WfIds &ids,
+                       int32_t *scan_tmp, int32_t *nreg0, uint64_t *key, int32_t *par) {
+    dim3 grid(nchunks > 0 ? nchunks : 1);
+    int rc = lc.run("wf_ids", k_root_bits<Src>, grid, dim3(NTHREADS), src_ch, nchunks, ids.coff, ids.rbits, ids.rpre);
+    if (rc) return rc;
+    if ((rc = launch_scan(lc, nchunks, ids.coff, scan_tmp, nreg0))) return rc;
+    return lc.run("wf_ids", k_wf_tables, list_grid(bound), dim3(NTHREADS), (const int32_t *)nreg0, key, par);
+}
+
+template <int CONN, typename T, class Src>
+static int wf_pix_t(Launch &lc, const Src &src, const TileGrid &tg, const WfIds &ids, const int32_t *nreg0,
+                    int32_t *cimg, int32_t *rlist, int32_t *tile_cnt0, uint64_t *key, int32_t *edges, int32_t *ecnt) {
+    const int32_t cap = wf_slab_cap(CONN);
+    size_t E = (size_t)tg.ntiles * (size_t)cap;
+    return lc.run("wf_pix", k_wf_pix<CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles,
+                  (const unsigned long long *)ids.rbits, (const uint16_t *)ids.rpre, (const int32_t *)ids.coff, nreg0,
+                  cimg, rlist, tile_cnt0, key, edges, edges + E, edges + 2 * E, ecnt, cap);
+}
+
+template <class Src>
+static int wf_pix_dispatch(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const WfIds &ids,
+                           const int32_t *nreg0, int32_t *cimg, int32_t *rlist, int32_t *tile_cnt0, uint64_t *key,
+                           int32_t *edges, int32_t *ecnt) {
+#define WF_PIX_ARGS lc, src, tg, ids, nreg0, cimg, rlist, tile_cnt0, key, edges, ecnt
+    switch (conn) {
+    case 4: return u16 ? wf_pix_t<4, uint16_t>(WF_PIX_ARGS) : wf_pix_t<4, uint8_t>(WF_PIX_ARGS);
+    case 8: return u16 ? wf_pix_t<8, uint16_t>(WF_PIX_ARGS) : wf_pix_t<8, uint8_t>(WF_PIX_ARGS);
+    case 6: return u16 ? wf_pix_t<6, uint16_t>(WF_PIX_ARGS) : wf_pix_t<6, uint8_t>(WF_PIX_ARGS);
+    case 26: return u16 ? wf_pix_t<26, uint16_t>(WF_PIX_ARGS) : wf_pix_t<26, uint8_t>(WF_PIX_ARGS);
+    default: return -1;
+    }
+#undef WF_PIX_ARGS
+}
+
+template <class Src>
+static int wf_out_impl(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t nl, const int32_t *cimg,
+                       const int32_t *nreg0, const int32_t *mlab, int64_t mstride, int32_t *tile_cnt) {
+    return ndim == 3 ? lc.run("wf_out", k_wf_out<3, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, nl, cimg,
+                              nreg0, mlab, mstride, tile_cnt)
+                     : lc.run("wf_out", k_wf_out<2, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, nl, cimg,
+                              nreg0, mlab, mstride, tile_cnt);
+}
+
+#define WF_SRC_FUNCS(Src)                                                                                          \
+    int launch_wf_ids(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t bound, const WfIds &ids,            \
+                      int32_t *scan_tmp, int32_t *nreg0, uint64_t *key, int32_t *par) {                           \
+        return wf_ids_impl(lc, src_ch, nchunks, bound, ids, scan_tmp, nreg0, key, par);                           \
+    }                                                                                                              \
+    int launch_wf_pix(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const WfIds &ids,       \
+                      const int32_t *nreg0, int32_t *cimg, int32_t *rlist, int32_t *tile_cnt0, uint64_t *key,     \
+                      int32_t *edges, int32_t *ecnt) {                                                            \
+        return wf_pix_dispatch(lc, src, tg, conn, u16, ids, nreg0, cimg, rlist, tile_cnt0, key, edges, ecnt);     \
+    }                                                                                                              \
+    int launch_wf_out(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t nl, const int32_t *cimg,   \
+                      const int32_t *nreg0, const int32_t *mlab, int64_t mstride, int32_t *tile_cnt) {            \
+        return wf_out_impl(lc, src, tg, ndim, nl, cimg, nreg0, mlab, mstride, tile_cnt);                          \
+    }
+
+WF_SRC_FUNCS(OneImg)
+WF_SRC_FUNCS(ImgTable)
 
 }  // namespace wsk

@@ -107,8 +107,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
     __shared__ int sI[S2::CELLS];
     __shared__ int sD[S2::CELLS];
     {
-        const int t = blockIdx.x;
-        if (t >= ntiles) return;
+        if ((int)blockIdx.x >= ntiles) return;
+        const int t = xcd_tile(blockIdx.x, ntiles);
         Img im;
         int lt;
         fetch(src, t, TK_WS, im, lt);
@@ -165,8 +165,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, 
     __shared__ int sI[S::CELLS];
     __shared__ int sD[S::CELLS];
     {
-        const int t = blockIdx.x;
-        if (t >= ntiles) return;
+        if ((int)blockIdx.x >= ntiles) return;
+        const int t = xcd_tile(blockIdx.x, ntiles);
         Img im;
         int lt;
         fetch(src, t, TK_WS, im, lt);
@@ -324,8 +324,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
     __shared__ int sD[S::CELLS];
     __shared__ int sP[PIX];
     {
-        const int t = blockIdx.x;
-        if (t >= ntiles) return;
+        if ((int)blockIdx.x >= ntiles) return;
+        const int t = xcd_tile(blockIdx.x, ntiles);
         Img im;
         int lt;
         fetch(src, t, TK_WS, im, lt);
@@ -435,8 +435,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_merge(Src src, int32_t ntiles, 
     using TS = TileShape<NDIM>;
     constexpr int NB = Border<NDIM>::NB;
     {
-        const int t = blockIdx.x;
-        if (t >= ntiles) return;
+        if ((int)blockIdx.x >= ntiles) return;
+        const int t = xcd_tile(blockIdx.x, ntiles);
         Img im;
         int lt;
         fetch(src, t, TK_WS, im, lt);
@@ -481,8 +481,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_find(Src src, int32_t ntiles) {
     constexpr int PIX = TS::X * TS::Y * TS::Z;
     constexpr int PER = PIX / NTHREADS;
     {
-        const int t = blockIdx.x;
-        if (t >= ntiles) return;
+        if ((int)blockIdx.x >= ntiles) return;
+        const int t = xcd_tile(blockIdx.x, ntiles);
         Img im;
         int lt;
         fetch(src, t, TK_WS, im, lt);
@@ -530,8 +530,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_jump(Src src, int32_t ntiles, i
     using TS = TileShape<NDIM>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
     {
-        const int t = blockIdx.x;
-        if (t >= ntiles) return;
+        if ((int)blockIdx.x >= ntiles) return;
+        const int t = xcd_tile(blockIdx.x, ntiles);
         Img im;
         int lt;
         fetch(src, t, TK_WS, im, lt);
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_jump(Src src, int32_t ntiles, i
             int32_t l = L[p];
             bool moved = false;
             for (int k = 0; k < rr; ++k) {
-                int32_t ll = ld_relaxed(L + l);
+                int32_t ll = ld_par(L + l);
                 if (ll == l) break;
                 l = ll;
                 moved = true;

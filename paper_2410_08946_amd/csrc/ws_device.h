@@ -13,7 +13,6 @@ namespace wsk {
 constexpr int32_t INF = 0x7fffffff;   // unresolved plateau distance
 constexpr int32_t SENT = 0x10000;     // grey value of out-of-image cells (> any uint16)
 constexpr int NTHREADS = 256;          // threads of every tile kernel (4 waves of 64)
-constexpr int MAXSLOTS = 64;           // words holding partial maxima of the gradient
 
 // Unsigned division by a runtime constant for dividends below 2^31
 // (multiply-high with a rounded-up magic number, shift s = ceil(log2 d)).
@@ -39,12 +38,12 @@ struct Geom {
 // call passes a device table of them plus, per tiling, a tile -> image map.
 // Scratch that spans the whole call (distances, region keys and parents) is
 // addressed with pix0 + local pixel index ("arena" index).
-enum TileKind { TK_WS = 0, TK_WF = 1, TK_GR = 2 };
+enum TileKind { TK_WS = 0, TK_WF = 1, TK_GR = 2, TK_CH = 3 };  // TK_CH: waterfall region-id chunks
 
 struct Img {
     Geom g;               // sizes (the ntx/nty/ntz fields hold the watershed tiling)
     int32_t pix0;         // arena offset of the image's pixel 0
-    int32_t tile0[3];     // first tile of the image in each tiling (global tile index)
+    int32_t tile0[4];     // first tile of the image in each tiling (global tile index)
     int32_t slot0;        // first partial-maximum word (gradient)
     const void *grey;     // quantised gradient (u8/u16)
     int32_t *lab;         // label layers: layer k at lab + k * g.n
@@ -69,6 +68,17 @@ __device__ __forceinline__ void fetch(const ImgTable &s, int t, int kind, Img &i
     int b = s.map[t];
     im = s.tab[b];
     lt = t - im.tile0[kind];
+}
+
+// Workgroups of a launch are dispatched to the chip's XCDs round-robin
+// (workgroup b to XCD b % NXCD). xcd_tile maps workgroup b to tile t so that
+// every XCD works through one contiguous range of tiles: neighbouring tiles,
+// whose halos share cache lines, then meet in the same L2. A bijection on
+// [0, n).
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    int q = n / NXCD, r = n % NXCD, x = b % NXCD, s = b / NXCD;
+    return x * q + (x < r ? x : r) + s;
 }
 
 // Origin of local tile lt of a tiling with tile shape (X, Y, Z).
@@ -157,21 +167,27 @@ __device__ __forceinline__ void load_box(const Geom &g, int bx, int by, int bz, 
     }
 }
 
-// Relaxed loads that always go to the coherent level of the memory hierarchy
-// (other workgroups of the same kernel may be updating the same words).
-__device__ __forceinline__ int32_t ld_relaxed(const int32_t *a) {
-    return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Parent loads and stores of the global union-find go through the caches
+// (wavefront-scope relaxed atomics compile to plain loads and stores): a
+// stale parent is still an ancestor, because parents only ever move to an
+// ancestor, and the one update that must be seen device-wide, hooking a root,
+// is a device-scope CAS that fails and returns the current parent when the
+// root was hooked meanwhile.
+__device__ __forceinline__ int32_t ld_par(const int32_t *a) {
+    return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
 // Union-find over a parent array in global memory with parent[x] <= x:
 // roots are self loops, and a union always hooks the larger root below the
-// smaller one, so a tree's root is the smallest index in it.
+// smaller one, so a tree's root is the smallest index in it. Every chase
+// moves to strictly smaller indices, so finds end even on stale parents, and
+// every failed CAS returns a smaller parent, so unions end too.
 __device__ __forceinline__ int32_t gfind(int32_t *par, int32_t x) {
     for (;;) {
-        int32_t px = ld_relaxed(par + x);
+        int32_t px = ld_par(par + x);
         if (px == x) return x;
-        int32_t ppx = ld_relaxed(par + px);
-        if (ppx != px) __hip_atomic_store(par + x, ppx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int32_t ppx = ld_par(par + px);
+        if (ppx != px) __hip_atomic_store(par + x, ppx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         x = px;
     }
 }
@@ -181,7 +197,7 @@ __device__ __forceinline__ int32_t gfind(int32_t *par, int32_t x) {
 // intermediate ancestor).
 __device__ __forceinline__ int32_t gfind_ro(const int32_t *par, int32_t x) {
     for (;;) {
-        int32_t px = ld_relaxed(par + x);
+        int32_t px = ld_par(par + x);
         if (px == x) return x;
         x = px;
     }

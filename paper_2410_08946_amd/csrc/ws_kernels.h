@@ -63,6 +63,14 @@ struct BlurTaps {
     float w[129];
 };
 
+// Region-id rank tables of the waterfall: per chunk of pixels, 64 root-bitmap
+// words, their in-chunk prefix counts, and the chunk's first id.
+struct WfIds {
+    unsigned long long *rbits;
+    uint16_t *rpre;
+    int32_t *coff;
+};
+
 // Tiles of one tiling and the launch grid that covers them (one workgroup per
 // tile).
 struct TileGrid {
@@ -81,12 +89,13 @@ struct TileGrid {
     int launch_ws_merge(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *rec); \
     int launch_ws_find(Launch &lc, const Src &src, const TileGrid &tg, int conn);                                \
     int launch_ws_jump(Launch &lc, const Src &src, const TileGrid &tg, int conn, int32_t rr, int32_t *changed);  \
-    int launch_wf_init(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t *list, int32_t *count,  \
-                       uint64_t *key, int32_t *par, int32_t *tile_tmp, int32_t *tile_cnt0);                       \
-    int launch_wf_edge(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t layer,        \
-                       int32_t relabel, const int32_t *par, uint64_t *key, int32_t *tile_cnt);                    \
-    int launch_wf_relabel(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t layer,               \
-                          const int32_t *par, int32_t *tile_cnt);
+    int launch_wf_ids(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t bound, const WfIds &ids,           \
+                      int32_t *scan_tmp, int32_t *nreg0, uint64_t *key, int32_t *par);                            \
+    int launch_wf_pix(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const WfIds &ids,      \
+                      const int32_t *nreg0, int32_t *cimg, int32_t *rlist, int32_t *tile_cnt0, uint64_t *key,    \
+                      int32_t *edges, int32_t *ecnt);                                                            \
+    int launch_wf_out(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t nl, const int32_t *cimg,  \
+                      const int32_t *nreg0, const int32_t *mlab, int64_t mstride, int32_t *tile_cnt);
 WS_DECL_SRC(OneImg)
 WS_DECL_SRC(ImgTable)
 #undef WS_DECL_SRC
@@ -97,21 +106,27 @@ int launch_ws_stages(Launch &lc, const Geom &g, int conn, bool u16, const void *
 int launch_fill_i32(Launch &lc, int32_t *a, int32_t n, int32_t v);
 
 // waterfall.hip
-int compact_chunks(int32_t bound);
 int wf_tiles(const Geom &g, int ndim);
-int launch_wf_union(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, uint64_t *key, int32_t *par);
-int launch_wf_compress(Launch &lc, int32_t bound, const int32_t *list, const int32_t *count, int32_t *par);
-int launch_wf_compact(Launch &lc, int32_t bound, const int32_t *list_in, const int32_t *count_in, int32_t *list_out,
-                      int32_t *count_out, const int32_t *par, uint64_t *key, int32_t *chunk_tmp);
+int wf_chunks(int32_t n);               // region-id chunks of an image of n pixels
+int wf_slab_cap(int conn);              // edge slab entries per tile
+int wf_max_merge();                     // largest group merge factor of launch_wf_level
+int scan_tmp_len(int32_t n);            // ints of scratch launch_scan needs for n
+int launch_scan(Launch &lc, int32_t n, int32_t *data, int32_t *tmp, int32_t *total_out);
+int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, int32_t cap, const int32_t *par, uint64_t *key,
+                    int32_t *edges, int32_t *ecnt);
+int launch_wf_union(Launch &lc, int32_t bound, const int32_t *nreg0, uint64_t *key, int32_t *par);
+int launch_wf_compress(Launch &lc, int32_t bound, const int32_t *nreg0, int32_t *par, const int32_t *rlist,
+                       int32_t *mlab_k);
 int launch_img_counts(Launch &lc, const Img *tab, const Img &one, int32_t nimg, int32_t nl, int32_t ntiles_total,
                       const int32_t *tile_cnt, int64_t *const *outs, int64_t *one_out);
 
 // gradient.hip
 constexpr int FUSED_MAX_R = 16;   // largest blur radius of the fused 2D kernel
-int launch_grad_fused2d(Launch &lc, const Geom &g, const float *img, float *mag, unsigned int *slots, const BlurTaps &taps);
+int grad_parts(const Geom &g, int ndim, int r);   // partial maxima the magnitude kernels write
+int launch_grad_fused2d(Launch &lc, const Geom &g, const float *img, float *mag, float *part, const BlurTaps &taps);
 int launch_grad_blur(Launch &lc, const Geom &g, const float *in, float *out, int axis, const BlurTaps &taps);
-int launch_grad_sobel(Launch &lc, const Geom &g, int ndim, const float *a, float *mag, unsigned int *slots);
-int launch_grad_quant(Launch &lc, int32_t n, bool u16, const float *mag, void *out, const unsigned int *slots);
-int launch_grad_zero_slots(Launch &lc, unsigned int *slots);
+int launch_grad_sobel(Launch &lc, const Geom &g, int ndim, const float *a, float *mag, float *part);
+int launch_grad_max(Launch &lc, int32_t nparts, const float *part, float *tmp, float *gmax);
+int launch_grad_quant(Launch &lc, int32_t n, bool u16, const float *mag, void *out, const float *gmax);
 
 }  // namespace wsk

@@ -46,7 +46,7 @@ def job_footprint(job: Job) -> int:
     lib = load_library()
     nx, ny, nz = _dims(tuple(job.grad.shape))
     code = 1 if job.grad.element_size() == 1 else 2
-    return int(lib.ws_footprint_bytes(nx, ny, nz, code, int(job.NL)))
+    return int(lib.ws_footprint_bytes(nx, ny, nz, int(job.conn), code, int(job.NL)))
 
 
 class Server:

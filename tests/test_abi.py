@@ -38,12 +38,18 @@ def test_header_symbols_exported():
 def test_footprint_is_host_arithmetic():
     lib = _lib()
     n = 4096 * 4096
-    fp = lib.ws_footprint_bytes(4096, 4096, 1, 2, 6)
+    fp = lib.ws_footprint_bytes(4096, 4096, 1, 8, 2, 6)
     assert fp >= n * (2 + 4 * 6)
-    assert lib.ws_footprint_bytes(0, 4, 1, 1, 3) == 0
-    assert lib.ws_footprint_bytes(4, 4, 1, 3, 3) == 0
-    assert lib.ws_footprint_bytes(4, 4, 1, 1, 0) == 0
-    assert lib.ws_footprint_bytes(1 << 16, 1 << 16, 1, 1, 1) == 0
+    # the edge slabs grow with the neighbourhood; a single layer needs no waterfall tables
+    assert lib.ws_footprint_bytes(4096, 4096, 1, 4, 2, 6) < fp
+    assert lib.ws_footprint_bytes(4096, 4096, 1, 8, 2, 1) < lib.ws_footprint_bytes(4096, 4096, 1, 8, 2, 2)
+    assert lib.ws_footprint_bytes(64, 64, 64, 26, 1, 3) > lib.ws_footprint_bytes(64, 64, 64, 6, 1, 3)
+    assert lib.ws_footprint_bytes(0, 4, 1, 8, 1, 3) == 0
+    assert lib.ws_footprint_bytes(4, 4, 1, 8, 3, 3) == 0
+    assert lib.ws_footprint_bytes(4, 4, 1, 8, 1, 0) == 0
+    assert lib.ws_footprint_bytes(4, 4, 1, 6, 1, 3) == 0   # 3D connectivity on a 2D image
+    assert lib.ws_footprint_bytes(4, 4, 4, 8, 1, 3) == 0   # 2D connectivity on a 3D image
+    assert lib.ws_footprint_bytes(1 << 16, 1 << 16, 1, 8, 1, 1) == 0
 
 
 def test_null_context_is_rejected_without_device():
