@@ -54,9 +54,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--workload", choices=("single", "batch", "serve"), default="single",
-                    help="single: the 4096x4096 image (default); batch: 512 uneven 2D images, "
-                         "one batched call vs one call per image; serve: Poisson arrivals of mixed "
+    ap.add_argument("--workload", choices=("single", "c2", "batch", "serve"), default="single",
+                    help="single: the 4096x4096 image (default); c2: the 928^3 uint8 volume; batch: 512 uneven "
+                         "2D images, one batched call vs one call per image; serve: Poisson arrivals of mixed "
                          "2D/3D jobs through the continuous-batching server")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="serve workload: request rates (req/s)")
     ap.add_argument("--requests", type=int, default=200, help="serve workload: requests per rate")
@@ -242,17 +242,28 @@ def main():
     import gen
     import paper_2410_08946_amd as ws
 
-    cfg = gen.CONFIGS["c1"]
-    ny, nx = cfg["shape"]
-    sigma, conn, NL = cfg["sigma"], cfg["conn"], cfg["NL"]
-    N = nx * ny
-    b = 2
+    name = "c2" if args.workload == "c2" else "c1"
+    cfg = gen.CONFIGS[name]
+    shape = tuple(cfg["shape"])
+    sigma, conn, NL, gdt = cfg["sigma"], cfg["conn"], cfg["NL"], cfg["dtype"]
+    N = int(np.prod(shape))
+    b = 2 if gdt == "u16" else 1
     dev = torch.device("cuda:0")
-    print("bench: generating the 4096x4096 image", file=sys.stderr, flush=True)
-    img = gen.config_image("c1")
-    img_d = torch.from_numpy(img).to(dev)
-    grad_d = torch.empty((ny, nx), dtype=torch.uint16, device=dev)
-    out_d = torch.empty((NL, ny, nx), dtype=torch.int32, device=dev)
+    if name == "c2":
+        # too large for the host generator: the same recipe evaluated on the device
+        print("bench: generating the 928^3 volume on the device", file=sys.stderr, flush=True)
+        img = None
+        img_d = gen.synth.blobs3d_device(shape, seed=cfg["seed"], device=dev)
+        workload = ("3D 928x928x928 uint8 gradient (f32 5000 blobs + N(0,2^2), 3D Sobel), 6-connectivity, "
+                    "watershed + NL=6 waterfall")
+    else:
+        print("bench: generating the 4096x4096 image", file=sys.stderr, flush=True)
+        img = gen.config_image("c1")
+        img_d = torch.from_numpy(img).to(dev)
+        workload = ("2D 4096x4096 uint16 gradient (f32 ellipses+noise, blur sigma=1, Sobel), 8-connectivity, "
+                    "watershed + NL=6 waterfall")
+    grad_d = torch.empty(shape, dtype=torch.uint16 if gdt == "u16" else torch.uint8, device=dev)
+    out_d = torch.empty((NL,) + shape, dtype=torch.int32, device=dev)
     nreg_d = torch.zeros(NL, dtype=torch.int64, device=dev)
     ctx = ws.Context(0)
     if args.calib_copy:
@@ -265,7 +276,7 @@ def main():
         del a, bb
 
     def step():
-        ctx.gradient(img_d, sigma, "u16", out=grad_d)
+        ctx.gradient(img_d, sigma, gdt, out=grad_d)
         ctx.watershed(grad_d, conn, out=out_d[0])
         ctx.waterfall(out_d[0], grad_d, conn, NL, out=out_d, nregions=nreg_d)
 
@@ -295,7 +306,7 @@ def main():
 
     # Stage split (host-synchronised, separate pass).
     stages = {}
-    for name, fn in (("gradient", lambda: ctx.gradient(img_d, sigma, "u16", out=grad_d)),
+    for stage, fn in (("gradient", lambda: ctx.gradient(img_d, sigma, gdt, out=grad_d)),
                      ("watershed", lambda: ctx.watershed(grad_d, conn, out=out_d[0])),
                      ("waterfall", lambda: ctx.waterfall(out_d[0], grad_d, conn, NL, out=out_d, nregions=nreg_d))):
         a = torch.cuda.Event(enable_timing=True)
@@ -306,7 +317,7 @@ def main():
             fn()
         z.record(stream)
         torch.cuda.synchronize()
-        stages[name] = round(a.elapsed_time(z) / max(1, args.steps // 2), 4)
+        stages[stage] = round(a.elapsed_time(z) / max(1, args.steps // 2), 4)
 
     roofline = None
     kernels = {}
@@ -334,7 +345,7 @@ def main():
                         "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and name == "c1":
         print("bench: timing the CPU oracle on one step", file=sys.stderr, flush=True)
         import oracle
         t = time.perf_counter()
@@ -357,11 +368,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u16",
+        "dtype": gdt,
         "data": "synthetic",
-        "config": {"workload": "2D 4096x4096 uint16 gradient (f32 ellipses+noise, blur sigma=1, Sobel), "
-                               "8-connectivity, watershed + NL=6 waterfall", "pixels": N, "NL": NL, "conn": conn,
-                   "parallelism": "single GPU"},
+        "config": {"workload": workload, "pixels": N, "NL": NL, "conn": conn, "parallelism": "single GPU"},
         "stages_ms": stages,
         "step2_sweeps": stats.get("sweeps_launched"),
         "nregions": nregions,

@@ -226,6 +226,25 @@ def blobs_device(shape, seed, n_blobs, sigma, amp=(0.2, 1.0), scale=1.0, noise=0
     return f
 
 
+def blobs3d_device(shape=(928, 928, 928), seed: int = 2, n_blobs=None, sigma=(4.0, 32.0), amp=(0.2, 1.0),
+                   scale: float = 255.0, noise: float = 2.0, device="cuda:0"):
+    """The 928^3 volume recipe (blobs3d's parameters) evaluated on a torch
+    device in float32, for volumes too large for numpy. Blob centres, sigmas and
+    amplitudes are drawn with PCG64 in blobs3d's order; n_blobs defaults to
+    5000 scaled by volume / 928^3 (the 928^3 density). The N(0, noise^2) field
+    comes from torch's seeded device generator (Philox), so it differs from
+    blobs3d's host noise but is fixed by (seed, shape)."""
+    import torch
+    if n_blobs is None:
+        n_blobs = max(1, int(round(5000 * float(np.prod(shape)) / 928.0 ** 3)))
+    f = blobs_device(shape, seed, n_blobs, sigma, amp=amp, scale=scale, noise=0.0, device=device)
+    if noise > 0:
+        g = torch.Generator(device=device)
+        g.manual_seed(int(seed) * 1_000_003 + 17)
+        f += noise * torch.randn(tuple(shape), generator=g, device=device, dtype=torch.float32)
+    return f
+
+
 def serving_pool_specs(n2d: int = 24, n3d: int = 8, seed: int = 4):
     """Job shapes of the serving mix: square 2D sides log-uniform in
     [512, 4096] (8-connectivity), cubic 3D sides log-uniform in [128, 512]

@@ -243,22 +243,26 @@ int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const Src &src_ch, int3
         if ((rc = ensure(c, c->mlab, (size_t)(NL - 1) * arena * 4, "layer labels")) != WS_OK) return rc;
         if ((rc = ensure(c, c->edges, 3 * E * 4, "edge slabs")) != WS_OK) return rc;
         if ((rc = ensure(c, c->ecnt, (size_t)tg.ntiles * 4, "edge counts")) != WS_OK) return rc;
-        // rank tables: [chunk offsets | scan scratch | bitmap words (8 B) | word prefixes (2 B)]
-        size_t off_bits = (((size_t)nchunks + wsk::scan_tmp_len(nchunks)) * 4 + 7) & ~(size_t)7;
-        size_t off_pre = off_bits + (size_t)nchunks * 64 * 8;
-        if ((rc = ensure(c, c->chunks, off_pre + (size_t)nchunks * 64 * 2, "region-id tables")) != WS_OK) return rc;
+        // rank tables: [chunk offsets | scan scratch | 64 rank words per chunk]
+        size_t off_words = (((size_t)nchunks + wsk::scan_tmp_len(nchunks)) * 4 + 15) & ~(size_t)15;
+        if ((rc = ensure(c, c->chunks, off_words + (size_t)nchunks * 64 * sizeof(wsk::RankWord), "region-id tables")) !=
+            WS_OK)
+            return rc;
         uint64_t *key = (uint64_t *)c->key.p;
         int32_t *par = (int32_t *)c->par.p, *ci = (int32_t *)c->cimg.p, *rl = (int32_t *)c->rlist.p;
         int32_t *ml = (int32_t *)c->mlab.p, *edges = (int32_t *)c->edges.p, *ecnt = (int32_t *)c->ecnt.p;
         char *tb = (char *)c->chunks.p;
-        wsk::WfIds ids{(unsigned long long *)(tb + off_bits), (uint16_t *)(tb + off_pre), (int32_t *)tb};
+        wsk::WfIds ids{(wsk::RankWord *)(tb + off_words), (int32_t *)tb};
         WS_TRY(wsk::launch_wf_ids(lc, src_ch, nchunks, bound, ids, (int32_t *)tb + nchunks, nreg0, key, par));
         WS_TRY(wsk::launch_wf_pix(lc, src, tg, conn, u16, ids, nreg0, ci, rl, tcnt, key, edges, ecnt));
         WS_TRY(wsk::launch_wf_union(lc, bound, nreg0, key, par));
         WS_TRY(wsk::launch_wf_compress(lc, bound, nreg0, par, rl, ml));
         int32_t gin = 1;
         for (int k = 2; k < NL; ++k) {
-            int32_t f = (k == 2 || gin >= tg.ntiles) ? 1 : 4;
+            // groups grow fourfold per layer: regions spanning several tiles
+            // then share one group (fewer key atomics) while a group's
+            // distinct edges still fit its LDS hash
+            int32_t f = gin >= tg.ntiles ? 1 : 4;
             WS_TRY(wsk::launch_wf_level(lc, tg.ntiles, gin, f, cap, par, key, edges, ecnt));
             gin *= f;
             WS_TRY(wsk::launch_wf_union(lc, bound, nreg0, key, par));
@@ -292,7 +296,7 @@ int reserve(ws_ctx *c, int64_t n) {
     if ((rc = ensure(c, c->rec, tiles * (size_t)wsk::border_cells(3) * 4, "reserved records")) != WS_OK) return rc;
     if ((rc = ensure(c, c->tilecnt, tiles * 16 * 4, "reserved tile counts")) != WS_OK) return rc;
     int32_t nch = (int32_t)std::min<int64_t>(n / 4096 + 4096, 0x7fffffff / 2);
-    size_t tbl = (((size_t)nch + wsk::scan_tmp_len(nch)) * 4 + 7) / 8 * 8 + (size_t)nch * 64 * 10;
+    size_t tbl = (((size_t)nch + wsk::scan_tmp_len(nch)) * 4 + 15) / 16 * 16 + (size_t)nch * 64 * sizeof(wsk::RankWord);
     if ((rc = ensure(c, c->chunks, tbl, "reserved region-id tables")) != WS_OK) return rc;
     if ((rc = ensure(c, c->wfcnt, 16 * 4, "reserved counts")) != WS_OK) return rc;
     if ((rc = ensure(c, c->cnt, kCounterSlots * 4, "counters")) != WS_OK) return rc;
@@ -384,7 +388,7 @@ size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int conn, int dtyp
         size_t tiles = (size_t)wsk::wf_tiles(make_geom(nx, ny, nz, ndim), ndim);
         wf = N * (8 /* keys */ + 4 /* parents */ + 4 /* ids */ + 4 /* labels */ + 4 * (size_t)(NL - 1) /* layers */) +
              tiles * (12 * (size_t)wsk::wf_slab_cap(conn) + 4 + 4 * (size_t)NL) +
-             ((size_t)wsk::wf_chunks((int32_t)N) + 2) * (64 * 10 + 8) /* region-id rank tables */;
+             ((size_t)wsk::wf_chunks((int32_t)N) + 2) * (64 * 16 + 8) /* region-id rank tables */;
     }
     return job + ws + wf + (1 <<20);
 }

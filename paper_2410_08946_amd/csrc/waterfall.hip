@@ -8,12 +8,11 @@
 //   0. Region ids. Layer-0 regions (pixels carrying their own label) get dense
 //      ids in pixel order, so id order is label order and every region table
 //      is dense (rlist[id] = local label, par, key, mlab). The id of label l
-//      is a rank: a bitmap of the roots (one word per 64 pixels) with, per
-//      word, the count of roots before it in its chunk of RCH pixels, and the
-//      chunks' exclusive prefix: id(l) = coff[chunk] + rpre[word] + popcount
-//      of the bits below l. These tables hold 10 bytes per 64 pixels, so the
-//      lookups stay in L2, unlike a pixel-indexed table whose few live
-//      entries each cost a cache line.
+//      is a rank: per 64 pixels one 16-byte record holds the root bitmap
+//      word and the id of the first root at or after the word's first pixel,
+//      so id(l) = base + popcount of the bits below l. These tables hold
+//      0.25 byte per pixel, so the lookups stay in L2, unlike a pixel-indexed
+//      table whose few live entries each cost a cache line.
 //   1. Pixel pass, one workgroup per tile (it also writes every pixel's
 //      region id, cimg, for step 4): every pixel pair (p, q), q in the
 //      forward half of N(p), whose regions a != b differ is an edge
@@ -87,8 +86,14 @@ __device__ __forceinline__ uint64_t lanes_below() { return (1ull << __lane_id())
 // LDS hash tables. Inserts return false when MAXPROBE slots were taken by
 // other keys; the caller then applies the update directly in global memory.
 // ---------------------------------------------------------------------------
+// Slot hashes from full-rate 24-bit multiplies (the ids' low bits vary most).
+__device__ __forceinline__ uint32_t mix24(uint32_t a, uint32_t b) {
+    uint32_t x = __umul24(a, 0x9E3779u) + __umul24(b, 0x45D9F3u);
+    return x ^ (x >> 11);
+}
+
 __device__ __forceinline__ bool edge_insert(unsigned long long *ek, unsigned int *ew, uint64_t pair, uint32_t w) {
-    uint32_t h = (uint32_t)((pair * 0x9E3779B97F4A7C15ull) >> (64 - EBITS));
+    uint32_t h = mix24((uint32_t)(pair >> 32), (uint32_t)pair) & (ESLOTS - 1);
     for (int probe = 0; probe < MAXPROBE; ++probe) {
         unsigned long long cur = ek[h];
         if (cur == NOPAIR) cur = atomicCAS(&ek[h], (unsigned long long)NOPAIR, (unsigned long long)pair);
@@ -103,7 +108,7 @@ __device__ __forceinline__ bool edge_insert(unsigned long long *ek, unsigned int
 
 template <int BITS>
 __device__ __forceinline__ bool region_insert(int *hk, unsigned long long *hv, int l, uint64_t v) {
-    uint32_t h = ((uint32_t)l * 2654435761u) >> (32 - BITS);
+    uint32_t h = mix24((uint32_t)l, (uint32_t)l >> 16) & ((1 << BITS) - 1);
     for (int probe = 0; probe < MAXPROBE; ++probe) {
         int cur = hk[h];
         if (cur == -1) cur = atomicCAS(&hk[h], -1, l);
@@ -254,12 +259,12 @@ __global__ __launch_bounds__(NTHREADS) void k_scan_apply(int32_t n, int32_t *__r
 // ---------------------------------------------------------------------------
 template <class Src>
 __global__ __launch_bounds__(NTHREADS) void k_root_bits(Src src, int32_t nchunks, int32_t *__restrict__ ccnt,
-                                                        unsigned long long *__restrict__ rbits,
-                                                        uint16_t *__restrict__ rpre) {
+                                                        RankWord *__restrict__ words) {
     constexpr int PER = RCH / NTHREADS;
     constexpr int NW = NTHREADS / 64;
     static_assert(PER * NW == 64, "one wave scans the chunk's words");
     __shared__ int wc[64];
+    __shared__ unsigned long long wb[64];
     const int t = blockIdx.x;
     if (t >= nchunks) return;
     Img im;
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(NTHREADS) void k_root_bits(Src src, int32_t nchunks
     for (int j = 0; j < PER; ++j) {
         uint64_t m = __ballot(l[j] == base + j * NTHREADS + (int)threadIdx.x);
         if (lane == 0) {
-            rbits[(size_t)t * 64 + j * NW + w] = m;
+            wb[j * NW + w] = m;
             wc[j * NW + w] = __popcll(m);
         }
     }
@@ -288,19 +293,26 @@ __global__ __launch_bounds__(NTHREADS) void k_root_bits(Src src, int32_t nchunks
             int y = __shfl_up(x, off);
             if (lane >= off) x += y;
         }
-        rpre[(size_t)t * 64 + lane] = (uint16_t)(x - v);
+        RankWord rw;
+        rw.bits = wb[lane];
+        rw.base = x - v;  // in-chunk prefix; the chunk's first id is added after the scan
+        rw.pad = 0;
+        words[(size_t)t * 64 + lane] = rw;
         if (lane == 63) ccnt[t] = x;
     }
 }
 
-// Keys and parents of the nreg0 regions.
+// Keys and parents of the nreg0 regions; chunk offsets into the rank words.
 __global__ __launch_bounds__(NTHREADS) void k_wf_tables(const int32_t *__restrict__ nreg0, uint64_t *__restrict__ key,
-                                                        int32_t *__restrict__ par) {
+                                                        int32_t *__restrict__ par, int32_t nwords,
+                                                        RankWord *__restrict__ words, const int32_t *__restrict__ coff) {
     const int32_t n = *nreg0;
     for (int32_t c = blockIdx.x * NTHREADS + threadIdx.x; c < n; c += gridDim.x * NTHREADS) {
         key[c] = NOKEY;
         par[c] = c;
     }
+    for (int32_t i = blockIdx.x * NTHREADS + threadIdx.x; i < nwords; i += gridDim.x * NTHREADS)
+        words[i].base += coff[i >> 6];
 }
 
 // ---------------------------------------------------------------------------
@@ -311,8 +323,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_tables(const int32_t *__restric
 // outside the tables.
 // ---------------------------------------------------------------------------
 template <int CONN, typename T, class Src>
-__global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, const unsigned long long *__restrict__ rbits,
-                                                     const uint16_t *__restrict__ rpre, const int32_t *__restrict__ coff,
+__global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, const RankWord *__restrict__ words,
                                                      const int32_t *__restrict__ nreg0, int32_t *__restrict__ cimg,
                                                      int32_t *__restrict__ rlist, int32_t *__restrict__ tile_cnt0,
                                                      uint64_t *__restrict__ key, int32_t *__restrict__ ea,
@@ -368,23 +379,19 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
         for (int j = 0; j < PER; ++j) lv[j] = L0[idx[j]];
 #pragma unroll
         for (int j = 0; j < PER; ++j) gv[j] = I[idx[j]];
-        // rank lookups, all loads issued together
-        const int32_t ch0 = im.tile0[TK_CH];
-        unsigned long long bw[PER];
-        int32_t pw[PER], cw[PER];
+        // region ids by rank, one record load per cell
+        const size_t w0 = (size_t)im.tile0[TK_CH] * 64;
+        RankWord rw[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             int32_t l = (uint32_t)lv[j] < (uint32_t)g.n ? lv[j] : 0;
-            int32_t ch = ch0 + l / RCH;
-            size_t wi = (size_t)ch * 64 + (size_t)((l % RCH) >> 6);
-            bw[j] = rbits[wi] & ((1ull << (l & 63)) - 1ull);
-            pw[j] = rpre[wi];
-            cw[j] = coff[ch];
+            rw[j] = words[w0 + (l >> 6)];
         }
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             int c = threadIdx.x + j * NTHREADS;
-            uint32_t cv = (uint32_t)(cw[j] + pw[j] + __popcll(bw[j]));
+            uint64_t below = (1ull << (lv[j] & 63)) - 1ull;
+            uint32_t cv = (uint32_t)(rw[j].base + __popcll(rw[j].bits & below));
             cv = cv <= cmax ? cv : cmax;
             if (c < CELLS) {
                 sL[c] = ok[j] ? (int)cv : -1;
@@ -520,9 +527,25 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_level(int32_t ntiles, int32_t g
 }
 
 // ---------------------------------------------------------------------------
-// 2. Union of every live region with the target of its key, then compression.
+// 2. Union of every live region with the target of its key, in two kernels so
+// that most hooks are plain stores (device atomics execute at the memory side
+// and cost far more): first every region whose target has a smaller id hooks
+// to it -- only the region itself writes its parent, and it is a root, so no
+// other write can race -- then the regions whose target has a larger id are
+// united by CAS hooking, which finds most of them already joined. Parents
+// keep pointing to smaller ids, so every root is its tree's smallest id.
 // Keys are reset to NOKEY as they are consumed; only roots ever get new ones.
 // ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NTHREADS) void k_wf_hook(const int32_t *__restrict__ nreg0,
+                                                      const uint64_t *__restrict__ key, int32_t *__restrict__ par) {
+    const int32_t n = *nreg0;
+    for (int32_t c = blockIdx.x * NTHREADS + threadIdx.x; c < n; c += gridDim.x * NTHREADS) {
+        uint64_t kk = key[c];
+        int32_t tg = (int32_t)(uint32_t)(kk & 0xffffffffull);
+        if (kk != NOKEY && tg < c) par[c] = tg;
+    }
+}
+
 __global__ __launch_bounds__(NTHREADS) void k_wf_union(const int32_t *__restrict__ nreg0, uint64_t *__restrict__ key,
                                                        int32_t *__restrict__ par) {
     const int32_t n = *nreg0;
@@ -530,7 +553,8 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_union(const int32_t *__restrict
         uint64_t kk = key[c];
         if (kk == NOKEY) continue;
         key[c] = NOKEY;
-        gunion(par, c, (int32_t)(uint32_t)(kk & 0xffffffffull));
+        int32_t tg = (int32_t)(uint32_t)(kk & 0xffffffffull);
+        if (tg > c) gunion(par, c, tg);
     }
 }
 
@@ -691,6 +715,8 @@ int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, int32_t 
 }
 
 int launch_wf_union(Launch &lc, int32_t bound, const int32_t *nreg0, uint64_t *key, int32_t *par) {
+    int rc = lc.run("wf_union", k_wf_hook, list_grid(bound), dim3(NTHREADS), nreg0, (const uint64_t *)key, par);
+    if (rc) return rc;
     return lc.run("wf_union", k_wf_union, list_grid(bound), dim3(NTHREADS), nreg0, key, par);
 }
 int launch_wf_compress(Launch &lc, int32_t bound, const int32_t *nreg0, int32_t *par, const int32_t *rlist,
@@ -707,10 +733,12 @@ template <class Src>
 static int wf_ids_impl(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t bound, const WfIds &ids,
                        int32_t *scan_tmp, int32_t *nreg0, uint64_t *key, int32_t *par) {
     dim3 grid(nchunks > 0 ? nchunks : 1);
-    int rc = lc.run("wf_ids", k_root_bits<Src>, grid, dim3(NTHREADS), src_ch, nchunks, ids.coff, ids.rbits, ids.rpre);
+    int rc = lc.run("wf_ids", k_root_bits<Src>, grid, dim3(NTHREADS), src_ch, nchunks, ids.coff, ids.words);
     if (rc) return rc;
     if ((rc = launch_scan(lc, nchunks, ids.coff, scan_tmp, nreg0))) return rc;
-    return lc.run("wf_ids", k_wf_tables, list_grid(bound), dim3(NTHREADS), (const int32_t *)nreg0, key, par);
+    int32_t nwords = nchunks * 64;
+    return lc.run("wf_ids", k_wf_tables, list_grid(bound > nwords ? bound : nwords), dim3(NTHREADS),
+                  (const int32_t *)nreg0, key, par, nwords, ids.words, (const int32_t *)ids.coff);
 }
 
 template <int CONN, typename T, class Src>
@@ -719,8 +747,8 @@ static int wf_pix_t(Launch &lc, const Src &src, const TileGrid &tg, const WfIds 
     const int32_t cap = wf_slab_cap(CONN);
     size_t E = (size_t)tg.ntiles * (size_t)cap;
     return lc.run("wf_pix", k_wf_pix<CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles,
-                  (const unsigned long long *)ids.rbits, (const uint16_t *)ids.rpre, (const int32_t *)ids.coff, nreg0,
-                  cimg, rlist, tile_cnt0, key, edges, edges + E, edges + 2 * E, ecnt, cap);
+                  (const RankWord *)ids.words, nreg0, cimg, rlist, tile_cnt0, key, edges, edges + E, edges + 2 * E,
+                  ecnt, cap);
 }
 
 template <class Src>

@@ -63,11 +63,16 @@ struct BlurTaps {
     float w[129];
 };
 
-// Region-id rank tables of the waterfall: per chunk of pixels, 64 root-bitmap
-// words, their in-chunk prefix counts, and the chunk's first id.
+// Region-id rank tables of the waterfall: per 64 pixels of a chunk, the root
+// bitmap word and the id of the first root at or after it; per chunk, its
+// first id (the scanned root counts).
+struct alignas(16) RankWord {
+    unsigned long long bits;
+    int32_t base;
+    int32_t pad;
+};
 struct WfIds {
-    unsigned long long *rbits;
-    uint16_t *rpre;
+    RankWord *words;
     int32_t *coff;
 };
 
