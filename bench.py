@@ -42,9 +42,38 @@ def kernel_bytes_per_pixel(b, NL):
         "ws_init": b + 4.0,        # read grey, write distance
         "ws_label": b + 8.0,       # read grey + distance, write label
         "ws_find": 8.0,            # read label, write label
-        "wf_pix": 4.0 + b,         # read layer-0 label + grey
+        "wf_pix": 8.0 + b,         # read layer-0 label + grey, write the pixel's region id
         "wf_out": 4.0 * NL,        # read layer 0, write layers 1 .. NL-1
     }
+
+
+def recorded_traffic(kernel, workload="c1"):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of the workload, or None when there is none or when the
+    kernel sources changed since the counters were taken (the summary records
+    the sha256 of the sources it measured)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "c1_4096x4096_u16_conn8_nl6_traffic.md")
+    if workload != "c1" or not os.path.exists(path):
+        return None
+    vals, sha, srcs = {}, None, []
+    for line in open(path):
+        f = line.split()
+        if len(f) == 3 and f[0] == "traffic":
+            vals[f[1]] = int(f[2])
+        elif len(f) == 2 and f[0] == "sources_sha256":
+            sha = f[1]
+        elif len(f) > 1 and f[0] == "sources":
+            srcs = f[1:]
+    if kernel not in vals or not sha or not srcs:
+        return None
+    h = hashlib.sha256()
+    for s_ in srcs:
+        p_ = os.path.join(ROOT, s_)
+        if not os.path.exists(p_):
+            return None
+        h.update(open(p_, "rb").read())
+    return vals[kernel] if h.hexdigest() == sha else None
 
 
 def parse():
@@ -341,7 +370,8 @@ def main():
             bytes_per_launch = per[dom] * N
             achieved = bytes_per_launch / avg_s / 1e9
             roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": recorded_traffic(dom, name),
                         "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
 
     cpu = None
