@@ -230,10 +230,20 @@ int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const Src &src_ch, int3
     int rc;
     int32_t bound = (int32_t)arena;
     if ((rc = ensure(c, c->wfcnt, 4, "region count")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->tilecnt, (size_t)NL * tg.ntiles * 4, "tile counts")) != WS_OK) return rc;
-    int32_t *nreg0 = (int32_t *)c->wfcnt.p, *tcnt = (int32_t *)c->tilecnt.p;
+    if ((rc = ensure(c, c->tilecnt, (size_t)NL * nchunks * 4, "chunk counts")) != WS_OK) return rc;
+    // region-id tables: [chunk offsets | scan scratch | 64 rank words per chunk]
+    size_t off_words = (((size_t)nchunks + wsk::scan_tmp_len(nchunks)) * 4 + 15) & ~(size_t)15;
+    if ((rc = ensure(c, c->chunks, off_words + (size_t)nchunks * 64 * sizeof(wsk::RankWord), "region-id tables")) !=
+        WS_OK)
+        return rc;
+    int32_t *nreg0 = (int32_t *)c->wfcnt.p, *ccnt = (int32_t *)c->tilecnt.p;
+    char *tb = (char *)c->chunks.p;
+    wsk::WfIds ids{(wsk::RankWord *)(tb + off_words), (int32_t *)tb};
+    int32_t *scan_tmp = (int32_t *)tb + nchunks;
     const int32_t *cimg = nullptr, *mlab = nullptr;
-    if (NL >= 2) {
+    if (NL == 1) {
+        WS_TRY(wsk::launch_wf_ids(lc, src_ch, nchunks, bound, ids, scan_tmp, nreg0, nullptr, nullptr));
+    } else {
         const int32_t cap = wsk::wf_slab_cap(conn);
         const size_t E = (size_t)tg.ntiles * (size_t)cap;
         if ((rc = ensure(c, c->key, arena * 8, "region keys")) != WS_OK) return rc;
@@ -243,18 +253,11 @@ int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const Src &src_ch, int3
         if ((rc = ensure(c, c->mlab, (size_t)(NL - 1) * arena * 4, "layer labels")) != WS_OK) return rc;
         if ((rc = ensure(c, c->edges, 3 * E * 4, "edge slabs")) != WS_OK) return rc;
         if ((rc = ensure(c, c->ecnt, (size_t)tg.ntiles * 4, "edge counts")) != WS_OK) return rc;
-        // rank tables: [chunk offsets | scan scratch | 64 rank words per chunk]
-        size_t off_words = (((size_t)nchunks + wsk::scan_tmp_len(nchunks)) * 4 + 15) & ~(size_t)15;
-        if ((rc = ensure(c, c->chunks, off_words + (size_t)nchunks * 64 * sizeof(wsk::RankWord), "region-id tables")) !=
-            WS_OK)
-            return rc;
         uint64_t *key = (uint64_t *)c->key.p;
         int32_t *par = (int32_t *)c->par.p, *ci = (int32_t *)c->cimg.p, *rl = (int32_t *)c->rlist.p;
         int32_t *ml = (int32_t *)c->mlab.p, *edges = (int32_t *)c->edges.p, *ecnt = (int32_t *)c->ecnt.p;
-        char *tb = (char *)c->chunks.p;
-        wsk::WfIds ids{(wsk::RankWord *)(tb + off_words), (int32_t *)tb};
-        WS_TRY(wsk::launch_wf_ids(lc, src_ch, nchunks, bound, ids, (int32_t *)tb + nchunks, nreg0, key, par));
-        WS_TRY(wsk::launch_wf_pix(lc, src, tg, conn, u16, ids, nreg0, ci, rl, tcnt, key, edges, ecnt));
+        WS_TRY(wsk::launch_wf_ids(lc, src_ch, nchunks, bound, ids, scan_tmp, nreg0, key, par));
+        WS_TRY(wsk::launch_wf_pix(lc, src, tg, conn, u16, ids, nreg0, ci, rl, key, edges, ecnt));
         WS_TRY(wsk::launch_wf_union(lc, bound, nreg0, key, par));
         WS_TRY(wsk::launch_wf_compress(lc, bound, nreg0, par, rl, ml));
         int32_t gin = 1;
@@ -271,9 +274,9 @@ int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const Src &src_ch, int3
         cimg = ci;
         mlab = ml;
     }
-    WS_TRY(wsk::launch_wf_out(lc, src, tg, ndim, NL, cimg, nreg0, mlab, (int64_t)arena, tcnt));
+    WS_TRY(wsk::launch_wf_out(lc, src_ch, nchunks, NL, cimg, nreg0, ids.coff, mlab, (int64_t)arena, ccnt));
     if (outs_dev || one_out)
-        WS_TRY(wsk::launch_img_counts(lc, tab_dev, one, nimg, NL, tg.ntiles, tcnt, outs_dev, one_out));
+        WS_TRY(wsk::launch_img_counts(lc, tab_dev, one, nimg, NL, nchunks, ccnt, outs_dev, one_out));
     return WS_OK;
 }
 
@@ -545,7 +548,7 @@ int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, 
         if (!valid_dims(it.nx, it.ny, it.nz, why)) return fail(c, WS_EINVAL, "ws_batch: item " + std::to_string(i) + ": " + why);
         if (!valid_conn(it.nz, conn))
             return fail(c, WS_EINVAL, "ws_batch: item " + std::to_string(i) + " does not match the connectivity");
-        arena += it.nx * it.ny * it.nz;
+        arena += (it.nx * it.ny * it.nz + 63) / 64 * 64;  // image offsets stay 64-pixel aligned
         wsk::Geom g = make_geom(it.nx, it.ny, it.nz, ndim);
         tws += (int64_t)g.ntx * g.nty * g.ntz;
         twf += wsk::wf_tiles(g, ndim);
@@ -605,7 +608,7 @@ int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, 
         for (int32_t k = 0; k < nch; ++k) mch[t2 + k] = i;
         outs[i] = it.nregions;
         any_counts = any_counts || it.nregions;
-        pix += im.g.n;
+        pix += (im.g.n + 63) / 64 * 64;
         t0 += nws;
         t1 += nwf;
         t2 += nch;

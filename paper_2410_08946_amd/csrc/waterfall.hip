@@ -318,15 +318,15 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_tables(const int32_t *__restric
 // ---------------------------------------------------------------------------
 // 1. Pixel pass of layer 0 (keys of layer 1 and the tiles' edge slabs; the
 // region id of every own pixel into cimg, the labels of the own roots into
-// rlist, the tile's layer-0 region count). Labels are clamped to the image
+// rlist). Labels are clamped to the image
 // and ids to [0, nreg0) so that labels that are not canonical cannot address
 // outside the tables.
 // ---------------------------------------------------------------------------
 template <int CONN, typename T, class Src>
 __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, const RankWord *__restrict__ words,
                                                      const int32_t *__restrict__ nreg0, int32_t *__restrict__ cimg,
-                                                     int32_t *__restrict__ rlist, int32_t *__restrict__ tile_cnt0,
-                                                     uint64_t *__restrict__ key, int32_t *__restrict__ ea,
+                                                     int32_t *__restrict__ rlist, uint64_t *__restrict__ key,
+                                                     int32_t *__restrict__ ea,
                                                      int32_t *__restrict__ eb, int32_t *__restrict__ eww,
                                                      int32_t *__restrict__ ecnt, int32_t cap) {
     constexpr int NDIM = ndim_of<CONN>();
@@ -358,7 +358,6 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
     tile_xyz<TS::X, TS::Y, TS::Z>(g, lt, ox, oy, oz);
     const int32_t nr = *nreg0;
     const uint32_t cmax = nr > 0 ? (uint32_t)(nr - 1) : 0u;
-    int nroots = 0;
     {
         constexpr int PER = (CELLS + NTHREADS - 1) / NTHREADS;
         int32_t idx[PER];
@@ -399,10 +398,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
             }
             if (own[j]) {
                 cimg[(size_t)im.pix0 + idx[j]] = (int32_t)cv;
-                if (lv[j] == idx[j]) {
-                    rlist[cv] = idx[j];
-                    ++nroots;
-                }
+                if (lv[j] == idx[j]) rlist[cv] = idx[j];
             }
         }
     }
@@ -441,12 +437,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
     emit_edges<RBITS>(ek, ew, hk, hv, &ectr, key, ea, eb, eww, base);
     __syncthreads();
     flush_keys<RBITS>(hk, hv, key);
-    int excl;
-    int roots = block_scan_excl(nroots, excl);
-    if (threadIdx.x == 0) {
-        ecnt[t] = ectr;
-        tile_cnt0[t] = roots;
-    }
+    if (threadIdx.x == 0) ecnt[t] = ectr;
 }
 
 // ---------------------------------------------------------------------------
@@ -570,93 +561,93 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_compress(const int32_t *__restr
 }
 
 // ---------------------------------------------------------------------------
-// 4. Layers 1 .. nl-1 of every pixel from its region id, and per tile the
-// number of pixels carrying their own label in each of them (layer k at
-// tile_cnt[k * ntiles + t]; layer 0's count comes from the pixel pass). With
-// nl == 1 only layer 0 is counted, from the labels.
+// 4. Layers 1 .. nl-1 of every pixel from its region id, chunk by chunk
+// (RCH consecutive pixels of one image), and per chunk the number of pixels
+// carrying their own label in each layer, cnt[k * nchunks + t]. Layer 0's
+// count is the chunk's root count, the difference of consecutive chunk
+// offsets. A thread owns runs of 4 consecutive pixels: 16-byte loads and
+// stores when the image's layers are 16-byte aligned, else scalar accesses.
+// With nl == 1 only layer 0 is counted.
 // ---------------------------------------------------------------------------
-template <int NDIM, class Src>
-__global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src, int32_t ntiles, int32_t nl,
+template <class Src>
+__global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks, int32_t nl,
                                                      const int32_t *__restrict__ cimg,
                                                      const int32_t *__restrict__ nreg0,
+                                                     const int32_t *__restrict__ coff,
                                                      const int32_t *__restrict__ mlab, int64_t mstride,
-                                                     int32_t *__restrict__ tile_cnt) {
-    using TS = WfTile<NDIM>;
-    constexpr int PER = WF_PIX / NTHREADS;
-    constexpr int KB = 8;  // layers counted per LDS round
-    __shared__ int kc[KB];
-    if ((int)blockIdx.x >= ntiles) return;
-    const int t = xcd_tile(blockIdx.x, ntiles);
+                                                     int32_t *__restrict__ cnt) {
+    constexpr int RUNS = RCH / (4 * NTHREADS);  // runs of 4 pixels per thread
+    static_assert(RUNS * 4 * NTHREADS == RCH, "whole runs per chunk");
+    __shared__ int kc;
+    const int t = blockIdx.x;
+    if (t >= nchunks) return;
     Img im;
-    int lt;
-    fetch(src, t, TK_WF, im, lt);
+    int lc;
+    fetch(src_ch, t, TK_CH, im, lc);
+    const int32_t nr = *nreg0;
+    if (threadIdx.x == 0) cnt[t] = (t + 1 < nchunks ? coff[t + 1] : nr) - coff[t];
+    if (nl == 1) return;
     const Geom &g = im.g;
-    int ox, oy, oz;
-    tile_xyz<TS::X, TS::Y, TS::Z>(g, lt, ox, oy, oz);
-    int32_t p[PER], c[PER];
-    bool ok[PER];
+    const int32_t base = lc * RCH, n = g.n;
+    const int32_t *ci = cimg + im.pix0;
+    const bool vec = ((im.pix0 | n) & 3) == 0 && ((uintptr_t)im.lab & 15) == 0;
+    const uint32_t cmax = nr > 0 ? (uint32_t)(nr - 1) : 0u;
+    int32_t c[RUNS][4];
+    int32_t p0[RUNS];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        int i = threadIdx.x + j * NTHREADS;
-        int x = ox + i % TS::X, y = oy + (i / TS::X) % TS::Y, z = oz + i / (TS::X * TS::Y);
-        ok[j] = in_image(g, x, y, z);
-        p[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
+    for (int r = 0; r < RUNS; ++r) {
+        p0[r] = base + (r * NTHREADS + (int)threadIdx.x) * 4;
+        if (vec && p0[r] + 3 < n) {
+            int4 q = *(const int4 *)(ci + p0[r]);
+            c[r][0] = q.x;
+            c[r][1] = q.y;
+            c[r][2] = q.z;
+            c[r][3] = q.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) c[r][e] = p0[r] + e < n ? ci[p0[r] + e] : 0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c[r][e] = (uint32_t)c[r][e] <= cmax ? c[r][e] : (int32_t)cmax;
     }
-    if (threadIdx.x < KB) kc[threadIdx.x] = 0;
-    if (nl == 1) {
+#pragma unroll 1
+    for (int k = 1; k < nl; ++k) {
+        const int32_t *m = mlab + (size_t)(k - 1) * (size_t)mstride;
+        int32_t *out = im.lab + (size_t)k * (size_t)n;
+        if (threadIdx.x == 0) kc = 0;
+        __syncthreads();
         int own = 0;
 #pragma unroll
-        for (int j = 0; j < PER; ++j) c[j] = im.lab[p[j]];
+        for (int r = 0; r < RUNS; ++r) {
+            int32_t v[4];
 #pragma unroll
-        for (int j = 0; j < PER; ++j) own += __popcll(__ballot(ok[j] && c[j] == p[j]));
-        __syncthreads();
-        if (__lane_id() == 0 && own) atomicAdd(&kc[0], own);
-        __syncthreads();
-        if (threadIdx.x == 0) tile_cnt[t] = kc[0];
-        return;
-    }
-    const int32_t nr = *nreg0;
-    const uint32_t cmax = nr > 0 ? (uint32_t)(nr - 1) : 0u;
+            for (int e = 0; e < 4; ++e) v[e] = m[c[r][e]];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) c[j] = cimg[(size_t)im.pix0 + p[j]];
+            for (int e = 0; e < 4; ++e) own += (p0[r] + e < n && v[e] == p0[r] + e) ? 1 : 0;
+            if (vec && p0[r] + 3 < n) {
+                *(int4 *)(out + p0[r]) = make_int4(v[0], v[1], v[2], v[3]);
+            } else {
 #pragma unroll
-    for (int j = 0; j < PER; ++j) c[j] = (uint32_t)c[j] <= cmax ? c[j] : (int32_t)cmax;
-    __syncthreads();
-    for (int k0 = 1; k0 < nl; k0 += KB) {
-        // one layer per round keeps the kernel at full occupancy
-#pragma unroll 1
-        for (int kk = 0; kk < KB && k0 + kk < nl; ++kk) {
-            const int32_t *m = mlab + (size_t)(k0 + kk - 1) * (size_t)mstride;
-            int32_t *out = im.lab + (size_t)(k0 + kk) * (size_t)g.n;
-            int32_t v[PER];
-#pragma unroll
-            for (int j = 0; j < PER; ++j) v[j] = m[c[j]];
-            int own = 0;
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                if (ok[j]) out[p[j]] = v[j];
-                own += __popcll(__ballot(ok[j] && v[j] == p[j]));
+                for (int e = 0; e < 4; ++e)
+                    if (p0[r] + e < n) out[p0[r] + e] = v[e];
             }
-            if (__lane_id() == 0 && own) atomicAdd(&kc[kk], own);
         }
+        for (int off = 32; off > 0; off >>= 1) own += __shfl_xor(own, off);
+        if (__lane_id() == 0 && own) atomicAdd(&kc, own);
         __syncthreads();
-        if ((int)threadIdx.x < KB && k0 + (int)threadIdx.x < nl) {
-            tile_cnt[(size_t)(k0 + threadIdx.x) * ntiles + t] = kc[threadIdx.x];
-            kc[threadIdx.x] = 0;
-        }
-        __syncthreads();
+        if (threadIdx.x == 0) cnt[(size_t)k * nchunks + t] = kc;
     }
 }
 
-// out[b][k] = sum of the per-tile region counts of image b in layer k.
+// out[b][k] = sum of the per-chunk region counts of image b in layer k.
 __global__ __launch_bounds__(NTHREADS) void k_img_counts(const Img *__restrict__ tab, Img one, int32_t nimg, int32_t nl,
                                                          int32_t ntiles_total, const int32_t *__restrict__ tile_cnt,
                                                          int64_t *const *__restrict__ outs, int64_t *one_out) {
     constexpr int U = 8;
     int b = blockIdx.x, k = blockIdx.y;
     if (b >= nimg || k >= nl) return;
-    int32_t t0 = tab ? tab[b].tile0[TK_WF] : one.tile0[TK_WF];
-    int32_t t1 = b + 1 < nimg ? tab[b + 1].tile0[TK_WF] : ntiles_total;
+    int32_t t0 = tab ? tab[b].tile0[TK_CH] : one.tile0[TK_CH];
+    int32_t t1 = b + 1 < nimg ? tab[b + 1].tile0[TK_CH] : ntiles_total;
     const int32_t *c = tile_cnt + (size_t)k * ntiles_total;
     int s = 0;
     for (int32_t t = t0 + threadIdx.x; t < t1; t += NTHREADS * U) {
@@ -736,6 +727,7 @@ static int wf_ids_impl(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t b
     int rc = lc.run("wf_ids", k_root_bits<Src>, grid, dim3(NTHREADS), src_ch, nchunks, ids.coff, ids.words);
     if (rc) return rc;
     if ((rc = launch_scan(lc, nchunks, ids.coff, scan_tmp, nreg0))) return rc;
+    if (!key) return 0;  // region counts only
     int32_t nwords = nchunks * 64;
     return lc.run("wf_ids", k_wf_tables, list_grid(bound > nwords ? bound : nwords), dim3(NTHREADS),
                   (const int32_t *)nreg0, key, par, nwords, ids.words, (const int32_t *)ids.coff);
@@ -743,19 +735,18 @@ static int wf_ids_impl(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t b
 
 template <int CONN, typename T, class Src>
 static int wf_pix_t(Launch &lc, const Src &src, const TileGrid &tg, const WfIds &ids, const int32_t *nreg0,
-                    int32_t *cimg, int32_t *rlist, int32_t *tile_cnt0, uint64_t *key, int32_t *edges, int32_t *ecnt) {
+                    int32_t *cimg, int32_t *rlist, uint64_t *key, int32_t *edges, int32_t *ecnt) {
     const int32_t cap = wf_slab_cap(CONN);
     size_t E = (size_t)tg.ntiles * (size_t)cap;
     return lc.run("wf_pix", k_wf_pix<CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles,
-                  (const RankWord *)ids.words, nreg0, cimg, rlist, tile_cnt0, key, edges, edges + E, edges + 2 * E,
-                  ecnt, cap);
+                  (const RankWord *)ids.words, nreg0, cimg, rlist, key, edges, edges + E, edges + 2 * E, ecnt, cap);
 }
 
 template <class Src>
 static int wf_pix_dispatch(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const WfIds &ids,
-                           const int32_t *nreg0, int32_t *cimg, int32_t *rlist, int32_t *tile_cnt0, uint64_t *key,
-                           int32_t *edges, int32_t *ecnt) {
-#define WF_PIX_ARGS lc, src, tg, ids, nreg0, cimg, rlist, tile_cnt0, key, edges, ecnt
+                           const int32_t *nreg0, int32_t *cimg, int32_t *rlist, uint64_t *key, int32_t *edges,
+                           int32_t *ecnt) {
+#define WF_PIX_ARGS lc, src, tg, ids, nreg0, cimg, rlist, key, edges, ecnt
     switch (conn) {
     case 4: return u16 ? wf_pix_t<4, uint16_t>(WF_PIX_ARGS) : wf_pix_t<4, uint8_t>(WF_PIX_ARGS);
     case 8: return u16 ? wf_pix_t<8, uint16_t>(WF_PIX_ARGS) : wf_pix_t<8, uint8_t>(WF_PIX_ARGS);
@@ -766,28 +757,21 @@ static int wf_pix_dispatch(Launch &lc, const Src &src, const TileGrid &tg, int c
 #undef WF_PIX_ARGS
 }
 
-template <class Src>
-static int wf_out_impl(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t nl, const int32_t *cimg,
-                       const int32_t *nreg0, const int32_t *mlab, int64_t mstride, int32_t *tile_cnt) {
-    return ndim == 3 ? lc.run("wf_out", k_wf_out<3, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, nl, cimg,
-                              nreg0, mlab, mstride, tile_cnt)
-                     : lc.run("wf_out", k_wf_out<2, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, nl, cimg,
-                              nreg0, mlab, mstride, tile_cnt);
-}
-
 #define WF_SRC_FUNCS(Src)                                                                                          \
     int launch_wf_ids(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t bound, const WfIds &ids,            \
                       int32_t *scan_tmp, int32_t *nreg0, uint64_t *key, int32_t *par) {                           \
         return wf_ids_impl(lc, src_ch, nchunks, bound, ids, scan_tmp, nreg0, key, par);                           \
     }                                                                                                              \
     int launch_wf_pix(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const WfIds &ids,       \
-                      const int32_t *nreg0, int32_t *cimg, int32_t *rlist, int32_t *tile_cnt0, uint64_t *key,     \
-                      int32_t *edges, int32_t *ecnt) {                                                            \
-        return wf_pix_dispatch(lc, src, tg, conn, u16, ids, nreg0, cimg, rlist, tile_cnt0, key, edges, ecnt);     \
+                      const int32_t *nreg0, int32_t *cimg, int32_t *rlist, uint64_t *key, int32_t *edges,         \
+                      int32_t *ecnt) {                                                                            \
+        return wf_pix_dispatch(lc, src, tg, conn, u16, ids, nreg0, cimg, rlist, key, edges, ecnt);                \
     }                                                                                                              \
-    int launch_wf_out(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t nl, const int32_t *cimg,   \
-                      const int32_t *nreg0, const int32_t *mlab, int64_t mstride, int32_t *tile_cnt) {            \
-        return wf_out_impl(lc, src, tg, ndim, nl, cimg, nreg0, mlab, mstride, tile_cnt);                          \
+    int launch_wf_out(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t nl, const int32_t *cimg,            \
+                      const int32_t *nreg0, const int32_t *coff, const int32_t *mlab, int64_t mstride,           \
+                      int32_t *cnt) {                                                                             \
+        return lc.run("wf_out", k_wf_out<Src>, dim3(nchunks > 0 ? nchunks : 1), dim3(NTHREADS), src_ch, nchunks, \
+                      nl, cimg, nreg0, coff, mlab, mstride, cnt);                                                 \
     }
 
 WF_SRC_FUNCS(OneImg)

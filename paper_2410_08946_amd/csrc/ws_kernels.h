@@ -97,10 +97,11 @@ struct TileGrid {
     int launch_wf_ids(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t bound, const WfIds &ids,           \
                       int32_t *scan_tmp, int32_t *nreg0, uint64_t *key, int32_t *par);                            \
     int launch_wf_pix(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const WfIds &ids,      \
-                      const int32_t *nreg0, int32_t *cimg, int32_t *rlist, int32_t *tile_cnt0, uint64_t *key,    \
-                      int32_t *edges, int32_t *ecnt);                                                            \
-    int launch_wf_out(Launch &lc, const Src &src, const TileGrid &tg, int ndim, int32_t nl, const int32_t *cimg,  \
-                      const int32_t *nreg0, const int32_t *mlab, int64_t mstride, int32_t *tile_cnt);
+                      const int32_t *nreg0, int32_t *cimg, int32_t *rlist, uint64_t *key, int32_t *edges,        \
+                      int32_t *ecnt);                                                                            \
+    int launch_wf_out(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t nl, const int32_t *cimg,           \
+                      const int32_t *nreg0, const int32_t *coff, const int32_t *mlab, int64_t mstride,          \
+                      int32_t *cnt);
 WS_DECL_SRC(OneImg)
 WS_DECL_SRC(ImgTable)
 #undef WS_DECL_SRC
