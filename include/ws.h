@@ -190,6 +190,14 @@ int ws_watershed_stages(ws_ctx *ctx, const void *grad, int dtype, int64_t nx, in
  *   "max_sweeps"   cap on Step II sweeps; reaching it returns WS_ENOCONV
  *                  (default 2^31-1).
  *   "timing"       1 = record a HIP event pair around every kernel launch.
+ *   "graph"        1 = ws_gradient and ws_waterfall replay launch graphs: a
+ *                  call is captured (hipStreamBeginCapture on a stream of the
+ *                  context) the second time the same arguments (pointers,
+ *                  sizes, options) are seen, and its instantiated graph is
+ *                  launched on `stream` for every later identical call.
+ *                  Buffers are read when the graph runs, so their contents
+ *                  may change between calls. Any scratch reallocation drops
+ *                  the graphs. Ignored while "timing" is on. Default 0.
  *   "reserve_pixels"  allocate now the scratch of calls covering up to this
  *                  many pixels (any 2D/3D mix, conn 4/6/8, NL <= 8), so later calls do
  *                  not allocate (allocation waits for the whole device);
@@ -201,7 +209,8 @@ int ws_set_option(ws_ctx *ctx, const char *name, int64_t value);
 /*
  * Counters of the last ws_watershed call: out[0] Step II sweeps launched
  * (including the initial tile pass), out[1] sweeps that changed a tile
- * border, out[2] Step III synchronisations (step3 = 1), out[3] tiles.
+ * border, out[2] Step III synchronisations (step3 = 1), out[3] tiles; and
+ * out[4] the launch graphs replayed by this context so far ("graph" option).
  * Returns the number of counters written (<= n).
  */
 int ws_get_stats(const ws_ctx *ctx, int64_t *out, int n);

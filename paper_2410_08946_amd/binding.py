@@ -133,9 +133,9 @@ class Context:
         self._check(self._lib.ws_set_option(self._h, name.encode(), int(value)))
 
     def stats(self):
-        out = (ctypes.c_int64 * 4)()
-        n = self._lib.ws_get_stats(self._h, out, 4)
-        keys = ("sweeps_launched", "sweeps_changing", "step3_syncs", "tiles")
+        out = (ctypes.c_int64 * 5)()
+        n = self._lib.ws_get_stats(self._h, out, 5)
+        keys = ("sweeps_launched", "sweeps_changing", "step3_syncs", "tiles", "graph_replays")
         return {k: int(out[i]) for i, k in enumerate(keys[:n])}
 
     def timing_reset(self):

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <map>
 #include <string>
+#include <vector>
 
 #include "ws.h"
 #include "ws_kernels.h"
@@ -21,6 +22,7 @@ namespace {
 
 constexpr int kCounterSlots = 64;   // Step II per-sweep change counters (ring)
 constexpr int kMaxSweepBatch = 32;
+constexpr size_t kMaxGraphs = 16;   // instantiated launch graphs kept per context
 
 struct Buf {
     void *p = nullptr;
@@ -48,8 +50,23 @@ struct ws_ctx {
     int step3 = 0, rr = 6, sweep_batch = 4;
     int64_t max_sweeps = 0x7fffffff;
     bool timing = false;
+    // launch graphs: a call signature seen once is captured on its next use
+    // and replayed from then on, while no scratch buffer has moved (gen)
+    bool graph = false;
+    bool capturing = false;
+    uint64_t gen = 0;
+    hipStream_t cap = nullptr;
+    struct Graph {
+        std::string sig;
+        uint64_t gen;
+        uint64_t used;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    std::map<std::string, uint64_t> seen;
+    uint64_t tick = 0;
     wsk::TimingSink sink;
-    int64_t stats[4] = {0, 0, 0, 0};
+    int64_t stats[5] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -67,6 +84,8 @@ int hip_fail(ws_ctx *c, hipError_t e, const char *where) {
 int ensure(ws_ctx *c, Buf &b, size_t bytes, const char *what) {
     if (bytes == 0) bytes = 256;
     if (b.n >= bytes) return WS_OK;
+    if (c->capturing) return fail(c, WS_EUNSUPPORTED, std::string("allocation during graph capture: ") + what);
+    ++c->gen;  // cached launch graphs hold the old address
     // grow geometrically: hipFree waits for the whole device, so a context
     // that serves growing batches should reallocate rarely
     if (b.n > 0 && bytes < b.n + b.n / 2) bytes = b.n + b.n / 2;
@@ -126,6 +145,72 @@ Launch make_launch(ws_ctx *c, void *stream) {
     lc.stream = (hipStream_t)stream;
     lc.timing = c->timing ? &c->sink : nullptr;
     return lc;
+}
+
+// Enqueues through `enqueue(Launch&)`, or replays its captured graph. Without
+// the graph option (or with per-launch timing) it simply enqueues on `stream`.
+// A signature's first use runs directly (allocating what it needs); its
+// second use is captured on the context's own stream (the caller's may be
+// the legacy stream, which cannot be captured), instantiated and launched on
+// `stream`; later uses replay. If capture fails the call runs directly.
+template <class F>
+int run_graphed(ws_ctx *c, void *stream, const std::string &sig, F &&enqueue) {
+    if (!c->graph || c->timing) {
+        Launch lc = make_launch(c, stream);
+        return enqueue(lc);
+    }
+    for (auto &g : c->graphs)
+        if (g.sig == sig && g.gen == c->gen) {
+            g.used = ++c->tick;
+            ++c->stats[4];
+            hipError_t e = hipGraphLaunch(g.exec, (hipStream_t)stream);
+            return e == hipSuccess ? WS_OK : hip_fail(c, e, "hipGraphLaunch");
+        }
+    auto it = c->seen.find(sig);
+    if (it == c->seen.end() || it->second != c->gen) {
+        c->seen[sig] = c->gen;
+        Launch lc = make_launch(c, stream);
+        return enqueue(lc);
+    }
+    hipError_t e;
+    if (!c->cap && (e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(c, e, "hipStreamCreateWithFlags");
+    if ((e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        (void)hipGetLastError();
+        Launch lc = make_launch(c, stream);
+        return enqueue(lc);
+    }
+    c->capturing = true;
+    Launch cl = make_launch(c, c->cap);
+    cl.timing = nullptr;
+    int rc = enqueue(cl);
+    c->capturing = false;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(c->cap, &graph);
+    hipGraphExec_t exec = nullptr;
+    if (rc == WS_OK && e == hipSuccess && graph) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc != WS_OK || e != hipSuccess || !exec) {
+        (void)hipGetLastError();
+        c->err.clear();
+        Launch lc = make_launch(c, stream);
+        return enqueue(lc);
+    }
+    if (c->graphs.size() >= kMaxGraphs) {
+        auto old = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                    [](const ws_ctx::Graph &a, const ws_ctx::Graph &b) { return a.used < b.used; });
+        (void)hipGraphExecDestroy(old->exec);
+        c->graphs.erase(old);
+    }
+    c->graphs.push_back({sig, c->gen, ++c->tick, exec});
+    e = hipGraphLaunch(exec, (hipStream_t)stream);
+    return e == hipSuccess ? WS_OK : hip_fail(c, e, "hipGraphLaunch");
+}
+
+std::string sig_of(const char *what, std::initializer_list<uint64_t> v) {
+    std::string s(what);
+    for (uint64_t x : v) s += ":" + std::to_string(x);
+    return s;
 }
 
 #define WS_TRY(expr)                                                      \
@@ -357,6 +442,8 @@ void ws_destroy(ws_ctx *c) {
                    &c->tilecnt, &c->tab};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
+    for (auto &gr : c->graphs) (void)hipGraphExecDestroy(gr.exec);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     for (auto &r : c->sink.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (auto e : c->sink.pool) (void)hipEventDestroy(e);
     if (c->host_cnt) (void)hipHostFree(c->host_cnt);
@@ -404,6 +491,7 @@ int ws_set_option(ws_ctx *c, const char *name, int64_t v) {
     else if (k == "sweep_batch" && v >= 1 && v <= kMaxSweepBatch) c->sweep_batch = (int)v;
     else if (k == "max_sweeps" && v >= 1) c->max_sweeps = v;
     else if (k == "timing" && (v == 0 || v == 1)) c->timing = v != 0;
+    else if (k == "graph" && (v == 0 || v == 1)) c->graph = v != 0;
     else if (k == "reserve_pixels" && v >= 0 && v < (1LL << 31)) {
         int rc = set_device(c);
         if (rc) return rc;
@@ -415,7 +503,7 @@ int ws_set_option(ws_ctx *c, const char *name, int64_t v) {
 
 int ws_get_stats(const ws_ctx *c, int64_t *out, int n) {
     if (!c || !out || n < 0) return WS_EINVAL;
-    int m = std::min(n, 4);
+    int m = std::min(n, 5);
     for (int i = 0; i < m; ++i) out[i] = c->stats[i];
     return m;
 }
@@ -435,44 +523,50 @@ int ws_gradient(ws_ctx *c, const float *img, int64_t nx, int64_t ny, int64_t nz,
     int ndim = nz > 1 ? 3 : 2;
     Geom g = make_geom(nx, ny, nz, ndim);
     size_t N = (size_t)g.n;
-    Launch lc = make_launch(c, stream);
-    const int32_t nparts = wsk::grad_parts(g, ndim, r);
-    if ((rc = ensure(c, c->gmax, ((size_t)nparts + 257) * 4, "partial maxima")) != WS_OK) return rc;
-    float *part = (float *)c->gmax.p, *part_tmp = part + nparts, *gmax = part_tmp + 256;
-    float *mag = mag_or_null;
-    if (!mag) {
-        if ((rc = ensure(c, c->mag, N * 4, "magnitude buffer")) != WS_OK) return rc;
-        mag = (float *)c->mag.p;
-    }
-    wsk::BlurTaps taps;
-    taps.r = r;
-    {
-        double w[129], sum = 0.0;
-        for (int k = -r; k <= r; ++k) {
-            w[k + r] = r > 0 ? exp(-0.5 * (double)k * (double)k / ((double)sigma * (double)sigma)) : 1.0;
-            sum += w[k + r];
+    uint32_t sbits;
+    memcpy(&sbits, &sigma, 4);
+    std::string sig = sig_of("gr", {(uint64_t)(uintptr_t)img, (uint64_t)nx, (uint64_t)ny, (uint64_t)nz, sbits,
+                                    (uint64_t)dtype, (uint64_t)(uintptr_t)grad, (uint64_t)(uintptr_t)mag_or_null});
+    return run_graphed(c, stream, sig, [&](Launch &lc) -> int {
+        int rc;
+        const int32_t nparts = wsk::grad_parts(g, ndim, r);
+        if ((rc = ensure(c, c->gmax, ((size_t)nparts + 257) * 4, "partial maxima")) != WS_OK) return rc;
+        float *part = (float *)c->gmax.p, *part_tmp = part + nparts, *gmax = part_tmp + 256;
+        float *mag = mag_or_null;
+        if (!mag) {
+            if ((rc = ensure(c, c->mag, N * 4, "magnitude buffer")) != WS_OK) return rc;
+            mag = (float *)c->mag.p;
         }
-        for (int k = 0; k <= 2 * r; ++k) taps.w[k] = (float)(w[k] / sum);
-    }
-    if (ndim == 2 && r <= wsk::FUSED_MAX_R) {
-        WS_TRY(wsk::launch_grad_fused2d(lc, g, img, mag, part, taps));
-    } else {
-        const float *src = img;
-        if (r > 0) {
-            if ((rc = ensure(c, c->g0, N * 4, "blur buffer")) != WS_OK) return rc;
-            if ((rc = ensure(c, c->g1, N * 4, "blur buffer")) != WS_OK) return rc;
-            float *bufs[2] = {(float *)c->g0.p, (float *)c->g1.p};
-            for (int ax = 0; ax < ndim; ++ax) {
-                float *dst = bufs[ax & 1];
-                WS_TRY(wsk::launch_grad_blur(lc, g, src, dst, ax, taps));
-                src = dst;
+        wsk::BlurTaps taps;
+        taps.r = r;
+        {
+            double w[129], sum = 0.0;
+            for (int k = -r; k <= r; ++k) {
+                w[k + r] = r > 0 ? exp(-0.5 * (double)k * (double)k / ((double)sigma * (double)sigma)) : 1.0;
+                sum += w[k + r];
             }
+            for (int k = 0; k <= 2 * r; ++k) taps.w[k] = (float)(w[k] / sum);
         }
-        WS_TRY(wsk::launch_grad_sobel(lc, g, ndim, src, mag, part));
-    }
-    WS_TRY(wsk::launch_grad_max(lc, nparts, part, part_tmp, gmax));
-    WS_TRY(wsk::launch_grad_quant(lc, g.n, dtype == WS_U16, mag, grad, gmax));
-    return WS_OK;
+        if (ndim == 2 && r <= wsk::FUSED_MAX_R) {
+            WS_TRY(wsk::launch_grad_fused2d(lc, g, img, mag, part, taps));
+        } else {
+            const float *src = img;
+            if (r > 0) {
+                if ((rc = ensure(c, c->g0, N * 4, "blur buffer")) != WS_OK) return rc;
+                if ((rc = ensure(c, c->g1, N * 4, "blur buffer")) != WS_OK) return rc;
+                float *bufs[2] = {(float *)c->g0.p, (float *)c->g1.p};
+                for (int ax = 0; ax < ndim; ++ax) {
+                    float *dst = bufs[ax & 1];
+                    WS_TRY(wsk::launch_grad_blur(lc, g, src, dst, ax, taps));
+                    src = dst;
+                }
+            }
+            WS_TRY(wsk::launch_grad_sobel(lc, g, ndim, src, mag, part));
+        }
+        WS_TRY(wsk::launch_grad_max(lc, nparts, part, part_tmp, gmax));
+        WS_TRY(wsk::launch_grad_quant(lc, g.n, dtype == WS_U16, mag, grad, gmax));
+        return WS_OK;
+    });
 }
 
 static int ws_validate_ws(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz, int conn,
@@ -522,15 +616,19 @@ int ws_waterfall(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, 
     if (NL < 1) return fail(c, WS_EINVAL, "ws_waterfall: NL must be >= 1");
     if ((rc = set_device(c))) return rc;
     int ndim = nz > 1 ? 3 : 2;
-    Launch lc = make_launch(c, stream);
     wsk::OneImg src{single_img(nx, ny, nz, grad, out)};
     const wsk::Geom &g = src.im.g;
-    if (labels != out) {
-        hipError_t e = hipMemcpyAsync(out, labels, (size_t)g.n * 4, hipMemcpyDeviceToDevice, lc.stream);
-        if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
-    }
-    return run_waterfall(c, lc, src, src, wsk::wf_chunks(g.n), full_grid(wsk::wf_tiles(g, ndim)), ndim, conn,
-                         dtype == WS_U16, NL, (size_t)g.n, nullptr, src.im, 1, nullptr, nregions);
+    std::string sig = sig_of("wf", {(uint64_t)(uintptr_t)labels, (uint64_t)(uintptr_t)grad, (uint64_t)dtype,
+                                    (uint64_t)nx, (uint64_t)ny, (uint64_t)nz, (uint64_t)conn, (uint64_t)NL,
+                                    (uint64_t)(uintptr_t)out, (uint64_t)(uintptr_t)nregions});
+    return run_graphed(c, stream, sig, [&](Launch &lc) -> int {
+        if (labels != out) {
+            hipError_t e = hipMemcpyAsync(out, labels, (size_t)g.n * 4, hipMemcpyDeviceToDevice, lc.stream);
+            if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+        }
+        return run_waterfall(c, lc, src, src, wsk::wf_chunks(g.n), full_grid(wsk::wf_tiles(g, ndim)), ndim, conn,
+                             dtype == WS_U16, NL, (size_t)g.n, nullptr, src.im, 1, nullptr, nregions);
+    });
 }
 
 int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, int NL, void *stream) {

@@ -378,3 +378,47 @@ def test_serving_mix_identity(ctx):
         srv2.close()
     assert big.error is not None and small.error is None
     assert np.array_equal(to_host(small.out), solo[0][0])
+
+
+def test_graph_replay_matches_direct():
+    """Launch graphs (option "graph"): the same calls on the same buffers, with
+    the buffers' contents changed between calls and eager work between the
+    replays, give exactly the direct path's results on every replay."""
+    import torch
+
+    import paper_2410_08946_amd as ws
+    gctx, dctx = ws.Context(0), ws.Context(0)
+    gctx.set_option("graph", 1)
+    ny, nx, conn, NL = 300, 280, 8, 4
+    dev = "cuda:0"
+    bufs = {}
+    for name, c in (("g", gctx), ("d", dctx)):
+        bufs[name] = dict(img=torch.empty((ny, nx), dtype=torch.float32, device=dev),
+                          grad=torch.empty((ny, nx), dtype=torch.uint8, device=dev),
+                          out=torch.empty((NL, ny, nx), dtype=torch.int32, device=dev),
+                          nreg=torch.zeros(NL, dtype=torch.int64, device=dev))
+    imgs = [gen.blobs2d(ny, nx, seed=s) for s in (5, 6, 7)]
+    try:
+        for rep in range(6):
+            im = torch.from_numpy(imgs[rep % 3]).to(dev)
+            res = {}
+            for name, c in (("g", gctx), ("d", dctx)):
+                b = bufs[name]
+                b["img"].copy_(im)
+                c.gradient(b["img"], 0.0, "u8", out=b["grad"])
+                c.watershed(b["grad"], conn, out=b["out"][0])
+                c.waterfall(b["out"][0], b["grad"], conn, NL, out=b["out"], nregions=b["nreg"])
+                torch.cuda.synchronize()
+                res[name] = (b["grad"].cpu().numpy(), b["out"].cpu().numpy(), b["nreg"].cpu().numpy())
+            say("  graph replay round", rep, "replays so far", gctx.stats().get("graph_replays"))
+            for a, d in zip(res["g"], res["d"]):
+                assert np.array_equal(a, d)
+            float((im * 2).sum())  # eager work between replays
+            torch.cuda.synchronize()
+        assert gctx.stats()["graph_replays"] >= 6  # gradient + waterfall replayed from the third round on
+        lab = oracle.watershed(res["d"][0], conn)
+        wf, n = oracle.waterfall_g1(lab, res["d"][0], conn, NL)
+        assert np.array_equal(res["g"][1], wf) and np.array_equal(res["g"][2], n)
+    finally:
+        gctx.close()
+        dctx.close()
