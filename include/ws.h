@@ -153,6 +153,24 @@ typedef struct {
 } ws_item;
 
 /*
+ * Reconstruction waterfall, the paper's literal procedure (Alg. 4 Steps V-VI
+ * followed by the watershed again, as in the Alg. 5 layer loop): layer 0 is
+ * `labels`; for every later layer each region R of the previous layer gets
+ * newmin(R) = min over pixel pairs (p in R, q in N(p) outside R) of
+ * max(I(p), I(q)) (65535 for a region without boundary), the image is raised
+ * to I(p) = max(I(p), newmin(region of p)), and layer k is the watershed
+ * (canonical labels) of the raised image. The raised image starts from `grad`
+ * and is kept by the context as uint16; `grad` is not written.
+ *   labels, grad, dtype, sizes, conn, NL, out, nregions: as for ws_waterfall.
+ * Unlike ws_waterfall the layers need not be nested (a region can be split).
+ * Waits on `stream` like ws_watershed (once per layer after the first).
+ * Returns WS_ENOCONV if a watershed reached the sweep cap.
+ */
+int ws_waterfall_recon(ws_ctx *ctx, const int32_t *labels, const void *grad, int dtype, int64_t nx,
+                       int64_t ny, int64_t nz, int conn, int NL, int32_t *out,
+                       int64_t *nregions_or_null, void *stream);
+
+/*
  * Watershed + NL-layer waterfall of many images of uneven sizes in one set of
  * launches (every kernel covers the tiles of all images through a tile ->
  * image table; the Step II convergence loop is shared). The result of every

@@ -9,6 +9,7 @@ Functions named like the C entry points take and return torch tensors:
   ws_gradient(img, sigma, dtype)                  -> uint8/uint16 gradient
   ws_watershed(grad, conn)                         -> int32 canonical labels
   ws_waterfall(labels, grad, conn, NL)             -> (int32 [NL, ...], int64 [NL])
+  ws_waterfall_recon(labels, grad, conn, NL)       -> (int32 [NL, ...], int64 [NL]), Alg. 4 + 5
   ws_watershed_stages(grad, conn)                  -> (balanced states, arrows)
   ws_batch([grad, ...], conn, NL)                  -> ([int32 [NL, ...]], [int64 [NL]])
 Image tensors are C-contiguous (nx,), (ny, nx) or (nz, ny, nx) with x fastest.
@@ -24,6 +25,7 @@ from .binding import (  # noqa: F401
     ws_gradient,
     ws_watershed,
     ws_waterfall,
+    ws_waterfall_recon,
     ws_watershed_stages,
     ws_batch,
     WS_U8,

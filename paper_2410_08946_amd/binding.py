@@ -31,6 +31,7 @@ SIGNATURES = {
     "ws_gradient": (_int, [_ptr, _ptr, _i64, _i64, _i64, _f32, _int, _ptr, _ptr, _ptr]),
     "ws_watershed": (_int, [_ptr, _ptr, _int, _i64, _i64, _i64, _int, _ptr, _ptr]),
     "ws_waterfall": (_int, [_ptr, _ptr, _ptr, _int, _i64, _i64, _i64, _int, _int, _ptr, _ptr, _ptr]),
+    "ws_waterfall_recon": (_int, [_ptr, _ptr, _ptr, _int, _i64, _i64, _i64, _int, _int, _ptr, _ptr, _ptr]),
     "ws_watershed_stages": (_int, [_ptr, _ptr, _int, _i64, _i64, _i64, _int, _ptr, _ptr, _ptr]),
     "ws_batch": (_int, [_ptr, ctypes.POINTER(WsItem), _int, _int, _int, _int, _ptr]),
     "ws_set_option": (_int, [_ptr, ctypes.c_char_p, _i64]),
@@ -230,6 +231,21 @@ class Context:
                                            _dev(nregions, "nregions"), _stream(grad)))
         return out, nregions
 
+    def waterfall_recon(self, labels, grad, conn: int, NL: int, out=None, nregions=None):
+        """Reconstruction waterfall (ws_waterfall_recon): same arguments as waterfall."""
+        import torch
+        nx, ny, nz = _dims(grad.shape)
+        if labels.shape != grad.shape or labels.dtype != torch.int32:
+            raise ValueError("labels must be int32 with the gradient's shape")
+        if out is None:
+            out = torch.empty((int(NL),) + tuple(grad.shape), dtype=torch.int32, device=grad.device)
+        if nregions is None:
+            nregions = torch.zeros(int(NL), dtype=torch.int64, device=grad.device)
+        self._check(self._lib.ws_waterfall_recon(self._h, _dev(labels, "labels"), _dev(grad, "gradient"),
+                                                 _grey_code(grad), nx, ny, nz, int(conn), int(NL),
+                                                 _dev(out, "out"), _dev(nregions, "nregions"), _stream(grad)))
+        return out, nregions
+
 
 _default = {}
 
@@ -250,6 +266,10 @@ def ws_watershed(grad, conn, out=None):
 
 def ws_waterfall(labels, grad, conn, NL, out=None, nregions=None):
     return default_context(grad.device.index or 0).waterfall(labels, grad, conn, NL, out=out, nregions=nregions)
+
+
+def ws_waterfall_recon(labels, grad, conn, NL, out=None, nregions=None):
+    return default_context(grad.device.index or 0).waterfall_recon(labels, grad, conn, NL, out=out, nregions=nregions)
 
 
 def ws_batch(grads, conn, NL, outs=None, nregions=None):

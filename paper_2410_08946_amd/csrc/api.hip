@@ -38,6 +38,7 @@ struct ws_ctx {
     std::string err;
     Buf D, stamp, cnt, rec;               // watershed scratch
     Buf key, par, cimg, rlist, mlab;      // waterfall: region tables (dense by id), per-pixel region ids
+    Buf rimg;                             // reconstruction waterfall: the raised image (uint16)
     Buf edges, ecnt, wfcnt;               // edge slabs, their counts, region count
     Buf g0, g1, mag, gmax;                // gradient scratch
     Buf chunks, tilecnt;                  // region-id rank tables + scan scratch, per-tile counts
@@ -303,6 +304,51 @@ int run_watershed(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg
     return WS_OK;
 }
 
+// The waterfall's device buffers for `arena` pixels: region-id tables and
+// per-chunk counts always; with `tables`, the region tables, the per-pixel ids,
+// NL - 1 layer tables and the edge slabs.
+struct WfBufs {
+    wsk::WfIds ids;
+    int32_t *scan_tmp, *nreg0, *cnt;
+    uint64_t *key;
+    int32_t *par, *cimg, *rlist, *mlab, *edges, *ecnt;
+};
+
+int wf_buffers(ws_ctx *c, size_t arena, int32_t ntiles, int32_t nchunks, int conn, int NL, bool tables, WfBufs &b) {
+    int rc;
+    if ((rc = ensure(c, c->wfcnt, 4, "region count")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->tilecnt, (size_t)NL * nchunks * 4, "chunk counts")) != WS_OK) return rc;
+    // region-id tables: [chunk offsets | scan scratch | 64 rank words per chunk]
+    size_t off_words = (((size_t)nchunks + wsk::scan_tmp_len(nchunks)) * 4 + 15) & ~(size_t)15;
+    if ((rc = ensure(c, c->chunks, off_words + (size_t)nchunks * 64 * sizeof(wsk::RankWord), "region-id tables")) !=
+        WS_OK)
+        return rc;
+    char *tb = (char *)c->chunks.p;
+    b.ids = wsk::WfIds{(wsk::RankWord *)(tb + off_words), (int32_t *)tb};
+    b.scan_tmp = (int32_t *)tb + nchunks;
+    b.nreg0 = (int32_t *)c->wfcnt.p;
+    b.cnt = (int32_t *)c->tilecnt.p;
+    b.key = nullptr;
+    b.par = b.cimg = b.rlist = b.mlab = b.edges = b.ecnt = nullptr;
+    if (!tables) return WS_OK;
+    const size_t E = (size_t)ntiles * (size_t)wsk::wf_slab_cap(conn);
+    if ((rc = ensure(c, c->key, arena * 8, "region keys")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->par, arena * 4, "region parents")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->cimg, arena * 4, "pixel region ids")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->rlist, arena * 4, "region labels")) != WS_OK) return rc;
+    if (NL >= 2 && (rc = ensure(c, c->mlab, (size_t)(NL - 1) * arena * 4, "layer labels")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->edges, 3 * E * 4, "edge slabs")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->ecnt, (size_t)ntiles * 4, "edge counts")) != WS_OK) return rc;
+    b.key = (uint64_t *)c->key.p;
+    b.par = (int32_t *)c->par.p;
+    b.cimg = (int32_t *)c->cimg.p;
+    b.rlist = (int32_t *)c->rlist.p;
+    b.mlab = (int32_t *)c->mlab.p;
+    b.edges = (int32_t *)c->edges.p;
+    b.ecnt = (int32_t *)c->ecnt.p;
+    return WS_OK;
+}
+
 // NL waterfall layers of every image of `src` (layer 0 already in lab):
 // region ids, the layer-0 pixel pass, then per layer union + compression and
 // (from layer 2) an edge pass over tile groups growing fourfold, and one pass
@@ -314,54 +360,31 @@ int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const Src &src_ch, int3
                   int nimg, int64_t *const *outs_dev, int64_t *one_out) {
     int rc;
     int32_t bound = (int32_t)arena;
-    if ((rc = ensure(c, c->wfcnt, 4, "region count")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->tilecnt, (size_t)NL * nchunks * 4, "chunk counts")) != WS_OK) return rc;
-    // region-id tables: [chunk offsets | scan scratch | 64 rank words per chunk]
-    size_t off_words = (((size_t)nchunks + wsk::scan_tmp_len(nchunks)) * 4 + 15) & ~(size_t)15;
-    if ((rc = ensure(c, c->chunks, off_words + (size_t)nchunks * 64 * sizeof(wsk::RankWord), "region-id tables")) !=
-        WS_OK)
-        return rc;
-    int32_t *nreg0 = (int32_t *)c->wfcnt.p, *ccnt = (int32_t *)c->tilecnt.p;
-    char *tb = (char *)c->chunks.p;
-    wsk::WfIds ids{(wsk::RankWord *)(tb + off_words), (int32_t *)tb};
-    int32_t *scan_tmp = (int32_t *)tb + nchunks;
-    const int32_t *cimg = nullptr, *mlab = nullptr;
+    WfBufs b;
+    if ((rc = wf_buffers(c, arena, tg.ntiles, nchunks, conn, NL, NL >= 2, b)) != WS_OK) return rc;
     if (NL == 1) {
-        WS_TRY(wsk::launch_wf_ids(lc, src_ch, nchunks, bound, ids, scan_tmp, nreg0, nullptr, nullptr));
+        WS_TRY(wsk::launch_wf_ids(lc, src_ch, nchunks, bound, b.ids, b.scan_tmp, b.nreg0, nullptr, nullptr));
     } else {
         const int32_t cap = wsk::wf_slab_cap(conn);
-        const size_t E = (size_t)tg.ntiles * (size_t)cap;
-        if ((rc = ensure(c, c->key, arena * 8, "region keys")) != WS_OK) return rc;
-        if ((rc = ensure(c, c->par, arena * 4, "region parents")) != WS_OK) return rc;
-        if ((rc = ensure(c, c->cimg, arena * 4, "pixel region ids")) != WS_OK) return rc;
-        if ((rc = ensure(c, c->rlist, arena * 4, "region labels")) != WS_OK) return rc;
-        if ((rc = ensure(c, c->mlab, (size_t)(NL - 1) * arena * 4, "layer labels")) != WS_OK) return rc;
-        if ((rc = ensure(c, c->edges, 3 * E * 4, "edge slabs")) != WS_OK) return rc;
-        if ((rc = ensure(c, c->ecnt, (size_t)tg.ntiles * 4, "edge counts")) != WS_OK) return rc;
-        uint64_t *key = (uint64_t *)c->key.p;
-        int32_t *par = (int32_t *)c->par.p, *ci = (int32_t *)c->cimg.p, *rl = (int32_t *)c->rlist.p;
-        int32_t *ml = (int32_t *)c->mlab.p, *edges = (int32_t *)c->edges.p, *ecnt = (int32_t *)c->ecnt.p;
-        WS_TRY(wsk::launch_wf_ids(lc, src_ch, nchunks, bound, ids, scan_tmp, nreg0, key, par));
-        WS_TRY(wsk::launch_wf_pix(lc, src, tg, conn, u16, ids, nreg0, ci, rl, key, edges, ecnt));
-        WS_TRY(wsk::launch_wf_union(lc, bound, nreg0, key, par));
-        WS_TRY(wsk::launch_wf_compress(lc, bound, nreg0, par, rl, ml));
+        WS_TRY(wsk::launch_wf_ids(lc, src_ch, nchunks, bound, b.ids, b.scan_tmp, b.nreg0, b.key, b.par));
+        WS_TRY(wsk::launch_wf_pix(lc, src, tg, conn, u16, b.ids, b.nreg0, b.cimg, b.rlist, b.key, b.edges, b.ecnt));
+        WS_TRY(wsk::launch_wf_union(lc, bound, b.nreg0, b.key, b.par));
+        WS_TRY(wsk::launch_wf_compress(lc, bound, b.nreg0, b.par, b.rlist, b.mlab));
         int32_t gin = 1;
         for (int k = 2; k < NL; ++k) {
             // groups grow fourfold per layer: regions spanning several tiles
             // then share one group (fewer key atomics) while a group's
             // distinct edges still fit its LDS hash
             int32_t f = gin >= tg.ntiles ? 1 : 4;
-            WS_TRY(wsk::launch_wf_level(lc, tg.ntiles, gin, f, cap, par, key, edges, ecnt));
+            WS_TRY(wsk::launch_wf_level(lc, tg.ntiles, gin, f, cap, b.par, b.key, b.edges, b.ecnt));
             gin *= f;
-            WS_TRY(wsk::launch_wf_union(lc, bound, nreg0, key, par));
-            WS_TRY(wsk::launch_wf_compress(lc, bound, nreg0, par, rl, ml + (size_t)(k - 1) * arena));
+            WS_TRY(wsk::launch_wf_union(lc, bound, b.nreg0, b.key, b.par));
+            WS_TRY(wsk::launch_wf_compress(lc, bound, b.nreg0, b.par, b.rlist, b.mlab + (size_t)(k - 1) * arena));
         }
-        cimg = ci;
-        mlab = ml;
     }
-    WS_TRY(wsk::launch_wf_out(lc, src_ch, nchunks, NL, cimg, nreg0, ids.coff, mlab, (int64_t)arena, ccnt));
+    WS_TRY(wsk::launch_wf_out(lc, src_ch, nchunks, NL, b.cimg, b.nreg0, b.ids.coff, b.mlab, (int64_t)arena, b.cnt));
     if (outs_dev || one_out)
-        WS_TRY(wsk::launch_img_counts(lc, tab_dev, one, nimg, NL, nchunks, ccnt, outs_dev, one_out));
+        WS_TRY(wsk::launch_img_counts(lc, tab_dev, one, nimg, NL, nchunks, b.cnt, outs_dev, one_out));
     return WS_OK;
 }
 
@@ -437,7 +460,7 @@ int ws_create(ws_ctx **out, int device) {
 void ws_destroy(ws_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    Buf *bufs[] = {&c->D,     &c->stamp, &c->cnt,  &c->rec, &c->key, &c->par,    &c->cimg,    &c->rlist, &c->mlab,
+    Buf *bufs[] = {&c->rimg,  &c->D,     &c->stamp, &c->cnt,  &c->rec, &c->key, &c->par,    &c->cimg,    &c->rlist, &c->mlab,
                    &c->edges, &c->ecnt,  &c->wfcnt, &c->g0, &c->g1,  &c->mag,    &c->gmax,    &c->chunks,
                    &c->tilecnt, &c->tab};
     for (Buf *b : bufs)
@@ -629,6 +652,48 @@ int ws_waterfall(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, 
         return run_waterfall(c, lc, src, src, wsk::wf_chunks(g.n), full_grid(wsk::wf_tiles(g, ndim)), ndim, conn,
                              dtype == WS_U16, NL, (size_t)g.n, nullptr, src.im, 1, nullptr, nregions);
     });
+}
+
+int ws_waterfall_recon(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, int64_t nx, int64_t ny,
+                       int64_t nz, int conn, int NL, int32_t *out, int64_t *nregions, void *stream) {
+    int rc = ws_validate_ws(c, grad, dtype, nx, ny, nz, conn, out, "ws_waterfall_recon");
+    if (rc) return rc;
+    if (!labels) return fail(c, WS_EINVAL, "ws_waterfall_recon: NULL labels");
+    if (NL < 1) return fail(c, WS_EINVAL, "ws_waterfall_recon: NL must be >= 1");
+    if ((rc = set_device(c))) return rc;
+    const int ndim = nz > 1 ? 3 : 2;
+    Launch lc = make_launch(c, stream);
+    const Geom g = make_geom(nx, ny, nz, ndim);
+    const size_t N = (size_t)g.n;
+    const int32_t nchunks = wsk::wf_chunks(g.n), bound = g.n;
+    const wsk::TileGrid tgw = full_grid(wsk::wf_tiles(g, ndim)), tgs = full_grid(g.ntx * g.nty * g.ntz);
+    WfBufs b;
+    if ((rc = wf_buffers(c, N, tgw.ntiles, nchunks, conn, 1, NL >= 2, b)) != WS_OK) return rc;
+    if ((rc = ensure(c, c->rimg, N * 2, "raised image")) != WS_OK) return rc;
+    uint16_t *I = (uint16_t *)c->rimg.p;
+    if (labels != out) {
+        hipError_t e = hipMemcpyAsync(out, labels, N * 4, hipMemcpyDeviceToDevice, lc.stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+    }
+    WS_TRY(wsk::launch_grey_u16(lc, grad, dtype == WS_U16, I, g.n));
+    for (int k = 0; k < NL; ++k) {
+        wsk::OneImg src{single_img(nx, ny, nz, I, out + (size_t)k * N)};
+        // region ids and the layer's region count
+        WS_TRY(wsk::launch_wf_ids(lc, src, nchunks, bound, b.ids, b.scan_tmp, b.nreg0, k + 1 < NL ? b.key : nullptr,
+                                  b.par));
+        if (nregions) {
+            WS_TRY(wsk::launch_wf_out(lc, src, nchunks, 1, nullptr, b.nreg0, b.ids.coff, nullptr, 0, b.cnt));
+            WS_TRY(wsk::launch_img_counts(lc, nullptr, src.im, 1, 1, nchunks, b.cnt, nullptr, nregions + k));
+        }
+        if (k + 1 == NL) break;
+        // Step V (lowest boundary pass of every region, the keys' heights) on
+        // the current image, Step VI (raise), then the watershed again
+        WS_TRY(wsk::launch_wf_pix(lc, src, tgw, conn, true, b.ids, b.nreg0, b.cimg, b.rlist, b.key, b.edges, b.ecnt));
+        WS_TRY(wsk::launch_recon_raise(lc, I, b.cimg, b.key, b.nreg0, g.n));
+        wsk::OneImg next{single_img(nx, ny, nz, I, out + (size_t)(k + 1) * N)};
+        if ((rc = run_watershed(c, lc, next, tgs, ndim, conn, true, N)) != WS_OK) return rc;
+    }
+    return WS_OK;
 }
 
 int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, int NL, void *stream) {

@@ -663,15 +663,52 @@ __global__ __launch_bounds__(NTHREADS) void k_img_counts(const Img *__restrict__
     if (threadIdx.x == 0 && dst) dst[k] = total;
 }
 
-// ---------------------------------------------------------------------------
-// Host side
-// ---------------------------------------------------------------------------
 static inline dim3 list_grid(int32_t n) {
     int32_t b = (n + NTHREADS - 1) / NTHREADS;
     if (b > 8192) b = 8192;
     if (b < 1) b = 1;
     return dim3(b);
 }
+
+// ---------------------------------------------------------------------------
+// Reconstruction waterfall (Alg. 4 Steps V-VI before each re-run of the
+// watershed, Alg. 5). The raised image is kept as uint16.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_grey_u16(const T *__restrict__ in, uint16_t *__restrict__ out, int32_t n) {
+    for (int32_t p = blockIdx.x * NTHREADS + threadIdx.x; p < n; p += gridDim.x * NTHREADS) out[p] = (uint16_t)in[p];
+}
+
+// Step VI: I(p) = max(I(p), newmin(region of p)), where newmin is the height
+// part of the region's key (Step V's lowest boundary pass) and M = 65535 for
+// a region without boundary.
+__global__ __launch_bounds__(NTHREADS) void k_recon_raise(uint16_t *__restrict__ I, const int32_t *__restrict__ cimg,
+                                                          const uint64_t *__restrict__ key,
+                                                          const int32_t *__restrict__ nreg0, int32_t n) {
+    const int32_t nr = *nreg0;
+    const uint32_t cmax = nr > 0 ? (uint32_t)(nr - 1) : 0u;
+    for (int32_t p = blockIdx.x * NTHREADS + threadIdx.x; p < n; p += gridDim.x * NTHREADS) {
+        uint32_t c = (uint32_t)cimg[p];
+        c = c <= cmax ? c : cmax;
+        uint64_t kk = key[c];
+        uint32_t m = kk == NOKEY ? 65535u : (uint32_t)(kk >> 32);
+        if (I[p] < m) I[p] = (uint16_t)m;
+    }
+}
+
+int launch_grey_u16(Launch &lc, const void *in, bool u16, uint16_t *out, int32_t n) {
+    dim3 grid = list_grid(n);
+    return u16 ? lc.run("recon", k_grey_u16<uint16_t>, grid, dim3(NTHREADS), (const uint16_t *)in, out, n)
+               : lc.run("recon", k_grey_u16<uint8_t>, grid, dim3(NTHREADS), (const uint8_t *)in, out, n);
+}
+int launch_recon_raise(Launch &lc, uint16_t *I, const int32_t *cimg, const uint64_t *key, const int32_t *nreg0,
+                       int32_t n) {
+    return lc.run("recon", k_recon_raise, list_grid(n), dim3(NTHREADS), I, cimg, key, nreg0, n);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
 
 int wf_tiles(const Geom &g, int ndim) {
     if (ndim == 3)

@@ -121,6 +121,9 @@ int launch_scan(Launch &lc, int32_t n, int32_t *data, int32_t *tmp, int32_t *tot
 int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, int32_t cap, const int32_t *par, uint64_t *key,
                     int32_t *edges, int32_t *ecnt);
 int launch_wf_union(Launch &lc, int32_t bound, const int32_t *nreg0, uint64_t *key, int32_t *par);
+int launch_grey_u16(Launch &lc, const void *in, bool u16, uint16_t *out, int32_t n);
+int launch_recon_raise(Launch &lc, uint16_t *I, const int32_t *cimg, const uint64_t *key, const int32_t *nreg0,
+                       int32_t n);
 int launch_wf_compress(Launch &lc, int32_t bound, const int32_t *nreg0, int32_t *par, const int32_t *rlist,
                        int32_t *mlab_k);
 int launch_img_counts(Launch &lc, const Img *tab, const Img &one, int32_t nimg, int32_t nl, int32_t ntiles_total,

@@ -422,3 +422,48 @@ def test_graph_replay_matches_direct():
     finally:
         gctx.close()
         dctx.close()
+
+
+def check_recon(ctx, grad, conn, NL):
+    import torch
+    say("  recon", grad.shape, grad.dtype, "conn", conn, "NL", NL)
+    ref, nref = oracle.waterfall_recon(grad, conn, NL)
+    g = to_dev(grad)
+    lab = ctx.watershed(g, conn)
+    out, n = ctx.waterfall_recon(lab, g, conn, NL)
+    got = to_host(out)
+    for k in range(NL):
+        if not np.array_equal(got[k], ref[k]):
+            bad = np.argwhere(got[k] != ref[k])
+            raise AssertionError("recon layer %d differs at %d pixels, first %s" % (k, len(bad), bad[0].tolist()))
+    assert np.array_equal(to_host(n), nref)
+    torch.cuda.synchronize()
+
+
+def test_recon_fixture(ctx):
+    # the 1x8 row where the reconstruction splits old region 4 (not nested)
+    row = np.array([[0, 4, 0, 2, 9, 1, 6, 3]], np.uint8)
+    import torch
+    g = to_dev(row)
+    lab = ctx.watershed(g, 4)
+    out, n = ctx.waterfall_recon(lab, g, 4, 3)
+    got = to_host(out)
+    assert got[0].tolist() == [[0, 1, 1, 1, 4, 4, 4, 7]]
+    assert got[1].tolist() == [[0, 0, 0, 0, 0, 5, 5, 5]]
+    check_recon(ctx, row, 4, 3)
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_recon_blobs_2d(ctx, conn):
+    img = gen.blobs2d(200, 230, seed=11)
+    check_recon(ctx, oracle.gradient(img, 0.0, "u8"), conn, 5)
+    check_recon(ctx, oracle.gradient(gen.ellipses2d(160, 170, seed=3, n_ellipses=40), 1.0, "u16"), conn, 4)
+
+
+def test_recon_random_and_3d(ctx):
+    rng = np.random.default_rng(12)
+    check_recon(ctx, rng.integers(0, 6, size=(90, 110)).astype(np.uint8), 8, 6)
+    vol = oracle.gradient(gen.blobs3d(40, 44, 48, seed=4, n_blobs=12), 0.0, "u8")
+    check_recon(ctx, vol, 6, 4)
+    check_recon(ctx, vol, 26, 4)
+    check_recon(ctx, np.full((33, 40), 7, np.uint8), 4, 3)
