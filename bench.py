@@ -186,7 +186,8 @@ def bench_serve(args):
     """Poisson arrivals (rates swept) of mixed jobs: 70 % square 2D u8 images
     (sides 512-4096, 8-connectivity), 30 % cubic 3D u8 volumes (sides 128-512,
     6-connectivity), NL = 4, through the continuous-batching server with
-    device-memory admission. Latency = arrival -> labels ready on the device."""
+    device-memory admission. Latency = arrival -> labels ready on the device;
+    the client then releases each result (a consumer that hands labels on)."""
     import numpy as np
     import torch
 
@@ -206,13 +207,17 @@ def bench_serve(args):
         del f
     torch.cuda.synchronize()
     print("bench: pool ready (%d 2D, %d 3D)" % (len(pool2), len(pool3)), file=sys.stderr, flush=True)
+    def release(j):
+        # the client hands each result on once its labels are ready
+        j.out = j.nregions = None
+
     results = []
     for rate in [float(r) for r in args.rates.split(",")]:
         rng = np.random.default_rng(4)
         gaps = rng.exponential(1.0 / rate, size=args.requests)
         picks = rng.random(args.requests)
         idx = rng.integers(0, 1 << 30, size=args.requests)
-        srv = serve.Server(slots=args.slots)
+        srv = serve.Server(slots=args.slots, max_job_pixels=max(int(g.numel()) for g, _ in pool2 + pool3))
         jobs = []
         t0 = time.perf_counter()
         t_next = t0
@@ -221,7 +226,7 @@ def bench_serve(args):
             while time.perf_counter() < t_next:
                 time.sleep(max(0.0, min(0.001, t_next - time.perf_counter())))
             g, conn = (pool2[idx[k] % len(pool2)] if picks[k] < 0.7 else pool3[idx[k] % len(pool3)])
-            jobs.append(srv.submit(serve.Job(grad=g, conn=conn, NL=NL, jid=k)))
+            jobs.append(srv.submit(serve.Job(grad=g, conn=conn, NL=NL, jid=k, on_done=release)))
         srv.drain()
         t_end = max(j.t_done for j in jobs)
         lat = [1e3 * (j.t_done - j.t_arrival) for j in jobs if j.error is None]

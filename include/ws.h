@@ -171,6 +171,25 @@ int ws_waterfall_recon(ws_ctx *ctx, const int32_t *labels, const void *grad, int
                        int64_t *nregions_or_null, void *stream);
 
 /*
+ * Region adjacency graph of one labelling (the graph the waterfall's layers
+ * are built on, Section 4): every pair of regions a < b (canonical labels)
+ * that share a boundary, with h = min over pixel pairs (p in a, q in N(p) in
+ * b) of max(I(p), I(q)), the pair's lowest pass.
+ *   labels    int32[N] canonical labels (the watershed's, or any layer of
+ *             ws_waterfall / ws_waterfall_recon); read only.
+ *   grad, dtype, sizes, conn: as for ws_waterfall.
+ *   capacity  entries the three edge buffers hold (may be 0).
+ *   edge_a, edge_b, edge_h  int32[capacity] device outputs: the edges sorted
+ *             by (a, b); the first min(count, capacity) are written.
+ *   n_edges   int64 device output (may be NULL): the number of edges (count).
+ * Waits on `stream` once (to size its sort buffers). A call with capacity 0
+ * returns the count only, so a caller can size the buffers and call again.
+ */
+int ws_rag(ws_ctx *ctx, const int32_t *labels, const void *grad, int dtype, int64_t nx, int64_t ny,
+           int64_t nz, int conn, int64_t capacity, int32_t *edge_a, int32_t *edge_b, int32_t *edge_h,
+           int64_t *n_edges, void *stream);
+
+/*
  * Watershed + NL-layer waterfall of many images of uneven sizes in one set of
  * launches (every kernel covers the tiles of all images through a tile ->
  * image table; the Step II convergence loop is shared). The result of every
@@ -216,10 +235,15 @@ int ws_watershed_stages(ws_ctx *ctx, const void *grad, int dtype, int64_t nx, in
  *                  Buffers are read when the graph runs, so their contents
  *                  may change between calls. Any scratch reallocation drops
  *                  the graphs. Ignored while "timing" is on. Default 0.
- *   "reserve_pixels"  allocate now the scratch of calls covering up to this
- *                  many pixels (any 2D/3D mix, conn 4/6/8, NL <= 8), so later calls do
- *                  not allocate (allocation waits for the whole device);
- *                  may return WS_ENOMEM.
+ *   "reserve_pixels"  allocate now the scratch (device buffers, batch tables
+ *                  and the pinned staging) of calls covering up to this many
+ *                  pixels, so later calls do not allocate (allocation waits
+ *                  for the whole device): any 2D/3D mix, conn 4/6/8, NL <= 8,
+ *                  up to 1024 images per ws_batch call, each image either
+ *                  smaller than one tile or with sides of at least about 300
+ *                  (2D) / 100 (3D) pixels (thinner images need more partial
+ *                  tiles and may still grow the scratch); out[5] of
+ *                  ws_get_stats counts the allocations. May return WS_ENOMEM.
  * Returns WS_EINVAL for an unknown name or out-of-range value.
  */
 int ws_set_option(ws_ctx *ctx, const char *name, int64_t value);
@@ -227,8 +251,9 @@ int ws_set_option(ws_ctx *ctx, const char *name, int64_t value);
 /*
  * Counters of the last ws_watershed call: out[0] Step II sweeps launched
  * (including the initial tile pass), out[1] sweeps that changed a tile
- * border, out[2] Step III synchronisations (step3 = 1), out[3] tiles; and
- * out[4] the launch graphs replayed by this context so far ("graph" option).
+ * border, out[2] Step III synchronisations (step3 = 1), out[3] tiles;
+ * out[4] the launch graphs replayed by this context so far ("graph" option);
+ * out[5] the device and pinned host allocations this context has made.
  * Returns the number of counters written (<= n).
  */
 int ws_get_stats(const ws_ctx *ctx, int64_t *out, int n);

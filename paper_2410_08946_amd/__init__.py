@@ -11,6 +11,7 @@ Functions named like the C entry points take and return torch tensors:
   ws_waterfall(labels, grad, conn, NL)             -> (int32 [NL, ...], int64 [NL])
   ws_waterfall_recon(labels, grad, conn, NL)       -> (int32 [NL, ...], int64 [NL]), Alg. 4 + 5
   ws_watershed_stages(grad, conn)                  -> (balanced states, arrows)
+  ws_rag(labels, grad, conn)                       -> (a, b, h) region adjacency graph, sorted by (a, b)
   ws_batch([grad, ...], conn, NL)                  -> ([int32 [NL, ...]], [int64 [NL]])
 Image tensors are C-contiguous (nx,), (ny, nx) or (nz, ny, nx) with x fastest.
 """
@@ -26,6 +27,7 @@ from .binding import (  # noqa: F401
     ws_watershed,
     ws_waterfall,
     ws_waterfall_recon,
+    ws_rag,
     ws_watershed_stages,
     ws_batch,
     WS_U8,

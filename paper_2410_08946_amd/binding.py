@@ -32,6 +32,7 @@ SIGNATURES = {
     "ws_watershed": (_int, [_ptr, _ptr, _int, _i64, _i64, _i64, _int, _ptr, _ptr]),
     "ws_waterfall": (_int, [_ptr, _ptr, _ptr, _int, _i64, _i64, _i64, _int, _int, _ptr, _ptr, _ptr]),
     "ws_waterfall_recon": (_int, [_ptr, _ptr, _ptr, _int, _i64, _i64, _i64, _int, _int, _ptr, _ptr, _ptr]),
+    "ws_rag": (_int, [_ptr, _ptr, _ptr, _int, _i64, _i64, _i64, _int, _i64, _ptr, _ptr, _ptr, _ptr, _ptr]),
     "ws_watershed_stages": (_int, [_ptr, _ptr, _int, _i64, _i64, _i64, _int, _ptr, _ptr, _ptr]),
     "ws_batch": (_int, [_ptr, ctypes.POINTER(WsItem), _int, _int, _int, _int, _ptr]),
     "ws_set_option": (_int, [_ptr, ctypes.c_char_p, _i64]),
@@ -134,9 +135,9 @@ class Context:
         self._check(self._lib.ws_set_option(self._h, name.encode(), int(value)))
 
     def stats(self):
-        out = (ctypes.c_int64 * 5)()
-        n = self._lib.ws_get_stats(self._h, out, 5)
-        keys = ("sweeps_launched", "sweeps_changing", "step3_syncs", "tiles", "graph_replays")
+        out = (ctypes.c_int64 * 6)()
+        n = self._lib.ws_get_stats(self._h, out, 6)
+        keys = ("sweeps_launched", "sweeps_changing", "step3_syncs", "tiles", "graph_replays", "allocations")
         return {k: int(out[i]) for i, k in enumerate(keys[:n])}
 
     def timing_reset(self):
@@ -231,6 +232,23 @@ class Context:
                                            _dev(nregions, "nregions"), _stream(grad)))
         return out, nregions
 
+    def rag(self, labels, grad, conn: int):
+        """Region adjacency graph of `labels` (ws_rag): int32 tensors (a, b, h),
+        a < b canonical labels of adjacent regions, h their lowest pass, sorted
+        by (a, b). Two calls: the first returns the edge count only."""
+        import torch
+        nx, ny, nz = _dims(grad.shape)
+        if labels.shape != grad.shape or labels.dtype != torch.int32:
+            raise ValueError("labels must be int32 with the gradient's shape")
+        n = torch.zeros(1, dtype=torch.int64, device=grad.device)
+        args = (_dev(labels, "labels"), _dev(grad, "gradient"), _grey_code(grad), nx, ny, nz, int(conn))
+        self._check(self._lib.ws_rag(self._h, *args, 0, None, None, None, _dev(n, "n_edges"), _stream(grad)))
+        cnt = int(n.item())
+        a, b, h = (torch.empty(max(cnt, 1), dtype=torch.int32, device=grad.device) for _ in range(3))
+        self._check(self._lib.ws_rag(self._h, *args, cnt, _dev(a, "a"), _dev(b, "b"), _dev(h, "h"),
+                                     _dev(n, "n_edges"), _stream(grad)))
+        return a[:cnt], b[:cnt], h[:cnt]
+
     def waterfall_recon(self, labels, grad, conn: int, NL: int, out=None, nregions=None):
         """Reconstruction waterfall (ws_waterfall_recon): same arguments as waterfall."""
         import torch
@@ -270,6 +288,10 @@ def ws_waterfall(labels, grad, conn, NL, out=None, nregions=None):
 
 def ws_waterfall_recon(labels, grad, conn, NL, out=None, nregions=None):
     return default_context(grad.device.index or 0).waterfall_recon(labels, grad, conn, NL, out=out, nregions=nregions)
+
+
+def ws_rag(labels, grad, conn):
+    return default_context(grad.device.index or 0).rag(labels, grad, conn)
 
 
 def ws_batch(grads, conn, NL, outs=None, nregions=None):

@@ -39,6 +39,7 @@ struct ws_ctx {
     Buf D, stamp, cnt, rec;               // watershed scratch
     Buf key, par, cimg, rlist, mlab;      // waterfall: region tables (dense by id), per-pixel region ids
     Buf rimg;                             // reconstruction waterfall: the raised image (uint16)
+    Buf ragoff, ragbuf;                   // adjacency graph export: edge offsets, sort buffers
     Buf edges, ecnt, wfcnt;               // edge slabs, their counts, region count
     Buf g0, g1, mag, gmax;                // gradient scratch
     Buf chunks, tilecnt;                  // region-id rank tables + scan scratch, per-tile counts
@@ -67,7 +68,7 @@ struct ws_ctx {
     std::map<std::string, uint64_t> seen;
     uint64_t tick = 0;
     wsk::TimingSink sink;
-    int64_t stats[5] = {0, 0, 0, 0, 0};
+    int64_t stats[6] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -97,12 +98,36 @@ int ensure(ws_ctx *c, Buf &b, size_t bytes, const char *what) {
         if (e != hipSuccess) return hip_fail(c, e, "hipFree");
     }
     hipError_t e = hipMalloc(&b.p, bytes);
+    ++c->stats[5];
     if (e != hipSuccess) {
         (void)hipGetLastError();
         b.p = nullptr;
         return fail(c, WS_ENOMEM, std::string("cannot allocate ") + std::to_string(bytes) + " bytes for " + what);
     }
     b.n = bytes;
+    return WS_OK;
+}
+
+// Pinned host staging of at least `bytes` for the batch tables. A previous
+// batch's copy out of it must have finished before it is rewritten or freed.
+int ensure_stage(ws_ctx *c, size_t bytes) {
+    if (c->stage_pending) {
+        hipError_t e = hipEventSynchronize(c->stage_ev);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+        c->stage_pending = false;
+    }
+    if (!c->stage_ev) {
+        hipError_t e = hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+    }
+    if (c->stage_n >= bytes) return WS_OK;
+    if (c->stage) (void)hipHostFree(c->stage);
+    c->stage = nullptr;
+    c->stage_n = 0;
+    hipError_t e = hipHostMalloc(&c->stage, bytes, hipHostMallocDefault);
+    ++c->stats[5];
+    if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc");
+    c->stage_n = bytes;
     return WS_OK;
 }
 
@@ -389,9 +414,12 @@ int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const Src &src_ch, int3
 }
 
 // Pre-allocates the scratch of calls covering up to n pixels (any mix of 2D
-// and 3D images, NL <= 16), so that later calls allocate nothing.
+// and 3D images, NL <= 8, batches of up to kReserveItems images), so that later
+// calls allocate nothing.
+constexpr int64_t kReserveItems = 1024;
 int reserve(ws_ctx *c, int64_t n) {
-    size_t N = (size_t)n;
+    // a batch starts every image on a 64-pixel boundary: room for that padding
+    size_t N = (size_t)n + 64 * (size_t)kReserveItems;
     size_t tiles = N / 256 + 1024;         // partial tiles of many small images
     size_t wft = N / 1024 + N / 4096 + 1024;  // waterfall tiles of such a mix
     constexpr int kLayers = 8;             // layer tables for NL <= 8
@@ -406,9 +434,14 @@ int reserve(ws_ctx *c, int64_t n) {
     if ((rc = ensure(c, c->stamp, tiles * 4, "reserved stamps")) != WS_OK) return rc;
     if ((rc = ensure(c, c->rec, tiles * (size_t)wsk::border_cells(3) * 4, "reserved records")) != WS_OK) return rc;
     if ((rc = ensure(c, c->tilecnt, tiles * 16 * 4, "reserved tile counts")) != WS_OK) return rc;
-    int32_t nch = (int32_t)std::min<int64_t>(n / 4096 + 4096, 0x7fffffff / 2);
+    int32_t nch = (int32_t)std::min<int64_t>((int64_t)N / 4096 + 2 * kReserveItems, 0x7fffffff / 2);
     size_t tbl = (((size_t)nch + wsk::scan_tmp_len(nch)) * 4 + 15) / 16 * 16 + (size_t)nch * 64 * sizeof(wsk::RankWord);
     if ((rc = ensure(c, c->chunks, tbl, "reserved region-id tables")) != WS_OK) return rc;
+    // batch tables (device and pinned staging), laid out as ws_batch does
+    size_t bt = sizeof(wsk::Img) * (size_t)kReserveItems + 4 * (tiles + wft + (size_t)nch) +
+                sizeof(int64_t *) * (size_t)kReserveItems + 4 * 256;
+    if ((rc = ensure(c, c->tab, bt, "reserved batch tables")) != WS_OK) return rc;
+    if ((rc = ensure_stage(c, bt)) != WS_OK) return rc;
     if ((rc = ensure(c, c->wfcnt, 16 * 4, "reserved counts")) != WS_OK) return rc;
     if ((rc = ensure(c, c->cnt, kCounterSlots * 4, "counters")) != WS_OK) return rc;
     return WS_OK;
@@ -460,7 +493,7 @@ int ws_create(ws_ctx **out, int device) {
 void ws_destroy(ws_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    Buf *bufs[] = {&c->rimg,  &c->D,     &c->stamp, &c->cnt,  &c->rec, &c->key, &c->par,    &c->cimg,    &c->rlist, &c->mlab,
+    Buf *bufs[] = {&c->ragoff, &c->ragbuf, &c->rimg,  &c->D,     &c->stamp, &c->cnt,  &c->rec, &c->key, &c->par,    &c->cimg,    &c->rlist, &c->mlab,
                    &c->edges, &c->ecnt,  &c->wfcnt, &c->g0, &c->g1,  &c->mag,    &c->gmax,    &c->chunks,
                    &c->tilecnt, &c->tab};
     for (Buf *b : bufs)
@@ -526,7 +559,7 @@ int ws_set_option(ws_ctx *c, const char *name, int64_t v) {
 
 int ws_get_stats(const ws_ctx *c, int64_t *out, int n) {
     if (!c || !out || n < 0) return WS_EINVAL;
-    int m = std::min(n, 5);
+    int m = std::min(n, 6);
     for (int i = 0; i < m; ++i) out[i] = c->stats[i];
     return m;
 }
@@ -696,6 +729,57 @@ int ws_waterfall_recon(ws_ctx *c, const int32_t *labels, const void *grad, int d
     return WS_OK;
 }
 
+int ws_rag(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz, int conn,
+           int64_t capacity, int32_t *edge_a, int32_t *edge_b, int32_t *edge_h, int64_t *n_edges, void *stream) {
+    int rc = ws_validate_ws(c, grad, dtype, nx, ny, nz, conn, labels, "ws_rag");
+    if (rc) return rc;
+    if (capacity < 0) return fail(c, WS_EINVAL, "ws_rag: capacity must be >= 0");
+    if (capacity > 0 && (!edge_a || !edge_b || !edge_h)) return fail(c, WS_EINVAL, "ws_rag: NULL edge buffer");
+    if ((rc = set_device(c))) return rc;
+    const int ndim = nz > 1 ? 3 : 2;
+    Launch lc = make_launch(c, stream);
+    const Geom g = make_geom(nx, ny, nz, ndim);
+    const size_t N = (size_t)g.n;
+    const int32_t nchunks = wsk::wf_chunks(g.n), bound = g.n;
+    const wsk::TileGrid tg = full_grid(wsk::wf_tiles(g, ndim));
+    WfBufs b;
+    if ((rc = wf_buffers(c, N, tg.ntiles, nchunks, conn, 1, true, b)) != WS_OK) return rc;
+    // the labels are read, never written (the pixel pass only reads its layer 0)
+    wsk::OneImg src{single_img(nx, ny, nz, grad, const_cast<int32_t *>(labels))};
+    WS_TRY(wsk::launch_wf_ids(lc, src, nchunks, bound, b.ids, b.scan_tmp, b.nreg0, b.key, b.par));
+    WS_TRY(wsk::launch_wf_pix(lc, src, tg, conn, dtype == WS_U16, b.ids, b.nreg0, b.cimg, b.rlist, b.key, b.edges,
+                              b.ecnt));
+    // offsets of the tiles' edges in one list, and their total (read back once)
+    const int32_t nt = tg.ntiles;
+    if ((rc = ensure(c, c->ragoff, ((size_t)nt + 1 + wsk::scan_tmp_len(nt)) * 4, "edge offsets")) != WS_OK) return rc;
+    int32_t *eoff = (int32_t *)c->ragoff.p, *etot = eoff + nt, *etmp = etot + 1;
+    hipError_t e = hipMemcpyAsync(eoff, b.ecnt, (size_t)nt * 4, hipMemcpyDeviceToDevice, lc.stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+    WS_TRY(wsk::launch_scan(lc, nt, eoff, etmp, etot));
+    if ((e = hipMemcpyAsync(c->host_cnt, etot, 4, hipMemcpyDeviceToHost, lc.stream)) != hipSuccess)
+        return hip_fail(c, e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(lc.stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    const int32_t total = c->host_cnt[0];
+    const size_t tmp_bytes = wsk::rag_sort_tmp_bytes(total > 0 ? total : 1);
+    const size_t M = (size_t)(total > 0 ? total : 1);
+    // [keys | keys2 | ukeys | h | h2 | uh | count | sort scratch]
+    size_t o_k2 = M * 8, o_uk = 2 * M * 8, o_h = 3 * M * 8, o_h2 = o_h + M * 4, o_uh = o_h2 + M * 4;
+    size_t o_cnt = (o_uh + M * 4 + 255) & ~(size_t)255, o_tmp = o_cnt + 256;
+    if ((rc = ensure(c, c->ragbuf, o_tmp + tmp_bytes, "adjacency sort buffers")) != WS_OK) return rc;
+    char *rb = (char *)c->ragbuf.p;
+    auto *keys = (unsigned long long *)rb, *keys2 = (unsigned long long *)(rb + o_k2),
+         *ukeys = (unsigned long long *)(rb + o_uk);
+    auto *h = (int32_t *)(rb + o_h), *h2 = (int32_t *)(rb + o_h2), *uh = (int32_t *)(rb + o_uh);
+    auto *ucount = (unsigned int *)(rb + o_cnt);
+    WS_TRY(wsk::launch_fill_i32(lc, (int32_t *)ucount, 1, 0));
+    if (total > 0) {
+        WS_TRY(wsk::launch_rag_gather(lc, nt, wsk::wf_slab_cap(conn), b.edges, b.ecnt, eoff, keys, h));
+        WS_TRY(wsk::rag_sort_reduce(lc, total, keys, h, keys2, h2, ukeys, uh, ucount, rb + o_tmp, tmp_bytes));
+    }
+    WS_TRY(wsk::launch_rag_final(lc, ukeys, uh, ucount, b.rlist, capacity, edge_a, edge_b, edge_h, n_edges));
+    return WS_OK;
+}
+
 int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, int NL, void *stream) {
     if (!c) return fail(c, WS_EINVAL, "ws_batch: ctx is NULL");
     if (!items || n_items < 1) return fail(c, WS_EINVAL, "ws_batch: no items");
@@ -728,23 +812,7 @@ int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, 
     size_t off_ch = (off_wf + 4 * (size_t)twf + 255) & ~(size_t)255;
     size_t off_outs = (off_ch + 4 * (size_t)tch + 255) & ~(size_t)255;
     size_t total = off_outs + sizeof(int64_t *) * (size_t)n_items;
-    if (c->stage_pending) {
-        hipError_t e = hipEventSynchronize(c->stage_ev);
-        if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
-        c->stage_pending = false;
-    }
-    if (c->stage_n < total) {
-        if (c->stage) (void)hipHostFree(c->stage);
-        c->stage = nullptr;
-        c->stage_n = 0;
-        hipError_t e = hipHostMalloc(&c->stage, total, hipHostMallocDefault);
-        if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc");
-        c->stage_n = total;
-    }
-    if (!c->stage_ev) {
-        hipError_t e = hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming);
-        if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
-    }
+    if ((rc = ensure_stage(c, total)) != WS_OK) return rc;
     if ((rc = ensure(c, c->tab, total, "batch tables")) != WS_OK) return rc;
     char *h = (char *)c->stage;
     wsk::Img *tab = (wsk::Img *)h;

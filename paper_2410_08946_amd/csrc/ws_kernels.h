@@ -129,6 +129,16 @@ int launch_wf_compress(Launch &lc, int32_t bound, const int32_t *nreg0, int32_t 
 int launch_img_counts(Launch &lc, const Img *tab, const Img &one, int32_t nimg, int32_t nl, int32_t ntiles_total,
                       const int32_t *tile_cnt, int64_t *const *outs, int64_t *one_out);
 
+// rag.hip
+int launch_rag_gather(Launch &lc, int32_t ntiles, int32_t cap, const int32_t *edges, const int32_t *ecnt,
+                      const int32_t *eoff, unsigned long long *keys, int32_t *h);
+size_t rag_sort_tmp_bytes(int32_t n);
+int rag_sort_reduce(Launch &lc, int32_t n, unsigned long long *keys, int32_t *h, unsigned long long *keys2,
+                    int32_t *h2, unsigned long long *ukeys, int32_t *uh, unsigned int *ucount, void *tmp,
+                    size_t tmp_bytes);
+int launch_rag_final(Launch &lc, const unsigned long long *ukeys, const int32_t *uh, const unsigned int *ucount,
+                     const int32_t *rlist, int64_t cap, int32_t *a, int32_t *b, int32_t *hh, int64_t *n_edges);
+
 // gradient.hip
 constexpr int FUSED_MAX_R = 16;   // largest blur radius of the fused 2D kernel
 int grad_parts(const Geom &g, int ndim, int r);   // partial maxima the magnitude kernels write

@@ -10,6 +10,14 @@ Jobs that arrive while others are on the GPU wait for the next free slot and
 join the next micro-batch. A job whose footprint alone exceeds the budget is
 rejected without affecting any other job.
 
+Every slot reserves the scratch of a max_batch_pixels batch up front, so
+serving allocates no library scratch (device allocation and freeing wait for
+the whole device). A micro-batch can exceed that only through one job larger
+than the cap; such jobs run alone on slot 0, which also reserves
+max_job_pixels when that is given, so the other slots never reallocate. While
+an oversized job waits for slot 0, the other slots take the ordinary jobs
+queued behind it.
+
 All arithmetic is in the library (ws_batch); this module only schedules. The
 result of a job is bit-identical to running it alone: the batched kernels
 never mix images (see include/ws.h, ws_batch).
@@ -19,8 +27,9 @@ from __future__ import annotations
 import collections
 import threading
 import time
+import traceback
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import Callable, List, Optional
 
 from .binding import Context, WSError, load_library, _dims
 
@@ -40,6 +49,7 @@ class Job:
     slot: int = -1
     footprint: int = 0
     done: threading.Event = field(default_factory=threading.Event)
+    on_done: Optional[Callable[["Job"], None]] = None  # called by the slot's thread once the labels are ready
 
 
 def job_footprint(job: Job) -> int:
@@ -53,7 +63,8 @@ class Server:
     """K execution slots, micro-batches of queued jobs, footprint admission."""
 
     def __init__(self, slots: int = 4, budget_bytes: Optional[int] = None, max_batch_jobs: int = 64,
-                 max_batch_pixels: int = 1 << 26, device: int = 0):
+                 max_batch_pixels: int = 1 << 26, max_job_pixels: Optional[int] = None, device: int = 0,
+                 warm_layers: int = 4):
         import torch
         self.device = torch.device("cuda", device)
         if budget_bytes is None:
@@ -73,8 +84,19 @@ class Server:
         self.slots = []
         for k in range(slots):
             ctx = Context(device)
-            ctx.set_option("reserve_pixels", self.max_batch_pixels)
+            reserve = self.max_batch_pixels
+            if k == 0 and max_job_pixels:
+                reserve = max(reserve, int(max_job_pixels))
+            ctx.set_option("reserve_pixels", min(reserve, (1 << 31) - 1))
             stream = torch.cuda.Stream(device=self.device)  # default priority
+            if warm_layers > 0:
+                # the outputs are torch tensors allocated on the slot's stream:
+                # leave a block of warm_layers int32 layers of the reserve in
+                # that stream's cache, so outputs are carved from it rather than
+                # allocated (allocation stalls every slot)
+                with torch.cuda.stream(stream):
+                    warm = torch.empty(int(warm_layers) * reserve, dtype=torch.int32, device=self.device)
+                    del warm
             slot = {"k": k, "ctx": ctx, "stream": stream, "work": None, "cv": threading.Condition()}
             slot["thread"] = threading.Thread(target=self._worker, args=(slot,), daemon=True)
             self.slots.append(slot)
@@ -122,13 +144,22 @@ class Server:
             s["ctx"].close()
 
     # -- scheduling ---------------------------------------------------------
-    def _take_batch(self):
-        """Under the lock: the longest prefix-compatible micro-batch that fits."""
-        head = self.queue[0]
+    def _oversized(self, job: Job) -> bool:
+        return int(job.grad.numel()) > self.max_batch_pixels
+
+    def _take_batch(self, allow_big: bool):
+        """Under the lock: the longest compatible micro-batch that fits, led by
+        the oldest queued job (the oldest ordinary one unless allow_big)."""
         batch, pix, foot = [], 0, 0
+        head = None
         rest = collections.deque()
         while self.queue and len(batch) < self.max_batch_jobs:
             j = self.queue.popleft()
+            if not allow_big and self._oversized(j):
+                rest.append(j)
+                continue
+            if head is None:
+                head = j
             n = int(j.grad.numel())
             same = (j.conn == head.conn and j.NL == head.NL and j.grad.dtype == head.grad.dtype
                     and (j.grad.dim() == 3) == (head.grad.dim() == 3))
@@ -145,6 +176,20 @@ class Server:
             self.queue.appendleft(rest.pop())
         return batch, foot
 
+    def _pick_slot(self):
+        """Under the lock: (slot, allow_big) for the next micro-batch, or None.
+        Oversized jobs run on slot 0 only; ordinary batches prefer the other
+        slots, so an oversized job at the head of the queue delays no one."""
+        zero = self.slots[0]
+        if zero["work"] is None and self._oversized(self.queue[0]):
+            return zero, True
+        for s in self.slots[1:]:
+            if s["work"] is None:
+                return s, False
+        if zero["work"] is None:
+            return zero, True
+        return None
+
     def _dispatch(self):
         while True:
             with self.lock:
@@ -152,11 +197,14 @@ class Server:
                     self.lock.wait(0.05)
                 if not self.running:
                     return
-                slot = next(s for s in self.slots if s["work"] is None)
-                batch, foot = self._take_batch()
+                pick = self._pick_slot()
+                batch, foot = self._take_batch(pick[1]) if pick else ([], 0)
                 if not batch:
-                    self.lock.wait(0.001)  # memory is busy: wait for a completion
+                    # only oversized jobs wait for slot 0, or memory is busy:
+                    # every completion and submission notifies
+                    self.lock.wait(0.05)
                     continue
+                slot = pick[0]
                 self.in_use += foot
                 self._busy += 1
                 self.max_concurrent = max(self.max_concurrent, self._busy)
@@ -179,6 +227,7 @@ class Server:
                 if slot["work"] is None:
                     return
                 batch, foot = slot["work"]
+            outs = nregs = None
             try:
                 with torch.cuda.stream(stream):
                     grads = [j.grad for j in batch]
@@ -194,6 +243,13 @@ class Server:
                 t = time.perf_counter()
                 for j in batch:
                     j.error, j.t_done = str(e), t
+            outs = nregs = None  # the jobs hold the results now
+            for j in batch:
+                if j.on_done is not None:
+                    try:
+                        j.on_done(j)
+                    except Exception:  # a client's callback must not stop the slot
+                        traceback.print_exc()
             with self.lock:
                 self.in_use -= foot
                 self._busy -= 1

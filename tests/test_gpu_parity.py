@@ -12,6 +12,7 @@ import pytest
 
 import gen
 import oracle
+from tests import brute
 
 pytestmark = pytest.mark.gpu
 
@@ -380,6 +381,57 @@ def test_serving_mix_identity(ctx):
     assert np.array_equal(to_host(small.out), solo[0][0])
 
 
+def test_reserve_covers_padded_and_ragged_batches():
+    """reserve_pixels(n): later ws_batch calls of up to n pixels allocate
+    nothing, also when the images' 64-pixel alignment pads the batch past n
+    (a lone image of n - 5 pixels) and for a ragged mix of 2D and 3D batches;
+    the results equal those of a context that allocates as it goes."""
+    import torch
+
+    import paper_2410_08946_amd as ws
+    rng = np.random.default_rng(33)
+    n = 2053 * 2043 + 5  # the lone image pads to 2^22 > n
+    res, ref = ws.Context(0), ws.Context(0)
+    try:
+        res.set_option("reserve_pixels", n)
+        a0 = res.stats()["allocations"]
+        say("  reserved", n, "pixels with", a0, "allocations")
+        batches = [[(gen.blobs2d(2043, 2053, seed=61), 8)]]
+        sides = []
+        while sum(a * b for a, b in sides) < n - 400 * 400:
+            sides.append((int(rng.integers(300, 500)), int(rng.integers(300, 500))))
+        batches.append([(gen.blobs2d(a, b, seed=70 + k), 8) for k, (a, b) in enumerate(sides[:-1])])
+        vols, tot = [], 0
+        while True:
+            s = tuple(int(v) for v in rng.integers(100, 140, size=3))
+            if tot + s[0] * s[1] * s[2] > n:
+                break
+            tot += s[0] * s[1] * s[2]
+            vols.append(s)
+        batches.append([(rng.integers(0, 60, size=s).astype(np.uint8), 6) for s in vols])
+        for bi, items in enumerate(batches):
+            grads = []
+            for g, conn in items:
+                if g.dtype != np.uint8:
+                    g = oracle.gradient(g, 0.0, "u8")
+                grads.append(to_dev(g))
+            conn = items[0][1]
+            say("  batch", bi, "images", len(grads), "pixels", sum(int(g.numel()) for g in grads))
+            outs = [torch.empty((4,) + tuple(g.shape), dtype=torch.int32, device="cuda:0") for g in grads]
+            nregs = [torch.zeros(4, dtype=torch.int64, device="cuda:0") for _ in grads]
+            res.batch(grads, conn, 4, outs=outs, nregions=nregs)
+            torch.cuda.synchronize()
+            assert res.stats()["allocations"] == a0, "batch %d allocated" % bi
+            for k in (0, len(grads) - 1):
+                lab = ref.watershed(grads[k], conn)
+                o, nr = ref.waterfall(lab, grads[k], conn, 4)
+                assert np.array_equal(to_host(outs[k]), to_host(o))
+                assert to_host(nregs[k]).tolist() == to_host(nr).tolist()
+    finally:
+        res.close()
+        ref.close()
+
+
 def test_graph_replay_matches_direct():
     """Launch graphs (option "graph"): the same calls on the same buffers, with
     the buffers' contents changed between calls and eager work between the
@@ -467,3 +519,29 @@ def test_recon_random_and_3d(ctx):
     check_recon(ctx, vol, 6, 4)
     check_recon(ctx, vol, 26, 4)
     check_recon(ctx, np.full((33, 40), 7, np.uint8), 4, 3)
+
+
+def check_rag(ctx, labels, grad, conn):
+    import torch
+    say("  rag", labels.shape, "conn", conn)
+    a, b, h = ctx.rag(to_dev(np.ascontiguousarray(labels, np.int32)), to_dev(grad), conn)
+    got = list(zip(to_host(a).tolist(), to_host(b).tolist(), to_host(h).tolist()))
+    ref = sorted((x, y, w) for (x, y), w in brute.rag(labels, grad, conn).items())
+    assert got == ref, "rag differs: %d vs %d edges" % (len(got), len(ref))
+    torch.cuda.synchronize()
+
+
+def test_rag_export(ctx):
+    img = gen.blobs2d(64, 70, seed=21)
+    grad = oracle.gradient(img, 0.0, "u8")
+    for conn in (4, 8):
+        lab = oracle.watershed(grad, conn)
+        check_rag(ctx, lab, grad, conn)
+        wf, _ = oracle.waterfall_g1(lab, grad, conn, 4)
+        for k in (1, 3):
+            check_rag(ctx, wf[k], grad, conn)
+    vol = oracle.gradient(gen.blobs3d(14, 15, 16, seed=6, n_blobs=6), 0.0, "u8")
+    for conn in (6, 26):
+        check_rag(ctx, oracle.watershed(vol, conn), vol, conn)
+    const = np.full((20, 30), 3, np.uint8)
+    check_rag(ctx, oracle.watershed(const, 4), const, 4)  # one region, no edge
