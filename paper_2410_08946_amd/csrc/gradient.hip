@@ -10,7 +10,7 @@
 // 2D images run one fused kernel per tile: the raw tile with its halo is staged
 // in LDS, blurred along x, then along y, then the Sobel magnitude is taken, so
 // the float image is read once and only the magnitude is written. 3D volumes
-// use separable passes. Every workgroup stores its maximum in its own word (no
+// use separable blur passes and a z-marching Sobel kernel. Every workgroup stores its maximum in its own word (no
 // atomics: same-line atomics from thousands of workgroups serialise), a small
 // reduction takes the global maximum, and the quantiser reads that one word.
 #include "ws_device.h"
@@ -189,7 +189,8 @@ __global__ __launch_bounds__(NTHREADS) void k_grad_blur(Geom g, const float *__r
     out[p] = s;
 }
 
-// Unnormalised Sobel magnitude (replicated borders) and its maximum.
+// Unnormalised Sobel magnitude (replicated borders) and its maximum, one
+// thread per pixel (2D images whose blur radius exceeds the fused kernel's).
 template <int NDIM>
 __global__ __launch_bounds__(NTHREADS) void k_grad_sobel(Geom g, const float *__restrict__ a, float *__restrict__ mag,
                                                          float *__restrict__ part) {
@@ -232,20 +233,131 @@ __global__ __launch_bounds__(NTHREADS) void k_grad_sobel(Geom g, const float *__
     block_max_store(m, part);
 }
 
+// 3D Sobel magnitude, separable and marching along z. A workgroup owns an
+// S3X x S3Y column of a slab of S3Z planes; every plane it touches (the slab
+// and one plane on each side) is staged with a one-voxel halo in LDS, using
+// clamped coordinates (replicated border). From a plane's 3 x 3 neighbourhood
+// a thread forms the plane partials
+//   A = [1 2 1]_y [-1 0 1]_x a,  B = [1 2 1]_y [1 2 1]_x a,  C = [-1 0 1]_y [1 2 1]_x a,
+// and from three consecutive planes
+//   gx = A(z-1) + 2 A(z) + A(z+1),  gy = C(z-1) + 2 C(z) + C(z+1),  gz = B(z+1) - B(z-1),
+// the unnormalised Sobel derivatives. Each voxel is read from HBM about once
+// (plus halos) instead of 54 times through the cache hierarchy.
+constexpr int S3X = 64, S3Y = 4, S3Z = 16;
+constexpr int S3W = S3X + 2, S3H = S3Y + 2, S3CELLS = S3W * S3H;
+static_assert(S3X * S3Y == NTHREADS, "one column per thread");
+static_assert(S3CELLS <= 2 * NTHREADS, "two staging loads per thread");
+
+__global__ __launch_bounds__(NTHREADS) void k_grad_sobel3(Geom g, int32_t nblocks, const float *__restrict__ a,
+                                                          float *__restrict__ mag, float *__restrict__ part) {
+    __shared__ float sp[2][S3CELLS];
+    if ((int32_t)blockIdx.x >= nblocks) return;
+    const int b = xcd_tile(blockIdx.x, nblocks);
+    const int ntx = (g.nx + S3X - 1) / S3X, nty = (g.ny + S3Y - 1) / S3Y;
+    const int x0 = (b % ntx) * S3X, y0 = ((b / ntx) % nty) * S3Y, zlo = (b / ntx / nty) * S3Z;
+    const int tx = threadIdx.x % S3X, ty = threadIdx.x / S3X;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool own = x < g.nx && y < g.ny;
+    const int32_t plane = g.nx * g.ny;
+    // staging cells of this thread (clamped source offsets within a plane)
+    int32_t src[2];
+    bool has[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        int c = threadIdx.x + h * NTHREADS;
+        has[h] = c < S3CELLS;
+        int cy = c / S3W, cx = c % S3W;
+        src[h] = (int32_t)clampi(y0 - 1 + cy, 0, g.ny - 1) * g.nx + clampi(x0 - 1 + cx, 0, g.nx - 1);
+    }
+    const int jmax = min(S3Z + 1, g.nz - zlo + 1);  // planes zlo-1 .. zlo+jmax-1 (clamped)
+    float A0 = 0.f, A1 = 0.f, B0 = 0.f, B1 = 0.f, C0 = 0.f, C1 = 0.f, m = 0.f;
+    for (int j = 0; j <= jmax; ++j) {
+        const int zz = clampi(zlo - 1 + j, 0, g.nz - 1);
+        float *cur = sp[j & 1];
+        const float *pa = a + (size_t)zz * (size_t)plane;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (has[h]) cur[threadIdx.x + h * NTHREADS] = pa[src[h]];
+        __syncthreads();
+        const float *r0 = cur + ty * S3W + tx, *r1 = r0 + S3W, *r2 = r1 + S3W;
+        float d0 = r0[2] - r0[0], d1 = r1[2] - r1[0], d2 = r2[2] - r2[0];
+        float s0 = r0[0] + 2.f * r0[1] + r0[2], s1 = r1[0] + 2.f * r1[1] + r1[2], s2 = r2[0] + 2.f * r2[1] + r2[2];
+        float A2 = d0 + 2.f * d1 + d2, B2 = s0 + 2.f * s1 + s2, C2 = s2 - s0;
+        if (j >= 2) {
+            const int zo = zlo + j - 2;
+            float gx = A0 + 2.f * A1 + A2, gy = C0 + 2.f * C1 + C2, gz = B2 - B0;
+            float v = sqrtf(gx * gx + gy * gy + gz * gz);
+            if (own) {
+                mag[(size_t)zo * (size_t)plane + (size_t)y * g.nx + x] = v;
+                m = fmaxf(m, v);
+            }
+        }
+        A0 = A1;
+        A1 = A2;
+        B0 = B1;
+        B1 = B2;
+        C0 = C1;
+        C1 = C2;
+        // the next plane goes to the other buffer; the barrier after its
+        // staging orders this plane's reads before that buffer's reuse
+    }
+    block_max_store(m, part);
+}
+
+// g_q = rint(mag Q / max) clamped to [0, Q], 0 when the maximum is 0. A
+// thread quantises 4 consecutive pixels: one 16-byte load when vec & 2 (the
+// magnitudes are 16-byte aligned) and one 4- or 8-byte store when vec & 1 (the
+// output is aligned for it).
+template <typename T> struct Vec4;
+template <> struct Vec4<uint8_t> { using type = uchar4; };
+template <> struct Vec4<uint16_t> { using type = ushort4; };
+
 template <typename T>
 __global__ __launch_bounds__(NTHREADS) void k_grad_quant(int32_t n, const float *__restrict__ mag, T *__restrict__ out,
-                                                         const float *__restrict__ gmax, float Q) {
+                                                         const float *__restrict__ gmax, float Q, int vec) {
     const float mx = *gmax;
-    for (int32_t p = blockIdx.x * NTHREADS * 4 + threadIdx.x; p < n && p < (blockIdx.x + 1) * NTHREADS * 4; p += NTHREADS) {
-        float v = 0.f;
-        if (mx > 0.f) v = rintf(__fdiv_rn(mag[p] * Q, mx));
-        v = fminf(fmaxf(v, 0.f), Q);
-        out[p] = (T)v;
+    const int32_t p = (int32_t)(blockIdx.x * NTHREADS + threadIdx.x) * 4;
+    if (p >= n) return;
+    const bool full = p + 3 < n;
+    float v[4];
+    if (full && (vec & 2)) {
+        float4 q = *(const float4 *)(mag + p);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = p + e < n ? mag[p + e] : 0.f;
     }
+    T o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        float u = 0.f;
+        if (mx > 0.f) u = rintf(__fdiv_rn(v[e] * Q, mx));
+        o[e] = (T)fminf(fmaxf(u, 0.f), Q);
+    }
+    if (full && (vec & 1)) {
+        typename Vec4<T>::type w;
+        w.x = o[0];
+        w.y = o[1];
+        w.z = o[2];
+        w.w = o[3];
+        *(typename Vec4<T>::type *)(out + p) = w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (p + e < n) out[p + e] = o[e];
+    }
+}
+
+static int32_t sobel3_blocks(const Geom &g) {
+    return ((g.nx + S3X - 1) / S3X) * ((g.ny + S3Y - 1) / S3Y) * ((g.nz + S3Z - 1) / S3Z);
 }
 
 int grad_parts(const Geom &g, int ndim, int r) {
     if (ndim == 2 && r <= FUSED_MAX_R) return ((g.nx + GX - 1) / GX) * ((g.ny + GY - 1) / GY);
+    if (ndim == 3) return sobel3_blocks(g);
     return (g.n + NTHREADS - 1) / NTHREADS;
 }
 
@@ -274,8 +386,10 @@ int launch_grad_blur(Launch &lc, const Geom &g, const float *in, float *out, int
     return lc.run("grad_blur", k_grad_blur, dim3((g.n + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), g, in, out, axis, taps);
 }
 int launch_grad_sobel(Launch &lc, const Geom &g, int ndim, const float *a, float *mag, float *part) {
-    if (ndim == 3)
-        return lc.run("grad_sobel", k_grad_sobel<3>, dim3((g.n + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), g, a, mag, part);
+    if (ndim == 3) {
+        int32_t nb = sobel3_blocks(g);
+        return lc.run("grad_sobel", k_grad_sobel3, dim3(nb), dim3(NTHREADS), g, nb, a, mag, part);
+    }
     return lc.run("grad_sobel", k_grad_sobel<2>, dim3((g.n + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), g, a, mag, part);
 }
 // Maximum of nparts partial maxima into *gmax: one workgroup per 64 Ki
@@ -289,10 +403,12 @@ int launch_grad_max(Launch &lc, int32_t nparts, const float *part, float *tmp, f
     return lc.run("grad_max", k_grad_max, dim3(1), dim3(NTHREADS), G, (const float *)tmp, gmax);
 }
 int launch_grad_quant(Launch &lc, int32_t n, bool u16, const float *mag, void *out, const float *gmax) {
-    dim3 grid((n + NTHREADS * 4 - 1) / (NTHREADS * 4));
+    dim3 grid((uint32_t)(((int64_t)n + NTHREADS * 4 - 1) / (NTHREADS * 4)));
+    const int vec = (((uintptr_t)out % (u16 ? 8 : 4)) == 0 ? 1 : 0) | (((uintptr_t)mag % 16) == 0 ? 2 : 0);
     if (u16)
-        return lc.run("grad_quant", k_grad_quant<uint16_t>, grid, dim3(NTHREADS), n, mag, (uint16_t *)out, gmax, 65535.f);
-    return lc.run("grad_quant", k_grad_quant<uint8_t>, grid, dim3(NTHREADS), n, mag, (uint8_t *)out, gmax, 255.f);
+        return lc.run("grad_quant", k_grad_quant<uint16_t>, grid, dim3(NTHREADS), n, mag, (uint16_t *)out, gmax, 65535.f,
+                      vec);
+    return lc.run("grad_quant", k_grad_quant<uint8_t>, grid, dim3(NTHREADS), n, mag, (uint8_t *)out, gmax, 255.f, vec);
 }
 
 }  // namespace wsk

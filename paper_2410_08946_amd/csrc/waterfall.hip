@@ -55,32 +55,16 @@ constexpr int MAXPROBE = 64;        // probes before a hash insert falls back
 constexpr int RCH = 4096;           // pixels per region-id chunk (16 per thread)
 constexpr int SCAN_B = NTHREADS * 16;  // elements per workgroup of the scans
 constexpr int MAX_F = NTHREADS;     // tile groups merged per workgroup (one count per thread)
+// Workgroup -> item runs per XCD (xcd_group): region ids and chunks that are
+// close share table lines, so each XCD takes runs of 64 neighbouring items
+// (measured best: fully contiguous ranges per XCD leave the 8 XCDs writing
+// far-apart streams, runs of 1 re-fetch every table line into all 8 L2s).
+constexpr int XG_OUT = 64;          // chunks per run in the output pass
+constexpr int XG_REG = 64;          // workgroups of 256 region ids per run
 
 // Forward half of a neighbourhood: the neighbours with a larger linear index.
 template <int CONN> __host__ __device__ constexpr bool forward(int k) { return nb_j<CONN>(k) > 13; }
 
-// Block-wide exclusive scan of one int per thread; returns the block total.
-__device__ __forceinline__ int block_scan_excl(int v, int &excl) {
-    __shared__ int wsum[NTHREADS / 64];
-    int lane = __lane_id(), w = threadIdx.x >> 6;
-    int x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        int t = __shfl_up(x, off);
-        if (lane >= off) x += t;
-    }
-    if (lane == 63) wsum[w] = x;
-    __syncthreads();
-    int base = 0, total = 0;
-    for (int k = 0; k < NTHREADS / 64; ++k) {
-        if (k < w) base += wsum[k];
-        total += wsum[k];
-    }
-    excl = base + x - v;
-    __syncthreads();
-    return total;
-}
-
-__device__ __forceinline__ uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
 
 // ---------------------------------------------------------------------------
 // LDS hash tables. Inserts return false when MAXPROBE slots were taken by
@@ -530,7 +514,8 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_level(int32_t ntiles, int32_t g
 __global__ __launch_bounds__(NTHREADS) void k_wf_hook(const int32_t *__restrict__ nreg0,
                                                       const uint64_t *__restrict__ key, int32_t *__restrict__ par) {
     const int32_t n = *nreg0;
-    for (int32_t c = blockIdx.x * NTHREADS + threadIdx.x; c < n; c += gridDim.x * NTHREADS) {
+    for (int32_t c = xcd_group(blockIdx.x, gridDim.x, XG_REG) * NTHREADS + threadIdx.x; c < n;
+         c += gridDim.x * NTHREADS) {
         uint64_t kk = key[c];
         int32_t tg = (int32_t)(uint32_t)(kk & 0xffffffffull);
         if (kk != NOKEY && tg < c) par[c] = tg;
@@ -540,7 +525,8 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_hook(const int32_t *__restrict_
 __global__ __launch_bounds__(NTHREADS) void k_wf_union(const int32_t *__restrict__ nreg0, uint64_t *__restrict__ key,
                                                        int32_t *__restrict__ par) {
     const int32_t n = *nreg0;
-    for (int32_t c = blockIdx.x * NTHREADS + threadIdx.x; c < n; c += gridDim.x * NTHREADS) {
+    for (int32_t c = xcd_group(blockIdx.x, gridDim.x, XG_REG) * NTHREADS + threadIdx.x; c < n;
+         c += gridDim.x * NTHREADS) {
         uint64_t kk = key[c];
         if (kk == NOKEY) continue;
         key[c] = NOKEY;
@@ -553,7 +539,8 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_compress(const int32_t *__restr
                                                           const int32_t *__restrict__ rlist,
                                                           int32_t *__restrict__ mlab_k) {
     const int32_t n = *nreg0;
-    for (int32_t c = blockIdx.x * NTHREADS + threadIdx.x; c < n; c += gridDim.x * NTHREADS) {
+    for (int32_t c = xcd_group(blockIdx.x, gridDim.x, XG_REG) * NTHREADS + threadIdx.x; c < n;
+         c += gridDim.x * NTHREADS) {
         int32_t r = gfind_ro(par, c);
         par[c] = r;
         mlab_k[c] = rlist[r];
@@ -567,7 +554,10 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_compress(const int32_t *__restr
 // count is the chunk's root count, the difference of consecutive chunk
 // offsets. A thread owns runs of 4 consecutive pixels: 16-byte loads and
 // stores when the image's layers are 16-byte aligned, else scalar accesses.
-// With nl == 1 only layer 0 is counted.
+// With nl == 1 only layer 0 is counted. Layers are written one after the
+// other, each as one contiguous span per chunk: a variant that gathered all
+// layers of a run before storing (interleaving the layers' spans) measured
+// slower.
 // ---------------------------------------------------------------------------
 template <class Src>
 __global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks, int32_t nl,
@@ -579,8 +569,8 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks
     constexpr int RUNS = RCH / (4 * NTHREADS);  // runs of 4 pixels per thread
     static_assert(RUNS * 4 * NTHREADS == RCH, "whole runs per chunk");
     __shared__ int kc;
-    const int t = blockIdx.x;
-    if (t >= nchunks) return;
+    if ((int)blockIdx.x >= nchunks) return;
+    const int t = xcd_group(blockIdx.x, nchunks, XG_OUT);
     Img im;
     int lc;
     fetch(src_ch, t, TK_CH, im, lc);

@@ -14,7 +14,8 @@
 // which both the synchronous sweeps of Section 3.3 and the balanced
 // block-asynchronous sweeps of Section 3.4 (Alg. 3) converge to. Tiles relax
 // to a local fixpoint in LDS with frozen halos; a tile re-runs only when a
-// neighbouring tile changed one of its border distances (tile "stamps").
+// neighbouring tile changed border distances next to it (tile "stamps" with
+// the faces that changed).
 //
 // Arrows (Eq. (1) for pixels with a lower neighbour; the equal neighbour at
 // distance d-1 with the smallest index for resolved plateau pixels) are then
@@ -85,27 +86,127 @@ __device__ __forceinline__ bool on_tile_border(int x, int y, int z) {
     return b;
 }
 
+// Faces of the tile a pixel lies on: bit 0 / 1 the low / high x face, 2 / 3
+// y, 4 / 5 z.
+template <int NDIM>
+__device__ __forceinline__ uint32_t face_bits(int x, int y, int z) {
+    using TS = TileShape<NDIM>;
+    uint32_t b = (x == 0 ? 1u : 0u) | (x == TS::X - 1 ? 2u : 0u) | (y == 0 ? 4u : 0u) | (y == TS::Y - 1 ? 8u : 0u);
+    if (NDIM == 3) b |= (z == 0 ? 16u : 0u) | (z == TS::Z - 1 ? 32u : 0u);
+    return b;
+}
+
+template <int NDIM>
+__device__ __forceinline__ void tile_pixel(int i, int &x, int &y, int &z) {
+    using TS = TileShape<NDIM>;
+    x = i % TS::X;
+    y = (i / TS::X) % TS::Y;
+    z = i / (TS::X * TS::Y);
+}
+
 template <int NDIM>
 __device__ __forceinline__ void ws_tile(const Geom &g, int lt, int &ox, int &oy, int &oz) {
     using TS = TileShape<NDIM>;
     tile_xyz<TS::X, TS::Y, TS::Z>(g, lt, ox, oy, oz);
 }
 
+// Step II relaxes only the pixels whose distance can still change: the
+// unresolved plateau pixels of a tile are compacted once into an LDS list (in
+// index order), and every relaxation pass visits the list instead of the whole
+// tile. Plateau pixels are a few per cent of a tile on natural gradients; a
+// tile with more than LCAP of them relaxes the whole tile instead.
+constexpr int LCAP = NTHREADS;  // one list entry per thread
+
+// Tile pixels i with sI != SENT and (sweep ? D != 0 : D == INF) into lst, in
+// index order; returns their number (entries beyond LCAP are not stored).
+template <int NDIM, int R>
+__device__ __forceinline__ int build_list(const int *sI, const int *sD, unsigned short *lst, bool sweep) {
+    using TS = TileShape<NDIM>;
+    using S = Lds<NDIM, R>;
+    constexpr int PIX = TS::X * TS::Y * TS::Z;
+    constexpr int PER = PIX / NTHREADS;
+    static_assert(PIX % NTHREADS == 0 && PER <= 32, "pixels per thread fit one mask");
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int x, y, z;
+        tile_pixel<NDIM>(threadIdx.x + j * NTHREADS, x, y, z);
+        int sc = S::at(x, y, z), d = sD[sc];
+        bool take = sI[sc] != SENT && (sweep ? d != 0 : d == INF);
+        m |= (take ? 1u : 0u) << j;
+    }
+    int excl;
+    const int total = block_scan_excl(__popc(m), excl);
+    if (total <= LCAP) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (m >> j & 1u) lst[excl++] = (unsigned short)(threadIdx.x + j * NTHREADS);
+    }
+    __syncthreads();
+    return total;
+}
+
+// relax_tile restricted to the n <= LCAP listed pixels (entry threadIdx.x).
+template <int NDIM, int CONN, int R>
+__device__ __forceinline__ void relax_list(const int *sI, int *sD, const unsigned short *lst, int n) {
+    using S = Lds<NDIM, R>;
+    int sc = -1, v = 0;
+    if ((int)threadIdx.x < n) {
+        int x, y, z;
+        tile_pixel<NDIM>(lst[threadIdx.x], x, y, z);
+        sc = S::at(x, y, z);
+        v = sI[sc];
+    }
+    for (;;) {
+        int changed = 0;
+        if (sc >= 0) {
+            int d = sD[sc], best = d;
+#pragma unroll
+            for (int k = 0; k < CONN; ++k) {
+                int o = sc + S::template off<CONN>(k);
+                int dq = sD[o];
+                if (sI[o] == v && dq != INF && dq + 1 < best) best = dq + 1;
+            }
+            if (best < d) {
+                sD[sc] = best;
+                changed = 1;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+}
+
+// Tile t changed border distances in sweep s: record s and the faces.
+__device__ __forceinline__ void stamp_tile(int *smk, int32_t *stamp, int32_t *smask, int32_t *changed, int t, int32_t s,
+                                           uint32_t faces) {
+    if (faces) atomicOr(smk, (int)faces);
+    __syncthreads();
+    if (threadIdx.x == 0 && *smk) {
+        stamp[t] = s;
+        smask[t] = *smk;
+        atomicAdd(changed, 1);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Step I + first Step II pass: initial distances of the tile and its ring
 // (0 = has a lower neighbour or no equal one, INF = plateau pixel), then a
-// local fixpoint. Stamps the tile with sweep 0 when a border pixel obtained a
-// finite distance its neighbours could not have known.
+// local fixpoint. Stamps the tile with sweep 0, and the faces concerned, when
+// a border pixel obtained a finite distance its neighbours could not have
+// known.
 // ---------------------------------------------------------------------------
 template <int NDIM, int CONN, typename T, class Src>
 __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, int32_t *__restrict__ Darena,
-                                                      int32_t *__restrict__ stamp, int32_t *__restrict__ changed) {
+                                                      int32_t *__restrict__ stamp, int32_t *__restrict__ smask,
+                                                      int32_t *__restrict__ changed) {
     using TS = TileShape<NDIM>;
     using S2 = Lds<NDIM, 2>;
     using S1 = Lds<NDIM, 1>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
     __shared__ int sI[S2::CELLS];
     __shared__ int sD[S2::CELLS];
+    __shared__ unsigned short lst[LCAP];
+    __shared__ int smk;
     {
         if ((int)blockIdx.x >= ntiles) return;
         const int t = xcd_tile(blockIdx.x, ntiles);
@@ -116,6 +217,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
         int32_t *D = Darena + im.pix0;
         int ox, oy, oz;
         ws_tile<NDIM>(g, lt, ox, oy, oz);
+        if (threadIdx.x == 0) smk = 0;
         load_grey<NDIM, 2, T>(g, (const T *)im.grey, sI, ox, oy, oz);
         __syncthreads();
         // Initial distances on the tile plus a ring of width 1 (Step I state test).
@@ -133,37 +235,41 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
             sD[s] = d;
         }
         __syncthreads();
-        relax_tile<NDIM, CONN, 2>(sI, sD);
-        int border = 0;
+        const int n = build_list<NDIM, 2>(sI, sD, lst, false);
+        if (n <= LCAP) relax_list<NDIM, CONN, 2>(sI, sD, lst, n);
+        else relax_tile<NDIM, CONN, 2>(sI, sD);
+        uint32_t faces = 0;
         for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
-            int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+            int x, y, z;
+            tile_pixel<NDIM>(i, x, y, z);
             int gx = ox + x, gy = oy + y, gz = oz + z;
             if (!in_image(g, gx, gy, gz)) continue;
             int d = sD[S2::at(x, y, z)];
             D[gx + g.nx * (gy + g.ny * gz)] = d;
-            if (d != 0 && d != INF && on_tile_border<NDIM>(x, y, z)) border = 1;
+            if (d != 0 && d != INF) faces |= face_bits<NDIM>(x, y, z);
         }
-        if (__syncthreads_or(border) && threadIdx.x == 0) {
-            stamp[t] = 0;
-            atomicAdd(changed, 1);
-        }
+        stamp_tile(&smk, stamp, smask, changed, t, 0, faces);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Step II sweep s >= 1: tiles next to a tile stamped in sweep s-1 reload their
-// ring from global memory and relax again.
+// Step II sweep s >= 1: tiles next to a tile that changed, in sweep s-1, the
+// distances on the face (4/6-connectivity) or anywhere on the border (8/26)
+// next to them reload their ring from global memory and relax again.
 // ---------------------------------------------------------------------------
 template <int NDIM, int CONN, typename T, class Src>
 __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, int32_t *__restrict__ Darena,
-                                                       int32_t *__restrict__ stamp, int32_t *__restrict__ changed,
-                                                       int32_t s) {
+                                                       int32_t *__restrict__ stamp, int32_t *__restrict__ smask,
+                                                       int32_t *__restrict__ changed, int32_t s) {
     using TS = TileShape<NDIM>;
     using S = Lds<NDIM, 1>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
     constexpr int PER = (PIX + NTHREADS - 1) / NTHREADS;
+    constexpr bool FACES = CONN == 4 || CONN == 6;  // only face neighbours interact
     __shared__ int sI[S::CELLS];
     __shared__ int sD[S::CELLS];
+    __shared__ unsigned short lst[LCAP];
+    __shared__ int smk;
     {
         if ((int)blockIdx.x >= ntiles) return;
         const int t = xcd_tile(blockIdx.x, ntiles);
@@ -178,46 +284,72 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, 
             if (j < 27) {
                 int dx = j % 3 - 1, dy = (j / 3) % 3 - 1, dz = j / 9 - 1;
                 int ux = tx + dx, uy = ty + dy, uz = tz + dz;
-                bool used = (NDIM == 3 || dz == 0) && (dx != 0 || dy != 0 || dz != 0);
-                if (used && ux >= 0 && ux < g.ntx && uy >= 0 && uy < g.nty && uz >= 0 && uz < g.ntz)
-                    active = stamp[im.tile0[TK_WS] + ux + g.ntx * (uy + g.nty * uz)] == s - 1;
+                bool face = (dx != 0) + (dy != 0) + (dz != 0) == 1;
+                bool used = (NDIM == 3 || dz == 0) && (dx != 0 || dy != 0 || dz != 0) && (!FACES || face);
+                if (used && ux >= 0 && ux < g.ntx && uy >= 0 && uy < g.nty && uz >= 0 && uz < g.ntz) {
+                    int32_t u = im.tile0[TK_WS] + ux + g.ntx * (uy + g.nty * uz);
+                    if (stamp[u] == s - 1) {
+                        // the neighbour's face towards this tile
+                        uint32_t need = !FACES ? 63u
+                                        : dx > 0 ? 1u : dx < 0 ? 2u : dy > 0 ? 4u : dy < 0 ? 8u : dz > 0 ? 16u : 32u;
+                        active = ((uint32_t)smask[u] & need) != 0;
+                    }
+                }
             }
         }
         if (!__syncthreads_or(active)) return;
+        if (threadIdx.x == 0) smk = 0;
         int32_t *D = Darena + im.pix0;
         int ox = tx * TS::X, oy = ty * TS::Y, oz = tz * TS::Z;
         load_grey<NDIM, 1, T>(g, (const T *)im.grey, sI, ox, oy, oz);
         load_dist<NDIM>(g, D, sD, ox, oy, oz);
         __syncthreads();
-        int before[PER];
+        const int n = build_list<NDIM, 1>(sI, sD, lst, true);
+        uint32_t faces = 0;
+        if (n <= LCAP) {
+            int x = 0, y = 0, z = 0, sc = -1, before = 0;
+            if ((int)threadIdx.x < n) {
+                tile_pixel<NDIM>(lst[threadIdx.x], x, y, z);
+                sc = S::at(x, y, z);
+                before = sD[sc];
+            }
+            relax_list<NDIM, CONN, 1>(sI, sD, lst, n);
+            if (sc >= 0) {
+                int d = sD[sc];
+                if (d != before) {
+                    D[(ox + x) + g.nx * ((oy + y) + g.ny * (oz + z))] = d;  // listed pixels are in the image
+                    faces |= face_bits<NDIM>(x, y, z);
+                }
+            }
+        } else {
+            int before[PER];
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            int i = threadIdx.x + j * NTHREADS;
-            before[j] = INF;
-            if (i < PIX) {
-                int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-                before[j] = sD[S::at(x, y, z)];
+            for (int j = 0; j < PER; ++j) {
+                int i = threadIdx.x + j * NTHREADS;
+                before[j] = INF;
+                if (i < PIX) {
+                    int x, y, z;
+                    tile_pixel<NDIM>(i, x, y, z);
+                    before[j] = sD[S::at(x, y, z)];
+                }
+            }
+            relax_tile<NDIM, CONN, 1>(sI, sD);
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                int i = threadIdx.x + j * NTHREADS;
+                if (i >= PIX) continue;
+                int x, y, z;
+                tile_pixel<NDIM>(i, x, y, z);
+                int gx = ox + x, gy = oy + y, gz = oz + z;
+                if (!in_image(g, gx, gy, gz)) continue;
+                int d = sD[S::at(x, y, z)];
+                if (d != before[j]) {
+                    D[gx + g.nx * (gy + g.ny * gz)] = d;
+                    faces |= face_bits<NDIM>(x, y, z);
+                }
             }
         }
-        relax_tile<NDIM, CONN, 1>(sI, sD);
-        int border = 0;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            int i = threadIdx.x + j * NTHREADS;
-            if (i >= PIX) continue;
-            int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-            int gx = ox + x, gy = oy + y, gz = oz + z;
-            if (!in_image(g, gx, gy, gz)) continue;
-            int d = sD[S::at(x, y, z)];
-            if (d != before[j]) {
-                D[gx + g.nx * (gy + g.ny * gz)] = d;
-                if (on_tile_border<NDIM>(x, y, z)) border = 1;
-            }
-        }
-        if (__syncthreads_or(border) && threadIdx.x == 0) {
-            stamp[t] = s;
-            atomicAdd(changed, 1);
-        }
+        stamp_tile(&smk, stamp, smask, changed, t, s, faces);
     }
 }
 
@@ -633,14 +765,14 @@ static int launch_ws_init_t(Launch &lc, const Src &src, const TileGrid &tg, int3
                             int32_t *changed) {
     constexpr int ND = ndim_of<CONN>();
     return lc.run("ws_init", k_ws_init<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, D, stamp,
-                  changed);
+                  stamp + tg.ntiles, changed);
 }
 template <int CONN, typename T, class Src>
 static int launch_ws_sweep_t(Launch &lc, const Src &src, const TileGrid &tg, int32_t *D, int32_t *stamp,
                              int32_t *changed, int32_t s) {
     constexpr int ND = ndim_of<CONN>();
     return lc.run("ws_sweep", k_ws_sweep<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, D, stamp,
-                  changed, s);
+                  stamp + tg.ntiles, changed, s);
 }
 template <int CONN, typename T, class Src>
 static int launch_ws_label_t(Launch &lc, const Src &src, const TileGrid &tg, const int32_t *D, int32_t *rec) {

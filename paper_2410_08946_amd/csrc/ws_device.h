@@ -81,6 +81,41 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
     return x * q + (x < r ? x : r) + s;
 }
 
+// Like xcd_tile, but every XCD takes runs of G consecutive items in turn, so
+// that the XCDs together sweep one front of 8 G items through [0, n) while
+// each reuses the cache lines its own run shares. Items past the last whole
+// front map to themselves. A bijection on [0, n).
+__device__ __forceinline__ int xcd_group(int b, int n, int G) {
+    if (G < 1) G = 1;
+    const int F = NXCD * G, full = n / F * F;
+    if (b >= full) return b;
+    const int w = b % F;
+    return b - w + (w % NXCD) * G + w / NXCD;
+}
+
+// Block-wide exclusive scan of one int per thread; returns the block total.
+__device__ __forceinline__ int block_scan_excl(int v, int &excl) {
+    __shared__ int wsum[NTHREADS / 64];
+    int lane = __lane_id(), w = threadIdx.x >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        int t = __shfl_up(x, off);
+        if (lane >= off) x += t;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int k = 0; k < NTHREADS / 64; ++k) {
+        if (k < w) base += wsum[k];
+        total += wsum[k];
+    }
+    excl = base + x - v;
+    __syncthreads();
+    return total;
+}
+
+__device__ __forceinline__ uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
+
 // Origin of local tile lt of a tiling with tile shape (X, Y, Z).
 template <int X, int Y, int Z>
 __device__ __forceinline__ void tile_xyz(const Geom &g, int lt, int &ox, int &oy, int &oz) {

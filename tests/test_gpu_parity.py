@@ -184,13 +184,18 @@ def test_schedule_invariance(ctx):
         ctx.set_option("sweep_batch", 4)
 
 
-def _check_gradient(ctx, img, sigma, dtype):
+def _check_gradient(ctx, img, sigma, dtype, offset=0):
+    """offset > 0 places the magnitude and the output `offset` elements into
+    their allocations (buffers not aligned for vector accesses)."""
     import torch
-    say("  gradient", img.shape, "sigma", sigma, dtype)
+    say("  gradient", img.shape, "sigma", sigma, dtype, "offset", offset)
     q_ref, mag_ref = oracle.gradient(img, sigma, dtype, return_mag=True)
     d_img = torch.from_numpy(img).to("cuda:0")
-    mag = torch.empty(img.shape, dtype=torch.float32, device="cuda:0")
-    q = ctx.gradient(d_img, sigma, dtype, mag=mag)
+    n = img.size
+    mag = torch.empty(n + offset, dtype=torch.float32, device="cuda:0")[offset:].view(img.shape)
+    qt = torch.uint8 if dtype == "u8" else torch.uint16
+    out = torch.empty(n + offset, dtype=qt, device="cuda:0")[offset:].view(img.shape)
+    q = ctx.gradient(d_img, sigma, dtype, out=out, mag=mag)
     m = to_host(mag).astype(np.float64)
     mx = mag_ref.max()
     assert np.abs(m - mag_ref).max() <= GRAD_RTOL * mx
@@ -212,6 +217,12 @@ def test_gradient(ctx):
     _check_gradient(ctx, (rng.normal(0, 10, (17, 19, 23))).astype(np.float32), 1.0, "u16")
     _check_gradient(ctx, (rng.normal(0, 10, (1, 300))).astype(np.float32), 1.0, "u16")
     _check_gradient(ctx, np.full((20, 30), 3.0, np.float32), 1.0, "u8")
+    # 3D Sobel slabs of 16 planes and 64 x 4 columns: several slabs, partial
+    # columns, a single row, a thin volume; unaligned magnitudes and outputs
+    for shape, dt, off in [((33, 9, 70), "u8", 0), ((40, 13, 130), "u16", 0), ((2, 5, 7), "u8", 0),
+                           ((17, 1, 65), "u16", 0), ((20, 6, 67), "u8", 1), ((19, 5, 33), "u16", 3)]:
+        _check_gradient(ctx, (rng.normal(0, 10, shape) + 40).astype(np.float32), 0.0, dt, offset=off)
+    _check_gradient(ctx, (rng.normal(0, 100, (61, 77)) + 500).astype(np.float32), 1.0, "u8", offset=1)
 
 
 def test_argument_errors(ctx):
