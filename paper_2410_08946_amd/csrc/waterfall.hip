@@ -555,9 +555,8 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_compress(const int32_t *__restr
 // offsets. A thread owns runs of 4 consecutive pixels: 16-byte loads and
 // stores when the image's layers are 16-byte aligned, else scalar accesses.
 // With nl == 1 only layer 0 is counted. Layers are written one after the
-// other, each as one contiguous span per chunk: a variant that gathered all
-// layers of a run before storing (interleaving the layers' spans) measured
-// slower.
+// other, each as one contiguous span per chunk. This form serves any nl;
+// k_wf_out_p below serves 2 <= nl <= 8.
 // ---------------------------------------------------------------------------
 template <class Src>
 __global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks, int32_t nl,
@@ -626,6 +625,122 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks
         if (__lane_id() == 0 && own) atomicAdd(&kc, own);
         __syncthreads();
         if (threadIdx.x == 0) cnt[(size_t)k * nchunks + t] = kc;
+    }
+}
+
+// The same pass for NLM = nl - 1 <= 7 layers above layer 0, software-
+// pipelined over the layers: a thread issues the gathers of layer k+1 before
+// it stores layer k, from two register sets used in turn. Loads and stores
+// share one in-order completion counter, so in the layer-by-layer form every
+// layer's gathers also waited for the previous layer's stores; here a layer's
+// stores drain while the next layer's gathers are in flight. The layer loop is
+// unrolled (the table bases stay scalar, one offset register per pixel).
+// Own-label counts are wave ballots summed into one LDS counter per layer,
+// with a single barrier per chunk.
+constexpr int WF_OUT_MAXNL = 8;
+constexpr int WF_RUNS = RCH / (4 * NTHREADS);  // runs of 4 pixels per thread
+
+// byte offsets from a uniform table base: one offset register per pixel
+__device__ __forceinline__ void wf_gather(int32_t (&v)[WF_RUNS][4], const uint32_t (&off)[WF_RUNS][4],
+                                          const char *__restrict__ m) {
+#pragma unroll
+    for (int r = 0; r < WF_RUNS; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[r][e] = *(const int32_t *)(m + off[r][e]);
+}
+
+__device__ __forceinline__ void wf_emit(const int32_t (&v)[WF_RUNS][4], const int32_t (&p0)[WF_RUNS], int32_t n,
+                                        bool vec, int32_t *__restrict__ out, int *kc) {
+    int own = 0;
+#pragma unroll
+    for (int r = 0; r < WF_RUNS; ++r) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) own += __popcll(__ballot(p0[r] + e < n && v[r][e] == p0[r] + e));
+        if (vec && p0[r] + 3 < n) {
+            *(int4 *)(out + p0[r]) = make_int4(v[r][0], v[r][1], v[r][2], v[r][3]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (p0[r] + e < n) out[p0[r] + e] = v[r][e];
+        }
+    }
+    if (__lane_id() == 0 && own) atomicAdd(kc, own);
+}
+
+template <class Src, int NLM>
+__global__ __launch_bounds__(NTHREADS) void k_wf_out_p(Src src_ch, int32_t nchunks,
+                                                       const int32_t *__restrict__ cimg,
+                                                       const int32_t *__restrict__ nreg0,
+                                                       const int32_t *__restrict__ coff,
+                                                       const int32_t *__restrict__ mlab, int64_t mstride,
+                                                       int32_t *__restrict__ cnt) {
+    static_assert(WF_RUNS * 4 * NTHREADS == RCH, "whole runs per chunk");
+    __shared__ int kc[WF_OUT_MAXNL];
+    if ((int)blockIdx.x >= nchunks) return;
+    const int t = xcd_group(blockIdx.x, nchunks, XG_OUT);
+    Img im;
+    int lc;
+    fetch(src_ch, t, TK_CH, im, lc);
+    const int32_t nr = *nreg0;
+    if (threadIdx.x == 0) cnt[t] = (t + 1 < nchunks ? coff[t + 1] : nr) - coff[t];
+    if ((int)threadIdx.x < WF_OUT_MAXNL) kc[threadIdx.x] = 0;
+    __syncthreads();
+    const int32_t base = lc * RCH, n = im.g.n;
+    const int32_t *ci = cimg + im.pix0;
+    const bool vec = ((im.pix0 | n) & 3) == 0 && ((uintptr_t)im.lab & 15) == 0;
+    const uint32_t cmax = nr > 0 ? (uint32_t)(nr - 1) : 0u;
+    uint32_t off[WF_RUNS][4];
+    int32_t p0[WF_RUNS];
+#pragma unroll
+    for (int r = 0; r < WF_RUNS; ++r) {
+        p0[r] = base + (r * NTHREADS + (int)threadIdx.x) * 4;
+        int32_t c[4];
+        if (vec && p0[r] + 3 < n) {
+            int4 q = *(const int4 *)(ci + p0[r]);
+            c[0] = q.x;
+            c[1] = q.y;
+            c[2] = q.z;
+            c[3] = q.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) c[e] = p0[r] + e < n ? ci[p0[r] + e] : 0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) off[r][e] = ((uint32_t)c[e] <= cmax ? (uint32_t)c[e] : cmax) * 4u;
+    }
+    const char *mb = (const char *)mlab;
+    const size_t mstep = (size_t)mstride * sizeof(int32_t);
+    int32_t V[2][WF_RUNS][4];
+    wf_gather(V[0], off, mb);
+#pragma unroll
+    for (int k = 0; k < NLM; ++k) {  // V[k & 1] holds layer k + 1
+        if (k + 1 < NLM) wf_gather(V[(k + 1) & 1], off, mb + (size_t)(k + 1) * mstep);
+        wf_emit(V[k & 1], p0, n, vec, im.lab + (size_t)(k + 1) * (size_t)n, &kc[k + 1]);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x >= 1 && (int)threadIdx.x <= NLM) cnt[(size_t)threadIdx.x * nchunks + t] = kc[threadIdx.x];
+}
+
+template <class Src>
+static int wf_out_pipelined(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t nl, const int32_t *cimg,
+                            const int32_t *nreg0, const int32_t *coff, const int32_t *mlab, int64_t mstride,
+                            int32_t *cnt) {
+    dim3 grid(nchunks > 0 ? nchunks : 1);
+    switch (nl - 1) {
+#define WF_OUT_P(M)                                                                                               \
+    case M:                                                                                                       \
+        return lc.run("wf_out", k_wf_out_p<Src, M>, grid, dim3(NTHREADS), src_ch, nchunks, cimg, nreg0, coff, mlab, \
+                      mstride, cnt);
+        WF_OUT_P(1)
+        WF_OUT_P(2)
+        WF_OUT_P(3)
+        WF_OUT_P(4)
+        WF_OUT_P(5)
+        WF_OUT_P(6)
+        WF_OUT_P(7)
+#undef WF_OUT_P
+        default:
+            return -1;
     }
 }
 
@@ -797,6 +912,8 @@ static int wf_pix_dispatch(Launch &lc, const Src &src, const TileGrid &tg, int c
     int launch_wf_out(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t nl, const int32_t *cimg,            \
                       const int32_t *nreg0, const int32_t *coff, const int32_t *mlab, int64_t mstride,           \
                       int32_t *cnt) {                                                                             \
+        if (nl >= 2 && nl <= WF_OUT_MAXNL)                                                                        \
+            return wf_out_pipelined<Src>(lc, src_ch, nchunks, nl, cimg, nreg0, coff, mlab, mstride, cnt);        \
         return lc.run("wf_out", k_wf_out<Src>, dim3(nchunks > 0 ? nchunks : 1), dim3(NTHREADS), src_ch, nchunks, \
                       nl, cimg, nreg0, coff, mlab, mstride, cnt);                                                 \
     }
