@@ -340,9 +340,18 @@ struct WfBufs {
     int32_t *par, *cimg, *rlist, *mlab, *edges, *ecnt;
 };
 
+// Layer tables: layer 1 by region id; for NL >= 3 also the ranks of the
+// layer-1 roots, the root list, the tables of layers 2 .. NL-1 by rank (each
+// arena ints: the counts are only known on the device) and the root scan's
+// scratch.
+size_t mlab_ints(size_t arena, int NL) {
+    if (NL < 3) return arena;
+    return (size_t)(NL + 1) * arena + (size_t)wsk::root_list_tmp_len((int32_t)arena);
+}
+
 int wf_buffers(ws_ctx *c, size_t arena, int32_t ntiles, int32_t nchunks, int conn, int NL, bool tables, WfBufs &b) {
     int rc;
-    if ((rc = ensure(c, c->wfcnt, 4, "region count")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->wfcnt, 8, "region counts")) != WS_OK) return rc;
     if ((rc = ensure(c, c->tilecnt, (size_t)NL * nchunks * 4, "chunk counts")) != WS_OK) return rc;
     // region-id tables: [chunk offsets | scan scratch | 64 rank words per chunk]
     size_t off_words = (((size_t)nchunks + wsk::scan_tmp_len(nchunks)) * 4 + 15) & ~(size_t)15;
@@ -362,7 +371,7 @@ int wf_buffers(ws_ctx *c, size_t arena, int32_t ntiles, int32_t nchunks, int con
     if ((rc = ensure(c, c->par, arena * 4, "region parents")) != WS_OK) return rc;
     if ((rc = ensure(c, c->cimg, arena * 4, "pixel region ids")) != WS_OK) return rc;
     if ((rc = ensure(c, c->rlist, arena * 4, "region labels")) != WS_OK) return rc;
-    if (NL >= 2 && (rc = ensure(c, c->mlab, (size_t)(NL - 1) * arena * 4, "layer labels")) != WS_OK) return rc;
+    if (NL >= 2 && (rc = ensure(c, c->mlab, mlab_ints(arena, NL) * 4, "layer labels")) != WS_OK) return rc;
     if ((rc = ensure(c, c->edges, 3 * E * 4, "edge slabs")) != WS_OK) return rc;
     if ((rc = ensure(c, c->ecnt, (size_t)ntiles * 4, "edge counts")) != WS_OK) return rc;
     b.key = (uint64_t *)c->key.p;
@@ -395,17 +404,25 @@ int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const Src &src_ch, int3
         WS_TRY(wsk::launch_wf_ids(lc, src_ch, nchunks, bound, b.ids, b.scan_tmp, b.nreg0, b.key, b.par));
         WS_TRY(wsk::launch_wf_pix(lc, src, tg, conn, u16, b.ids, b.nreg0, b.cimg, b.rlist, b.key, b.edges, b.ecnt));
         WS_TRY(wsk::launch_wf_union(lc, bound, b.nreg0, b.key, b.par));
-        WS_TRY(wsk::launch_wf_compress(lc, bound, b.nreg0, b.par, b.rlist, b.mlab));
-        int32_t gin = 1;
-        for (int k = 2; k < NL; ++k) {
-            // groups grow fourfold per layer: regions spanning several tiles
-            // then share one group (fewer key atomics) while a group's
-            // distinct edges still fit its LDS hash
-            int32_t f = gin >= tg.ntiles ? 1 : 4;
-            WS_TRY(wsk::launch_wf_level(lc, tg.ntiles, gin, f, cap, b.par, b.key, b.edges, b.ecnt));
-            gin *= f;
-            WS_TRY(wsk::launch_wf_union(lc, bound, b.nreg0, b.key, b.par));
-            WS_TRY(wsk::launch_wf_compress(lc, bound, b.nreg0, b.par, b.rlist, b.mlab + (size_t)(k - 1) * arena));
+        if (NL == 2) {
+            WS_TRY(wsk::launch_wf_compress(lc, bound, b.nreg0, b.par, b.rlist, b.mlab));
+        } else {
+            // later layers only concern the roots of layer 1: list them
+            int32_t *id1 = b.mlab + arena, *R1 = b.mlab + 2 * arena, *n1 = b.nreg0 + 1;
+            int32_t *scr = b.mlab + (size_t)(NL + 1) * arena;
+            WS_TRY(wsk::launch_root_list(lc, bound, b.nreg0, b.par, R1, id1, scr, n1));
+            WS_TRY(wsk::launch_wf_compress1(lc, bound, b.nreg0, b.par, b.rlist, b.mlab, id1));
+            int32_t gin = 1;
+            for (int k = 2; k < NL; ++k) {
+                // groups grow fourfold per layer: regions spanning several tiles
+                // then share one group (fewer key atomics) while a group's
+                // distinct edges still fit its LDS hash
+                int32_t f = gin >= tg.ntiles ? 1 : 4;
+                WS_TRY(wsk::launch_wf_level(lc, tg.ntiles, gin, f, cap, b.par, b.key, b.edges, b.ecnt));
+                gin *= f;
+                WS_TRY(wsk::launch_wf_union_l(lc, bound, n1, R1, b.key, b.par));
+                WS_TRY(wsk::launch_wf_compress_l(lc, bound, n1, R1, b.par, b.rlist, b.mlab + (size_t)(k + 1) * arena));
+            }
         }
     }
     WS_TRY(wsk::launch_wf_out(lc, src_ch, nchunks, NL, b.cimg, b.nreg0, b.ids.coff, b.mlab, (int64_t)arena, b.cnt));
@@ -429,7 +446,7 @@ int reserve(ws_ctx *c, int64_t n) {
     for (Buf *b : four)
         if ((rc = ensure(c, *b, N * 4, "reserved scratch")) != WS_OK) return rc;
     if ((rc = ensure(c, c->key, N * 8, "reserved keys")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->mlab, N * 4 * (kLayers - 1), "reserved layer labels")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->mlab, mlab_ints(N, kLayers) * 4, "reserved layer labels")) != WS_OK) return rc;
     if ((rc = ensure(c, c->edges, wft * (size_t)wsk::wf_slab_cap(8) * 12, "reserved edge slabs")) != WS_OK) return rc;
     if ((rc = ensure(c, c->ecnt, wft * 4, "reserved edge counts")) != WS_OK) return rc;
     if ((rc = ensure(c, c->stamp, tiles * 8, "reserved stamps")) != WS_OK) return rc;
@@ -533,7 +550,7 @@ size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int conn, int dtyp
     size_t wf = 0;
     if (NL >= 2) {
         size_t tiles = (size_t)wsk::wf_tiles(make_geom(nx, ny, nz, ndim), ndim);
-        wf = N * (8 /* keys */ + 4 /* parents */ + 4 /* ids */ + 4 /* labels */ + 4 * (size_t)(NL - 1) /* layers */) +
+        wf = N * (8 /* keys */ + 4 /* parents */ + 4 /* ids */ + 4 /* labels */) + mlab_ints(N, NL) * 4 /* layers */ +
              tiles * (12 * (size_t)wsk::wf_slab_cap(conn) + 4 + 4 * (size_t)NL) +
              ((size_t)wsk::wf_chunks((int32_t)N) + 2) * (64 * 16 + 8) /* region-id rank tables */;
     }

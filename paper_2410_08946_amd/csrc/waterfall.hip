@@ -548,7 +548,125 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_compress(const int32_t *__restr
 }
 
 // ---------------------------------------------------------------------------
-// 4. Layers 1 .. nl-1 of every pixel from its region id, chunk by chunk
+// 2b. Layers >= 2 over the roots of layer 1 only. After layer 1's union the
+// regions that are still roots (par[c] == c) are listed in increasing id
+// order, R1[i], with their rank in id1[r]; layer 1's compression then gives
+// every region c the rank of its layer-1 root, id1[c]. Keys and parent
+// changes of later layers only ever concern such roots, so their union and
+// compression walk R1 (a fraction of the regions), and their label tables are
+// indexed by rank: M_k[i] = label of R1[i] in layer k.
+// ---------------------------------------------------------------------------
+// Roots among c in [0, nreg0) per SCAN_B block of ids (a run of 16 ids per thread).
+__device__ __forceinline__ uint32_t root_mask16(const int32_t *__restrict__ par, int32_t c0, int32_t n) {
+    uint32_t m = 0;
+    if (c0 + 16 <= n) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int4 v = *(const int4 *)(par + c0 + 4 * q);
+            m |= (v.x == c0 + 4 * q ? 1u : 0u) << (4 * q);
+            m |= (v.y == c0 + 4 * q + 1 ? 1u : 0u) << (4 * q + 1);
+            m |= (v.z == c0 + 4 * q + 2 ? 1u : 0u) << (4 * q + 2);
+            m |= (v.w == c0 + 4 * q + 3 ? 1u : 0u) << (4 * q + 3);
+        }
+    } else {
+        for (int j = 0; j < 16; ++j)
+            if (c0 + j < n && par[c0 + j] == c0 + j) m |= 1u << j;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_root_count(const int32_t *__restrict__ nreg0,
+                                                         const int32_t *__restrict__ par, int32_t *__restrict__ bcnt) {
+    static_assert(SCAN_B == NTHREADS * 16, "16 ids per thread");
+    const int32_t n = *nreg0;
+    if ((int64_t)blockIdx.x * SCAN_B >= n) {
+        if (threadIdx.x == 0) bcnt[blockIdx.x] = 0;
+        return;
+    }
+    const int32_t c0 = blockIdx.x * SCAN_B + threadIdx.x * 16;
+    int excl;
+    const int total = block_scan_excl(__popc(root_mask16(par, c0, n)), excl);
+    if (threadIdx.x == 0) bcnt[blockIdx.x] = total;
+}
+
+// R1[rank] = root and id1[root] = rank, from the scanned block counts.
+__global__ __launch_bounds__(NTHREADS) void k_root_scatter(const int32_t *__restrict__ nreg0,
+                                                           const int32_t *__restrict__ par,
+                                                           const int32_t *__restrict__ bcnt, int32_t *__restrict__ R1,
+                                                           int32_t *__restrict__ id1) {
+    const int32_t n = *nreg0;
+    if ((int64_t)blockIdx.x * SCAN_B >= n) return;
+    const int32_t c0 = blockIdx.x * SCAN_B + threadIdx.x * 16;
+    const uint32_t m = root_mask16(par, c0, n);
+    int excl;
+    block_scan_excl(__popc(m), excl);
+    int32_t rank = bcnt[blockIdx.x] + excl;
+    for (uint32_t b = m; b; b &= b - 1) {
+        const int32_t c = c0 + __ffs(b) - 1;
+        R1[rank] = c;
+        id1[c] = rank++;
+    }
+}
+
+// Layer 1's compression, also giving every region the rank of its root.
+__global__ __launch_bounds__(NTHREADS) void k_wf_compress1(const int32_t *__restrict__ nreg0, int32_t *__restrict__ par,
+                                                           const int32_t *__restrict__ rlist,
+                                                           int32_t *__restrict__ mlab1, int32_t *__restrict__ id1) {
+    const int32_t n = *nreg0;
+    for (int32_t c = xcd_group(blockIdx.x, gridDim.x, XG_REG) * NTHREADS + threadIdx.x; c < n;
+         c += gridDim.x * NTHREADS) {
+        int32_t r = gfind_ro(par, c);
+        par[c] = r;
+        mlab1[c] = rlist[r];
+        if (r != c) id1[c] = id1[r];  // roots already hold their rank
+    }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_wf_hook_l(const int32_t *__restrict__ n1p, const int32_t *__restrict__ R1,
+                                                        const uint64_t *__restrict__ key, int32_t *__restrict__ par) {
+    const int32_t n = *n1p;
+    for (int32_t i = xcd_group(blockIdx.x, gridDim.x, XG_REG) * NTHREADS + threadIdx.x; i < n;
+         i += gridDim.x * NTHREADS) {
+        const int32_t c = R1[i];
+        uint64_t kk = key[c];
+        int32_t tg = (int32_t)(uint32_t)(kk & 0xffffffffull);
+        if (kk != NOKEY && tg < c) par[c] = tg;
+    }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_wf_union_l(const int32_t *__restrict__ n1p, const int32_t *__restrict__ R1,
+                                                         uint64_t *__restrict__ key, int32_t *__restrict__ par) {
+    const int32_t n = *n1p;
+    for (int32_t i = xcd_group(blockIdx.x, gridDim.x, XG_REG) * NTHREADS + threadIdx.x; i < n;
+         i += gridDim.x * NTHREADS) {
+        const int32_t c = R1[i];
+        uint64_t kk = key[c];
+        if (kk == NOKEY) continue;
+        key[c] = NOKEY;
+        int32_t tg = (int32_t)(uint32_t)(kk & 0xffffffffull);
+        if (tg > c) gunion(par, c, tg);
+    }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_wf_compress_l(const int32_t *__restrict__ n1p,
+                                                            const int32_t *__restrict__ R1, int32_t *__restrict__ par,
+                                                            const int32_t *__restrict__ rlist,
+                                                            int32_t *__restrict__ Mk) {
+    const int32_t n = *n1p;
+    for (int32_t i = xcd_group(blockIdx.x, gridDim.x, XG_REG) * NTHREADS + threadIdx.x; i < n;
+         i += gridDim.x * NTHREADS) {
+        const int32_t c = R1[i];
+        int32_t r = gfind_ro(par, c);
+        par[c] = r;
+        Mk[i] = rlist[r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. Layers 1 .. nl-1 of every pixel from its region id, chunk by chunk. The
+// label tables (mstride ints apart): layer 1 by region id at mlab; for
+// nl >= 3 the rank of every region's layer-1 root at mlab + mstride, and
+// layer k >= 2 by that rank at mlab + (k + 1) mstride.
 // (RCH consecutive pixels of one image), and per chunk the number of pixels
 // carrying their own label in each layer, cnt[k * nchunks + t]. Layer 0's
 // count is the chunk's root count, the difference of consecutive chunk
@@ -599,9 +717,16 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks
 #pragma unroll
         for (int e = 0; e < 4; ++e) c[r][e] = (uint32_t)c[r][e] <= cmax ? c[r][e] : (int32_t)cmax;
     }
+    int32_t rk[RUNS][4];  // rank of the layer-1 root (tables of layers >= 2)
+    if (nl >= 3) {
+#pragma unroll
+        for (int r = 0; r < RUNS; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rk[r][e] = mlab[(size_t)mstride + c[r][e]];
+    }
 #pragma unroll 1
     for (int k = 1; k < nl; ++k) {
-        const int32_t *m = mlab + (size_t)(k - 1) * (size_t)mstride;
+        const int32_t *m = mlab + (k == 1 ? 0 : (size_t)(k + 1) * (size_t)mstride);
         int32_t *out = im.lab + (size_t)k * (size_t)n;
         if (threadIdx.x == 0) kc = 0;
         __syncthreads();
@@ -610,7 +735,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks
         for (int r = 0; r < RUNS; ++r) {
             int32_t v[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = m[c[r][e]];
+            for (int e = 0; e < 4; ++e) v[e] = m[k == 1 ? c[r][e] : rk[r][e]];
 #pragma unroll
             for (int e = 0; e < 4; ++e) own += (p0[r] + e < n && v[e] == p0[r] + e) ? 1 : 0;
             if (vec && p0[r] + 3 < n) {
@@ -711,10 +836,19 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out_p(Src src_ch, int32_t nchun
     const char *mb = (const char *)mlab;
     const size_t mstep = (size_t)mstride * sizeof(int32_t);
     int32_t V[2][WF_RUNS][4];
-    wf_gather(V[0], off, mb);
+    wf_gather(V[0], off, mb);  // layer 1, by region id
+    uint32_t off2[WF_RUNS][4];  // layers >= 2, by the rank of the layer-1 root
+    if (NLM >= 2) {
+        int32_t rk[WF_RUNS][4];
+        wf_gather(rk, off, mb + mstep);
+#pragma unroll
+        for (int r = 0; r < WF_RUNS; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) off2[r][e] = (uint32_t)rk[r][e] * 4u;
+    }
 #pragma unroll
     for (int k = 0; k < NLM; ++k) {  // V[k & 1] holds layer k + 1
-        if (k + 1 < NLM) wf_gather(V[(k + 1) & 1], off, mb + (size_t)(k + 1) * mstep);
+        if (k + 1 < NLM) wf_gather(V[(k + 1) & 1], off2, mb + (size_t)(k + 3) * mstep);
         wf_emit(V[k & 1], p0, n, vec, im.lab + (size_t)(k + 1) * (size_t)n, &kc[k + 1]);
     }
     __syncthreads();
@@ -847,6 +981,36 @@ int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, int32_t 
                   key, edges, edges + E, edges + 2 * E, ecnt);
 }
 
+int launch_root_list(Launch &lc, int32_t bound, const int32_t *nreg0, const int32_t *par, int32_t *R1, int32_t *id1,
+                     int32_t *scratch, int32_t *n1) {
+    const int32_t nb = (bound + SCAN_B - 1) / SCAN_B > 0 ? (bound + SCAN_B - 1) / SCAN_B : 1;
+    int32_t *bcnt = scratch, *tmp = scratch + nb;
+    int rc = lc.run("wf_union", k_root_count, dim3(nb), dim3(NTHREADS), nreg0, par, bcnt);
+    if (rc) return rc;
+    if ((rc = launch_scan(lc, nb, bcnt, tmp, n1))) return rc;
+    return lc.run("wf_union", k_root_scatter, dim3(nb), dim3(NTHREADS), nreg0, par, (const int32_t *)bcnt, R1, id1);
+}
+int root_list_tmp_len(int32_t bound) {
+    const int32_t nb = (bound + SCAN_B - 1) / SCAN_B > 0 ? (bound + SCAN_B - 1) / SCAN_B : 1;
+    return nb + scan_tmp_len(nb);
+}
+int launch_wf_compress1(Launch &lc, int32_t bound, const int32_t *nreg0, int32_t *par, const int32_t *rlist,
+                        int32_t *mlab1, int32_t *id1) {
+    return lc.run("wf_compress", k_wf_compress1, list_grid(bound), dim3(NTHREADS), nreg0, par, rlist, mlab1, id1);
+}
+// The root list holds a few per cent of the pixels on natural images: its
+// grids are sized for bound / 32 ids (grid-stride loops cover any length), so
+// later layers do not dispatch thousands of empty workgroups.
+static inline dim3 root_grid(int32_t bound) { return list_grid(bound / 32 > 0 ? bound / 32 : 1); }
+int launch_wf_union_l(Launch &lc, int32_t bound, const int32_t *n1, const int32_t *R1, uint64_t *key, int32_t *par) {
+    int rc = lc.run("wf_union", k_wf_hook_l, root_grid(bound), dim3(NTHREADS), n1, R1, (const uint64_t *)key, par);
+    if (rc) return rc;
+    return lc.run("wf_union", k_wf_union_l, root_grid(bound), dim3(NTHREADS), n1, R1, key, par);
+}
+int launch_wf_compress_l(Launch &lc, int32_t bound, const int32_t *n1, const int32_t *R1, int32_t *par,
+                         const int32_t *rlist, int32_t *Mk) {
+    return lc.run("wf_compress", k_wf_compress_l, root_grid(bound), dim3(NTHREADS), n1, R1, par, rlist, Mk);
+}
 int launch_wf_union(Launch &lc, int32_t bound, const int32_t *nreg0, uint64_t *key, int32_t *par) {
     int rc = lc.run("wf_union", k_wf_hook, list_grid(bound), dim3(NTHREADS), nreg0, (const uint64_t *)key, par);
     if (rc) return rc;
