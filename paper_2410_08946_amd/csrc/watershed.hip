@@ -47,6 +47,42 @@ __device__ __forceinline__ void load_dist(const Geom &g, const int32_t *__restri
     load_box<S::SX, S::SY, S::SZ, int32_t, int>(g, ox - 1, oy - 1, oz - S::RZ, D, sD, INF);
 }
 
+// Grey values and D of the tile plus a ring of width 1 in one batch of loads
+// (one wait for both arrays instead of one each); cells outside the image get
+// SENT and INF.
+template <int NDIM, typename T>
+__device__ __forceinline__ void load_grey_dist(const Geom &g, const T *__restrict__ I, const int32_t *__restrict__ D,
+                                               int *sI, int *sD, int ox, int oy, int oz) {
+    using S = Lds<NDIM, 1>;
+    constexpr int PER = (S::CELLS + NTHREADS - 1) / NTHREADS;
+    int32_t idx[PER];
+    uint32_t okm = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int c = threadIdx.x + j * NTHREADS;
+        int cx = c % S::SX, cy = (c / S::SX) % S::SY, cz = c / (S::SX * S::SY);
+        int x = ox - 1 + cx, y = oy - 1 + cy, z = oz - S::RZ + cz;
+        bool ok = c < S::CELLS && in_image(g, x, y, z);
+        okm |= (ok ? 1u : 0u) << j;
+        idx[j] = ok ? x + g.nx * (y + g.ny * z) : 0;
+    }
+    T v[PER];
+    int32_t d[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) v[j] = I[idx[j]];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) d[j] = D[idx[j]];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int c = threadIdx.x + j * NTHREADS;
+        if (c < S::CELLS) {
+            bool ok = okm >> j & 1u;
+            sI[c] = ok ? (int)v[j] : SENT;
+            sD[c] = ok ? d[j] : INF;
+        }
+    }
+}
+
 // Relaxes the plateau distances of the tile's pixels to a local fixpoint
 // (ring cells frozen). Returns after an iteration in which no thread changed
 // anything. Gauss-Seidel order inside LDS; any order reaches the same fixpoint
@@ -301,8 +337,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, 
         if (threadIdx.x == 0) smk = 0;
         int32_t *D = Darena + im.pix0;
         int ox = tx * TS::X, oy = ty * TS::Y, oz = tz * TS::Z;
-        load_grey<NDIM, 1, T>(g, (const T *)im.grey, sI, ox, oy, oz);
-        load_dist<NDIM>(g, D, sD, ox, oy, oz);
+        load_grey_dist<NDIM, T>(g, (const T *)im.grey, D, sI, sD, ox, oy, oz);
         __syncthreads();
         const int n = build_list<NDIM, 1>(sI, sD, lst, true);
         uint32_t faces = 0;
@@ -465,8 +500,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
         int32_t *L = im.lab;
         int ox, oy, oz;
         ws_tile<NDIM>(g, lt, ox, oy, oz);
-        load_grey<NDIM, 1, T>(g, (const T *)im.grey, sI, ox, oy, oz);
-        load_dist<NDIM>(g, Darena + im.pix0, sD, ox, oy, oz);
+        load_grey_dist<NDIM, T>(g, (const T *)im.grey, Darena + im.pix0, sI, sD, ox, oy, oz);
         __syncthreads();
         uint32_t minzone = 0, inimg = 0;
         int32_t *trec = rec + (size_t)t * Border<NDIM>::NB;
