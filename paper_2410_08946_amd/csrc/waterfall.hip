@@ -470,28 +470,54 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_level(int32_t ntiles, int32_t g
     __syncthreads();
     const int32_t total = stotal;
     const size_t base = (size_t)t0 * (size_t)cap;
-    for (int32_t e0 = 0; e0 < total; e0 += NTHREADS) {  // uniform trip count
-        int32_t e = e0 + threadIdx.x;
-        int32_t ra = 0, rb = 0;
-        uint32_t w = 0;
-        if (e < total) {
-            int lo = 0, hi = nsub - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (soff[mid] <= e) lo = mid;
-                else hi = mid - 1;
+    // LEV_U edges per thread per batch: all their loads, then all their parent
+    // gathers, are issued before the first wait (two round trips per batch)
+    constexpr int LEV_U = 4;
+    for (int32_t e0 = 0; e0 < total; e0 += NTHREADS * LEV_U) {  // uniform trip count
+        int32_t ra[LEV_U], rb[LEV_U];
+        uint32_t w[LEV_U];
+        size_t at[LEV_U];
+#pragma unroll
+        for (int u = 0; u < LEV_U; ++u) {
+            int32_t e = e0 + u * NTHREADS + (int)threadIdx.x;
+            at[u] = 0;
+            if (e < total) {
+                int lo = 0, hi = nsub - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (soff[mid] <= e) lo = mid;
+                    else hi = mid - 1;
+                }
+                at[u] = (size_t)(t0 + lo * gin) * (size_t)cap + (size_t)(e - soff[lo]);
             }
-            size_t at = (size_t)(t0 + lo * gin) * (size_t)cap + (size_t)(e - soff[lo]);
-            int32_t a = ea[at], b = eb[at];
-            w = (uint32_t)eww[at];
-            ra = par[a];
-            rb = par[b];
         }
+        // branch-free: lanes past the end read slab entry 0 (allocated, any
+        // contents) and parent 0, and use neither
+        int32_t a[LEV_U], b[LEV_U];
+#pragma unroll
+        for (int u = 0; u < LEV_U; ++u) {
+            a[u] = ea[at[u]];
+            b[u] = eb[at[u]];
+            w[u] = (uint32_t)eww[at[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < LEV_U; ++u) {
+            const bool ok = e0 + u * NTHREADS + (int)threadIdx.x < total;
+            ra[u] = par[ok ? a[u] : 0];
+            rb[u] = par[ok ? b[u] : 0];
+        }
+        // this batch's reads precede every write below: a workgroup's vector
+        // memory operations pass through its CU's cache in issue order, so a
+        // store issued after the barrier cannot overtake a load issued before it
         __syncthreads();
-        if (e < total && ra != rb) {
-            int32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
-            uint64_t pair = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi;
-            if (!edge_insert(ek, ew, pair, w)) edge_direct(&ectr, key, ea, eb, eww, base, lo, hi, w);
+#pragma unroll
+        for (int u = 0; u < LEV_U; ++u) {
+            int32_t e = e0 + u * NTHREADS + (int)threadIdx.x;
+            if (e < total && ra[u] != rb[u]) {
+                int32_t lo = ra[u] < rb[u] ? ra[u] : rb[u], hi = ra[u] < rb[u] ? rb[u] : ra[u];
+                uint64_t pair = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi;
+                if (!edge_insert(ek, ew, pair, w[u])) edge_direct(&ectr, key, ea, eb, eww, base, lo, hi, w[u]);
+            }
         }
     }
     __syncthreads();
