@@ -612,12 +612,24 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_merge(Src src, int32_t ntiles, 
         int ox, oy, oz;
         ws_tile<NDIM>(g, lt, ox, oy, oz);
         const int32_t *trec = rec + (size_t)t * NB;
-        for (int b = threadIdx.x; b < NB; b += NTHREADS) {
+        // all of this thread's records are loaded in one batch (cells past
+        // the border count read record 0 and are skipped)
+        constexpr int MU = (NB + NTHREADS - 1) / NTHREADS;
+        int32_t codes[MU];
+#pragma unroll
+        for (int u = 0; u < MU; ++u) {
+            int b = threadIdx.x + u * NTHREADS;
+            codes[u] = trec[b < NB ? b : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < MU; ++u) {
+            int b = threadIdx.x + u * NTHREADS;
+            if (b >= NB) continue;
             int x, y, z;
             border_cell<NDIM>(b, x, y, z);
             int gx = ox + x, gy = oy + y, gz = oz + z;
             if (!in_image(g, gx, gy, gz)) continue;
-            int32_t code = trec[b];
+            int32_t code = codes[u];
             if (code == -1) continue;
             int32_t p = gx + g.nx * (gy + g.ny * gz);
             if (code >= 0) {
