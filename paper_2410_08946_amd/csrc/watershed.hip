@@ -32,12 +32,19 @@
 
 namespace wsk {
 
-// Loads grey values of the tile plus a ring of width R into LDS as int32;
-// cells outside the image get SENT.
-template <int NDIM, int R, typename T>
-__device__ __forceinline__ void load_grey(const Geom &g, const T *__restrict__ I, int *sI, int ox, int oy, int oz) {
+// LDS cells of grey values: 16-bit for uint8 images (out-of-image sentinel
+// 0x100, above every uint8 value), int32 for uint16 images (SENT, above every
+// uint16 value). Smaller cells let more 3D tiles share a CU's LDS.
+template <typename T> struct GreyCell { using type = int; };
+template <> struct GreyCell<uint8_t> { using type = uint16_t; };
+template <typename GC> __host__ __device__ constexpr int sent_of() { return sizeof(GC) == 2 ? 0x100 : SENT; }
+
+// Loads grey values of the tile plus a ring of width R into LDS; cells
+// outside the image get the sentinel.
+template <int NDIM, int R, typename T, typename GC>
+__device__ __forceinline__ void load_grey(const Geom &g, const T *__restrict__ I, GC *sI, int ox, int oy, int oz) {
     using S = Lds<NDIM, R>;
-    load_box<S::SX, S::SY, S::SZ, T, int>(g, ox - R, oy - R, oz - S::RZ, I, sI, SENT);
+    load_box<S::SX, S::SY, S::SZ, T, GC>(g, ox - R, oy - R, oz - S::RZ, I, sI, (GC)sent_of<GC>());
 }
 
 // Loads D of the tile plus a ring of width 1; cells outside the image get INF.
@@ -50,9 +57,9 @@ __device__ __forceinline__ void load_dist(const Geom &g, const int32_t *__restri
 // Grey values and D of the tile plus a ring of width 1 in one batch of loads
 // (one wait for both arrays instead of one each); cells outside the image get
 // SENT and INF.
-template <int NDIM, typename T>
+template <int NDIM, typename T, typename GC>
 __device__ __forceinline__ void load_grey_dist(const Geom &g, const T *__restrict__ I, const int32_t *__restrict__ D,
-                                               int *sI, int *sD, int ox, int oy, int oz) {
+                                               GC *sI, int *sD, int ox, int oy, int oz) {
     using S = Lds<NDIM, 1>;
     constexpr int PER = (S::CELLS + NTHREADS - 1) / NTHREADS;
     int32_t idx[PER];
@@ -77,7 +84,7 @@ __device__ __forceinline__ void load_grey_dist(const Geom &g, const T *__restric
         int c = threadIdx.x + j * NTHREADS;
         if (c < S::CELLS) {
             bool ok = okm >> j & 1u;
-            sI[c] = ok ? (int)v[j] : SENT;
+            sI[c] = ok ? (GC)v[j] : (GC)sent_of<GC>();
             sD[c] = ok ? d[j] : INF;
         }
     }
@@ -87,8 +94,8 @@ __device__ __forceinline__ void load_grey_dist(const Geom &g, const T *__restric
 // (ring cells frozen). Returns after an iteration in which no thread changed
 // anything. Gauss-Seidel order inside LDS; any order reaches the same fixpoint
 // because distances only decrease and every value stays an upper bound.
-template <int NDIM, int CONN, int R>
-__device__ __forceinline__ void relax_tile(int *sI, int *sD) {
+template <int NDIM, int CONN, int R, typename GC>
+__device__ __forceinline__ void relax_tile(const GC *sI, int *sD) {
     using TS = TileShape<NDIM>;
     using S = Lds<NDIM, R>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
@@ -99,8 +106,8 @@ __device__ __forceinline__ void relax_tile(int *sI, int *sD) {
             int s = S::at(x, y, z);
             int d = sD[s];
             if (d == 0) continue;          // fixed (lower neighbour / minimum) or
-            int v = sI[s];                 // out of image (d == INF, v == SENT)
-            if (v == SENT) continue;
+            int v = sI[s];                 // out of image (d == INF, v == sentinel)
+            if (v == sent_of<GC>()) continue;
             int best = d;
 #pragma unroll
             for (int k = 0; k < CONN; ++k) {
@@ -153,10 +160,10 @@ __device__ __forceinline__ void ws_tile(const Geom &g, int lt, int &ox, int &oy,
 // tile with more than LCAP of them relaxes the whole tile instead.
 constexpr int LCAP = NTHREADS;  // one list entry per thread
 
-// Tile pixels i with sI != SENT and (sweep ? D != 0 : D == INF) into lst, in
+// Tile pixels i in the image and with (sweep ? D != 0 : D == INF) into lst, in
 // index order; returns their number (entries beyond LCAP are not stored).
-template <int NDIM, int R>
-__device__ __forceinline__ int build_list(const int *sI, const int *sD, unsigned short *lst, bool sweep) {
+template <int NDIM, int R, typename GC>
+__device__ __forceinline__ int build_list(const GC *sI, const int *sD, unsigned short *lst, bool sweep) {
     using TS = TileShape<NDIM>;
     using S = Lds<NDIM, R>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
@@ -168,7 +175,7 @@ __device__ __forceinline__ int build_list(const int *sI, const int *sD, unsigned
         int x, y, z;
         tile_pixel<NDIM>(threadIdx.x + j * NTHREADS, x, y, z);
         int sc = S::at(x, y, z), d = sD[sc];
-        bool take = sI[sc] != SENT && (sweep ? d != 0 : d == INF);
+        bool take = (int)sI[sc] != sent_of<GC>() && (sweep ? d != 0 : d == INF);
         m |= (take ? 1u : 0u) << j;
     }
     int excl;
@@ -183,8 +190,8 @@ __device__ __forceinline__ int build_list(const int *sI, const int *sD, unsigned
 }
 
 // relax_tile restricted to the n <= LCAP listed pixels (entry threadIdx.x).
-template <int NDIM, int CONN, int R>
-__device__ __forceinline__ void relax_list(const int *sI, int *sD, const unsigned short *lst, int n) {
+template <int NDIM, int CONN, int R, typename GC>
+__device__ __forceinline__ void relax_list(const GC *sI, int *sD, const unsigned short *lst, int n) {
     using S = Lds<NDIM, R>;
     int sc = -1, v = 0;
     if ((int)threadIdx.x < n) {
@@ -239,7 +246,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
     using S2 = Lds<NDIM, 2>;
     using S1 = Lds<NDIM, 1>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
-    __shared__ int sI[S2::CELLS];
+    using GC = typename GreyCell<T>::type;
+    __shared__ GC sI[S2::CELLS];
     __shared__ int sD[S2::CELLS];
     __shared__ unsigned short lst[LCAP];
     __shared__ int smk;
@@ -262,10 +270,10 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
             int s = S2::at(cx - 1, cy - 1, cz - S1::RZ);
             int v = sI[s];
             int d = INF;
-            if (v != SENT) {
-                int m = SENT;
+            if (v != sent_of<GC>()) {
+                int m = sent_of<GC>();
 #pragma unroll
-                for (int k = 0; k < CONN; ++k) m = min(m, sI[s + S2::template off<CONN>(k)]);
+                for (int k = 0; k < CONN; ++k) m = min(m, (int)sI[s + S2::template off<CONN>(k)]);
                 d = (m == v) ? INF : 0;
             }
             sD[s] = d;
@@ -302,7 +310,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, 
     constexpr int PIX = TS::X * TS::Y * TS::Z;
     constexpr int PER = (PIX + NTHREADS - 1) / NTHREADS;
     constexpr bool FACES = CONN == 4 || CONN == 6;  // only face neighbours interact
-    __shared__ int sI[S::CELLS];
+    using GC = typename GreyCell<T>::type;
+    __shared__ GC sI[S::CELLS];
     __shared__ int sD[S::CELLS];
     __shared__ unsigned short lst[LCAP];
     __shared__ int smk;
@@ -393,16 +402,16 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, 
 // the pixel points to, -1 for a root (local minimum), -2 for a minimal
 // plateau pixel (joined with its equal neighbours instead).
 // ---------------------------------------------------------------------------
-template <int NDIM, int CONN>
-__device__ __forceinline__ int lds_arrow(const int *sI, const int *sD, int s) {
+template <int NDIM, int CONN, typename GC>
+__device__ __forceinline__ int lds_arrow(const GC *sI, const int *sD, int s) {
     using S = Lds<NDIM, 1>;
     int v = sI[s], d = sD[s];
     if (d == INF) return -2;
     if (d == 0) {
-        int m = SENT, kq = -1;
+        int m = sent_of<GC>(), kq = -1;
 #pragma unroll
         for (int k = 0; k < CONN; ++k) {
-            int w = sI[s + S::template off<CONN>(k)];
+            int w = sI[s + S::template off<CONN>(k)];  // promoted to int
             if (w <= m) { m = w; kq = k; }     // Eq. (1): last of the lowest
         }
         return (m < v) ? kq : -1;
@@ -487,7 +496,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
     constexpr int PIX = TS::X * TS::Y * TS::Z;
     constexpr int PER = PIX / NTHREADS;
     static_assert(PIX % NTHREADS == 0, "tile must be a multiple of the workgroup");
-    __shared__ int sI[S::CELLS];
+    using GC = typename GreyCell<T>::type;
+    __shared__ GC sI[S::CELLS];
     __shared__ int sD[S::CELLS];
     __shared__ int sP[PIX];
     {
