@@ -322,12 +322,16 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
     // sL/sI hold the tile's ids and grey values; once the edges are collected
     // the same words hold the region hash (keys, then 64-bit minima)
     constexpr int RBITS = 9;
-    static_assert((1 << RBITS) * 12 <= CELLS * 8, "region hash fits the id/grey arrays");
-    __shared__ unsigned long long sbuf[CELLS];
+    // ids int32 + grey uint16 per cell (6 B: a 2D tile's arrays and hashes
+    // stay within the 20 KB of eight workgroups per CU)
+    constexpr int SBUF = (CELLS * 6 + 7) / 8;
+    static_assert((1 << RBITS) * 12 <= SBUF * 8, "region hash fits the id/grey arrays");
+    __shared__ unsigned long long sbuf[SBUF];
     __shared__ unsigned long long ek[ESLOTS];
     __shared__ unsigned int ew[ESLOTS];
     __shared__ int ectr;
-    int *sL = (int *)sbuf, *sI = sL + CELLS;
+    int *sL = (int *)sbuf;
+    uint16_t *sI = (uint16_t *)(sL + CELLS);
     int *hk = (int *)sbuf;
     unsigned long long *hv = sbuf + (1 << RBITS) / 2;
     if ((int)blockIdx.x >= ntiles) return;
@@ -378,7 +382,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
             cv = cv <= cmax ? cv : cmax;
             if (c < CELLS) {
                 sL[c] = ok[j] ? (int)cv : -1;
-                sI[c] = ok[j] ? (int)gv[j] : 0;
+                sI[c] = ok[j] ? (uint16_t)gv[j] : (uint16_t)0;
             }
             if (own[j]) {
                 cimg[(size_t)im.pix0 + idx[j]] = (int32_t)cv;
