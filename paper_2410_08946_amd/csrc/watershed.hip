@@ -496,10 +496,13 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
     constexpr int PIX = TS::X * TS::Y * TS::Z;
     constexpr int PER = PIX / NTHREADS;
     static_assert(PIX % NTHREADS == 0, "tile must be a multiple of the workgroup");
+    static_assert(S::CELLS >= PIX, "the parent array fits the distance array");
     using GC = typename GreyCell<T>::type;
+    // two LDS arrays: grey values, and distances that become the tile's
+    // parent array once every arrow is known
     __shared__ GC sI[S::CELLS];
     __shared__ int sD[S::CELLS];
-    __shared__ int sP[PIX];
+    int *sP = sD;
     {
         if ((int)blockIdx.x >= ntiles) return;
         const int t = xcd_tile(blockIdx.x, ntiles);
@@ -513,6 +516,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
         load_grey_dist<NDIM, T>(g, (const T *)im.grey, Darena + im.pix0, sI, sD, ox, oy, oz);
         __syncthreads();
         uint32_t minzone = 0, inimg = 0;
+        int tos[PER];
         int32_t *trec = rec + (size_t)t * Border<NDIM>::NB;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
@@ -543,8 +547,11 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
                 }
                 if (on_tile_border<NDIM>(x, y, z)) trec[border_index<NDIM>(x, y, z)] = code;
             }
-            sP[i] = to;
+            tos[j] = to;
         }
+        __syncthreads();  // every distance read: the array becomes the parents
+#pragma unroll
+        for (int j = 0; j < PER; ++j) sP[threadIdx.x + j * NTHREADS] = tos[j];
         __syncthreads();
         // pointer jumping to the in-tile terminals
         for (;;) {
@@ -576,18 +583,18 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
             }
         }
         __syncthreads();
-        // smallest pixel of every tile-local component (sD reused)
-        int *cm = sD;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) cm[threadIdx.x + j * NTHREADS] = 0x7fffffff;
-        __syncthreads();
+        // smallest pixel of every tile-local component, in the root's own
+        // parent entry once every root is known: a root holds its own index,
+        // and the root of an in-image pixel is itself in the image (arrows and
+        // plateau unions never reach a cell outside), so it is a candidate
         int root[PER];
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            int i = threadIdx.x + j * NTHREADS;
-            root[j] = lfind(sP, i);
-            if (inimg >> j & 1u) atomicMin(&cm[root[j]], i);
-        }
+        for (int j = 0; j < PER; ++j) root[j] = lfind(sP, threadIdx.x + j * NTHREADS);
+        __syncthreads();
+        int *cm = sP;
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (inimg >> j & 1u) atomicMin(&cm[root[j]], (int)(threadIdx.x + j * NTHREADS));
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
