@@ -795,24 +795,36 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks
 constexpr int WF_OUT_MAXNL = 8;
 constexpr int WF_RUNS = RCH / (4 * NTHREADS);  // runs of 4 pixels per thread
 
-// byte offsets from a uniform table base: one offset register per pixel
+// Table gathers as raw buffer loads: a 32-bit byte offset per pixel against a
+// per-table descriptor (base, size), so no 64-bit per-lane address is formed
+// (with global loads the compiler kept one register pair per pixel and layer,
+// 106 registers at six layers). Offsets past the table's size read 0.
+constexpr int BUF_CONFIG = 0x00020000;  // raw 32-bit buffer, gfx9 family
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const int32_t *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, BUF_CONFIG);
+}
 __device__ __forceinline__ void wf_gather(int32_t (&v)[WF_RUNS][4], const uint32_t (&off)[WF_RUNS][4],
-                                          const char *__restrict__ m) {
+                                          __amdgpu_buffer_rsrc_t rs) {
 #pragma unroll
     for (int r = 0; r < WF_RUNS; ++r)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[r][e] = *(const int32_t *)(m + off[r][e]);
+        for (int e = 0; e < 4; ++e) v[r][e] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off[r][e], 0, 0);
 }
 
+typedef int wf_v4i __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void wf_emit(const int32_t (&v)[WF_RUNS][4], const int32_t (&p0)[WF_RUNS], int32_t n,
                                         bool vec, int32_t *__restrict__ out, int *kc) {
     int own = 0;
+    // 16-byte runs as raw buffer stores (32-bit offsets against the layer's
+    // descriptor); a layer of n < 2^30 pixels stays below 4 GiB
+    const __amdgpu_buffer_rsrc_t rs = table_rsrc(out, (uint32_t)((size_t)n * 4));
 #pragma unroll
     for (int r = 0; r < WF_RUNS; ++r) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) own += __popcll(__ballot(p0[r] + e < n && v[r][e] == p0[r] + e));
         if (vec && p0[r] + 3 < n) {
-            *(int4 *)(out + p0[r]) = make_int4(v[r][0], v[r][1], v[r][2], v[r][3]);
+            wf_v4i d = {v[r][0], v[r][1], v[r][2], v[r][3]};
+            __builtin_amdgcn_raw_buffer_store_b128(d, rs, p0[r] * 4, 0, 0);
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
@@ -822,12 +834,33 @@ __device__ __forceinline__ void wf_emit(const int32_t (&v)[WF_RUNS][4], const in
     if (__lane_id() == 0 && own) atomicAdd(kc, own);
 }
 
+// Table bases passed one by one (t[0] layer 1 by id, t[1] the ranks, t[k]
+// layer k by rank): unrelated scalar bases, so every gather addresses its
+// table as base + 32-bit offset and no per-layer 64-bit address is kept.
+struct WfTabs {
+    const int32_t *t[WF_OUT_MAXNL];
+    uint32_t bytes;  // size of each table (< 4 GiB: larger arenas take the layer-by-layer kernel)
+};
+
+// Layers K+1 .. NLM of the pipeline, unrolled at compile time (the register
+// sets and the table bases are then indexed by constants): V[K & 1] holds
+// layer K + 1; the gathers of layer K + 2 are issued before it is stored.
+template <int K, int NLM>
+__device__ __forceinline__ void wf_layers(int32_t (&V)[2][WF_RUNS][4], const uint32_t (&off2)[WF_RUNS][4],
+                                          const int32_t (&p0)[WF_RUNS], int32_t n, bool vec, int32_t *lab,
+                                          const WfTabs &tabs, int *kc) {
+    if constexpr (K < NLM) {
+        if constexpr (K + 1 < NLM) wf_gather(V[(K + 1) & 1], off2, table_rsrc(tabs.t[K + 2], tabs.bytes));
+        wf_emit(V[K & 1], p0, n, vec, lab + (size_t)(K + 1) * (size_t)n, &kc[K + 1]);
+        wf_layers<K + 1, NLM>(V, off2, p0, n, vec, lab, tabs, kc);
+    }
+}
+
 template <class Src, int NLM>
 __global__ __launch_bounds__(NTHREADS) void k_wf_out_p(Src src_ch, int32_t nchunks,
                                                        const int32_t *__restrict__ cimg,
                                                        const int32_t *__restrict__ nreg0,
-                                                       const int32_t *__restrict__ coff,
-                                                       const int32_t *__restrict__ mlab, int64_t mstride,
+                                                       const int32_t *__restrict__ coff, WfTabs tabs,
                                                        int32_t *__restrict__ cnt) {
     static_assert(WF_RUNS * 4 * NTHREADS == RCH, "whole runs per chunk");
     __shared__ int kc[WF_OUT_MAXNL];
@@ -863,24 +896,18 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out_p(Src src_ch, int32_t nchun
 #pragma unroll
         for (int e = 0; e < 4; ++e) off[r][e] = ((uint32_t)c[e] <= cmax ? (uint32_t)c[e] : cmax) * 4u;
     }
-    const char *mb = (const char *)mlab;
-    const size_t mstep = (size_t)mstride * sizeof(int32_t);
     int32_t V[2][WF_RUNS][4];
-    wf_gather(V[0], off, mb);  // layer 1, by region id
+    wf_gather(V[0], off, table_rsrc(tabs.t[0], tabs.bytes));  // layer 1, by region id
     uint32_t off2[WF_RUNS][4];  // layers >= 2, by the rank of the layer-1 root
     if (NLM >= 2) {
         int32_t rk[WF_RUNS][4];
-        wf_gather(rk, off, mb + mstep);
+        wf_gather(rk, off, table_rsrc(tabs.t[1], tabs.bytes));
 #pragma unroll
         for (int r = 0; r < WF_RUNS; ++r)
 #pragma unroll
             for (int e = 0; e < 4; ++e) off2[r][e] = (uint32_t)rk[r][e] * 4u;
     }
-#pragma unroll
-    for (int k = 0; k < NLM; ++k) {  // V[k & 1] holds layer k + 1
-        if (k + 1 < NLM) wf_gather(V[(k + 1) & 1], off2, mb + (size_t)(k + 3) * mstep);
-        wf_emit(V[k & 1], p0, n, vec, im.lab + (size_t)(k + 1) * (size_t)n, &kc[k + 1]);
-    }
+    wf_layers<0, NLM>(V, off2, p0, n, vec, im.lab, tabs, kc);
     __syncthreads();
     if ((int)threadIdx.x >= 1 && (int)threadIdx.x <= NLM) cnt[(size_t)threadIdx.x * nchunks + t] = kc[threadIdx.x];
 }
@@ -890,11 +917,16 @@ static int wf_out_pipelined(Launch &lc, const Src &src_ch, int32_t nchunks, int3
                             const int32_t *nreg0, const int32_t *coff, const int32_t *mlab, int64_t mstride,
                             int32_t *cnt) {
     dim3 grid(nchunks > 0 ? nchunks : 1);
+    WfTabs tabs{};
+    tabs.bytes = (uint32_t)((size_t)mstride * 4);
+    tabs.t[0] = mlab;
+    if (nl >= 3) tabs.t[1] = mlab + mstride;
+    for (int k = 2; k < nl && k < WF_OUT_MAXNL; ++k) tabs.t[k] = mlab + (size_t)(k + 1) * (size_t)mstride;
     switch (nl - 1) {
 #define WF_OUT_P(M)                                                                                               \
     case M:                                                                                                       \
-        return lc.run("wf_out", k_wf_out_p<Src, M>, grid, dim3(NTHREADS), src_ch, nchunks, cimg, nreg0, coff, mlab, \
-                      mstride, cnt);
+        return lc.run("wf_out", k_wf_out_p<Src, M>, grid, dim3(NTHREADS), src_ch, nchunks, cimg, nreg0, coff, tabs, \
+                      cnt);
         WF_OUT_P(1)
         WF_OUT_P(2)
         WF_OUT_P(3)
@@ -1106,7 +1138,7 @@ static int wf_pix_dispatch(Launch &lc, const Src &src, const TileGrid &tg, int c
     int launch_wf_out(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t nl, const int32_t *cimg,            \
                       const int32_t *nreg0, const int32_t *coff, const int32_t *mlab, int64_t mstride,           \
                       int32_t *cnt) {                                                                             \
-        if (nl >= 2 && nl <= WF_OUT_MAXNL)                                                                        \
+        if (nl >= 2 && nl <= WF_OUT_MAXNL && (size_t)mstride * 4 <= 0xffffffffu)                                 \
             return wf_out_pipelined<Src>(lc, src_ch, nchunks, nl, cimg, nreg0, coff, mlab, mstride, cnt);        \
         return lc.run("wf_out", k_wf_out<Src>, dim3(nchunks > 0 ? nchunks : 1), dim3(NTHREADS), src_ch, nchunks, \
                       nl, cimg, nreg0, coff, mlab, mstride, cnt);                                                 \
