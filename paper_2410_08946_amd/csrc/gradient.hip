@@ -81,9 +81,15 @@ __global__ __launch_bounds__(NTHREADS) void k_grad_fused2d(Geom g, const float *
     constexpr int RW = GX + 2 + 2 * RB, RH = GY + 2 + 2 * RB;  // raw
     constexpr int BW = GX + 2, BH = GY + 2;                    // blurred
     constexpr int NT = 2 * RB + 1;
-    __shared__ float raw[RW * RH];
-    __shared__ float bx[BW * RH];
-    __shared__ float bb[BW * BH];
+    // rows padded to whole float4s: the blurs compute 4 outputs per item from
+    // 16-byte LDS reads (the 2 extra columns per row are never read back)
+    constexpr int BQ = (BW + 3) / 4;          // float4 blocks per blurred row
+    constexpr int BWP = 4 * BQ;               // blurred row pitch
+    constexpr int RWP = BWP + 2 * RB + ((BWP + 2 * RB) % 4 ? 4 - (BWP + 2 * RB) % 4 : 0);  // raw row pitch
+    static_assert(RWP >= RW && RWP % 4 == 0, "raw pitch");
+    __shared__ __align__(16) float raw[RWP * RH];
+    __shared__ __align__(16) float bx[BWP * RH];
+    __shared__ __align__(16) float bb[BWP * BH];
     float w[NT];
 #pragma unroll
     for (int k = 0; k < NT; ++k) w[k] = taps.w[k];
@@ -117,24 +123,48 @@ __global__ __launch_bounds__(NTHREADS) void k_grad_fused2d(Geom g, const float *
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             int c = threadIdx.x + j * NTHREADS;
-            if (c < CELLS) raw[c] = v[j];
+            if (c < CELLS) raw[(c / RW) * RWP + c % RW] = v[j];
         }
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < BW * RH; c += NTHREADS) {
-        const float *row = raw + (c / BW) * RW + c % BW;  // virtual x = x0-1+i-RB+k at row[k]
-        float s = 0.f;
+    // x blur: item = (row, block of 4 columns); output column i reads raw
+    // columns i .. i + 2RB of its row (the taps in order, as before)
+    for (int c = threadIdx.x; c < BQ * RH; c += NTHREADS) {
+        const int r = c / BQ, q = c % BQ;
+        const float4 *row = (const float4 *)(raw + r * RWP + 4 * q);
+        float in[4 + 2 * RB + 3];
 #pragma unroll
-        for (int k = 0; k < NT; ++k) s = __fmaf_rn(w[k], row[k], s);
-        bx[c] = s;
+        for (int u = 0; u < (4 + 2 * RB + 3) / 4; ++u) {
+            float4 f = row[u];
+            in[4 * u] = f.x;
+            in[4 * u + 1] = f.y;
+            in[4 * u + 2] = f.z;
+            in[4 * u + 3] = f.w;
+        }
+        float o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float s = 0.f;
+#pragma unroll
+            for (int k = 0; k < NT; ++k) s = __fmaf_rn(w[k], in[e + k], s);
+            o[e] = s;
+        }
+        *(float4 *)(bx + r * BWP + 4 * q) = make_float4(o[0], o[1], o[2], o[3]);
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < BW * BH; c += NTHREADS) {
-        const float *col = bx + c;  // rows j .. j+2RB of column i
-        float s = 0.f;
+    // y blur: item = (row, block of 4 columns); rows j .. j+2RB in order
+    for (int c = threadIdx.x; c < BQ * BH; c += NTHREADS) {
+        const int j = c / BQ, q = c % BQ;
+        float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int k = 0; k < NT; ++k) s = __fmaf_rn(w[k], col[k * BW], s);
-        bb[c] = s;
+        for (int k = 0; k < NT; ++k) {
+            float4 f = *(const float4 *)(bx + (j + k) * BWP + 4 * q);
+            s.x = __fmaf_rn(w[k], f.x, s.x);
+            s.y = __fmaf_rn(w[k], f.y, s.y);
+            s.z = __fmaf_rn(w[k], f.z, s.z);
+            s.w = __fmaf_rn(w[k], f.w, s.w);
+        }
+        *(float4 *)(bb + j * BWP + 4 * q) = s;
     }
     __syncthreads();
     float m = 0.f;
@@ -155,7 +185,7 @@ __global__ __launch_bounds__(NTHREADS) void k_grad_fused2d(Geom g, const float *
             yp = clampi(gy + 1, 0, g.ny - 1) - y0 + 1;
         }
         const int xc = i + 1, yc = j + 1;
-        const float *r0 = bb + ym * BW, *r1 = bb + yc * BW, *r2 = bb + yp * BW;
+        const float *r0 = bb + ym * BWP, *r1 = bb + yc * BWP, *r2 = bb + yp * BWP;
         float gxv = (r0[xp] - r0[xm]) + 2.f * (r1[xp] - r1[xm]) + (r2[xp] - r2[xm]);
         float gyv = (r2[xm] - r0[xm]) + 2.f * (r2[xc] - r0[xc]) + (r2[xp] - r0[xp]);
         float vv = sqrtf(gxv * gxv + gyv * gyv);
