@@ -139,6 +139,31 @@ __device__ __forceinline__ uint32_t face_bits(int x, int y, int z) {
     return b;
 }
 
+// Faces across which a border pixel's new distance d can shorten a neighbour's:
+// for every neighbour q of the pixel (LDS cell sc) outside the tile, with the
+// same grey value and a ring distance above d + 1 (the ring holds upper
+// bounds: distances only decrease), the faces that step crosses. A tile whose
+// neighbours report no such face cannot change in the next sweep.
+template <int NDIM, int CONN, int R, typename GC>
+__device__ __forceinline__ uint32_t cross_faces(const GC *sI, const int *sD, int sc, int x, int y, int z, int d) {
+    using TS = TileShape<NDIM>;
+    using S = Lds<NDIM, R>;
+    const int v = sI[sc];
+    uint32_t b = 0;
+#pragma unroll
+    for (int k = 0; k < CONN; ++k) {
+        const int dx = nb_dx<CONN>(k), dy = nb_dy<CONN>(k), dz = nb_dz<CONN>(k);
+        const int xx = x + dx, yy = y + dy, zz = z + dz;
+        const bool out = xx < 0 || xx >= TS::X || yy < 0 || yy >= TS::Y || zz < 0 || zz >= TS::Z;
+        if (!out) continue;
+        const int o = sc + S::template off<CONN>(k);
+        if ((int)sI[o] != v || sD[o] <= d + 1) continue;  // d + 1 cannot overflow: d < INF here
+        b |= (xx < 0 ? 1u : 0u) | (xx >= TS::X ? 2u : 0u) | (yy < 0 ? 4u : 0u) | (yy >= TS::Y ? 8u : 0u) |
+             (zz < 0 ? 16u : 0u) | (zz >= TS::Z ? 32u : 0u);
+    }
+    return b;
+}
+
 template <int NDIM>
 __device__ __forceinline__ void tile_pixel(int i, int &x, int &y, int &z) {
     using TS = TileShape<NDIM>;
@@ -288,9 +313,10 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
             tile_pixel<NDIM>(i, x, y, z);
             int gx = ox + x, gy = oy + y, gz = oz + z;
             if (!in_image(g, gx, gy, gz)) continue;
-            int d = sD[S2::at(x, y, z)];
+            const int sc = S2::at(x, y, z);
+            int d = sD[sc];
             D[gx + g.nx * (gy + g.ny * gz)] = d;
-            if (d != 0 && d != INF) faces |= face_bits<NDIM>(x, y, z);
+            if (d != 0 && d != INF && face_bits<NDIM>(x, y, z)) faces |= cross_faces<NDIM, CONN, 2>(sI, sD, sc, x, y, z, d);
         }
         stamp_tile(&smk, stamp, smask, changed, t, 0, faces);
     }
@@ -362,7 +388,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, 
                 int d = sD[sc];
                 if (d != before) {
                     D[(ox + x) + g.nx * ((oy + y) + g.ny * (oz + z))] = d;  // listed pixels are in the image
-                    faces |= face_bits<NDIM>(x, y, z);
+                    if (face_bits<NDIM>(x, y, z)) faces |= cross_faces<NDIM, CONN, 1>(sI, sD, sc, x, y, z, d);
                 }
             }
         } else {
@@ -386,10 +412,11 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, 
                 tile_pixel<NDIM>(i, x, y, z);
                 int gx = ox + x, gy = oy + y, gz = oz + z;
                 if (!in_image(g, gx, gy, gz)) continue;
-                int d = sD[S::at(x, y, z)];
+                const int sc = S::at(x, y, z);
+                int d = sD[sc];
                 if (d != before[j]) {
                     D[gx + g.nx * (gy + g.ny * gz)] = d;
-                    faces |= face_bits<NDIM>(x, y, z);
+                    if (face_bits<NDIM>(x, y, z)) faces |= cross_faces<NDIM, CONN, 1>(sI, sD, sc, x, y, z, d);
                 }
             }
         }
