@@ -99,10 +99,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--workload", choices=("single", "c2", "batch", "serve"), default="single",
+    ap.add_argument("--workload", choices=("single", "c2", "batch", "serve", "recon"), default="single",
                     help="single: the 4096x4096 image (default); c2: the 928^3 uint8 volume; batch: 512 uneven "
                          "2D images, one batched call vs one call per image; serve: Poisson arrivals of mixed "
-                         "2D/3D jobs through the continuous-batching server")
+                         "2D/3D jobs through the continuous-batching server; recon: the reconstruction waterfall "
+                         "against the graph waterfall on the three single-image workloads (differing pixels per "
+                         "layer, time per layer)")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="serve workload: request rates (req/s)")
     ap.add_argument("--requests", type=int, default=200, help="serve workload: requests per rate")
     ap.add_argument("--slots", type=int, default=4, help="serve workload: execution slots")
@@ -277,6 +279,85 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_recon(args):
+    """Reconstruction waterfall (Alg. 4 Steps V-VI, re-watershed per layer)
+    against the graph waterfall on the 256^2, 4096^2 and 928^3 workloads, from
+    the same watershed: region counts and differing pixels per layer, and the
+    time each added layer costs (cumulative runs with NL = 2 .. N; the paper
+    reports later reconstruction layers to be slower)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2410_08946_amd as ws
+
+    dev = torch.device("cuda:0")
+    ctx = ws.Context(0)
+    reps = max(1, min(args.steps, 5))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        z = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        z.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(z) / reps
+
+    results = {}
+    for name in ("c0", "c1", "c2"):
+        cfg = gen.CONFIGS[name]
+        shape = tuple(cfg["shape"])
+        print("bench: recon %s %s" % (name, shape), file=sys.stderr, flush=True)
+        if name == "c2":
+            img = gen.synth.blobs3d_device(shape, seed=cfg["seed"], device=dev)
+        else:
+            img = torch.from_numpy(gen.config_image(name)).to(dev)
+        grad = ctx.gradient(img, cfg["sigma"], cfg["dtype"])
+        del img
+        conn, NL = cfg["conn"], cfg["NL"]
+        lab = ctx.watershed(grad, conn)
+        g1, n1 = ctx.waterfall(lab, grad, conn, NL)
+        rc, nr = ctx.waterfall_recon(lab, grad, conn, NL)
+        torch.cuda.synchronize()
+        diff = [int((g1[k] != rc[k]).sum()) for k in range(NL)]
+        t_g1 = timed(lambda: ctx.waterfall(lab, grad, conn, NL, out=g1, nregions=n1))
+        cum = [timed(lambda k=k: ctx.waterfall_recon(lab, grad, conn, k, out=rc[:k], nregions=nr[:k]))
+               for k in range(1, NL + 1)]
+        N = int(np.prod(shape))
+        results[name] = {
+            "pixels": N, "NL": NL, "conn": conn,
+            "regions_g1": n1.cpu().tolist(), "regions_recon": nr.cpu().tolist(),
+            "differing_pixels": diff, "differing_fraction": [round(d / N, 6) for d in diff],
+            "ms_g1_all_layers": round(t_g1, 3),
+            "ms_recon_all_layers": round(cum[-1], 3),
+            "ms_recon_per_layer": [round(cum[0], 3)] + [round(cum[k] - cum[k - 1], 3) for k in range(1, NL)],
+        }
+        del g1, rc, lab, grad
+        torch.cuda.empty_cache()
+    line = {
+        "metric": "reconstruction vs graph waterfall: differing pixels per layer",
+        "value": results["c1"]["differing_pixels"][-1],
+        "unit": "pixels",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": 1,
+        "ms_per_step": results["c1"]["ms_recon_all_layers"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "config": {"workload": "256^2 u8 NL=3, 4096^2 u16 NL=6, 928^3 u8 NL=6: reconstruction waterfall vs graph "
+                               "waterfall from the same watershed", "parallelism": "single GPU"},
+        "per_workload": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -288,6 +369,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "recon":
+        bench_recon(args)
         return
     import numpy as np
     import torch

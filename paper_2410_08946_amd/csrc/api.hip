@@ -254,11 +254,12 @@ template <class Src>
 int run_distances(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg, int conn, bool u16, size_t arena) {
     int rc;
     if ((rc = ensure(c, c->D, arena * 4, "distances")) != WS_OK) return rc;
-    // per tile: the last sweep that changed its border, then the faces it changed
-    if ((rc = ensure(c, c->stamp, (size_t)tg.ntiles * 8, "tile stamps")) != WS_OK) return rc;
+    // per tile and sweep parity: the last sweep that changed its border, and
+    // the faces it changed
+    if ((rc = ensure(c, c->stamp, (size_t)tg.ntiles * 16, "tile stamps")) != WS_OK) return rc;
     if ((rc = ensure(c, c->cnt, kCounterSlots * 4, "counters")) != WS_OK) return rc;
     int32_t *D = (int32_t *)c->D.p, *stamp = (int32_t *)c->stamp.p, *cnt = (int32_t *)c->cnt.p;
-    WS_TRY(wsk::launch_fill_i32(lc, stamp, tg.ntiles, -1));
+    WS_TRY(wsk::launch_fill_i32(lc, stamp, 2 * tg.ntiles, -1));
     WS_TRY(wsk::launch_fill_i32(lc, cnt, kCounterSlots, 0));
     WS_TRY(wsk::launch_ws_init(lc, src, tg, conn, u16, D, stamp, cnt));
     int64_t launched = 1, changing = 0;
@@ -449,7 +450,7 @@ int reserve(ws_ctx *c, int64_t n) {
     if ((rc = ensure(c, c->mlab, mlab_ints(N, kLayers) * 4, "reserved layer labels")) != WS_OK) return rc;
     if ((rc = ensure(c, c->edges, wft * (size_t)wsk::wf_slab_cap(8) * 12, "reserved edge slabs")) != WS_OK) return rc;
     if ((rc = ensure(c, c->ecnt, wft * 4, "reserved edge counts")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->stamp, tiles * 8, "reserved stamps")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->stamp, tiles * 16, "reserved stamps")) != WS_OK) return rc;
     if ((rc = ensure(c, c->rec, tiles * (size_t)wsk::border_cells(3) * 4, "reserved records")) != WS_OK) return rc;
     if ((rc = ensure(c, c->tilecnt, tiles * 16 * 4, "reserved tile counts")) != WS_OK) return rc;
     int32_t nch = (int32_t)std::min<int64_t>((int64_t)N / 4096 + 2 * kReserveItems, 0x7fffffff / 2);
@@ -546,7 +547,7 @@ size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int conn, int dtyp
     size_t b = dtype == WS_U8 ? 1 : 2;
     size_t job = N * (b + 4 * (size_t)NL);
     size_t ws = N * 4 /* D */ + (size_t)make_geom(nx, ny, nz, ndim).ntx * make_geom(nx, ny, nz, ndim).nty *
-                                    make_geom(nx, ny, nz, ndim).ntz * (8 + 4 * (size_t)wsk::border_cells(ndim));
+                                    make_geom(nx, ny, nz, ndim).ntz * (16 + 4 * (size_t)wsk::border_cells(ndim));
     size_t wf = 0;
     if (NL >= 2) {
         size_t tiles = (size_t)wsk::wf_tiles(make_geom(nx, ny, nz, ndim), ndim);

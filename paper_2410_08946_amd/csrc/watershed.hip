@@ -244,14 +244,25 @@ __device__ __forceinline__ void relax_list(const GC *sI, int *sD, const unsigned
     }
 }
 
+// Stamps are double-buffered by sweep parity: stamp[(s & 1) * n + t] holds
+// the last sweep of parity s & 1 in which tile t changed distances that a
+// neighbour can use, stamp[(2 + (s & 1)) * n + t] the faces concerned. Sweep s
+// reads only the buffers of sweep s - 1, which no tile writes during sweep s
+// (with one buffer, a neighbour that re-stamped earlier in the same sweep hid
+// its previous sweep's faces from the tiles next to them).
+__device__ __forceinline__ int32_t *stamp_of(int32_t *stamp, int32_t n, int32_t s) { return stamp + (size_t)(s & 1) * n; }
+__device__ __forceinline__ int32_t *faces_of(int32_t *stamp, int32_t n, int32_t s) {
+    return stamp + (size_t)(2 + (s & 1)) * n;
+}
+
 // Tile t changed border distances in sweep s: record s and the faces.
-__device__ __forceinline__ void stamp_tile(int *smk, int32_t *stamp, int32_t *smask, int32_t *changed, int t, int32_t s,
+__device__ __forceinline__ void stamp_tile(int *smk, int32_t *stamp, int32_t n, int32_t *changed, int t, int32_t s,
                                            uint32_t faces) {
     if (faces) atomicOr(smk, (int)faces);
     __syncthreads();
     if (threadIdx.x == 0 && *smk) {
-        stamp[t] = s;
-        smask[t] = *smk;
+        stamp_of(stamp, n, s)[t] = s;
+        faces_of(stamp, n, s)[t] = *smk;
         atomicAdd(changed, 1);
     }
 }
@@ -265,8 +276,7 @@ __device__ __forceinline__ void stamp_tile(int *smk, int32_t *stamp, int32_t *sm
 // ---------------------------------------------------------------------------
 template <int NDIM, int CONN, typename T, class Src>
 __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, int32_t *__restrict__ Darena,
-                                                      int32_t *__restrict__ stamp, int32_t *__restrict__ smask,
-                                                      int32_t *__restrict__ changed) {
+                                                      int32_t *__restrict__ stamp, int32_t *__restrict__ changed) {
     using TS = TileShape<NDIM>;
     using S2 = Lds<NDIM, 2>;
     using S1 = Lds<NDIM, 1>;
@@ -318,7 +328,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
             D[gx + g.nx * (gy + g.ny * gz)] = d;
             if (d != 0 && d != INF && face_bits<NDIM>(x, y, z)) faces |= cross_faces<NDIM, CONN, 2>(sI, sD, sc, x, y, z, d);
         }
-        stamp_tile(&smk, stamp, smask, changed, t, 0, faces);
+        stamp_tile(&smk, stamp, ntiles, changed, t, 0, faces);
     }
 }
 
@@ -329,8 +339,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
 // ---------------------------------------------------------------------------
 template <int NDIM, int CONN, typename T, class Src>
 __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, int32_t *__restrict__ Darena,
-                                                       int32_t *__restrict__ stamp, int32_t *__restrict__ smask,
-                                                       int32_t *__restrict__ changed, int32_t s) {
+                                                       int32_t *__restrict__ stamp, int32_t *__restrict__ changed,
+                                                       int32_t s) {
     using TS = TileShape<NDIM>;
     using S = Lds<NDIM, 1>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
@@ -359,11 +369,11 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, 
                 bool used = (NDIM == 3 || dz == 0) && (dx != 0 || dy != 0 || dz != 0) && (!FACES || face);
                 if (used && ux >= 0 && ux < g.ntx && uy >= 0 && uy < g.nty && uz >= 0 && uz < g.ntz) {
                     int32_t u = im.tile0[TK_WS] + ux + g.ntx * (uy + g.nty * uz);
-                    if (stamp[u] == s - 1) {
+                    if (stamp_of(stamp, ntiles, s - 1)[u] == s - 1) {
                         // the neighbour's face towards this tile
                         uint32_t need = !FACES ? 63u
                                         : dx > 0 ? 1u : dx < 0 ? 2u : dy > 0 ? 4u : dy < 0 ? 8u : dz > 0 ? 16u : 32u;
-                        active = ((uint32_t)smask[u] & need) != 0;
+                        active = ((uint32_t)faces_of(stamp, ntiles, s - 1)[u] & need) != 0;
                     }
                 }
             }
@@ -420,7 +430,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, 
                 }
             }
         }
-        stamp_tile(&smk, stamp, smask, changed, t, s, faces);
+        stamp_tile(&smk, stamp, ntiles, changed, t, s, faces);
     }
 }
 
@@ -855,14 +865,14 @@ static int launch_ws_init_t(Launch &lc, const Src &src, const TileGrid &tg, int3
                             int32_t *changed) {
     constexpr int ND = ndim_of<CONN>();
     return lc.run("ws_init", k_ws_init<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, D, stamp,
-                  stamp + tg.ntiles, changed);
+                  changed);
 }
 template <int CONN, typename T, class Src>
 static int launch_ws_sweep_t(Launch &lc, const Src &src, const TileGrid &tg, int32_t *D, int32_t *stamp,
                              int32_t *changed, int32_t s) {
     constexpr int ND = ndim_of<CONN>();
     return lc.run("ws_sweep", k_ws_sweep<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, D, stamp,
-                  stamp + tg.ntiles, changed, s);
+                  changed, s);
 }
 template <int CONN, typename T, class Src>
 static int launch_ws_label_t(Launch &lc, const Src &src, const TileGrid &tg, const int32_t *D, int32_t *rec) {

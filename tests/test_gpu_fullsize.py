@@ -12,6 +12,11 @@ any size:
   basin: L[p] <= p and L[L[p]] == L[p]), and every voxel with a strictly lower
   neighbour carries the label of its Eq. (1) target (the last of its lowest
   neighbours in index order);
+* Step II (Section 3.3): the distances are the fixpoint of the relaxation,
+  checked locally on the stage output: every resolved plateau voxel (balanced
+  state -d) has d - 1 as the smallest distance among its equal-grey
+  neighbours, and no unresolved voxel (state 2/3, a minimal plateau) has an
+  equal-grey neighbour with a finite distance;
 * waterfall (Section 4): every layer is canonical and nested in the previous
   one (L_k[p] == L_k[L_{k-1}[p]]), the returned counts equal the number of
   voxels carrying their own label, and a layer has at most half the regions of
@@ -173,3 +178,44 @@ def test_c2_waterfall(c2):
                 assert torch.equal(flat[p0:p1], flat[prev[p0:p1].long()]), "layer %d not nested" % k
             if nreg[k - 1] > 1:
                 assert nreg[k] <= nreg[k - 1] // 2
+
+
+def test_c2_step2_fixpoint(c2):
+    """Step II converged: the local fixpoint conditions on the balanced states."""
+    import torch
+    import paper_2410_08946_amd as ws
+    grad = c2["grad"]
+    nz, ny, nx = c2["shape"]
+    ctx = ws.Context(0)
+    try:
+        bal, _ = ctx.watershed_stages(grad, 6)
+        torch.cuda.synchronize()
+    finally:
+        ctx.close()
+    BIG = 1 << 30
+    offs = [(-1, 0, 0), (0, -1, 0), (0, 0, -1), (0, 0, 1), (0, 1, 0), (1, 0, 0)]
+    bad_res = bad_min = 0
+    for z0 in range(0, nz, SLAB):
+        z1 = min(nz, z0 + SLAB)
+        Z = z1 - z0
+        lo, hi = max(0, z0 - 1), min(nz, z1 + 1)
+        gp = torch.full((Z + 2, ny + 2, nx + 2), -1, dtype=torch.int32, device=grad.device)
+        dp = torch.full((Z + 2, ny + 2, nx + 2), BIG, dtype=torch.int32, device=grad.device)
+        b = bal[lo:hi]
+        dist = torch.where(b < 0, -b, torch.where(b == 0, torch.zeros_like(b), torch.full_like(b, BIG)))
+        gp[lo - (z0 - 1):hi - (z0 - 1), 1:-1, 1:-1] = grad[lo:hi].int()
+        dp[lo - (z0 - 1):hi - (z0 - 1), 1:-1, 1:-1] = dist
+        g0 = grad[z0:z1].int()
+        b0 = bal[z0:z1]
+        m = torch.full((Z, ny, nx), BIG, dtype=torch.int32, device=grad.device)
+        for dz, dy, dx in offs:
+            gv = gp[1 + dz:1 + dz + Z, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+            dv = dp[1 + dz:1 + dz + Z, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+            m = torch.minimum(m, torch.where(gv == g0, dv, torch.full_like(dv, BIG)))
+        res = b0 < 0
+        bad_res += int((res & (m != -b0 - 1)).sum())
+        unres = (b0 == 2) | (b0 == 3)
+        bad_min += int((unres & (m < BIG)).sum())
+        del gp, dp, m, dist, b, g0, b0
+    assert bad_res == 0 and bad_min == 0, \
+        "%d resolved voxels off the fixpoint, %d unresolved voxels next to a finite distance" % (bad_res, bad_min)

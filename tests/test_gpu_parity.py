@@ -130,6 +130,22 @@ def test_random_3d(ctx, shape, conn):
         check_stages(ctx, img, conn)
 
 
+def test_volume_recipe_many_tiles(ctx):
+    """The 928^3 recipe (blob density, sigma, noise) at 160^3: about 2000
+    watershed tiles with the plateau structure of the full volume (a few per
+    cent of the voxels on plateaux touching and crossing tile borders), whole
+    labels, Step II stages and waterfall against the oracle."""
+    import torch
+    f = gen.synth.blobs3d_device((160, 160, 160), seed=7, device="cpu").numpy()
+    grad = oracle.gradient(f, 0.0, "u8")
+    check_ws(ctx, grad, 6)
+    check_stages(ctx, grad, 6)
+    check_wf(ctx, grad, 6, 4)
+    g2 = oracle.gradient(gen.synth.blobs3d_device((72, 96, 120), seed=8, device="cpu").numpy(), 0.0, "u8")
+    check_ws(ctx, g2, 26)
+    check_stages(ctx, g2, 26)
+
+
 def test_plateau_structures(ctx):
     check_ws(ctx, gen.serpentine(70, 150), 4)
     check_stages(ctx, gen.serpentine(70, 150), 8)
