@@ -99,12 +99,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--workload", choices=("single", "c2", "batch", "serve", "recon"), default="single",
+    ap.add_argument("--workload", choices=("single", "c2", "batch", "serve", "recon", "schedules"), default="single",
                     help="single: the 4096x4096 image (default); c2: the 928^3 uint8 volume; batch: 512 uneven "
                          "2D images, one batched call vs one call per image; serve: Poisson arrivals of mixed "
                          "2D/3D jobs through the continuous-batching server; recon: the reconstruction waterfall "
                          "against the graph waterfall on the three single-image workloads (differing pixels per "
-                         "layer, time per layer)")
+                         "layer, time per layer); schedules: the watershed alone under the tile schedule and the "
+                         "per-pixel synchronous schedule (APRUF / PRUF / PRW forms) on the same workloads")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="serve workload: request rates (req/s)")
     ap.add_argument("--requests", type=int, default=200, help="serve workload: requests per rate")
     ap.add_argument("--slots", type=int, default=4, help="serve workload: execution slots")
@@ -358,6 +359,95 @@ def bench_recon(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_schedules(args):
+    """The watershed alone (Alg. 1 Steps I-IV and canonical labels) under each
+    schedule on the 256^2, 4096^2 and 928^3 workloads: the tile schedule with
+    APRUF / PRUF Step III, and the per-pixel synchronous schedule of Section 3.3
+    with APRUF, PRUF and PRW (Alg. 2) forms. Every variant's labels must equal
+    the default's; reports time, Mvoxel/s and the sweep / synchronisation /
+    pass counts."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2410_08946_amd as ws
+
+    dev = torch.device("cuda:0")
+    ctx = ws.Context(0)
+    reps = max(1, min(args.steps, 5))
+    variants = [("tile_apruf", 0, 0, 0), ("tile_pruf", 0, 1, 0), ("pixel_apruf_sync", 1, 0, 0),
+                ("pixel_pruf_sync", 1, 1, 0), ("pixel_prw_sync", 1, 1, 1)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        z = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        z.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(z) / reps
+
+    results = {}
+    for name in ("c0", "c1", "c2"):
+        cfg = gen.CONFIGS[name]
+        shape = tuple(cfg["shape"])
+        if name == "c2":
+            img = gen.synth.blobs3d_device(shape, seed=cfg["seed"], device=dev)
+        else:
+            img = torch.from_numpy(gen.config_image(name)).to(dev)
+        grad = ctx.gradient(img, cfg["sigma"], cfg["dtype"])
+        del img
+        conn = cfg["conn"]
+        N = int(np.prod(shape))
+        ref = ctx.watershed(grad, conn)
+        lab = torch.empty_like(ref)
+        per = {}
+        for vname, sched, step3, step4 in variants:
+            print("bench: schedules %s %s" % (name, vname), file=sys.stderr, flush=True)
+            ctx.set_option("schedule", sched)
+            ctx.set_option("step3", step3)
+            ctx.set_option("step4", step4)
+            ctx.watershed(grad, conn, out=lab)
+            torch.cuda.synchronize()
+            same = bool(torch.equal(lab, ref))
+            st = ctx.stats()
+            ms = timed(lambda: ctx.watershed(grad, conn, out=lab))
+            per[vname] = {"ms": round(ms, 3), "mvoxel_s": round(N / ms / 1e3, 1), "identical": same,
+                          "step2_sweeps": st["sweeps_launched"], "step2_sweeps_changing": st["sweeps_changing"],
+                          "step3_syncs": st["step3_syncs"], "step4_passes": st["step4_passes"]}
+            print("bench: schedules %s %s %s" % (name, vname, per[vname]), file=sys.stderr, flush=True)
+        ctx.set_option("schedule", 0)
+        ctx.set_option("step3", 0)
+        ctx.set_option("step4", 0)
+        results[name] = {"pixels": N, "conn": conn, "variants": per}
+        del grad, ref, lab
+        torch.cuda.empty_cache()
+    c1 = results["c1"]["variants"]
+    line = {
+        "metric": "watershed Mvoxel/s by schedule",
+        "value": c1["tile_apruf"]["mvoxel_s"],
+        "unit": "Mvoxel/s",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": 1,
+        "ms_per_step": c1["tile_apruf"]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "config": {"workload": "watershed only (Steps I-IV + canonical labels) of the 256^2 u8, 4096^2 u16 and "
+                               "928^3 u8 gradients, tile vs per-pixel synchronous schedules",
+                   "parallelism": "single GPU"},
+        "all_identical": all(v["identical"] for r in results.values() for v in r["variants"].values()),
+        "per_workload": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -372,6 +462,9 @@ def main():
         return
     if args.workload == "recon":
         bench_recon(args)
+        return
+    if args.workload == "schedules":
+        bench_schedules(args)
         return
     import numpy as np
     import torch

@@ -220,8 +220,24 @@ int ws_watershed_stages(ws_ctx *ctx, const void *grad, int dtype, int64_t nx, in
 
 /*
  * Options. None of them changes any result, only time.
+ *   "schedule"     0 = tile schedule (default): LDS tiles, fused Steps
+ *                  III-IV inside tiles, global union-find across them.
+ *                  1 = per-pixel synchronous schedule of Section 3.3: one
+ *                  thread per pixel, one launch per Step II sweep, per Step
+ *                  III synchronisation and per Step IV pass, Step II decisions
+ *                  taken from the previous sweep's states. Applies to
+ *                  ws_watershed and ws_watershed_stages; ws_batch,
+ *                  ws_waterfall_recon and ws_rag always use the tile schedule.
+ *                  Step II needs as many sweeps as the longest geodesic
+ *                  distance in a non-minimal plateau (one counter read-back
+ *                  per "sweep_batch" sweeps).
  *   "step3"        0 = per-pixel Find (APRUF, Section 3.2), 1 = RR pointer
  *                  jumps per synchronisation (PRUF, Alg. 1 Step III).
+ *   "step4"        0 = union-find over adjacent minimal-plateau pixels
+ *                  (PRUF / APRUF, Alg. 1 Step IV); 1 = the label exchange
+ *                  passes of PRW (Alg. 2), repeated until a pass changes
+ *                  nothing. 1 needs schedule = 1: ws_watershed returns
+ *                  WS_EUNSUPPORTED for it under the tile schedule.
  *   "rr"           reduction rate for step3 = 1 (default 6, Section 5).
  *   "sweep_batch"  Step II sweeps launched per convergence read (default 4).
  *   "max_sweeps"   cap on Step II sweeps; reaching it returns WS_ENOCONV
@@ -253,7 +269,9 @@ int ws_set_option(ws_ctx *ctx, const char *name, int64_t value);
  * (including the initial tile pass), out[1] sweeps that changed a tile
  * border, out[2] Step III synchronisations (step3 = 1), out[3] tiles;
  * out[4] the launch graphs replayed by this context so far ("graph" option);
- * out[5] the device and pinned host allocations this context has made.
+ * out[5] the device and pinned host allocations this context has made;
+ * out[6] Step IV passes that changed a label (step4 = 1). Under schedule = 1,
+ * out[0] counts the Step I pass and the sweeps, out[3] is 0.
  * Returns the number of counters written (<= n).
  */
 int ws_get_stats(const ws_ctx *ctx, int64_t *out, int n);

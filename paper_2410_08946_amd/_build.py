@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libws.so")
-SOURCES = ["api.hip", "watershed.hip", "waterfall.hip", "gradient.hip", "rag.hip"]
+SOURCES = ["api.hip", "watershed.hip", "waterfall.hip", "gradient.hip", "rag.hip", "pixel.hip"]
 
 
 def hipcc() -> str:

@@ -135,9 +135,10 @@ class Context:
         self._check(self._lib.ws_set_option(self._h, name.encode(), int(value)))
 
     def stats(self):
-        out = (ctypes.c_int64 * 6)()
-        n = self._lib.ws_get_stats(self._h, out, 6)
-        keys = ("sweeps_launched", "sweeps_changing", "step3_syncs", "tiles", "graph_replays", "allocations")
+        out = (ctypes.c_int64 * 7)()
+        n = self._lib.ws_get_stats(self._h, out, 7)
+        keys = ("sweeps_launched", "sweeps_changing", "step3_syncs", "tiles", "graph_replays", "allocations",
+                "step4_passes")
         return {k: int(out[i]) for i, k in enumerate(keys[:n])}
 
     def timing_reset(self):

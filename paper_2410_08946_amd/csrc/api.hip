@@ -50,6 +50,7 @@ struct ws_ctx {
     hipEvent_t stage_ev = nullptr;        // last upload from `stage`
     bool stage_pending = false;
     int step3 = 0, rr = 6, sweep_batch = 4;
+    int schedule = 0, step4 = 0;           // per-pixel schedule, PRW Step IV
     int64_t max_sweeps = 0x7fffffff;
     bool timing = false;
     // launch graphs: a call signature seen once is captured on its next use
@@ -68,7 +69,7 @@ struct ws_ctx {
     std::map<std::string, uint64_t> seen;
     uint64_t tick = 0;
     wsk::TimingSink sink;
-    int64_t stats[6] = {0, 0, 0, 0, 0, 0};
+    int64_t stats[7] = {0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -305,6 +306,7 @@ int run_watershed(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg
                   size_t arena) {
     int rc;
     c->stats[2] = 0;
+    c->stats[6] = 0;
     if ((rc = run_distances(c, lc, src, tg, conn, u16, arena)) != WS_OK) return rc;
     size_t nrec = (size_t)tg.ntiles * wsk::border_cells(ndim);
     if ((rc = ensure(c, c->rec, nrec * 4, "border records")) != WS_OK) return rc;
@@ -328,6 +330,82 @@ int run_watershed(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg
         }
         c->stats[2] = syncs;
     }
+    return WS_OK;
+}
+
+// Launches launch(i, counter) for i = 1, 2, ... in batches of sweep_batch,
+// each with a change counter of its own, and reads the batch's counters back
+// once; stops after the first launch that changed nothing. `changing` counts
+// the launches that changed something; reaching `cap` of them is WS_ENOCONV.
+template <class F>
+int repeat_until_stable(ws_ctx *c, Launch &lc, int64_t cap, const char *what, int64_t &launched, int64_t &changing,
+                        F launch) {
+    int rc;
+    if ((rc = ensure(c, c->cnt, kCounterSlots * 4, "counters")) != WS_OK) return rc;
+    int32_t *cnt = (int32_t *)c->cnt.p;
+    const int batch = std::max(1, std::min(c->sweep_batch, kMaxSweepBatch));
+    launched = changing = 0;
+    for (;;) {
+        WS_TRY(wsk::launch_fill_i32(lc, cnt, batch, 0));
+        for (int b = 0; b < batch; ++b) WS_TRY(launch((int32_t)(launched + b + 1), cnt + b));
+        launched += batch;
+        hipError_t e = hipMemcpyAsync(c->host_cnt, cnt, (size_t)batch * 4, hipMemcpyDeviceToHost, lc.stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+        if ((e = hipStreamSynchronize(lc.stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+        for (int b = 0; b < batch; ++b) {
+            if (c->host_cnt[b] == 0) return WS_OK;
+            ++changing;
+        }
+        if (changing >= cap) return fail(c, WS_ENOCONV, std::string(what) + " did not converge within max_sweeps");
+    }
+}
+
+// The per-pixel synchronous schedule of one image (option "schedule" = 1):
+// Step I, Step II sweeps until one resolves nothing, Step III by Find (APRUF)
+// or RR jumps per launch (PRUF), Step IV by union-find or by the PRW
+// exchange passes, then canonical labels, all in L. With `bal`, stops after
+// Step II and writes the balanced states to bal (L then holds the arrows).
+int run_watershed_px(ws_ctx *c, Launch &lc, const wsk::Geom &g, const void *grad, int conn, bool u16, int32_t *L,
+                     int32_t *bal) {
+    int rc;
+    for (int i = 0; i < 4; ++i) c->stats[i] = 0;
+    c->stats[6] = 0;
+    if ((rc = ensure(c, c->D, (size_t)g.n * 4, "distances")) != WS_OK) return rc;
+    int32_t *S = (int32_t *)c->D.p;
+    WS_TRY(wsk::launch_px_step1(lc, g, conn, u16, grad, L, S));
+    int64_t launched = 0, changing = 0;
+    rc = repeat_until_stable(c, lc, c->max_sweeps, "Step II", launched, changing, [&](int32_t s, int32_t *cnt) {
+        return wsk::launch_px_sweep(lc, g, conn, u16, grad, L, S, s, cnt);
+    });
+    c->stats[0] = launched + 1;
+    c->stats[1] = changing;
+    if (rc != WS_OK) return rc;
+    if (bal) {
+        WS_TRY(wsk::launch_px_stages(lc, g, S, bal));
+        return WS_OK;
+    }
+    const int64_t no_cap = INT64_MAX;
+    if (c->step3 == 0) {
+        WS_TRY(wsk::launch_px_find(lc, g, L));
+    } else {
+        rc = repeat_until_stable(c, lc, no_cap, "Step III", launched, changing, [&](int32_t, int32_t *cnt) {
+            return wsk::launch_px_jump(lc, g, L, c->rr, cnt);
+        });
+        if (rc != WS_OK) return rc;
+        c->stats[2] = changing;
+    }
+    if (c->step4 == 0) {
+        WS_TRY(wsk::launch_px_union(lc, g, conn, S, L));
+        WS_TRY(wsk::launch_px_find(lc, g, L));
+    } else {
+        rc = repeat_until_stable(c, lc, no_cap, "Step IV", launched, changing, [&](int32_t, int32_t *cnt) {
+            return wsk::launch_px_prw(lc, g, conn, S, L, cnt);
+        });
+        if (rc != WS_OK) return rc;
+        c->stats[6] = changing;
+    }
+    WS_TRY(wsk::launch_fill_i32(lc, S, g.n, 0x7fffffff));
+    WS_TRY(wsk::launch_px_canon(lc, g, L, S));
     return WS_OK;
 }
 
@@ -562,6 +640,8 @@ int ws_set_option(ws_ctx *c, const char *name, int64_t v) {
     if (!c || !name) return fail(c, WS_EINVAL, "ws_set_option: NULL argument");
     std::string k(name);
     if (k == "step3" && (v == 0 || v == 1)) c->step3 = (int)v;
+    else if (k == "schedule" && (v == 0 || v == 1)) c->schedule = (int)v;
+    else if (k == "step4" && (v == 0 || v == 1)) c->step4 = (int)v;
     else if (k == "rr" && v >= 1 && v <= 64) c->rr = (int)v;
     else if (k == "sweep_batch" && v >= 1 && v <= kMaxSweepBatch) c->sweep_batch = (int)v;
     else if (k == "max_sweeps" && v >= 1) c->max_sweeps = v;
@@ -578,7 +658,7 @@ int ws_set_option(ws_ctx *c, const char *name, int64_t v) {
 
 int ws_get_stats(const ws_ctx *c, int64_t *out, int n) {
     if (!c || !out || n < 0) return WS_EINVAL;
-    int m = std::min(n, 6);
+    int m = std::min(n, 7);
     for (int i = 0; i < m; ++i) out[i] = c->stats[i];
     return m;
 }
@@ -665,6 +745,8 @@ int ws_watershed(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny,
     Launch lc = make_launch(c, stream);
     wsk::OneImg src{single_img(nx, ny, nz, grad, labels)};
     const wsk::Geom &g = src.im.g;
+    if (c->schedule == 1) return run_watershed_px(c, lc, g, grad, conn, dtype == WS_U16, labels, nullptr);
+    if (c->step4 == 1) return fail(c, WS_EUNSUPPORTED, "ws_watershed: step4 = 1 (PRW) needs schedule = 1");
     return run_watershed(c, lc, src, full_grid(g.ntx * g.nty * g.ntz), ndim, conn, dtype == WS_U16, (size_t)g.n);
 }
 
@@ -678,6 +760,7 @@ int ws_watershed_stages(ws_ctx *c, const void *grad, int dtype, int64_t nx, int6
     bool u16 = dtype == WS_U16;
     wsk::OneImg src{single_img(nx, ny, nz, grad, nullptr)};
     const wsk::Geom &g = src.im.g;
+    if (c->schedule == 1) return run_watershed_px(c, lc, g, grad, conn, u16, arrow, bal);
     if ((rc = run_distances(c, lc, src, full_grid(g.ntx * g.nty * g.ntz), conn, u16, (size_t)g.n)) != WS_OK) return rc;
     WS_TRY(wsk::launch_ws_stages(lc, g, conn, u16, grad, (const int32_t *)c->D.p, bal, arrow));
     return WS_OK;

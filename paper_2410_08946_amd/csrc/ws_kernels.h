@@ -111,6 +111,17 @@ int launch_ws_stages(Launch &lc, const Geom &g, int conn, bool u16, const void *
                      int32_t *arrow);
 int launch_fill_i32(Launch &lc, int32_t *a, int32_t n, int32_t v);
 
+// Per-pixel synchronous schedule (one thread per pixel, one launch per step).
+int launch_px_step1(Launch &lc, const Geom &g, int conn, bool u16, const void *I, int32_t *L, int32_t *S);
+int launch_px_sweep(Launch &lc, const Geom &g, int conn, bool u16, const void *I, int32_t *L, int32_t *S, int32_t s,
+                    int32_t *changed);
+int launch_px_jump(Launch &lc, const Geom &g, int32_t *L, int32_t rr, int32_t *changed);
+int launch_px_find(Launch &lc, const Geom &g, int32_t *L);
+int launch_px_union(Launch &lc, const Geom &g, int conn, const int32_t *S, int32_t *L);
+int launch_px_prw(Launch &lc, const Geom &g, int conn, const int32_t *S, int32_t *L, int32_t *changed);
+int launch_px_canon(Launch &lc, const Geom &g, int32_t *L, int32_t *M);
+int launch_px_stages(Launch &lc, const Geom &g, const int32_t *S, int32_t *bal);
+
 // waterfall.hip
 int wf_tiles(const Geom &g, int ndim);
 int wf_chunks(int32_t n);               // region-id chunks of an image of n pixels
