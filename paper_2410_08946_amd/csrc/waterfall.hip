@@ -65,6 +65,16 @@ constexpr int XG_REG = 64;          // workgroups of 256 region ids per run
 // Forward half of a neighbourhood: the neighbours with a larger linear index.
 template <int CONN> __host__ __device__ constexpr bool forward(int k) { return nb_j<CONN>(k) > 13; }
 
+// 1 if a forward neighbour can step back along x (axis 0) or y (axis 1): the
+// diagonal neighbours of 8- and 26-connectivity. No forward neighbour steps
+// back along z.
+template <int CONN> __host__ __device__ constexpr int forward_back(int axis) {
+    int r = 0;
+    for (int k = 0; k < CONN; ++k)
+        if (forward<CONN>(k) && (axis == 0 ? nb_dx<CONN>(k) : nb_dy<CONN>(k)) < 0) r = 1;
+    return r;
+}
+
 
 // ---------------------------------------------------------------------------
 // LDS hash tables. Inserts return false when MAXPROBE slots were taken by
@@ -315,23 +325,29 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
                                                      int32_t *__restrict__ ecnt, int32_t cap) {
     constexpr int NDIM = ndim_of<CONN>();
     using TS = WfTile<NDIM>;
-    constexpr int SX = TS::X + 2, SY = TS::Y + 2, SZ = NDIM == 3 ? TS::Z + 2 : 1, RZ = NDIM == 3 ? 1 : 0;
+    // Only forward pairs are formed, so the staged box extends one cell past
+    // the tile on the high side of every axis and one cell below it only along
+    // the axes where a forward neighbour steps back.
+    constexpr int LX = forward_back<CONN>(0), LY = forward_back<CONN>(1);
+    constexpr int SX = TS::X + LX + 1, SY = TS::Y + LY + 1, SZ = NDIM == 3 ? TS::Z + 1 : 1;
     constexpr int CELLS = SX * SY * SZ;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
     static_assert(PIX == WF_PIX && PIX % NTHREADS == 0, "whole waves per tile");
     // sL/sI hold the tile's ids and grey values; once the edges are collected
     // the same words hold the region hash (keys, then 64-bit minima)
     constexpr int RBITS = 9;
-    // ids int32 + grey uint16 per cell (6 B: a 2D tile's arrays and hashes
-    // stay within the 20 KB of eight workgroups per CU)
-    constexpr int SBUF = (CELLS * 6 + 7) / 8;
-    static_assert((1 << RBITS) * 12 <= SBUF * 8, "region hash fits the id/grey arrays");
+    // ids int32 + grey T per cell (5 or 6 B: the arrays and hashes of 2D
+    // tiles and of uint8 volumes stay within the 20 KB of eight workgroups
+    // per CU; uint16 volumes run seven)
+    constexpr int CBYTES = CELLS * (4 + (int)sizeof(T)), HBYTES = (1 << RBITS) * 12;
+    constexpr int SBUF = ((CBYTES > HBYTES ? CBYTES : HBYTES) + 7) / 8;
+    static_assert((NDIM == 3 && sizeof(T) == 2) || SBUF * 8 + ESLOTS * 12 + 16 <= 20480, "eight workgroups per CU");
     __shared__ unsigned long long sbuf[SBUF];
     __shared__ unsigned long long ek[ESLOTS];
     __shared__ unsigned int ew[ESLOTS];
     __shared__ int ectr;
     int *sL = (int *)sbuf;
-    uint16_t *sI = (uint16_t *)(sL + CELLS);
+    T *sI = (T *)(sL + CELLS);
     int *hk = (int *)sbuf;
     unsigned long long *hv = sbuf + (1 << RBITS) / 2;
     if ((int)blockIdx.x >= ntiles) return;
@@ -354,10 +370,9 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
         for (int j = 0; j < PER; ++j) {
             int c = threadIdx.x + j * NTHREADS;
             int cx = c % SX, cy = (c / SX) % SY, cz = c / (SX * SY);
-            int x = ox + cx - 1, y = oy + cy - 1, z = oz + cz - RZ;
+            int x = ox + cx - LX, y = oy + cy - LY, z = oz + cz;
             ok[j] = c < CELLS && in_image(g, x, y, z);
-            own[j] = ok[j] && cx >= 1 && cx <= TS::X && cy >= 1 && cy <= TS::Y &&
-                     (NDIM == 2 || (cz >= 1 && cz <= TS::Z));
+            own[j] = ok[j] && cx >= LX && cx < LX + TS::X && cy >= LY && cy < LY + TS::Y && cz < TS::Z;
             idx[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
         }
         int32_t lv[PER];
@@ -382,7 +397,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
             cv = cv <= cmax ? cv : cmax;
             if (c < CELLS) {
                 sL[c] = ok[j] ? (int)cv : -1;
-                sI[c] = ok[j] ? (uint16_t)gv[j] : (uint16_t)0;
+                sI[c] = ok[j] ? gv[j] : (T)0;
             }
             if (own[j]) {
                 cimg[(size_t)im.pix0 + idx[j]] = (int32_t)cv;
@@ -399,7 +414,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
     const size_t base = (size_t)t * (size_t)cap;
     for (int i = threadIdx.x; i < PIX; i += NTHREADS) {  // uniform trip count
         int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-        int s = ((z + RZ) * SY + (y + 1)) * SX + (x + 1);
+        int s = (z * SY + (y + LY)) * SX + (x + LX);
         int a = sL[s];
         if (a < 0) continue;
         uint32_t v = (uint32_t)sI[s];
