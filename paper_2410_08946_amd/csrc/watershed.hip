@@ -90,12 +90,17 @@ __device__ __forceinline__ void load_grey_dist(const Geom &g, const T *__restric
     }
 }
 
+// Unresolved distance in an LDS distance cell: INF in int32 cells; 0xffff in
+// the 16-bit cells of the initial tile pass, whose finite distances never
+// exceed the tile's pixel count (its ring holds 0 or unresolved only).
+template <typename DC> __device__ __forceinline__ constexpr int dinf_of() { return sizeof(DC) == 2 ? 0xffff : INF; }
+
 // Relaxes the plateau distances of the tile's pixels to a local fixpoint
 // (ring cells frozen). Returns after an iteration in which no thread changed
 // anything. Gauss-Seidel order inside LDS; any order reaches the same fixpoint
 // because distances only decrease and every value stays an upper bound.
-template <int NDIM, int CONN, int R, typename GC>
-__device__ __forceinline__ void relax_tile(const GC *sI, int *sD) {
+template <int NDIM, int CONN, int R, typename GC, typename DC>
+__device__ __forceinline__ void relax_tile(const GC *sI, DC *sD) {
     using TS = TileShape<NDIM>;
     using S = Lds<NDIM, R>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
@@ -113,7 +118,7 @@ __device__ __forceinline__ void relax_tile(const GC *sI, int *sD) {
             for (int k = 0; k < CONN; ++k) {
                 int o = s + S::template off<CONN>(k);
                 int dq = sD[o];
-                if (sI[o] == v && dq != INF && dq + 1 < best) best = dq + 1;
+                if (sI[o] == v && dq != dinf_of<DC>() && dq + 1 < best) best = dq + 1;
             }
             if (best < d) { sD[s] = best; changed = 1; }
         }
@@ -144,8 +149,8 @@ __device__ __forceinline__ uint32_t face_bits(int x, int y, int z) {
 // same grey value and a ring distance above d + 1 (the ring holds upper
 // bounds: distances only decrease), the faces that step crosses. A tile whose
 // neighbours report no such face cannot change in the next sweep.
-template <int NDIM, int CONN, int R, typename GC>
-__device__ __forceinline__ uint32_t cross_faces(const GC *sI, const int *sD, int sc, int x, int y, int z, int d) {
+template <int NDIM, int CONN, int R, typename GC, typename DC>
+__device__ __forceinline__ uint32_t cross_faces(const GC *sI, const DC *sD, int sc, int x, int y, int z, int d) {
     using TS = TileShape<NDIM>;
     using S = Lds<NDIM, R>;
     const int v = sI[sc];
@@ -187,8 +192,8 @@ constexpr int LCAP = NTHREADS;  // one list entry per thread
 
 // Tile pixels i in the image and with (sweep ? D != 0 : D == INF) into lst, in
 // index order; returns their number (entries beyond LCAP are not stored).
-template <int NDIM, int R, typename GC>
-__device__ __forceinline__ int build_list(const GC *sI, const int *sD, unsigned short *lst, bool sweep) {
+template <int NDIM, int R, typename GC, typename DC>
+__device__ __forceinline__ int build_list(const GC *sI, const DC *sD, unsigned short *lst, bool sweep) {
     using TS = TileShape<NDIM>;
     using S = Lds<NDIM, R>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
@@ -200,7 +205,7 @@ __device__ __forceinline__ int build_list(const GC *sI, const int *sD, unsigned 
         int x, y, z;
         tile_pixel<NDIM>(threadIdx.x + j * NTHREADS, x, y, z);
         int sc = S::at(x, y, z), d = sD[sc];
-        bool take = (int)sI[sc] != sent_of<GC>() && (sweep ? d != 0 : d == INF);
+        bool take = (int)sI[sc] != sent_of<GC>() && (sweep ? d != 0 : d == dinf_of<DC>());
         m |= (take ? 1u : 0u) << j;
     }
     int excl;
@@ -215,8 +220,8 @@ __device__ __forceinline__ int build_list(const GC *sI, const int *sD, unsigned 
 }
 
 // relax_tile restricted to the n <= LCAP listed pixels (entry threadIdx.x).
-template <int NDIM, int CONN, int R, typename GC>
-__device__ __forceinline__ void relax_list(const GC *sI, int *sD, const unsigned short *lst, int n) {
+template <int NDIM, int CONN, int R, typename GC, typename DC>
+__device__ __forceinline__ void relax_list(const GC *sI, DC *sD, const unsigned short *lst, int n) {
     using S = Lds<NDIM, R>;
     int sc = -1, v = 0;
     if ((int)threadIdx.x < n) {
@@ -233,7 +238,7 @@ __device__ __forceinline__ void relax_list(const GC *sI, int *sD, const unsigned
             for (int k = 0; k < CONN; ++k) {
                 int o = sc + S::template off<CONN>(k);
                 int dq = sD[o];
-                if (sI[o] == v && dq != INF && dq + 1 < best) best = dq + 1;
+                if (sI[o] == v && dq != dinf_of<DC>() && dq + 1 < best) best = dq + 1;
             }
             if (best < d) {
                 sD[sc] = best;
@@ -282,8 +287,10 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
     using S1 = Lds<NDIM, 1>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
     using GC = typename GreyCell<T>::type;
+    using DC = uint16_t;  // distances of the tile pass stay below the tile's pixel count
+    static_assert(PIX < 0xffff, "16-bit distance cells");
     __shared__ GC sI[S2::CELLS];
-    __shared__ int sD[S2::CELLS];
+    __shared__ DC sD[S2::CELLS];
     __shared__ unsigned short lst[LCAP];
     __shared__ int smk;
     {
@@ -304,14 +311,14 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
             int cx = c % S1::SX, cy = (c / S1::SX) % S1::SY, cz = c / (S1::SX * S1::SY);
             int s = S2::at(cx - 1, cy - 1, cz - S1::RZ);
             int v = sI[s];
-            int d = INF;
+            int d = dinf_of<DC>();
             if (v != sent_of<GC>()) {
                 int m = sent_of<GC>();
 #pragma unroll
                 for (int k = 0; k < CONN; ++k) m = min(m, (int)sI[s + S2::template off<CONN>(k)]);
-                d = (m == v) ? INF : 0;
+                d = (m == v) ? dinf_of<DC>() : 0;
             }
-            sD[s] = d;
+            sD[s] = (DC)d;
         }
         __syncthreads();
         const int n = build_list<NDIM, 2>(sI, sD, lst, false);
@@ -325,8 +332,9 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
             if (!in_image(g, gx, gy, gz)) continue;
             const int sc = S2::at(x, y, z);
             int d = sD[sc];
-            D[gx + g.nx * (gy + g.ny * gz)] = d;
-            if (d != 0 && d != INF && face_bits<NDIM>(x, y, z)) faces |= cross_faces<NDIM, CONN, 2>(sI, sD, sc, x, y, z, d);
+            const bool fin = d != dinf_of<DC>();
+            D[gx + g.nx * (gy + g.ny * gz)] = fin ? d : INF;
+            if (d != 0 && fin && face_bits<NDIM>(x, y, z)) faces |= cross_faces<NDIM, CONN, 2>(sI, sD, sc, x, y, z, d);
         }
         stamp_tile(&smk, stamp, ntiles, changed, t, 0, faces);
     }
@@ -539,6 +547,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
     // parent array once every arrow is known
     __shared__ GC sI[S::CELLS];
     __shared__ int sD[S::CELLS];
+    __shared__ int sany[3];
     int *sP = sD;
     {
         if ((int)blockIdx.x >= ntiles) return;
@@ -550,6 +559,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
         int32_t *L = im.lab;
         int ox, oy, oz;
         ws_tile<NDIM>(g, lt, ox, oy, oz);
+        if (threadIdx.x < 3) sany[threadIdx.x] = 0;
         load_grey_dist<NDIM, T>(g, (const T *)im.grey, Darena + im.pix0, sI, sD, ox, oy, oz);
         __syncthreads();
         uint32_t minzone = 0, inimg = 0;
@@ -591,6 +601,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
         for (int j = 0; j < PER; ++j) sP[threadIdx.x + j * NTHREADS] = tos[j];
         __syncthreads();
         // pointer jumping to the in-tile terminals
+        BlockAny any{sany};
         for (;;) {
             int changed = 0;
 #pragma unroll
@@ -600,7 +611,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
                 int pp = sP[p];
                 if (pp != p) { sP[i] = pp; changed = 1; }
             }
-            if (!__syncthreads_or(changed)) break;
+            if (!any(changed)) break;
         }
         // minimal plateaux: join equal neighbours after p inside the tile
         if (minzone) {
