@@ -260,18 +260,24 @@ int run_distances(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg
     if ((rc = ensure(c, c->stamp, (size_t)tg.ntiles * 16, "tile stamps")) != WS_OK) return rc;
     if ((rc = ensure(c, c->cnt, kCounterSlots * 4, "counters")) != WS_OK) return rc;
     int32_t *D = (int32_t *)c->D.p, *stamp = (int32_t *)c->stamp.p, *cnt = (int32_t *)c->cnt.p;
-    WS_TRY(wsk::launch_fill_i32(lc, stamp, 2 * tg.ntiles, -1));
-    WS_TRY(wsk::launch_fill_i32(lc, cnt, kCounterSlots, 0));
+    WS_TRY(wsk::launch_fill2_i32(lc, stamp, 2 * tg.ntiles, -1, cnt, kCounterSlots, 0));
     WS_TRY(wsk::launch_ws_init(lc, src, tg, conn, u16, D, stamp, cnt));
     int64_t launched = 1, changing = 0;
     int32_t s = 1;
     bool first = true;
     int batch = std::max(1, std::min(c->sweep_batch, kMaxSweepBatch));
     for (;;) {
-        if (!first) WS_TRY(wsk::launch_fill_i32(lc, cnt, kCounterSlots, 0));
+        if (!first) {
+            // this batch's counters only: each sweep reads the count of the
+            // sweep before it (the last of the previous batch included)
+            const int a = s % kCounterSlots, m = std::min(batch, kCounterSlots - a);
+            WS_TRY(wsk::launch_fill_i32(lc, cnt + a, m, 0));
+            if (m < batch) WS_TRY(wsk::launch_fill_i32(lc, cnt, batch - m, 0));
+        }
         int32_t s0 = s;
         for (int b = 0; b < batch; ++b, ++s)
-            WS_TRY(wsk::launch_ws_sweep(lc, src, tg, conn, u16, D, stamp, cnt + (s % kCounterSlots), s));
+            WS_TRY(wsk::launch_ws_sweep(lc, src, tg, conn, u16, D, stamp, cnt + (s % kCounterSlots),
+                                        cnt + ((s - 1) % kCounterSlots), s));
         launched += batch;
         hipError_t e = hipMemcpyAsync(c->host_cnt, cnt, kCounterSlots * 4, hipMemcpyDeviceToHost, lc.stream);
         if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");

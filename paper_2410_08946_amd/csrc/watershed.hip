@@ -348,7 +348,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
 template <int NDIM, int CONN, typename T, class Src>
 __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, int32_t *__restrict__ Darena,
                                                        int32_t *__restrict__ stamp, int32_t *__restrict__ changed,
-                                                       int32_t s) {
+                                                       const int32_t *__restrict__ prev, int32_t s) {
     using TS = TileShape<NDIM>;
     using S = Lds<NDIM, 1>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
@@ -360,7 +360,9 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, 
     __shared__ unsigned short lst[LCAP];
     __shared__ int smk;
     {
-        if ((int)blockIdx.x >= ntiles) return;
+        // no tile changed in sweep s - 1 (its counter is final: the launches
+        // are ordered on the stream): nothing can change now
+        if ((int)blockIdx.x >= ntiles || *prev == 0) return;
         const int t = xcd_tile(blockIdx.x, ntiles);
         Img im;
         int lt;
@@ -868,6 +870,13 @@ __global__ void k_fill_i32(int32_t *a, int32_t n, int32_t v) {
     if (i < n) a[i] = v;
 }
 
+// Two fills in one launch: a[0, na) = va, then b[0, nb) = vb.
+__global__ void k_fill2_i32(int32_t *a, int32_t na, int32_t va, int32_t *b, int32_t nb, int32_t vb) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < na) a[i] = va;
+    else if (i - na < nb) b[i - na] = vb;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers (instantiated per connectivity, grey type and source).
 // ---------------------------------------------------------------------------
@@ -880,10 +889,10 @@ static int launch_ws_init_t(Launch &lc, const Src &src, const TileGrid &tg, int3
 }
 template <int CONN, typename T, class Src>
 static int launch_ws_sweep_t(Launch &lc, const Src &src, const TileGrid &tg, int32_t *D, int32_t *stamp,
-                             int32_t *changed, int32_t s) {
+                             int32_t *changed, const int32_t *prev, int32_t s) {
     constexpr int ND = ndim_of<CONN>();
     return lc.run("ws_sweep", k_ws_sweep<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, D, stamp,
-                  changed, s);
+                  changed, prev, s);
 }
 template <int CONN, typename T, class Src>
 static int launch_ws_label_t(Launch &lc, const Src &src, const TileGrid &tg, const int32_t *D, int32_t *rec) {
@@ -926,8 +935,8 @@ static int launch_ws_stages_t(Launch &lc, const Geom &g, const void *I, const in
         WS_DISPATCH(launch_ws_init_t, conn, u16, lc, src, tg, D, stamp, changed)                                   \
     }                                                                                                              \
     int launch_ws_sweep(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,           \
-                        int32_t *stamp, int32_t *changed, int32_t s) {                                             \
-        WS_DISPATCH(launch_ws_sweep_t, conn, u16, lc, src, tg, D, stamp, changed, s)                               \
+                        int32_t *stamp, int32_t *changed, const int32_t *prev, int32_t s) {                        \
+        WS_DISPATCH(launch_ws_sweep_t, conn, u16, lc, src, tg, D, stamp, changed, prev, s)                         \
     }                                                                                                              \
     int launch_ws_label(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *D,     \
                         int32_t *rec) {                                                                            \
@@ -953,6 +962,11 @@ int launch_ws_stages(Launch &lc, const Geom &g, int conn, bool u16, const void *
 int launch_fill_i32(Launch &lc, int32_t *a, int32_t n, int32_t v) {
     if (n <= 0) return 0;
     return lc.run("fill", k_fill_i32, dim3((n + 255) / 256), dim3(256), a, n, v);
+}
+int launch_fill2_i32(Launch &lc, int32_t *a, int32_t na, int32_t va, int32_t *b, int32_t nb, int32_t vb) {
+    const int64_t n = (int64_t)na + nb;
+    if (n <= 0) return 0;
+    return lc.run("fill", k_fill2_i32, dim3((uint32_t)((n + 255) / 256)), dim3(256), a, na, va, b, nb, vb);
 }
 int border_cells(int ndim) { return ndim == 3 ? Border<3>::NB : Border<2>::NB; }
 

@@ -88,7 +88,7 @@ struct TileGrid {
     int launch_ws_init(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,           \
                        int32_t *stamp, int32_t *changed);                                                         \
     int launch_ws_sweep(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,          \
-                        int32_t *stamp, int32_t *changed, int32_t s);                                             \
+                        int32_t *stamp, int32_t *changed, const int32_t *prev, int32_t s);                       \
     int launch_ws_label(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *D,    \
                         int32_t *rec);                                                                            \
     int launch_ws_merge(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *rec); \
@@ -110,6 +110,7 @@ int border_cells(int ndim);
 int launch_ws_stages(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *bal,
                      int32_t *arrow);
 int launch_fill_i32(Launch &lc, int32_t *a, int32_t n, int32_t v);
+int launch_fill2_i32(Launch &lc, int32_t *a, int32_t na, int32_t va, int32_t *b, int32_t nb, int32_t vb);
 
 // Per-pixel synchronous schedule (one thread per pixel, one launch per step).
 int launch_px_step1(Launch &lc, const Geom &g, int conn, bool u16, const void *I, int32_t *L, int32_t *S);
