@@ -798,43 +798,55 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks
     }
 }
 
-// The same pass for NLM = nl - 1 <= 7 layers above layer 0, software-
-// pipelined over the layers: a thread issues the gathers of layer k+1 before
-// it stores layer k, from two register sets used in turn. Loads and stores
-// share one in-order completion counter, so in the layer-by-layer form every
-// layer's gathers also waited for the previous layer's stores; here a layer's
-// stores drain while the next layer's gathers are in flight. The layer loop is
-// unrolled (the table bases stay scalar, one offset register per pixel).
-// Own-label counts are wave ballots summed into one LDS counter per layer,
-// with a single barrier per chunk.
+// The same pass for NLM = nl - 1 <= 7 layers above layer 0. Loads and stores
+// of a wave complete through one in-order counter, so a wave that waits for a
+// gather also waits for every store it issued before it. Each thread
+// therefore gathers everything first (layer 1 and the rank of the layer-1
+// root by region id, then layers 2 .. NLM by that rank) and only then stores:
+// one wave's stores drain while other waves gather. 512 threads per chunk
+// keep that at 8 pixels (two runs of 4) per thread. A pixel whose region id
+// equals the previous pixel's in its run gathers nothing and copies that
+// pixel's values, so a gather instruction carries fewer active lanes (the
+// address unit, not HBM, bounds these gathers). Own-label counts are wave
+// ballots summed into one LDS counter per layer, with one barrier per chunk.
 constexpr int WF_OUT_MAXNL = 8;
-constexpr int WF_RUNS = RCH / (4 * NTHREADS);  // runs of 4 pixels per thread
+constexpr int OUT_T = 512;
+constexpr int OUT_RUNS = RCH / (4 * OUT_T);
 
 // Table gathers as raw buffer loads: a 32-bit byte offset per pixel against a
-// per-table descriptor (base, size), so no 64-bit per-lane address is formed
-// (with global loads the compiler kept one register pair per pixel and layer,
-// 106 registers at six layers). Offsets past the table's size read 0.
+// per-table descriptor (base, size), so no 64-bit per-lane address is formed.
+// Offsets past the table's size read 0.
 constexpr int BUF_CONFIG = 0x00020000;  // raw 32-bit buffer, gfx9 family
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const int32_t *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, BUF_CONFIG);
 }
-__device__ __forceinline__ void wf_gather(int32_t (&v)[WF_RUNS][4], const uint32_t (&off)[WF_RUNS][4],
-                                          __amdgpu_buffer_rsrc_t rs) {
+// Pixels with bit 4r + e of `need` gather; the others copy their run's
+// previous pixel in wf_fill, once the loads are back.
+__device__ __forceinline__ void wf_gather(int32_t (&v)[OUT_RUNS][4], const uint32_t (&off)[OUT_RUNS][4],
+                                          __amdgpu_buffer_rsrc_t rs, uint32_t need) {
 #pragma unroll
-    for (int r = 0; r < WF_RUNS; ++r)
+    for (int r = 0; r < OUT_RUNS; ++r)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[r][e] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off[r][e], 0, 0);
+        for (int e = 0; e < 4; ++e)
+            if (need >> (4 * r + e) & 1u) v[r][e] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off[r][e], 0, 0);
+}
+__device__ __forceinline__ void wf_fill(int32_t (&v)[OUT_RUNS][4], uint32_t need) {
+#pragma unroll
+    for (int r = 0; r < OUT_RUNS; ++r)
+#pragma unroll
+        for (int e = 1; e < 4; ++e)
+            if (!(need >> (4 * r + e) & 1u)) v[r][e] = v[r][e - 1];
 }
 
 typedef int wf_v4i __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void wf_emit(const int32_t (&v)[WF_RUNS][4], const int32_t (&p0)[WF_RUNS], int32_t n,
-                                        bool vec, int32_t *__restrict__ out, int *kc) {
+__device__ __forceinline__ int wf_emit(const int32_t (&v)[OUT_RUNS][4], const int32_t (&p0)[OUT_RUNS], int32_t n,
+                                       bool vec, int32_t *__restrict__ out) {
     int own = 0;
     // 16-byte runs as raw buffer stores (32-bit offsets against the layer's
     // descriptor); a layer of n < 2^30 pixels stays below 4 GiB
     const __amdgpu_buffer_rsrc_t rs = table_rsrc(out, (uint32_t)((size_t)n * 4));
 #pragma unroll
-    for (int r = 0; r < WF_RUNS; ++r) {
+    for (int r = 0; r < OUT_RUNS; ++r) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) own += __popcll(__ballot(p0[r] + e < n && v[r][e] == p0[r] + e));
         if (vec && p0[r] + 3 < n) {
@@ -846,38 +858,23 @@ __device__ __forceinline__ void wf_emit(const int32_t (&v)[WF_RUNS][4], const in
                 if (p0[r] + e < n) out[p0[r] + e] = v[r][e];
         }
     }
-    if (__lane_id() == 0 && own) atomicAdd(kc, own);
+    return own;
 }
 
 // Table bases passed one by one (t[0] layer 1 by id, t[1] the ranks, t[k]
 // layer k by rank): unrelated scalar bases, so every gather addresses its
-// table as base + 32-bit offset and no per-layer 64-bit address is kept.
+// table as base + 32-bit offset.
 struct WfTabs {
     const int32_t *t[WF_OUT_MAXNL];
     uint32_t bytes;  // size of each table (< 4 GiB: larger arenas take the layer-by-layer kernel)
 };
 
-// Layers K+1 .. NLM of the pipeline, unrolled at compile time (the register
-// sets and the table bases are then indexed by constants): V[K & 1] holds
-// layer K + 1; the gathers of layer K + 2 are issued before it is stored.
-template <int K, int NLM>
-__device__ __forceinline__ void wf_layers(int32_t (&V)[2][WF_RUNS][4], const uint32_t (&off2)[WF_RUNS][4],
-                                          const int32_t (&p0)[WF_RUNS], int32_t n, bool vec, int32_t *lab,
-                                          const WfTabs &tabs, int *kc) {
-    if constexpr (K < NLM) {
-        if constexpr (K + 1 < NLM) wf_gather(V[(K + 1) & 1], off2, table_rsrc(tabs.t[K + 2], tabs.bytes));
-        wf_emit(V[K & 1], p0, n, vec, lab + (size_t)(K + 1) * (size_t)n, &kc[K + 1]);
-        wf_layers<K + 1, NLM>(V, off2, p0, n, vec, lab, tabs, kc);
-    }
-}
-
 template <class Src, int NLM>
-__global__ __launch_bounds__(NTHREADS) void k_wf_out_p(Src src_ch, int32_t nchunks,
-                                                       const int32_t *__restrict__ cimg,
-                                                       const int32_t *__restrict__ nreg0,
-                                                       const int32_t *__restrict__ coff, WfTabs tabs,
-                                                       int32_t *__restrict__ cnt) {
-    static_assert(WF_RUNS * 4 * NTHREADS == RCH, "whole runs per chunk");
+__global__ __launch_bounds__(OUT_T) void k_wf_out_p(Src src_ch, int32_t nchunks, const int32_t *__restrict__ cimg,
+                                                    const int32_t *__restrict__ nreg0,
+                                                    const int32_t *__restrict__ coff, WfTabs tabs,
+                                                    int32_t *__restrict__ cnt) {
+    static_assert(OUT_RUNS * 4 * OUT_T == RCH, "whole runs per chunk");
     __shared__ int kc[WF_OUT_MAXNL];
     if ((int)blockIdx.x >= nchunks) return;
     const int t = xcd_group(blockIdx.x, nchunks, XG_OUT);
@@ -892,11 +889,12 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out_p(Src src_ch, int32_t nchun
     const int32_t *ci = cimg + im.pix0;
     const bool vec = ((im.pix0 | n) & 3) == 0 && ((uintptr_t)im.lab & 15) == 0;
     const uint32_t cmax = nr > 0 ? (uint32_t)(nr - 1) : 0u;
-    uint32_t off[WF_RUNS][4];
-    int32_t p0[WF_RUNS];
+    uint32_t off[OUT_RUNS][4];
+    int32_t p0[OUT_RUNS];
+    uint32_t need = 0;
 #pragma unroll
-    for (int r = 0; r < WF_RUNS; ++r) {
-        p0[r] = base + (r * NTHREADS + (int)threadIdx.x) * 4;
+    for (int r = 0; r < OUT_RUNS; ++r) {
+        p0[r] = base + (r * OUT_T + (int)threadIdx.x) * 4;
         int32_t c[4];
         if (vec && p0[r] + 3 < n) {
             int4 q = *(const int4 *)(ci + p0[r]);
@@ -909,20 +907,34 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out_p(Src src_ch, int32_t nchun
             for (int e = 0; e < 4; ++e) c[e] = p0[r] + e < n ? ci[p0[r] + e] : 0;
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) off[r][e] = ((uint32_t)c[e] <= cmax ? (uint32_t)c[e] : cmax) * 4u;
+        for (int e = 0; e < 4; ++e) {
+            off[r][e] = ((uint32_t)c[e] <= cmax ? (uint32_t)c[e] : cmax) * 4u;
+            if (e == 0 || off[r][e] != off[r][e - 1]) need |= 1u << (4 * r + e);
+        }
     }
-    int32_t V[2][WF_RUNS][4];
-    wf_gather(V[0], off, table_rsrc(tabs.t[0], tabs.bytes));  // layer 1, by region id
-    uint32_t off2[WF_RUNS][4];  // layers >= 2, by the rank of the layer-1 root
-    if (NLM >= 2) {
-        int32_t rk[WF_RUNS][4];
-        wf_gather(rk, off, table_rsrc(tabs.t[1], tabs.bytes));
+    int32_t V[NLM][OUT_RUNS][4];
+    wf_gather(V[0], off, table_rsrc(tabs.t[0], tabs.bytes), need);  // layer 1, by region id
+    if constexpr (NLM >= 2) {
+        int32_t rk[OUT_RUNS][4];  // layers >= 2, by the rank of the layer-1 root
+        wf_gather(rk, off, table_rsrc(tabs.t[1], tabs.bytes), need);
 #pragma unroll
-        for (int r = 0; r < WF_RUNS; ++r)
+        for (int r = 0; r < OUT_RUNS; ++r)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) off2[r][e] = (uint32_t)rk[r][e] * 4u;
+            for (int e = 0; e < 4; ++e) off[r][e] = (uint32_t)rk[r][e] * 4u;
+#pragma unroll
+        for (int k = 2; k <= NLM; ++k) wf_gather(V[k - 1], off, table_rsrc(tabs.t[k], tabs.bytes), need);
     }
-    wf_layers<0, NLM>(V, off2, p0, n, vec, im.lab, tabs, kc);
+    int own[NLM];
+#pragma unroll
+    for (int k = 1; k <= NLM; ++k) {
+        wf_fill(V[k - 1], need);
+        own[k - 1] = wf_emit(V[k - 1], p0, n, vec, im.lab + (size_t)k * (size_t)n);
+    }
+    if (__lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < NLM; ++k)
+            if (own[k]) atomicAdd(&kc[k + 1], own[k]);
+    }
     __syncthreads();
     if ((int)threadIdx.x >= 1 && (int)threadIdx.x <= NLM) cnt[(size_t)threadIdx.x * nchunks + t] = kc[threadIdx.x];
 }
@@ -940,7 +952,7 @@ static int wf_out_pipelined(Launch &lc, const Src &src_ch, int32_t nchunks, int3
     switch (nl - 1) {
 #define WF_OUT_P(M)                                                                                               \
     case M:                                                                                                       \
-        return lc.run("wf_out", k_wf_out_p<Src, M>, grid, dim3(NTHREADS), src_ch, nchunks, cimg, nreg0, coff, tabs, \
+        return lc.run("wf_out", k_wf_out_p<Src, M>, grid, dim3(OUT_T), src_ch, nchunks, cimg, nreg0, coff, tabs,    \
                       cnt);
         WF_OUT_P(1)
         WF_OUT_P(2)
