@@ -27,6 +27,8 @@
 //
 // Every tile kernel handles one tile per workgroup, of one image or of a batch
 // of images (through a tile -> image table); the same code serves both.
+#include <type_traits>
+
 #include "ws_device.h"
 #include "ws_kernels.h"
 
@@ -95,6 +97,21 @@ __device__ __forceinline__ void load_grey_dist(const Geom &g, const T *__restric
 // exceed the tile's pixel count (its ring holds 0 or unresolved only).
 template <typename DC> __device__ __forceinline__ constexpr int dinf_of() { return sizeof(DC) == 2 ? 0xffff : INF; }
 
+// Smallest of d and 1 + the distance of every equal-grey neighbour of LDS
+// cell s, branch-free: in unsigned arithmetic an unresolved neighbour
+// (INF + 1 or 0xffff + 1) lands above every finite candidate and above d.
+template <int CONN, class S, typename GC, typename DC>
+__device__ __forceinline__ int relax_best(const GC *sI, const DC *sD, int s, int v, int d) {
+    uint32_t best = (uint32_t)d;
+#pragma unroll
+    for (int k = 0; k < CONN; ++k) {
+        const int o = s + S::template off<CONN>(k);
+        const uint32_t c = (uint32_t)sD[o] + 1u;
+        best = ((int)sI[o] == v && c < best) ? c : best;
+    }
+    return (int)best;
+}
+
 // Relaxes the plateau distances of the tile's pixels to a local fixpoint
 // (ring cells frozen). Returns after an iteration in which no thread changed
 // anything. Gauss-Seidel order inside LDS; any order reaches the same fixpoint
@@ -113,14 +130,8 @@ __device__ __forceinline__ void relax_tile(const GC *sI, DC *sD) {
             if (d == 0) continue;          // fixed (lower neighbour / minimum) or
             int v = sI[s];                 // out of image (d == INF, v == sentinel)
             if (v == sent_of<GC>()) continue;
-            int best = d;
-#pragma unroll
-            for (int k = 0; k < CONN; ++k) {
-                int o = s + S::template off<CONN>(k);
-                int dq = sD[o];
-                if (sI[o] == v && dq != dinf_of<DC>() && dq + 1 < best) best = dq + 1;
-            }
-            if (best < d) { sD[s] = best; changed = 1; }
+            const int best = relax_best<CONN, S>(sI, sD, s, v, d);
+            if (best < d) { sD[s] = (DC)best; changed = 1; }
         }
         if (!__syncthreads_or(changed)) break;
     }
@@ -233,15 +244,9 @@ __device__ __forceinline__ void relax_list(const GC *sI, DC *sD, const unsigned 
     for (;;) {
         int changed = 0;
         if (sc >= 0) {
-            int d = sD[sc], best = d;
-#pragma unroll
-            for (int k = 0; k < CONN; ++k) {
-                int o = sc + S::template off<CONN>(k);
-                int dq = sD[o];
-                if (sI[o] == v && dq != dinf_of<DC>() && dq + 1 < best) best = dq + 1;
-            }
+            const int d = sD[sc], best = relax_best<CONN, S>(sI, sD, sc, v, d);
             if (best < d) {
-                sD[sc] = best;
+                sD[sc] = (DC)best;
                 changed = 1;
             }
         }
@@ -287,7 +292,11 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
     using S1 = Lds<NDIM, 1>;
     constexpr int PIX = TS::X * TS::Y * TS::Z;
     using GC = typename GreyCell<T>::type;
-    using DC = uint16_t;  // distances of the tile pass stay below the tile's pixel count
+    // Volumes keep 16-bit distance cells (the finite distances of the tile
+    // pass stay below the tile's pixel count) to fit more workgroups per CU;
+    // 2D tiles already fit eight with int32 cells, and their 16-bit LDS
+    // accesses measured slower on plateau-heavy tiles.
+    using DC = typename std::conditional<NDIM == 3, uint16_t, int>::type;
     static_assert(PIX < 0xffff, "16-bit distance cells");
     __shared__ GC sI[S2::CELLS];
     __shared__ DC sD[S2::CELLS];
