@@ -301,14 +301,22 @@ __global__ __launch_bounds__(NTHREADS) void k_grad_sobel3(Geom g, int32_t nblock
     }
     const int jmax = min(S3Z + 1, g.nz - zlo + 1);  // planes zlo-1 .. zlo+jmax-1 (clamped)
     float A0 = 0.f, A1 = 0.f, B0 = 0.f, B1 = 0.f, C0 = 0.f, C1 = 0.f, m = 0.f;
+    // the staging values of plane j + 1 are loaded into registers before
+    // plane j is computed, so their latency overlaps the computation
+    float nv[2];
+    auto load_plane = [&](int j) {
+        const float *pa = a + (size_t)clampi(zlo - 1 + j, 0, g.nz - 1) * (size_t)plane;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) nv[h] = has[h] ? pa[src[h]] : 0.f;
+    };
+    load_plane(0);
     for (int j = 0; j <= jmax; ++j) {
-        const int zz = clampi(zlo - 1 + j, 0, g.nz - 1);
         float *cur = sp[j & 1];
-        const float *pa = a + (size_t)zz * (size_t)plane;
 #pragma unroll
         for (int h = 0; h < 2; ++h)
-            if (has[h]) cur[threadIdx.x + h * NTHREADS] = pa[src[h]];
+            if (has[h]) cur[threadIdx.x + h * NTHREADS] = nv[h];
         __syncthreads();
+        if (j < jmax) load_plane(j + 1);
         const float *r0 = cur + ty * S3W + tx, *r1 = r0 + S3W, *r2 = r1 + S3W;
         float d0 = r0[2] - r0[0], d1 = r1[2] - r1[0], d2 = r2[2] - r2[0];
         float s0 = r0[0] + 2.f * r0[1] + r0[2], s1 = r1[0] + 2.f * r1[1] + r1[2], s2 = r2[0] + 2.f * r2[1] + r2[2];
