@@ -273,7 +273,7 @@ __global__ __launch_bounds__(NTHREADS) void k_grad_sobel(Geom g, const float *__
 //   gx = A(z-1) + 2 A(z) + A(z+1),  gy = C(z-1) + 2 C(z) + C(z+1),  gz = B(z+1) - B(z-1),
 // the unnormalised Sobel derivatives. Each voxel is read from HBM about once
 // (plus halos) instead of 54 times through the cache hierarchy.
-constexpr int S3X = 64, S3Y = 4, S3Z = 16;
+constexpr int S3X = 32, S3Y = 8, S3Z = 32;
 constexpr int S3W = S3X + 2, S3H = S3Y + 2, S3CELLS = S3W * S3H;
 static_assert(S3X * S3Y == NTHREADS, "one column per thread");
 static_assert(S3CELLS <= 2 * NTHREADS, "two staging loads per thread");
