@@ -668,6 +668,31 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
     }
 }
 
+// Union of p and r for the lanes with `want`, once per distinct pair of the
+// roots they had after the tile pass: border cells next to each other mostly
+// join the same two tile-local components, so a wave first elects one lane
+// per distinct (L[p], L[r]) pair (ballots, no memory traffic) and only those
+// lanes run the global union, all at once.
+__device__ __forceinline__ void wave_unique_union(int32_t *L, bool want, int32_t p, int32_t r) {
+    uint64_t pending = __ballot(want);
+    if (pending == 0) return;  // wave-uniform
+    int32_t a = -1, b = -1;
+    if (want) {
+        const int32_t lp = ld_par(L + p), lr = ld_par(L + r);
+        a = lp < lr ? lp : lr;
+        b = lp < lr ? lr : lp;
+    }
+    bool lead = false;
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int32_t la = __shfl(a, leader), lb = __shfl(b, leader);
+        const uint64_t same = __ballot(want && a == la && b == lb);
+        if (__lane_id() == leader) lead = true;
+        pending &= ~same;
+    }
+    if (lead && a != b) gunion(L, a, b);
+}
+
 // ---------------------------------------------------------------------------
 // Unions for every arrow / minimal-plateau adjacency that crosses a tile
 // border, driven by the records of k_ws_label. One thread per border cell.
@@ -697,29 +722,35 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_merge(Src src, int32_t ntiles, 
             int b = threadIdx.x + u * NTHREADS;
             codes[u] = trec[b < NB ? b : 0];
         }
+        // candidate slot 0: the arrow that leaves the tile; slots 1 .. CONN/2:
+        // equal minimal-plateau neighbours after p outside the tile
 #pragma unroll
         for (int u = 0; u < MU; ++u) {
-            int b = threadIdx.x + u * NTHREADS;
-            if (b >= NB) continue;
-            int x, y, z;
-            border_cell<NDIM>(b, x, y, z);
-            int gx = ox + x, gy = oy + y, gz = oz + z;
-            if (!in_image(g, gx, gy, gz)) continue;
-            int32_t code = codes[u];
-            if (code == -1) continue;
-            int32_t p = gx + g.nx * (gy + g.ny * gz);
-            if (code >= 0) {
-                gunion(L, p, code);
-                continue;
-            }
-            int v = I[p];
+            const int b = threadIdx.x + u * NTHREADS;
+            int x = 0, y = 0, z = 0;
+            if (b < NB) border_cell<NDIM>(b, x, y, z);
+            const int gx = ox + x, gy = oy + y, gz = oz + z;
+            const int32_t code = b < NB && in_image(g, gx, gy, gz) ? codes[u] : -1;
+            const int32_t p = gx + g.nx * (gy + g.ny * gz);
+            const int v = code == -2 ? (int)I[p] : 0;
 #pragma unroll
-            for (int k = CONN / 2; k < CONN; ++k) {
-                int xx = gx + nb_dx<CONN>(k), yy = gy + nb_dy<CONN>(k), zz = gz + nb_dz<CONN>(k);
-                if (!in_image(g, xx, yy, zz)) continue;
-                if (xx >= ox && xx < ox + TS::X && yy >= oy && yy < oy + TS::Y && zz >= oz && zz < oz + TS::Z) continue;
-                int32_t r = xx + g.nx * (yy + g.ny * zz);
-                if ((int)I[r] == v) gunion(L, p, r);
+            for (int k = CONN / 2 - 1; k < CONN; ++k) {
+                int32_t r = -1;
+                if (k == CONN / 2 - 1) {
+                    r = code >= 0 ? code : -1;
+                } else if (code == -2) {
+                    int xx = gx + nb_dx<CONN>(k), yy = gy + nb_dy<CONN>(k), zz = gz + nb_dz<CONN>(k);
+                    bool outside = !(xx >= ox && xx < ox + TS::X && yy >= oy && yy < oy + TS::Y && zz >= oz &&
+                                     zz < oz + TS::Z);
+                    if (outside && in_image(g, xx, yy, zz)) {
+                        int32_t q = xx + g.nx * (yy + g.ny * zz);
+                        if ((int)I[q] == v) r = q;
+                    }
+                }
+                // volumes (47 % border cells, many per component pair) elect
+                // one lane per pair; 2D tiles measured faster without
+                if constexpr (NDIM == 3) wave_unique_union(L, r >= 0, p, r);
+                else if (r >= 0) gunion(L, p, r);
             }
         }
     }
