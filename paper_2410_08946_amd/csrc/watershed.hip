@@ -784,8 +784,9 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_find(Src src, int32_t ntiles) {
             ok[j] = in_image(g, x, y, z);
             p[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
         }
+        int32_t l0[PER];
 #pragma unroll
-        for (int j = 0; j < PER; ++j) r[j] = L[p[j]];
+        for (int j = 0; j < PER; ++j) r[j] = l0[j] = L[p[j]];
         // chase all PER paths together so their loads overlap
         uint32_t live = 0;
 #pragma unroll
@@ -802,9 +803,10 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_find(Src src, int32_t ntiles) {
                 else r[j] = nxt[j];
             }
         }
+        // a pixel whose label already is its root keeps it (no store)
 #pragma unroll
         for (int j = 0; j < PER; ++j)
-            if (ok[j]) L[p[j]] = r[j];
+            if (ok[j] && r[j] != l0[j]) L[p[j]] = r[j];
     }
 }
 
