@@ -491,7 +491,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_level(int32_t ntiles, int32_t g
     const size_t base = (size_t)t0 * (size_t)cap;
     // LEV_U edges per thread per batch: all their loads, then all their parent
     // gathers, are issued before the first wait (two round trips per batch)
-    constexpr int LEV_U = 4;
+    constexpr int LEV_U = 8;
     for (int32_t e0 = 0; e0 < total; e0 += NTHREADS * LEV_U) {  // uniform trip count
         int32_t ra[LEV_U], rb[LEV_U];
         uint32_t w[LEV_U];
