@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the watershed + waterfall hot path on one MI355X.
 
-One step = the whole hot path over one image already resident in HBM:
-float32 image -> gradient (blur sigma 1 + Sobel, quantised to uint16) ->
-watershed (Alg. 1, 8-connectivity) -> waterfall, NL = 6 layers (layer 0 =
-the watershed). Workload: 4096 x 4096 synthetic image (2000 seeded ellipses
-with intensities U[0, 65535] plus Gaussian noise of std 500), the 16.8-Mpixel
-configuration the Mvoxel/s metric is quoted on.
+One step = the whole hot path over one volume already resident in HBM:
+float32 volume -> gradient (3D Sobel magnitude quantised to uint8) ->
+watershed (Alg. 1, 6-connectivity, int32 labels) -> waterfall, NL = 6 layers
+(layer 0 = the watershed). Default workload: the 928 x 928 x 928 (799 Mvoxel)
+synthetic volume (5000 seeded Gaussian blobs, sigma 4-32 voxels, plus
+Gaussian noise of std 2), the largest single-volume configuration, evaluated
+on the device. `--workload c1` runs the 4096 x 4096 uint16 image instead
+(blur sigma 1 + Sobel, 8-connectivity, NL = 6); by default its figures are
+also reported under "extra".
 
-Prints ONE JSON line. `value` is Mvoxel/s over the timed steps (hipEvents on
-the stream the library launches on). `roofline` is for the kernel with the
+Prints ONE JSON line. `value` is Mvoxel/s over the timed steps (a HIP event
+pair around every step on the stream the library launches on; p50 / p99 /
+min per step are reported). `roofline` is for the priced kernel with the
 largest share of device time, from a second pass of the same steps with a
-HIP event pair around every launch. `cpu_baseline` is the CPU oracle timed on
-the host on one full step of the same workload.
+HIP event pair around every launch; its `traffic` comes from the committed
+rocprofv3 counter summary of the workload. `hbm_path` is the whole step
+against the HBM roofline. `cpu_baseline` is the CPU oracle, pinned to one
+host core, on a same-recipe sample of the workload.
 """
 from __future__ import annotations
 
@@ -28,11 +34,25 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per pixel each kernel must move (compulsory reads and
-# writes of its inputs/outputs; b = bytes per grey value, NL = layers).
-# Region- and edge-level kernels (ws_merge, wf_union, wf_compress, wf_level)
-# touch a small, data-dependent share of the pixels' worth of bytes, and
-# wf_ids names three launches of different kinds: none of them is priced.
+TRAFFIC_FILES = {
+    "c1": "c1_4096x4096_u16_conn8_nl6_traffic.md",
+    "c2": "c2_928x928x928_u8_conn6_nl6_traffic.md",
+}
+
+WORKLOAD_NAMES = {
+    "c1": ("2D 4096x4096 uint16 gradient (f32 ellipses+noise, blur sigma=1, Sobel), 8-connectivity, "
+           "watershed + NL=6 waterfall"),
+    "c2": ("3D 928x928x928 uint8 gradient (f32 5000 blobs + N(0,2^2), 3D Sobel), 6-connectivity, int32 labels, "
+           "watershed + NL=6 waterfall"),
+}
+
+
+# Algorithmic bytes per pixel each kernel must move: the compulsory reads and
+# writes of the method's own inputs and outputs at that step (b = bytes per
+# grey value, NL = layers). Region- and edge-level kernels (ws_merge,
+# wf_union, wf_compress, wf_level) touch a small, data-dependent share of the
+# pixels' worth of bytes, and wf_ids names three launches of different kinds:
+# none of them is priced.
 def kernel_bytes_per_pixel(b, NL):
     return {
         "grad_fused": 8.0,         # read f32 image, write f32 magnitude
@@ -42,35 +62,42 @@ def kernel_bytes_per_pixel(b, NL):
         "ws_init": b + 4.0,        # read grey, write distance
         "ws_label": b + 8.0,       # read grey + distance, write label
         "ws_find": 8.0,            # read label, write label
-        "wf_pix": 8.0 + b,         # read layer-0 label + grey, write the pixel's region id
+        "wf_pix": 4.0 + b,         # Step V: read layer-0 label + grey
         "wf_out": 4.0 * NL,        # read layer 0, write layers 1 .. NL-1
     }
 
 
 def path_roofline(b, NL, N, ms_step, counter_bytes):
     """Whole-step HBM roofline: each step of the method streaming its arrays
-    once -- Step I b + 8, Step II b + 12, Step III 8, Step IV 12 and the
-    canonical relabel 12 bytes per pixel, and b + 12 per waterfall level --
-    so B_step = 2b + 52 + (NL - 1)(b + 12) bytes per pixel; the bytes counted
+    once -- the gradient 4 + b (read the float image, write the grey values),
+    Step I b + 8, Step II b + 12, Step III 8, Step IV 12 and the canonical
+    relabel 12 bytes per pixel, and b + 12 per waterfall level -- so
+    B_step = 4 + 3b + 52 + (NL - 1)(b + 12) bytes per pixel; the bytes counted
     are the smaller of B_step N and the measured HBM traffic of a step (fused
-    kernels cannot claim more than the method's bytes, extra sweeps count)."""
-    alg = (2 * b + 52 + (NL - 1) * (b + 12)) * N
+    kernels cannot claim more than the method's bytes, extra sweeps count).
+    `ws_wf` gives the same figure for the watershed and waterfall alone
+    (2b + 52 + (NL - 1)(b + 12) bytes per pixel, without the gradient)."""
+    per = 4 + 3 * b + 52 + (NL - 1) * (b + 12)
+    alg = per * N
     used = min(alg, counter_bytes) if counter_bytes else alg
     achieved = used / (ms_step / 1e3) / 1e9
-    return {"bound": "hbm", "bytes_per_pixel": 2 * b + 52 + (NL - 1) * (b + 12), "algorithmic_bytes": alg,
+    return {"bound": "hbm", "bytes_per_pixel": per, "algorithmic_bytes": alg,
             "counter_bytes": counter_bytes, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4)}
 
 
-def recorded_traffic(kernel, workload="c1"):
+def recorded_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` (or, for kernel "step", of all the
-    library's kernels over one step) from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary of the workload, or None when there is none or when the
-    kernel sources changed since the counters were taken (the summary records
-    the sha256 of the sources it measured)."""
+    library's kernels over one step; "step_ws_wf" without the gradient's) from
+    the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the workload, or
+    None when there is none or when the kernel sources changed since the
+    counters were taken (the summary records the sha256 of the sources it
+    measured)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "c1_4096x4096_u16_conn8_nl6_traffic.md")
-    if workload != "c1" or not os.path.exists(path):
+    if workload not in TRAFFIC_FILES:
+        return None
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES[workload])
+    if not os.path.exists(path):
         return None
     vals, sha, srcs = {}, None, []
     for line in open(path):
@@ -92,6 +119,71 @@ def recorded_traffic(kernel, workload="c1"):
     return vals[kernel] if h.hexdigest() == sha else None
 
 
+def host_info():
+    """CPU model, logical CPUs (all, and usable by this process) and RAM of the host."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ram = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                ram = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu": model, "nproc": os.cpu_count(), "usable_cpus": usable, "ram_gib": ram}
+
+
+def percentiles(xs):
+    import numpy as np
+    a = np.asarray(xs, dtype=np.float64)
+    return {"p50": round(float(np.percentile(a, 50)), 4), "p99": round(float(np.percentile(a, 99)), 4),
+            "min": round(float(a.min()), 4), "max": round(float(a.max()), 4)}
+
+
+def copy_bandwidth(dev):
+    """Measured plain device-to-device copy rate (read + write bytes), GB/s."""
+    import torch
+    a = torch.empty(64 << 20, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * a.numel() * 4 / (ms / 1e3) / 1e9
+    del a, b
+    return round(gbs, 1)
+
+
+def pinned(fn):
+    """Runs fn() with this thread pinned to one host core (the last usable
+    one); returns (result, core)."""
+    if not hasattr(os, "sched_setaffinity"):
+        return fn(), None
+    old = os.sched_getaffinity(0)
+    core = max(old)
+    os.sched_setaffinity(0, {core})
+    try:
+        return fn(), core
+    finally:
+        os.sched_setaffinity(0, old)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,8 +191,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--workload", choices=("single", "c2", "batch", "serve", "recon", "schedules"), default="single",
-                    help="single: the 4096x4096 image (default); c2: the 928^3 uint8 volume; batch: 512 uneven "
+    ap.add_argument("--no-extra", action="store_true", help="skip the 4096^2 figures reported under 'extra'")
+    ap.add_argument("--workload", choices=("c2", "c1", "batch", "serve", "recon", "schedules"), default="c2",
+                    help="c2: the 928^3 uint8 volume (default); c1: the 4096x4096 uint16 image; batch: 512 uneven "
                          "2D images, one batched call vs one call per image; serve: Poisson arrivals of mixed "
                          "2D/3D jobs through the continuous-batching server; recon: the reconstruction waterfall "
                          "against the graph waterfall on the three single-image workloads (differing pixels per "
@@ -111,8 +204,7 @@ def parse():
     ap.add_argument("--slots", type=int, default=4, help="serve workload: execution slots")
     ap.add_argument("--images", type=int, default=512, help="batch workload: number of images")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
-                    help="1: the library replays launch graphs of the gradient and waterfall calls (on this "
-                         "workload direct launches measured slightly faster, so 0 is the default)")
+                    help="1: the library replays launch graphs of the gradient and waterfall calls")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (counter calibration)")
     return ap.parse_args()
@@ -197,8 +289,58 @@ def bench_batch(args):
         "per_image_calls": {"value": round(N / (ms_s / 1e3) / 1e6, 2), "unit": "Mvoxel/s", "ms_per_step": round(ms_s, 3)},
         "batched_over_per_image": round(ms_s / ms_b, 3),
         "identical_outputs": bool(same),
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_batch(args.images),
+        "host": host_info(),
     }
     print(json.dumps(line), flush=True)
+
+
+def _oracle_batch_job(i):
+    """One image of the uneven batch through the oracle (gradient, watershed,
+    NL = 4 waterfall, 8-connectivity): (voxels, seconds)."""
+    import gen
+    import oracle
+    img = gen.synth.batch_image(i)
+    t = time.perf_counter()
+    g = oracle.gradient(img, 0.0, "u8")
+    lab = oracle.watershed(g, 8)
+    oracle.waterfall_g1(lab, g, 8, 4)
+    return img.size, time.perf_counter() - t
+
+
+def cpu_baseline_batch(n_images):
+    """The oracle over a process pool of all usable host cores (at most 16),
+    one image per task, on the first images of the batch until about 20 s of
+    wall time have passed."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.build()
+    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1))
+    print("bench: timing the CPU oracle over %d processes" % workers, file=sys.stderr, flush=True)
+    vox, done, busy = 0, 0, 0.0
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=workers) as pool:
+        nxt = 0
+        futs = set()
+        while nxt < n_images and len(futs) < workers:
+            futs.add(pool.submit(_oracle_batch_job, nxt))
+            nxt += 1
+        while futs:
+            fin, futs = cf.wait(futs, return_when=cf.FIRST_COMPLETED)
+            for f in fin:
+                v, t = f.result()
+                vox += v
+                busy += t
+                done += 1
+            while nxt < n_images and len(futs) < workers and time.perf_counter() - t0 < 20.0:
+                futs.add(pool.submit(_oracle_batch_job, nxt))
+                nxt += 1
+    dt = time.perf_counter() - t0
+    # the oracle's own time (image generation excluded), all processes busy
+    return {"value": round(vox / (busy / workers) / 1e6, 3), "unit": "Mvoxel/s", "cores": workers, "kind": "oracle",
+            "sample": "images 0..%d of the uneven batch (%d voxels), gradient + watershed + NL=4 waterfall each, "
+                      "one image per task over %d processes; rate = voxels / (summed oracle seconds / processes) "
+                      "= %.1f s, %.1f s wall with image generation" % (done - 1, vox, workers, busy / workers, dt)}
 
 
 def bench_serve(args):
@@ -448,6 +590,174 @@ def bench_schedules(args):
     print(json.dumps(line), flush=True)
 
 
+def measure_single(args, name, steps, warmup, kernel_timing, cpu_baseline):
+    """Times `steps` whole steps of workload `name` (c1 / c2) with the input
+    resident in HBM and returns the fields of its JSON line."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2410_08946_amd as ws
+
+    cfg = gen.CONFIGS[name]
+    shape = tuple(cfg["shape"])
+    sigma, conn, NL, gdt = cfg["sigma"], cfg["conn"], cfg["NL"], cfg["dtype"]
+    N = int(np.prod(shape))
+    b = 2 if gdt == "u16" else 1
+    dev = torch.device("cuda:0")
+    img = None
+    if name == "c2":
+        # too large for the host generator: the same recipe evaluated on the device
+        print("bench: generating the 928^3 volume on the device", file=sys.stderr, flush=True)
+        img_d = gen.synth.blobs3d_device(shape, seed=cfg["seed"], device=dev)
+    else:
+        print("bench: generating the 4096x4096 image", file=sys.stderr, flush=True)
+        img = gen.config_image(name)
+        img_d = torch.from_numpy(img).to(dev)
+    grad_d = torch.empty(shape, dtype=torch.uint16 if gdt == "u16" else torch.uint8, device=dev)
+    out_d = torch.empty((NL,) + shape, dtype=torch.int32, device=dev)
+    nreg_d = torch.zeros(NL, dtype=torch.int64, device=dev)
+    ctx = ws.Context(0)
+    ctx.set_option("graph", args.graph)
+
+    def step():
+        ctx.gradient(img_d, sigma, gdt, out=grad_d)
+        ctx.watershed(grad_d, conn, out=out_d[0])
+        ctx.waterfall(out_d[0], grad_d, conn, NL, out=out_d, nregions=nreg_d)
+
+    print("bench: %s warmup %d" % (name, warmup), file=sys.stderr, flush=True)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # one event pair per step on the stream the library launches on
+    stream = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        step()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_step = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    ms_total = ev[0].elapsed_time(ev[steps])
+    ms_step = ms_total / steps
+    value = N * steps / (ms_total / 1e3) / 1e6
+    print("bench: %s timed %d steps, %.3f ms/step (wall %.3f ms/step)" %
+          (name, steps, ms_step, wall * 1e3 / steps), file=sys.stderr, flush=True)
+    stats = ctx.stats()
+    nregions = nreg_d.cpu().tolist()
+
+    # Stage split (host-synchronised, separate pass).
+    stages = {}
+    for stage, fn in (("gradient", lambda: ctx.gradient(img_d, sigma, gdt, out=grad_d)),
+                      ("watershed", lambda: ctx.watershed(grad_d, conn, out=out_d[0])),
+                      ("waterfall", lambda: ctx.waterfall(out_d[0], grad_d, conn, NL, out=out_d, nregions=nreg_d))):
+        a = torch.cuda.Event(enable_timing=True)
+        z = torch.cuda.Event(enable_timing=True)
+        reps = max(1, steps // 2)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        z.record(stream)
+        torch.cuda.synchronize()
+        stages[stage] = round(a.elapsed_time(z) / reps, 4)
+
+    roofline = None
+    kernels = {}
+    if kernel_timing:
+        ctx.set_option("timing", 1)
+        ctx.timing_reset()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        kt = ctx.timing_read()
+        ctx.set_option("timing", 0)
+        per = kernel_bytes_per_pixel(b, NL)
+        for kname, (ms, cnt) in kt.items():
+            kernels[kname] = {"launches_per_step": cnt / steps, "avg_us": round(ms * 1e3 / cnt, 2),
+                              "ms_per_step": round(ms / steps, 4)}
+        priced = {k: v for k, v in kt.items() if k in per}
+        if priced:
+            dom = max(priced, key=lambda k: priced[k][0])
+            ms, cnt = priced[dom]
+            avg_s = ms / cnt / 1e3
+            bytes_per_launch = per[dom] * N
+            achieved = bytes_per_launch / avg_s / 1e9
+            roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": recorded_traffic(dom, name),
+                        "bytes_per_pixel": per[dom], "bytes_per_launch": bytes_per_launch,
+                        "avg_launch_us": round(avg_s * 1e6, 2)}
+
+    cpu = None
+    if cpu_baseline:
+        cpu = cpu_baseline_single(name, cfg, img, img_d)
+    ws_wf_ms = stages["watershed"] + stages["waterfall"]
+    bws = 2 * b + 52 + (NL - 1) * (b + 12)
+    cb = recorded_traffic("step_ws_wf", name)
+    used = min(bws * N, cb) if cb else bws * N
+    res = {
+        "value": round(value, 2),
+        "ms_per_step": round(ms_step, 4),
+        "step_ms": percentiles(per_step),
+        "config": {"workload": WORKLOAD_NAMES[name], "shape": list(shape), "pixels": N, "NL": NL, "conn": conn,
+                   "grey": gdt, "parallelism": "single GPU"},
+        "dtype": gdt,
+        "stages_ms": stages,
+        "step2_sweeps": stats.get("sweeps_launched"),
+        "nregions": nregions,
+        "kernels": kernels,
+        "roofline": roofline,
+        "hbm_path": path_roofline(b, NL, N, ms_step, recorded_traffic("step", name)),
+        "hbm_path_ws_wf": {"bytes_per_pixel": bws, "algorithmic_bytes": bws * N, "counter_bytes": cb,
+                           "ms": round(ws_wf_ms, 4), "achieved": round(used / (ws_wf_ms / 1e3) / 1e9, 1),
+                           "frac": round(used / (ws_wf_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "cpu_baseline": cpu,
+    }
+    del img_d, grad_d, out_d
+    ctx.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline_single(name, cfg, img, img_d):
+    """The CPU oracle, pinned to one host core, on whole steps (gradient +
+    watershed + NL-layer waterfall) of a same-recipe sample: the full
+    4096x4096 image, or a 24-plane slab of the 928^3 volume (the device's
+    float planes copied to the host; about 20 s of CPU work)."""
+    import oracle
+    sigma, conn, NL, gdt = cfg["sigma"], cfg["conn"], cfg["NL"], cfg["dtype"]
+    if name == "c2":
+        z0, z1 = 452, 476
+        sample = img_d[z0:z1].cpu().numpy()
+        what = "planes %d..%d of the 928^3 volume (928x928x%d = %d voxels)" % (z0, z1 - 1, z1 - z0, sample.size)
+    else:
+        sample = img
+        what = "the 4096x4096 image"
+    print("bench: timing the CPU oracle on %s" % what, file=sys.stderr, flush=True)
+
+    def run():
+        reps, dt = 0, 0.0
+        while reps < 4 and (reps == 0 or dt < 10.0):
+            t = time.perf_counter()
+            g = oracle.gradient(sample, sigma, gdt)
+            lab = oracle.watershed(g, conn)
+            oracle.waterfall_g1(lab, g, conn, NL)
+            dt += time.perf_counter() - t
+            reps += 1
+        return reps, dt
+
+    (reps, dt), core = pinned(run)
+    return {"value": round(sample.size * reps / dt / 1e6, 3), "unit": "Mvoxel/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full step(s) (gradient + watershed + NL=%d waterfall) of %s, single-threaded C oracle "
+                      "(gcc -O2) pinned to host core %s, %.1f s" % (reps, NL, what, core, dt),
+            "host": host_info()}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -466,37 +776,9 @@ def main():
     if args.workload == "schedules":
         bench_schedules(args)
         return
-    import numpy as np
     import torch
 
-    import gen
-    import paper_2410_08946_amd as ws
-
-    name = "c2" if args.workload == "c2" else "c1"
-    cfg = gen.CONFIGS[name]
-    shape = tuple(cfg["shape"])
-    sigma, conn, NL, gdt = cfg["sigma"], cfg["conn"], cfg["NL"], cfg["dtype"]
-    N = int(np.prod(shape))
-    b = 2 if gdt == "u16" else 1
     dev = torch.device("cuda:0")
-    if name == "c2":
-        # too large for the host generator: the same recipe evaluated on the device
-        print("bench: generating the 928^3 volume on the device", file=sys.stderr, flush=True)
-        img = None
-        img_d = gen.synth.blobs3d_device(shape, seed=cfg["seed"], device=dev)
-        workload = ("3D 928x928x928 uint8 gradient (f32 5000 blobs + N(0,2^2), 3D Sobel), 6-connectivity, "
-                    "watershed + NL=6 waterfall")
-    else:
-        print("bench: generating the 4096x4096 image", file=sys.stderr, flush=True)
-        img = gen.config_image("c1")
-        img_d = torch.from_numpy(img).to(dev)
-        workload = ("2D 4096x4096 uint16 gradient (f32 ellipses+noise, blur sigma=1, Sobel), 8-connectivity, "
-                    "watershed + NL=6 waterfall")
-    grad_d = torch.empty(shape, dtype=torch.uint16 if gdt == "u16" else torch.uint8, device=dev)
-    out_d = torch.empty((NL,) + shape, dtype=torch.int32, device=dev)
-    nreg_d = torch.zeros(NL, dtype=torch.int64, device=dev)
-    ctx = ws.Context(0)
-    ctx.set_option("graph", args.graph)
     if args.calib_copy:
         a = torch.empty(64 << 20, dtype=torch.int32, device=dev)
         bb = torch.empty_like(a)
@@ -505,115 +787,30 @@ def main():
         bb.copy_(a)
         torch.cuda.synchronize()
         del a, bb
-
-    def step():
-        ctx.gradient(img_d, sigma, gdt, out=grad_d)
-        ctx.watershed(grad_d, conn, out=out_d[0])
-        ctx.waterfall(out_d[0], grad_d, conn, NL, out=out_d, nregions=nreg_d)
-
-    print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream(dev)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
-    ms_step = ms_total / args.steps
-    value = N * args.steps / (ms_total / 1e3) / 1e6
-    print("bench: timed %d steps, %.3f ms/step (wall %.3f ms/step)" % (args.steps, ms_step, wall * 1e3 / args.steps),
-          file=sys.stderr, flush=True)
-    stats = ctx.stats()
-    nregions = nreg_d.cpu().tolist()
-
-    # Stage split (host-synchronised, separate pass).
-    stages = {}
-    for stage, fn in (("gradient", lambda: ctx.gradient(img_d, sigma, gdt, out=grad_d)),
-                     ("watershed", lambda: ctx.watershed(grad_d, conn, out=out_d[0])),
-                     ("waterfall", lambda: ctx.waterfall(out_d[0], grad_d, conn, NL, out=out_d, nregions=nreg_d))):
-        a = torch.cuda.Event(enable_timing=True)
-        z = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record(stream)
-        for _ in range(max(1, args.steps // 2)):
-            fn()
-        z.record(stream)
-        torch.cuda.synchronize()
-        stages[stage] = round(a.elapsed_time(z) / max(1, args.steps // 2), 4)
-
-    roofline = None
-    kernels = {}
-    if not args.no_kernel_timing:
-        ctx.set_option("timing", 1)
-        ctx.timing_reset()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        kt = ctx.timing_read()
-        ctx.set_option("timing", 0)
-        per = kernel_bytes_per_pixel(b, NL)
-        for kname, (ms, cnt) in kt.items():
-            kernels[kname] = {"launches_per_step": cnt / args.steps, "avg_us": round(ms * 1e3 / cnt, 2),
-                              "ms_per_step": round(ms / args.steps, 4)}
-        priced = {k: v for k, v in kt.items() if k in per}
-        if priced:
-            dom = max(priced, key=lambda k: priced[k][0])
-            ms, cnt = priced[dom]
-            avg_s = ms / cnt / 1e3
-            bytes_per_launch = per[dom] * N
-            achieved = bytes_per_launch / avg_s / 1e9
-            roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": recorded_traffic(dom, name),
-                        "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
-
-    cpu = None
-    if not args.no_cpu_baseline and name == "c1":
-        print("bench: timing the CPU oracle on one step", file=sys.stderr, flush=True)
-        import oracle
-        reps, dt = 0, 0.0
-        while reps < 4 and (reps == 0 or dt < 10.0):  # about 10 s of CPU work
-            t = time.perf_counter()
-            g = oracle.gradient(img, sigma, "u16")
-            lab = oracle.watershed(g, conn)
-            oracle.waterfall_g1(lab, g, conn, NL)
-            dt += time.perf_counter() - t
-            reps += 1
-        cpu = {"value": round(N * reps / dt / 1e6, 3), "unit": "Mvoxel/s", "cores": 1, "kind": "oracle",
-               "sample": "%d full step(s) (gradient + watershed + NL=6 waterfall) of the 4096x4096 image, "
-                         "single-threaded C oracle, %.1f s" % (reps, dt)}
-
+    name = args.workload
+    r = measure_single(args, name, args.steps, args.warmup, not args.no_kernel_timing, not args.no_cpu_baseline)
     line = {
         "metric": "Mvoxel/s watershed+NL waterfall",
-        "value": round(value, 2),
+        "value": r["value"],
         "unit": "Mvoxel/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": gdt,
+        "dtype": r["dtype"],
         "data": "synthetic",
-        "config": {"workload": workload, "pixels": N, "NL": NL, "conn": conn, "parallelism": "single GPU"},
-        "stages_ms": stages,
-        "step2_sweeps": stats.get("sweeps_launched"),
-        "nregions": nregions,
-        "kernels": kernels,
-        "roofline": roofline,
-        "hbm_path": path_roofline(b, NL, N, ms_step, recorded_traffic("step", name)),
-        "cpu_baseline": cpu,
     }
+    line.update({k: v for k, v in r.items() if k not in ("value", "ms_per_step", "dtype")})
+    line["copy_bandwidth_gbs"] = copy_bandwidth(dev)
+    line["host"] = host_info()
+    if name == "c2" and not args.no_extra:
+        # the 4096^2 image: a smaller, partly cache-resident workload
+        e = measure_single(args, "c1", max(1, args.steps // 2), 2, False, False)
+        line["extra"] = {"c1": {k: e[k] for k in ("value", "ms_per_step", "step_ms", "config", "stages_ms",
+                                                  "nregions", "hbm_path", "hbm_path_ws_wf")}}
     print(json.dumps(line), flush=True)
 
 

@@ -53,10 +53,17 @@ typedef struct ws_ctx ws_ctx;
 
 /*
  * Create a context bound to HIP device `device`. The context owns all device
- * scratch memory (grow-only; freed by ws_destroy). Returns WS_EINVAL for a bad
- * device index or NULL ctx, WS_EDEVICE if the device cannot be used.
+ * scratch memory (grow-only; freed by ws_destroy).
+ *   scratch_budget_bytes  upper bound on the device scratch the context may
+ *          hold at once (0 = no bound). A call whose scratch would exceed it
+ *          returns WS_ENOMEM; every call except ws_rag sizes all its scratch
+ *          before launching anything, so nothing was launched then (ws_rag
+ *          sizes its sort buffers after counting the edges on the device).
+ *          The caller's own buffers (images, labels) do not count.
+ * Returns WS_EINVAL for a bad device index or NULL ctx, WS_EDEVICE if the
+ * device cannot be used.
  */
-int ws_create(ws_ctx **ctx, int device);
+int ws_create(ws_ctx **ctx, int device, size_t scratch_budget_bytes);
 
 /* Free the context and its device scratch memory. NULL is ignored. The
  * caller must make sure no work of this context is still running. */
@@ -139,8 +146,9 @@ int ws_waterfall(ws_ctx *ctx, const int32_t *labels, const void *grad, int dtype
 /*
  * One image of a batched call (ws_batch).
  *   grad      grey values (device, u8/u16 as the batch's dtype), read only.
- *   nx,ny,nz  its size (same rules as ws_watershed; nz == 1 for conn 4/8 and
- *             nz > 1 for conn 6/26).
+ *   nx,ny,nz  its size (same rules as ws_watershed).
+ *   conn      its connectivity: 4 or 8 when nz == 1, 6 or 26 when nz > 1
+ *             (Section 3.1 neighbourhoods); items of one batch may differ.
  *   out       int32[NL*N] (device): layer k at out + k*N, canonical labels
  *             local to the image (smallest pixel index of the image).
  *   nregions  optional int64[NL] (device): region count per layer.
@@ -148,6 +156,7 @@ int ws_waterfall(ws_ctx *ctx, const int32_t *labels, const void *grad, int dtype
 typedef struct {
     const void *grad;
     int64_t nx, ny, nz;
+    int32_t conn;
     int32_t *out;
     int64_t *nregions;
 } ws_item;
@@ -190,18 +199,20 @@ int ws_rag(ws_ctx *ctx, const int32_t *labels, const void *grad, int dtype, int6
            int64_t *n_edges, void *stream);
 
 /*
- * Watershed + NL-layer waterfall of many images of uneven sizes in one set of
- * launches (every kernel covers the tiles of all images through a tile ->
- * image table; the Step II convergence loop is shared). The result of every
- * image is bit-identical to ws_watershed followed by ws_waterfall on it alone.
- *   items    host array of n_items >= 1 items; the total pixel count must be
- *            below 2^31.
- *   dtype    grey type of every item; conn: one connectivity for all items.
+ * Watershed + NL-layer waterfall of many images of uneven sizes, 2D and 3D
+ * mixed, in one set of launches: images are grouped by connectivity, every
+ * tile kernel covers the tiles of one group's images through a tile -> image
+ * table, and the Step II convergence loop and the region-level waterfall
+ * passes are shared by all images. The result of every image is
+ * bit-identical to ws_watershed followed by ws_waterfall on it alone.
+ *   items    host array of n_items >= 1 items (each with its own conn); the
+ *            total pixel count must be below 2^31.
+ *   dtype    grey type of every item.
  * Waits on `stream` a few times (Step II convergence, and to reuse the
  * pinned staging of the previous call's tables). Same errors as ws_watershed;
  * WS_EINVAL names the first offending item.
  */
-int ws_batch(ws_ctx *ctx, const ws_item *items, int n_items, int dtype, int conn, int NL, void *stream);
+int ws_batch(ws_ctx *ctx, const ws_item *items, int n_items, int dtype, int NL, void *stream);
 
 /*
  * Step-level outputs of the watershed for verification (Alg. 1, Steps I-II;

@@ -1,6 +1,11 @@
-"""Compiles the HIP sources of libws for gfx950 into paper_2410_08946_amd/libws.so."""
+"""Compiles the HIP sources of libws for gfx950 into paper_2410_08946_amd/libws.so.
+
+Every source is compiled to an object of its own (in parallel), then the
+objects are linked into one shared library.
+"""
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import shutil
 import subprocess
@@ -8,8 +13,12 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libws.so")
 SOURCES = ["api.hip", "watershed.hip", "waterfall.hip", "gradient.hip", "rag.hip", "pixel.hip"]
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-result"]
 
 
 def hipcc() -> str:
@@ -19,17 +28,35 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def _jobs() -> int:
+    n = os.cpu_count() or 1
+    return max(1, min(len(SOURCES), n, int(os.environ.get("MAX_JOBS", n))))
+
+
 def build(verbose: bool = False) -> str:
     """Always recompiles (the build check must exercise the compiler)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-result",
-           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
-           "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    os.makedirs(OBJ, exist_ok=True)
+    cc = hipcc()
+    inc = ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+    objs, cmds = [], []
+    for s in SOURCES:
+        o = os.path.join(OBJ, os.path.splitext(s)[0] + ".o")
+        objs.append(o)
+        cmds.append([cc] + FLAGS + inc + ["-c", "-o", o, os.path.join(CSRC, s)])
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+        for c in cmds:
+            print(" ".join(c), flush=True)
+    with cf.ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        futs = [ex.submit(subprocess.run, c, check=False) for c in cmds]
+        rcs = [f.result().returncode for f in futs]
+    for c, rc in zip(cmds, rcs):
+        if rc != 0:
+            raise subprocess.CalledProcessError(rc, c)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    link = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB
 

@@ -19,11 +19,12 @@ _i64, _int, _ptr, _f32 = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c
 class WsItem(ctypes.Structure):
     """ws_item of include/ws.h."""
     _fields_ = [("grad", ctypes.c_void_p), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
-                ("nz", ctypes.c_int64), ("out", ctypes.c_void_p), ("nregions", ctypes.c_void_p)]
+                ("nz", ctypes.c_int64), ("conn", ctypes.c_int32), ("out", ctypes.c_void_p),
+                ("nregions", ctypes.c_void_p)]
 
 
 SIGNATURES = {
-    "ws_create": (_int, [ctypes.POINTER(ctypes.c_void_p), _int]),
+    "ws_create": (_int, [ctypes.POINTER(ctypes.c_void_p), _int, ctypes.c_size_t]),
     "ws_destroy": (None, [_ptr]),
     "ws_last_error": (ctypes.c_char_p, [_ptr]),
     "ws_sync": (_int, [_ptr, _ptr]),
@@ -34,7 +35,7 @@ SIGNATURES = {
     "ws_waterfall_recon": (_int, [_ptr, _ptr, _ptr, _int, _i64, _i64, _i64, _int, _int, _ptr, _ptr, _ptr]),
     "ws_rag": (_int, [_ptr, _ptr, _ptr, _int, _i64, _i64, _i64, _int, _i64, _ptr, _ptr, _ptr, _ptr, _ptr]),
     "ws_watershed_stages": (_int, [_ptr, _ptr, _int, _i64, _i64, _i64, _int, _ptr, _ptr, _ptr]),
-    "ws_batch": (_int, [_ptr, ctypes.POINTER(WsItem), _int, _int, _int, _int, _ptr]),
+    "ws_batch": (_int, [_ptr, ctypes.POINTER(WsItem), _int, _int, _int, _ptr]),
     "ws_set_option": (_int, [_ptr, ctypes.c_char_p, _i64]),
     "ws_get_stats": (_int, [_ptr, ctypes.POINTER(ctypes.c_int64), _int]),
     "ws_timing_read": (_int, [_ptr, ctypes.c_char_p, _int, ctypes.POINTER(ctypes.c_double),
@@ -104,12 +105,13 @@ def _grey_code(t):
 
 
 class Context:
-    """Owns a ws_ctx (device scratch memory) on one device."""
+    """Owns a ws_ctx (device scratch memory) on one device; scratch_budget
+    bounds the device scratch it may hold (bytes, 0 = no bound)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, scratch_budget: int = 0):
         self._lib = load_library()
         h = ctypes.c_void_p()
-        rc = self._lib.ws_create(ctypes.byref(h), int(device))
+        rc = self._lib.ws_create(ctypes.byref(h), int(device), int(scratch_budget))
         if rc != WS_OK:
             raise WSError(rc, self._lib.ws_last_error(None).decode())
         self._h = h
@@ -194,13 +196,18 @@ class Context:
                                                   int(conn), _dev(bal, "bal"), _dev(arrow, "arrow"), _stream(grad)))
         return bal, arrow
 
-    def batch(self, grads, conn: int, NL: int, outs=None, nregions=None):
+    def batch(self, grads, conn, NL: int, outs=None, nregions=None):
         """Watershed + NL-layer waterfall of a list of gradient tensors (same
-        dtype, one connectivity) in one batched call. Returns (outs, nregions):
-        per image an int32 [NL, *shape] tensor and an int64 [NL] tensor."""
+        dtype; 2D and 3D may be mixed) in one batched call. `conn` is one
+        connectivity for every image or a list with one per image. Returns
+        (outs, nregions): per image an int32 [NL, *shape] tensor and an int64
+        [NL] tensor."""
         import torch
         if not grads:
             raise ValueError("empty batch")
+        conns = [int(conn)] * len(grads) if isinstance(conn, int) else [int(c) for c in conn]
+        if len(conns) != len(grads):
+            raise ValueError("one connectivity per image")
         code = _grey_code(grads[0])
         dev = grads[0].device
         if outs is None:
@@ -214,9 +221,10 @@ class Context:
             nx, ny, nz = _dims(g.shape)
             items[i].grad = _dev(g, "gradient").value
             items[i].nx, items[i].ny, items[i].nz = nx, ny, nz
+            items[i].conn = conns[i]
             items[i].out = _dev(outs[i], "out").value
             items[i].nregions = _dev(nregions[i], "nregions").value
-        self._check(self._lib.ws_batch(self._h, items, len(grads), code, int(conn), int(NL), _stream(grads[0])))
+        self._check(self._lib.ws_batch(self._h, items, len(grads), code, int(NL), _stream(grads[0])))
         return outs, nregions
 
     def waterfall(self, labels, grad, conn: int, NL: int, out=None, nregions=None):

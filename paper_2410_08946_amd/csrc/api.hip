@@ -35,6 +35,8 @@ thread_local std::string g_noctx_error;
 
 struct ws_ctx {
     int device = 0;
+    size_t budget = 0;                    // device scratch limit in bytes (0 = none)
+    size_t held = 0;                      // device scratch bytes held now
     std::string err;
     Buf D, stamp, cnt, rec;               // watershed scratch
     Buf key, par, cimg, rlist, mlab;      // waterfall: region tables (dense by id), per-pixel region ids
@@ -88,12 +90,21 @@ int ensure(ws_ctx *c, Buf &b, size_t bytes, const char *what) {
     if (bytes == 0) bytes = 256;
     if (b.n >= bytes) return WS_OK;
     if (c->capturing) return fail(c, WS_EUNSUPPORTED, std::string("allocation during graph capture: ") + what);
+    // the context's scratch budget: the exact size when geometric growth would
+    // exceed it, WS_ENOMEM when even that does
+    const size_t need = bytes;
+    if (c->budget && c->held - b.n + need > c->budget)
+        return fail(c, WS_ENOMEM, std::string("scratch budget of ") + std::to_string(c->budget) +
+                                      " bytes exceeded: " + what + " needs " + std::to_string(need) + " bytes, " +
+                                      std::to_string(c->held - b.n) + " held by other buffers");
     ++c->gen;  // cached launch graphs hold the old address
     // grow geometrically: hipFree waits for the whole device, so a context
     // that serves growing batches should reallocate rarely
     if (b.n > 0 && bytes < b.n + b.n / 2) bytes = b.n + b.n / 2;
+    if (c->budget && c->held - b.n + bytes > c->budget) bytes = need;
     if (b.p) {
         hipError_t e = hipFree(b.p);
+        c->held -= b.n;
         b.p = nullptr;
         b.n = 0;
         if (e != hipSuccess) return hip_fail(c, e, "hipFree");
@@ -106,6 +117,7 @@ int ensure(ws_ctx *c, Buf &b, size_t bytes, const char *what) {
         return fail(c, WS_ENOMEM, std::string("cannot allocate ") + std::to_string(bytes) + " bytes for " + what);
     }
     b.n = bytes;
+    c->held += bytes;
     return WS_OK;
 }
 
@@ -249,19 +261,75 @@ std::string sig_of(const char *what, std::initializer_list<uint64_t> v) {
         }                                                                 \
     } while (0)
 
-// Step II to convergence: the initial tile pass, then batches of sweeps with
-// one counter read-back per batch. Leaves D converged in c->D (arena-wide).
+// One connectivity's share of a call: its images' tiles in the watershed and
+// waterfall tilings (a contiguous range of each, starting at ws0 / wf0), with
+// sources that map those tiles to images (tile indices relative to the range).
+// A single-image call has one part; a batch has one per connectivity present.
 template <class Src>
-int run_distances(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg, int conn, bool u16, size_t arena) {
+struct Part {
+    Src ws, wf;
+    int32_t nws = 0, nwf = 0;
+    int32_t ws0 = 0, wf0 = 0;
+    int conn = 0, ndim = 0;
+};
+
+wsk::TileGrid full_grid(int32_t ntiles) {
+    wsk::TileGrid tg;
+    tg.ntiles = ntiles;
+    tg.grid = ntiles > 0 ? ntiles : 1;
+    return tg;
+}
+
+template <class Src>
+int32_t ws_tiles_of(const std::vector<Part<Src>> &parts) {
+    int32_t n = 0;
+    for (auto &p : parts) n += p.nws;
+    return n;
+}
+
+// Border records of every part, one after the other.
+template <class Src>
+size_t rec_ints(const std::vector<Part<Src>> &parts) {
+    size_t n = 0;
+    for (auto &p : parts) n += (size_t)p.nws * (size_t)wsk::border_cells(p.ndim);
+    return n;
+}
+
+// Device scratch of one watershed call: distances (one per pixel of the
+// arena), four stamp words per watershed tile, kCounterSlots sweep counters
+// and the parts' border records.
+struct WsScratch {
+    int32_t *D = nullptr, *stamp = nullptr, *cnt = nullptr, *rec = nullptr;
+};
+
+// The watershed's scratch for `arena` pixels in the context's buffers,
+// allocated before anything is launched.
+template <class Src>
+int prepare_watershed(ws_ctx *c, const std::vector<Part<Src>> &parts, size_t arena, bool records, WsScratch &ws) {
     int rc;
     if ((rc = ensure(c, c->D, arena * 4, "distances")) != WS_OK) return rc;
     // per tile and sweep parity: the last sweep that changed its border, and
     // the faces it changed
-    if ((rc = ensure(c, c->stamp, (size_t)tg.ntiles * 16, "tile stamps")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->stamp, (size_t)ws_tiles_of(parts) * 16, "tile stamps")) != WS_OK) return rc;
     if ((rc = ensure(c, c->cnt, kCounterSlots * 4, "counters")) != WS_OK) return rc;
-    int32_t *D = (int32_t *)c->D.p, *stamp = (int32_t *)c->stamp.p, *cnt = (int32_t *)c->cnt.p;
-    WS_TRY(wsk::launch_fill2_i32(lc, stamp, 2 * tg.ntiles, -1, cnt, kCounterSlots, 0));
-    WS_TRY(wsk::launch_ws_init(lc, src, tg, conn, u16, D, stamp, cnt));
+    if (records && (rc = ensure(c, c->rec, rec_ints(parts) * 4, "border records")) != WS_OK) return rc;
+    ws.D = (int32_t *)c->D.p;
+    ws.stamp = (int32_t *)c->stamp.p;
+    ws.cnt = (int32_t *)c->cnt.p;
+    ws.rec = records ? (int32_t *)c->rec.p : nullptr;
+    return WS_OK;
+}
+
+// Step II to convergence: the initial tile pass, then batches of sweeps with
+// one counter read-back per batch. Every part's sweep s reads the count of
+// sweep s - 1 over all parts. Leaves D converged in c->D (arena-wide).
+template <class Src>
+int run_distances(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, bool u16, const WsScratch &ws) {
+    const int32_t nt = ws_tiles_of(parts);
+    int32_t *D = ws.D, *stamp = ws.stamp, *cnt = ws.cnt;
+    WS_TRY(wsk::launch_fill2_i32(lc, stamp, 4 * nt, -1, cnt, kCounterSlots, 0));
+    for (auto &p : parts)
+        WS_TRY(wsk::launch_ws_init(lc, p.ws, full_grid(p.nws), p.conn, u16, D, stamp + 4 * (size_t)p.ws0, cnt));
     int64_t launched = 1, changing = 0;
     int32_t s = 1;
     bool first = true;
@@ -276,8 +344,9 @@ int run_distances(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg
         }
         int32_t s0 = s;
         for (int b = 0; b < batch; ++b, ++s)
-            WS_TRY(wsk::launch_ws_sweep(lc, src, tg, conn, u16, D, stamp, cnt + (s % kCounterSlots),
-                                        cnt + ((s - 1) % kCounterSlots), s));
+            for (auto &p : parts)
+                WS_TRY(wsk::launch_ws_sweep(lc, p.ws, full_grid(p.nws), p.conn, u16, D, stamp + 4 * (size_t)p.ws0,
+                                            cnt + (s % kCounterSlots), cnt + ((s - 1) % kCounterSlots), s));
         launched += batch;
         hipError_t e = hipMemcpyAsync(c->host_cnt, cnt, kCounterSlots * 4, hipMemcpyDeviceToHost, lc.stream);
         if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
@@ -302,32 +371,34 @@ int run_distances(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg
     }
     c->stats[0] = launched;
     c->stats[1] = changing;
-    c->stats[3] = tg.ntiles;
+    c->stats[3] = nt;
     return WS_OK;
 }
 
-// Watershed of every image of `src` into its lab (layer 0).
+// Watershed of every image of every part into its lab (layer 0). The scratch
+// must have been prepared (prepare_watershed with records).
 template <class Src>
-int run_watershed(ws_ctx *c, Launch &lc, const Src &src, const wsk::TileGrid &tg, int ndim, int conn, bool u16,
-                  size_t arena) {
+int run_watershed(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, bool u16, const WsScratch &ws) {
     int rc;
     c->stats[2] = 0;
     c->stats[6] = 0;
-    if ((rc = run_distances(c, lc, src, tg, conn, u16, arena)) != WS_OK) return rc;
-    size_t nrec = (size_t)tg.ntiles * wsk::border_cells(ndim);
-    if ((rc = ensure(c, c->rec, nrec * 4, "border records")) != WS_OK) return rc;
-    int32_t *rec = (int32_t *)c->rec.p;
-    const int32_t *D = (const int32_t *)c->D.p;
-    WS_TRY(wsk::launch_ws_label(lc, src, tg, conn, u16, D, rec));
-    WS_TRY(wsk::launch_ws_merge(lc, src, tg, conn, u16, rec));
+    if ((rc = run_distances(c, lc, parts, u16, ws)) != WS_OK) return rc;
+    int32_t *rec = ws.rec;
+    const int32_t *D = ws.D;
+    size_t ro = 0;
+    for (auto &p : parts) {
+        WS_TRY(wsk::launch_ws_label(lc, p.ws, full_grid(p.nws), p.conn, u16, D, rec + ro));
+        WS_TRY(wsk::launch_ws_merge(lc, p.ws, full_grid(p.nws), p.conn, u16, rec + ro));
+        ro += (size_t)p.nws * (size_t)wsk::border_cells(p.ndim);
+    }
     if (c->step3 == 0) {
-        WS_TRY(wsk::launch_ws_find(lc, src, tg, conn));
+        for (auto &p : parts) WS_TRY(wsk::launch_ws_find(lc, p.ws, full_grid(p.nws), p.conn));
     } else {
-        int32_t *cnt = (int32_t *)c->cnt.p;
+        int32_t *cnt = ws.cnt;
         int64_t syncs = 0;
         for (;;) {
             WS_TRY(wsk::launch_fill_i32(lc, cnt, 1, 0));
-            WS_TRY(wsk::launch_ws_jump(lc, src, tg, conn, c->rr, cnt));
+            for (auto &p : parts) WS_TRY(wsk::launch_ws_jump(lc, p.ws, full_grid(p.nws), p.conn, c->rr, cnt));
             hipError_t e = hipMemcpyAsync(c->host_cnt, cnt, 4, hipMemcpyDeviceToHost, lc.stream);
             if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
             if ((e = hipStreamSynchronize(lc.stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
@@ -422,7 +493,8 @@ struct WfBufs {
     wsk::WfIds ids;
     int32_t *scan_tmp, *nreg0, *cnt;
     uint64_t *key;
-    int32_t *par, *cimg, *rlist, *mlab, *edges, *ecnt;
+    int32_t *par, *cimg, *rlist, *mlab;
+    wsk::EdgeSlabs es;
 };
 
 // Layer tables: layer 1 by region id; for NL >= 3 also the ranks of the
@@ -434,7 +506,8 @@ size_t mlab_ints(size_t arena, int NL) {
     return (size_t)(NL + 1) * arena + (size_t)wsk::root_list_tmp_len((int32_t)arena);
 }
 
-int wf_buffers(ws_ctx *c, size_t arena, int32_t ntiles, int32_t nchunks, int conn, int NL, bool tables, WfBufs &b) {
+// `cap`: edge slab entries per waterfall tile (the largest any part needs).
+int wf_buffers(ws_ctx *c, size_t arena, int32_t ntiles, int32_t nchunks, int32_t cap, int NL, bool tables, WfBufs &b) {
     int rc;
     if ((rc = ensure(c, c->wfcnt, 8, "region counts")) != WS_OK) return rc;
     if ((rc = ensure(c, c->tilecnt, (size_t)NL * nchunks * 4, "chunk counts")) != WS_OK) return rc;
@@ -449,9 +522,10 @@ int wf_buffers(ws_ctx *c, size_t arena, int32_t ntiles, int32_t nchunks, int con
     b.nreg0 = (int32_t *)c->wfcnt.p;
     b.cnt = (int32_t *)c->tilecnt.p;
     b.key = nullptr;
-    b.par = b.cimg = b.rlist = b.mlab = b.edges = b.ecnt = nullptr;
+    b.par = b.cimg = b.rlist = b.mlab = nullptr;
+    b.es = wsk::EdgeSlabs{};
     if (!tables) return WS_OK;
-    const size_t E = (size_t)ntiles * (size_t)wsk::wf_slab_cap(conn);
+    const size_t E = (size_t)ntiles * (size_t)cap;
     if ((rc = ensure(c, c->key, arena * 8, "region keys")) != WS_OK) return rc;
     if ((rc = ensure(c, c->par, arena * 4, "region parents")) != WS_OK) return rc;
     if ((rc = ensure(c, c->cimg, arena * 4, "pixel region ids")) != WS_OK) return rc;
@@ -464,30 +538,48 @@ int wf_buffers(ws_ctx *c, size_t arena, int32_t ntiles, int32_t nchunks, int con
     b.cimg = (int32_t *)c->cimg.p;
     b.rlist = (int32_t *)c->rlist.p;
     b.mlab = (int32_t *)c->mlab.p;
-    b.edges = (int32_t *)c->edges.p;
-    b.ecnt = (int32_t *)c->ecnt.p;
+    int32_t *edges = (int32_t *)c->edges.p;
+    b.es.a = edges;
+    b.es.b = edges + E;
+    b.es.w = edges + 2 * E;
+    b.es.cnt = (int32_t *)c->ecnt.p;
+    b.es.cap = cap;
     return WS_OK;
 }
 
-// NL waterfall layers of every image of `src` (layer 0 already in lab):
-// region ids, the layer-0 pixel pass, then per layer union + compression and
-// (from layer 2) an edge pass over tile groups growing fourfold, and one pass
-// writing every layer. Region counts go to outs[b] (batch, device array of
-// device pointers) or one_out (single image).
 template <class Src>
-int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const Src &src_ch, int32_t nchunks, const wsk::TileGrid &tg,
-                  int ndim, int conn, bool u16, int NL, size_t arena, const wsk::Img *tab_dev, const wsk::Img &one,
+int32_t wf_tiles_of(const std::vector<Part<Src>> &parts) {
+    int32_t n = 0;
+    for (auto &p : parts) n += p.nwf;
+    return n;
+}
+
+template <class Src>
+int32_t slab_cap_of(const std::vector<Part<Src>> &parts) {
+    int32_t cap = 0;
+    for (auto &p : parts) cap = std::max(cap, (int32_t)wsk::wf_slab_cap(p.conn));
+    return cap;
+}
+
+// NL waterfall layers of every image of every part (layer 0 already in lab):
+// region ids over all chunks, the layer-0 pixel pass per part, then per layer
+// union + compression and (from layer 2) an edge pass over tile groups growing
+// fourfold, and one pass writing every layer. Region counts go to outs[b]
+// (batch, device array of device pointers) or one_out (single image). The
+// buffers `b` come from wf_buffers.
+template <class Src>
+int run_waterfall(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, const Src &src_ch, int32_t nchunks,
+                  bool u16, int NL, size_t arena, const WfBufs &b, const wsk::Img *tab_dev, const wsk::Img &one,
                   int nimg, int64_t *const *outs_dev, int64_t *one_out) {
-    int rc;
     int32_t bound = (int32_t)arena;
-    WfBufs b;
-    if ((rc = wf_buffers(c, arena, tg.ntiles, nchunks, conn, NL, NL >= 2, b)) != WS_OK) return rc;
+    const int32_t wft = wf_tiles_of(parts);
     if (NL == 1) {
         WS_TRY(wsk::launch_wf_ids(lc, src_ch, nchunks, bound, b.ids, b.scan_tmp, b.nreg0, nullptr, nullptr));
     } else {
-        const int32_t cap = wsk::wf_slab_cap(conn);
         WS_TRY(wsk::launch_wf_ids(lc, src_ch, nchunks, bound, b.ids, b.scan_tmp, b.nreg0, b.key, b.par));
-        WS_TRY(wsk::launch_wf_pix(lc, src, tg, conn, u16, b.ids, b.nreg0, b.cimg, b.rlist, b.key, b.edges, b.ecnt));
+        for (auto &p : parts)
+            WS_TRY(wsk::launch_wf_pix(lc, p.wf, full_grid(p.nwf), p.conn, u16, b.ids, b.nreg0, b.cimg, b.rlist, b.key,
+                                      b.es.at(p.wf0)));
         WS_TRY(wsk::launch_wf_union(lc, bound, b.nreg0, b.key, b.par));
         if (NL == 2) {
             WS_TRY(wsk::launch_wf_compress(lc, bound, b.nreg0, b.par, b.rlist, b.mlab));
@@ -502,8 +594,8 @@ int run_waterfall(ws_ctx *c, Launch &lc, const Src &src, const Src &src_ch, int3
                 // groups grow fourfold per layer: regions spanning several tiles
                 // then share one group (fewer key atomics) while a group's
                 // distinct edges still fit its LDS hash
-                int32_t f = gin >= tg.ntiles ? 1 : 4;
-                WS_TRY(wsk::launch_wf_level(lc, tg.ntiles, gin, f, cap, b.par, b.key, b.edges, b.ecnt));
+                int32_t f = gin >= wft ? 1 : 4;
+                WS_TRY(wsk::launch_wf_level(lc, wft, gin, f, b.es.cap, b.par, b.key, b.es.a, b.es.cnt));
                 gin *= f;
                 WS_TRY(wsk::launch_wf_union_l(lc, bound, n1, R1, b.key, b.par));
                 WS_TRY(wsk::launch_wf_compress_l(lc, bound, n1, R1, b.par, b.rlist, b.mlab + (size_t)(k + 1) * arena));
@@ -550,6 +642,17 @@ int reserve(ws_ctx *c, int64_t n) {
     return WS_OK;
 }
 
+// The one part of a single-image call.
+std::vector<Part<wsk::OneImg>> one_part(const wsk::OneImg &src, int conn) {
+    Part<wsk::OneImg> p;
+    p.ws = p.wf = src;
+    p.ndim = src.im.g.nz > 1 ? 3 : 2;
+    p.nws = src.im.g.ntx * src.im.g.nty * src.im.g.ntz;
+    p.nwf = wsk::wf_tiles(src.im.g, p.ndim);
+    p.conn = conn;
+    return {p};
+}
+
 wsk::Img single_img(int64_t nx, int64_t ny, int64_t nz, const void *grad, int32_t *lab) {
     wsk::Img im{};
     im.g = make_geom(nx, ny, nz, nz > 1 ? 3 : 2);
@@ -561,18 +664,11 @@ wsk::Img single_img(int64_t nx, int64_t ny, int64_t nz, const void *grad, int32_
     return im;
 }
 
-wsk::TileGrid full_grid(int32_t ntiles) {
-    wsk::TileGrid tg;
-    tg.ntiles = ntiles;
-    tg.grid = ntiles > 0 ? ntiles : 1;
-    return tg;
-}
-
 }  // namespace
 
 extern "C" {
 
-int ws_create(ws_ctx **out, int device) {
+int ws_create(ws_ctx **out, int device, size_t scratch_budget_bytes) {
     if (!out) return fail(nullptr, WS_EINVAL, "ws_create: ctx is NULL");
     *out = nullptr;
     int n = 0;
@@ -581,6 +677,7 @@ int ws_create(ws_ctx **out, int device) {
     if (device < 0 || device >= n) return fail(nullptr, WS_EINVAL, "ws_create: bad device index");
     ws_ctx *c = new ws_ctx();
     c->device = device;
+    c->budget = scratch_budget_bytes;
     if ((e = hipSetDevice(device)) != hipSuccess) {
         delete c;
         return fail(nullptr, WS_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
@@ -751,9 +848,13 @@ int ws_watershed(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny,
     Launch lc = make_launch(c, stream);
     wsk::OneImg src{single_img(nx, ny, nz, grad, labels)};
     const wsk::Geom &g = src.im.g;
+    (void)ndim;
     if (c->schedule == 1) return run_watershed_px(c, lc, g, grad, conn, dtype == WS_U16, labels, nullptr);
     if (c->step4 == 1) return fail(c, WS_EUNSUPPORTED, "ws_watershed: step4 = 1 (PRW) needs schedule = 1");
-    return run_watershed(c, lc, src, full_grid(g.ntx * g.nty * g.ntz), ndim, conn, dtype == WS_U16, (size_t)g.n);
+    auto parts = one_part(src, conn);
+    WsScratch ws;
+    if ((rc = prepare_watershed(c, parts, (size_t)g.n, true, ws)) != WS_OK) return rc;
+    return run_watershed(c, lc, parts, dtype == WS_U16, ws);
 }
 
 int ws_watershed_stages(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz, int conn,
@@ -767,8 +868,11 @@ int ws_watershed_stages(ws_ctx *c, const void *grad, int dtype, int64_t nx, int6
     wsk::OneImg src{single_img(nx, ny, nz, grad, nullptr)};
     const wsk::Geom &g = src.im.g;
     if (c->schedule == 1) return run_watershed_px(c, lc, g, grad, conn, u16, arrow, bal);
-    if ((rc = run_distances(c, lc, src, full_grid(g.ntx * g.nty * g.ntz), conn, u16, (size_t)g.n)) != WS_OK) return rc;
-    WS_TRY(wsk::launch_ws_stages(lc, g, conn, u16, grad, (const int32_t *)c->D.p, bal, arrow));
+    auto parts = one_part(src, conn);
+    WsScratch ws;
+    if ((rc = prepare_watershed(c, parts, (size_t)g.n, false, ws)) != WS_OK) return rc;
+    if ((rc = run_distances(c, lc, parts, u16, ws)) != WS_OK) return rc;
+    WS_TRY(wsk::launch_ws_stages(lc, g, conn, u16, grad, ws.D, bal, arrow));
     return WS_OK;
 }
 
@@ -785,13 +889,19 @@ int ws_waterfall(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, 
     std::string sig = sig_of("wf", {(uint64_t)(uintptr_t)labels, (uint64_t)(uintptr_t)grad, (uint64_t)dtype,
                                     (uint64_t)nx, (uint64_t)ny, (uint64_t)nz, (uint64_t)conn, (uint64_t)NL,
                                     (uint64_t)(uintptr_t)out, (uint64_t)(uintptr_t)nregions});
+    (void)ndim;
     return run_graphed(c, stream, sig, [&](Launch &lc) -> int {
+        auto parts = one_part(src, conn);
+        const int32_t nchunks = wsk::wf_chunks(g.n);
+        WfBufs b;
+        int rc2 = wf_buffers(c, (size_t)g.n, wf_tiles_of(parts), nchunks, slab_cap_of(parts), NL, NL >= 2, b);
+        if (rc2 != WS_OK) return rc2;
         if (labels != out) {
             hipError_t e = hipMemcpyAsync(out, labels, (size_t)g.n * 4, hipMemcpyDeviceToDevice, lc.stream);
             if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
         }
-        return run_waterfall(c, lc, src, src, wsk::wf_chunks(g.n), full_grid(wsk::wf_tiles(g, ndim)), ndim, conn,
-                             dtype == WS_U16, NL, (size_t)g.n, nullptr, src.im, 1, nullptr, nregions);
+        return run_waterfall(c, lc, parts, src, nchunks, dtype == WS_U16, NL, (size_t)g.n, b, nullptr, src.im, 1,
+                             nullptr, nregions);
     });
 }
 
@@ -807,10 +917,15 @@ int ws_waterfall_recon(ws_ctx *c, const int32_t *labels, const void *grad, int d
     const Geom g = make_geom(nx, ny, nz, ndim);
     const size_t N = (size_t)g.n;
     const int32_t nchunks = wsk::wf_chunks(g.n), bound = g.n;
-    const wsk::TileGrid tgw = full_grid(wsk::wf_tiles(g, ndim)), tgs = full_grid(g.ntx * g.nty * g.ntz);
+    const wsk::TileGrid tgw = full_grid(wsk::wf_tiles(g, ndim));
     WfBufs b;
-    if ((rc = wf_buffers(c, N, tgw.ntiles, nchunks, conn, 1, NL >= 2, b)) != WS_OK) return rc;
+    if ((rc = wf_buffers(c, N, tgw.ntiles, nchunks, wsk::wf_slab_cap(conn), 1, NL >= 2, b)) != WS_OK) return rc;
     if ((rc = ensure(c, c->rimg, N * 2, "raised image")) != WS_OK) return rc;
+    WsScratch ws;
+    {
+        wsk::OneImg probe{single_img(nx, ny, nz, grad, out)};
+        if ((rc = prepare_watershed(c, one_part(probe, conn), N, true, ws)) != WS_OK) return rc;
+    }
     uint16_t *I = (uint16_t *)c->rimg.p;
     if (labels != out) {
         hipError_t e = hipMemcpyAsync(out, labels, N * 4, hipMemcpyDeviceToDevice, lc.stream);
@@ -829,10 +944,10 @@ int ws_waterfall_recon(ws_ctx *c, const int32_t *labels, const void *grad, int d
         if (k + 1 == NL) break;
         // Step V (lowest boundary pass of every region, the keys' heights) on
         // the current image, Step VI (raise), then the watershed again
-        WS_TRY(wsk::launch_wf_pix(lc, src, tgw, conn, true, b.ids, b.nreg0, b.cimg, b.rlist, b.key, b.edges, b.ecnt));
+        WS_TRY(wsk::launch_wf_pix(lc, src, tgw, conn, true, b.ids, b.nreg0, b.cimg, b.rlist, b.key, b.es));
         WS_TRY(wsk::launch_recon_raise(lc, I, b.cimg, b.key, b.nreg0, g.n));
         wsk::OneImg next{single_img(nx, ny, nz, I, out + (size_t)(k + 1) * N)};
-        if ((rc = run_watershed(c, lc, next, tgs, ndim, conn, true, N)) != WS_OK) return rc;
+        if ((rc = run_watershed(c, lc, one_part(next, conn), true, ws)) != WS_OK) return rc;
     }
     return WS_OK;
 }
@@ -851,17 +966,16 @@ int ws_rag(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, int64_
     const int32_t nchunks = wsk::wf_chunks(g.n), bound = g.n;
     const wsk::TileGrid tg = full_grid(wsk::wf_tiles(g, ndim));
     WfBufs b;
-    if ((rc = wf_buffers(c, N, tg.ntiles, nchunks, conn, 1, true, b)) != WS_OK) return rc;
+    if ((rc = wf_buffers(c, N, tg.ntiles, nchunks, wsk::wf_slab_cap(conn), 1, true, b)) != WS_OK) return rc;
     // the labels are read, never written (the pixel pass only reads its layer 0)
     wsk::OneImg src{single_img(nx, ny, nz, grad, const_cast<int32_t *>(labels))};
     WS_TRY(wsk::launch_wf_ids(lc, src, nchunks, bound, b.ids, b.scan_tmp, b.nreg0, b.key, b.par));
-    WS_TRY(wsk::launch_wf_pix(lc, src, tg, conn, dtype == WS_U16, b.ids, b.nreg0, b.cimg, b.rlist, b.key, b.edges,
-                              b.ecnt));
+    WS_TRY(wsk::launch_wf_pix(lc, src, tg, conn, dtype == WS_U16, b.ids, b.nreg0, b.cimg, b.rlist, b.key, b.es));
     // offsets of the tiles' edges in one list, and their total (read back once)
     const int32_t nt = tg.ntiles;
     if ((rc = ensure(c, c->ragoff, ((size_t)nt + 1 + wsk::scan_tmp_len(nt)) * 4, "edge offsets")) != WS_OK) return rc;
     int32_t *eoff = (int32_t *)c->ragoff.p, *etot = eoff + nt, *etmp = etot + 1;
-    hipError_t e = hipMemcpyAsync(eoff, b.ecnt, (size_t)nt * 4, hipMemcpyDeviceToDevice, lc.stream);
+    hipError_t e = hipMemcpyAsync(eoff, b.es.cnt, (size_t)nt * 4, hipMemcpyDeviceToDevice, lc.stream);
     if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
     WS_TRY(wsk::launch_scan(lc, nt, eoff, etmp, etot));
     if ((e = hipMemcpyAsync(c->host_cnt, etot, 4, hipMemcpyDeviceToHost, lc.stream)) != hipSuccess)
@@ -881,60 +995,103 @@ int ws_rag(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, int64_
     auto *ucount = (unsigned int *)(rb + o_cnt);
     WS_TRY(wsk::launch_fill_i32(lc, (int32_t *)ucount, 1, 0));
     if (total > 0) {
-        WS_TRY(wsk::launch_rag_gather(lc, nt, wsk::wf_slab_cap(conn), b.edges, b.ecnt, eoff, keys, h));
+        WS_TRY(wsk::launch_rag_gather(lc, nt, b.es.cap, b.es.a, b.es.cnt, eoff, keys, h));
         WS_TRY(wsk::rag_sort_reduce(lc, total, keys, h, keys2, h2, ukeys, uh, ucount, rb + o_tmp, tmp_bytes));
     }
     WS_TRY(wsk::launch_rag_final(lc, ukeys, uh, ucount, b.rlist, capacity, edge_a, edge_b, edge_h, n_edges));
     return WS_OK;
 }
 
-int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, int NL, void *stream) {
+int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int NL, void *stream) {
     if (!c) return fail(c, WS_EINVAL, "ws_batch: ctx is NULL");
     if (!items || n_items < 1) return fail(c, WS_EINVAL, "ws_batch: no items");
     if (dtype != WS_U8 && dtype != WS_U16) return fail(c, WS_EINVAL, "ws_batch: dtype must be WS_U8 or WS_U16");
     if (NL < 1) return fail(c, WS_EINVAL, "ws_batch: NL must be >= 1");
-    int ndim = (conn == 4 || conn == 8) ? 2 : (conn == 6 || conn == 26) ? 3 : 0;
-    if (!ndim) return fail(c, WS_EINVAL, "ws_batch: conn must be 4, 8, 6 or 26");
-    int64_t arena = 0, tws = 0, twf = 0, tch = 0;
+    // images are grouped by connectivity: one part per connectivity present,
+    // each a contiguous range of the call's watershed and waterfall tiles
+    static const int kConns[4] = {4, 8, 6, 26};
+    int64_t arena = 0, tws[4] = {0, 0, 0, 0}, twf[4] = {0, 0, 0, 0}, tch = 0;
     std::string why;
     for (int i = 0; i < n_items; ++i) {
         const ws_item &it = items[i];
-        if (!it.grad || !it.out) return fail(c, WS_EINVAL, "ws_batch: item " + std::to_string(i) + " has a NULL buffer");
-        if (!valid_dims(it.nx, it.ny, it.nz, why)) return fail(c, WS_EINVAL, "ws_batch: item " + std::to_string(i) + ": " + why);
-        if (!valid_conn(it.nz, conn))
-            return fail(c, WS_EINVAL, "ws_batch: item " + std::to_string(i) + " does not match the connectivity");
+        const std::string who = "ws_batch: item " + std::to_string(i);
+        if (!it.grad || !it.out) return fail(c, WS_EINVAL, who + " has a NULL buffer");
+        if (!valid_dims(it.nx, it.ny, it.nz, why)) return fail(c, WS_EINVAL, who + ": " + why);
+        if (!valid_conn(it.nz, it.conn))
+            return fail(c, WS_EINVAL, who + ": conn must be 4 or 8 for 2D (nz == 1) and 6 or 26 for 3D");
         arena += (it.nx * it.ny * it.nz + 63) / 64 * 64;  // image offsets stay 64-pixel aligned
+        const int ndim = it.nz > 1 ? 3 : 2;
+        const int gi = (int)(std::find(kConns, kConns + 4, it.conn) - kConns);
         wsk::Geom g = make_geom(it.nx, it.ny, it.nz, ndim);
-        tws += (int64_t)g.ntx * g.nty * g.ntz;
-        twf += wsk::wf_tiles(g, ndim);
+        tws[gi] += (int64_t)g.ntx * g.nty * g.ntz;
+        twf[gi] += wsk::wf_tiles(g, ndim);
         tch += wsk::wf_chunks(g.n);
+        if (arena >= (1LL << 31)) return fail(c, WS_EINVAL, "ws_batch: total pixels must be < 2^31");
     }
-    if (arena >= (1LL << 31)) return fail(c, WS_EINVAL, "ws_batch: total pixels must be < 2^31");
+    int64_t ws_all = tws[0] + tws[1] + tws[2] + tws[3], wf_all = twf[0] + twf[1] + twf[2] + twf[3];
     int rc;
     if ((rc = set_device(c))) return rc;
     Launch lc = make_launch(c, stream);
     // host staging: [Img table][ws tile map][wf tile map][chunk map][nregions pointers]
     size_t tab_b = sizeof(wsk::Img) * (size_t)n_items;
     size_t off_ws = (tab_b + 255) & ~(size_t)255;
-    size_t off_wf = (off_ws + 4 * (size_t)tws + 255) & ~(size_t)255;
-    size_t off_ch = (off_wf + 4 * (size_t)twf + 255) & ~(size_t)255;
+    size_t off_wf = (off_ws + 4 * (size_t)ws_all + 255) & ~(size_t)255;
+    size_t off_ch = (off_wf + 4 * (size_t)wf_all + 255) & ~(size_t)255;
     size_t off_outs = (off_ch + 4 * (size_t)tch + 255) & ~(size_t)255;
     size_t total = off_outs + sizeof(int64_t *) * (size_t)n_items;
+    // every buffer of the call before anything is launched
     if ((rc = ensure_stage(c, total)) != WS_OK) return rc;
     if ((rc = ensure(c, c->tab, total, "batch tables")) != WS_OK) return rc;
+    char *d = (char *)c->tab.p;
+    const wsk::Img *tab_dev = (const wsk::Img *)d;
+    std::vector<Part<wsk::ImgTable>> parts;
+    int32_t ws0 = 0, wf0 = 0;
+    for (int gi = 0; gi < 4; ++gi) {
+        if (tws[gi] == 0) continue;
+        Part<wsk::ImgTable> p;
+        p.conn = kConns[gi];
+        p.ndim = gi < 2 ? 2 : 3;
+        p.ws0 = ws0;
+        p.wf0 = wf0;
+        p.nws = (int32_t)tws[gi];
+        p.nwf = (int32_t)twf[gi];
+        p.ws = wsk::ImgTable{tab_dev, (const int32_t *)(d + off_ws) + ws0};
+        p.wf = wsk::ImgTable{tab_dev, (const int32_t *)(d + off_wf) + wf0};
+        ws0 += p.nws;
+        wf0 += p.nwf;
+        parts.push_back(p);
+    }
+    const int32_t nchunks = (int32_t)tch;
+    WfBufs wb;
+    WsScratch ws;
+    if ((rc = prepare_watershed(c, parts, (size_t)arena, true, ws)) != WS_OK) return rc;
+    if ((rc = wf_buffers(c, (size_t)arena, (int32_t)wf_all, nchunks, slab_cap_of(parts), NL, NL >= 2, wb)) != WS_OK)
+        return rc;
     char *h = (char *)c->stage;
     wsk::Img *tab = (wsk::Img *)h;
     int32_t *mws = (int32_t *)(h + off_ws), *mwf = (int32_t *)(h + off_wf), *mch = (int32_t *)(h + off_ch);
     int64_t **outs = (int64_t **)(h + off_outs);
-    int32_t pix = 0, t0 = 0, t1 = 0, t2 = 0;
+    // tile ranges: the part's first tile plus the images of that part before it
+    int32_t next_ws[4], next_wf[4];
+    for (auto &p : parts) {
+        const int gi = (int)(std::find(kConns, kConns + 4, p.conn) - kConns);
+        next_ws[gi] = 0;  // relative to the part's range
+        next_wf[gi] = 0;
+    }
+    int32_t pix = 0, t2 = 0;
     bool any_counts = false;
     for (int i = 0; i < n_items; ++i) {
         const ws_item &it = items[i];
+        const int ndim = it.nz > 1 ? 3 : 2;
+        const int gi = (int)(std::find(kConns, kConns + 4, it.conn) - kConns);
+        const Part<wsk::ImgTable> *pp = nullptr;
+        for (auto &p : parts)
+            if (p.conn == it.conn) pp = &p;
         wsk::Img im{};
         im.g = make_geom(it.nx, it.ny, it.nz, ndim);
         im.pix0 = pix;
-        im.tile0[wsk::TK_WS] = t0;
-        im.tile0[wsk::TK_WF] = t1;
+        im.tile0[wsk::TK_WS] = next_ws[gi];
+        im.tile0[wsk::TK_WF] = next_wf[gi];
         im.tile0[wsk::TK_GR] = 0;
         im.tile0[wsk::TK_CH] = t2;
         im.slot0 = 0;
@@ -942,31 +1099,26 @@ int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int conn, 
         im.lab = it.out;
         tab[i] = im;
         int32_t nws = im.g.ntx * im.g.nty * im.g.ntz, nwf = wsk::wf_tiles(im.g, ndim), nch = wsk::wf_chunks(im.g.n);
-        for (int32_t k = 0; k < nws; ++k) mws[t0 + k] = i;
-        for (int32_t k = 0; k < nwf; ++k) mwf[t1 + k] = i;
+        for (int32_t k = 0; k < nws; ++k) mws[pp->ws0 + next_ws[gi] + k] = i;
+        for (int32_t k = 0; k < nwf; ++k) mwf[pp->wf0 + next_wf[gi] + k] = i;
         for (int32_t k = 0; k < nch; ++k) mch[t2 + k] = i;
         outs[i] = it.nregions;
         any_counts = any_counts || it.nregions;
         pix += (im.g.n + 63) / 64 * 64;
-        t0 += nws;
-        t1 += nwf;
+        next_ws[gi] += nws;
+        next_wf[gi] += nwf;
         t2 += nch;
     }
     hipError_t e = hipMemcpyAsync(c->tab.p, c->stage, total, hipMemcpyHostToDevice, lc.stream);
     if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
     if ((e = hipEventRecord(c->stage_ev, lc.stream)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
     c->stage_pending = true;
-    char *d = (char *)c->tab.p;
-    const wsk::Img *tab_dev = (const wsk::Img *)d;
-    wsk::ImgTable src_ws{tab_dev, (const int32_t *)(d + off_ws)};
-    wsk::ImgTable src_wf{tab_dev, (const int32_t *)(d + off_wf)};
     wsk::ImgTable src_ch{tab_dev, (const int32_t *)(d + off_ch)};
-    wsk::TileGrid tg_ws = full_grid((int32_t)tws), tg_wf = full_grid((int32_t)twf);
     bool u16 = dtype == WS_U16;
-    if ((rc = run_watershed(c, lc, src_ws, tg_ws, ndim, conn, u16, (size_t)arena)) != WS_OK) return rc;
+    if ((rc = run_watershed(c, lc, parts, u16, ws)) != WS_OK) return rc;
     wsk::Img none{};
-    return run_waterfall(c, lc, src_wf, src_ch, (int32_t)tch, tg_wf, ndim, conn, u16, NL, (size_t)arena, tab_dev, none,
-                         n_items, any_counts ? (int64_t *const *)(d + off_outs) : nullptr, nullptr);
+    return run_waterfall(c, lc, parts, src_ch, nchunks, u16, NL, (size_t)arena, wb, tab_dev, none, n_items,
+                         any_counts ? (int64_t *const *)(d + off_outs) : nullptr, nullptr);
 }
 
 int ws_timing_reset(ws_ctx *c) {

@@ -1130,18 +1130,16 @@ static int wf_ids_impl(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t b
 
 template <int CONN, typename T, class Src>
 static int wf_pix_t(Launch &lc, const Src &src, const TileGrid &tg, const WfIds &ids, const int32_t *nreg0,
-                    int32_t *cimg, int32_t *rlist, uint64_t *key, int32_t *edges, int32_t *ecnt) {
-    const int32_t cap = wf_slab_cap(CONN);
-    size_t E = (size_t)tg.ntiles * (size_t)cap;
+                    int32_t *cimg, int32_t *rlist, uint64_t *key, const EdgeSlabs &es) {
+    if (es.cap < wf_slab_cap(CONN)) return -1;  // a tile's forward pairs must fit its slab
     return lc.run("wf_pix", k_wf_pix<CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles,
-                  (const RankWord *)ids.words, nreg0, cimg, rlist, key, edges, edges + E, edges + 2 * E, ecnt, cap);
+                  (const RankWord *)ids.words, nreg0, cimg, rlist, key, es.a, es.b, es.w, es.cnt, es.cap);
 }
 
 template <class Src>
 static int wf_pix_dispatch(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const WfIds &ids,
-                           const int32_t *nreg0, int32_t *cimg, int32_t *rlist, uint64_t *key, int32_t *edges,
-                           int32_t *ecnt) {
-#define WF_PIX_ARGS lc, src, tg, ids, nreg0, cimg, rlist, key, edges, ecnt
+                           const int32_t *nreg0, int32_t *cimg, int32_t *rlist, uint64_t *key, const EdgeSlabs &es) {
+#define WF_PIX_ARGS lc, src, tg, ids, nreg0, cimg, rlist, key, es
     switch (conn) {
     case 4: return u16 ? wf_pix_t<4, uint16_t>(WF_PIX_ARGS) : wf_pix_t<4, uint8_t>(WF_PIX_ARGS);
     case 8: return u16 ? wf_pix_t<8, uint16_t>(WF_PIX_ARGS) : wf_pix_t<8, uint8_t>(WF_PIX_ARGS);
@@ -1158,9 +1156,8 @@ static int wf_pix_dispatch(Launch &lc, const Src &src, const TileGrid &tg, int c
         return wf_ids_impl(lc, src_ch, nchunks, bound, ids, scan_tmp, nreg0, key, par);                           \
     }                                                                                                              \
     int launch_wf_pix(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const WfIds &ids,       \
-                      const int32_t *nreg0, int32_t *cimg, int32_t *rlist, uint64_t *key, int32_t *edges,         \
-                      int32_t *ecnt) {                                                                            \
-        return wf_pix_dispatch(lc, src, tg, conn, u16, ids, nreg0, cimg, rlist, key, edges, ecnt);                \
+                      const int32_t *nreg0, int32_t *cimg, int32_t *rlist, uint64_t *key, const EdgeSlabs &es) {  \
+        return wf_pix_dispatch(lc, src, tg, conn, u16, ids, nreg0, cimg, rlist, key, es);                         \
     }                                                                                                              \
     int launch_wf_out(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t nl, const int32_t *cimg,            \
                       const int32_t *nreg0, const int32_t *coff, const int32_t *mlab, int64_t mstride,           \

@@ -83,6 +83,24 @@ struct TileGrid {
     int32_t grid = 0;
 };
 
+// The waterfall's per-tile edge slabs: entry j of tile t's slab is
+// (a[t * cap + j], b[t * cap + j], w[t * cap + j]); cnt[t] holds the tile's
+// edge count. A launch over a sub-range of the tiles gets pointers advanced
+// to its first tile (same cap).
+struct EdgeSlabs {
+    int32_t *a = nullptr, *b = nullptr, *w = nullptr, *cnt = nullptr;
+    int32_t cap = 0;
+    EdgeSlabs at(int32_t t0) const {
+        EdgeSlabs e = *this;
+        const size_t o = (size_t)t0 * (size_t)cap;
+        e.a += o;
+        e.b += o;
+        e.w += o;
+        e.cnt += t0;
+        return e;
+    }
+};
+
 // watershed.hip
 #define WS_DECL_SRC(Src)                                                                                          \
     int launch_ws_init(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,           \
@@ -97,8 +115,7 @@ struct TileGrid {
     int launch_wf_ids(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t bound, const WfIds &ids,           \
                       int32_t *scan_tmp, int32_t *nreg0, uint64_t *key, int32_t *par);                            \
     int launch_wf_pix(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const WfIds &ids,      \
-                      const int32_t *nreg0, int32_t *cimg, int32_t *rlist, uint64_t *key, int32_t *edges,        \
-                      int32_t *ecnt);                                                                            \
+                      const int32_t *nreg0, int32_t *cimg, int32_t *rlist, uint64_t *key, const EdgeSlabs &es);  \
     int launch_wf_out(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t nl, const int32_t *cimg,           \
                       const int32_t *nreg0, const int32_t *coff, const int32_t *mlab, int64_t mstride,          \
                       int32_t *cnt);

@@ -1,7 +1,8 @@
 """Continuous-batching server for watershed + waterfall partition jobs.
 
 Jobs (a quantised gradient already on the device, a connectivity and NL) arrive
-at any time. A dispatcher admits them into micro-batches while an execution
+at any time. A dispatcher admits them into micro-batches (2D and 3D jobs of any
+connectivity together; one NL and grey type per micro-batch) while an execution
 slot is free and the device-memory budget holds their footprint
 (ws_footprint_bytes: outputs plus the library's scratch). Each slot owns a
 library context (its own scratch) and a HIP stream and is driven by its own
@@ -161,8 +162,9 @@ class Server:
             if head is None:
                 head = j
             n = int(j.grad.numel())
-            same = (j.conn == head.conn and j.NL == head.NL and j.grad.dtype == head.grad.dtype
-                    and (j.grad.dim() == 3) == (head.grad.dim() == 3))
+            # one ws_batch call takes any mix of 2D and 3D images and
+            # connectivities; its NL and grey type are shared
+            same = j.NL == head.NL and j.grad.dtype == head.grad.dtype
             fits = self.in_use + foot + j.footprint <= self.budget and (not batch or pix + n <= self.max_batch_pixels)
             if same and fits:
                 batch.append(j)
@@ -234,7 +236,7 @@ class Server:
                     NL = batch[0].NL
                     outs = [torch.empty((NL,) + tuple(g.shape), dtype=torch.int32, device=self.device) for g in grads]
                     nregs = [torch.zeros(NL, dtype=torch.int64, device=self.device) for _ in grads]
-                    ctx.batch(grads, batch[0].conn, NL, outs=outs, nregions=nregs)
+                    ctx.batch(grads, [j.conn for j in batch], NL, outs=outs, nregions=nregs)
                 stream.synchronize()
                 t = time.perf_counter()
                 for j, o, n in zip(batch, outs, nregs):

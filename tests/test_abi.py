@@ -62,7 +62,7 @@ def test_null_context_is_rejected_without_device():
     assert lib.ws_watershed_stages(None, buf, 1, 8, 8, 1, 4, buf, buf, None) == -1
     assert lib.ws_set_option(None, b"rr", 2) == -1
     assert lib.ws_sync(None, None) == -1
-    assert lib.ws_create(None, 0) == -1
+    assert lib.ws_create(None, 0, 0) == -1
     lib.ws_destroy(None)
 
 
@@ -75,3 +75,27 @@ def test_product_path_has_no_oracle_dependency():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in txt.replace("the oracle", ""), f
                 assert "ws_oracle" not in txt, f
+
+
+def test_item_layout_matches_header(tmp_path):
+    """The binding's ws_item has the header's size and field offsets (a small
+    C program compiled against include/ws.h prints them)."""
+    import shutil
+    import subprocess
+
+    from paper_2410_08946_amd.binding import WsItem
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text(
+        "#include <stddef.h>\n#include <stdio.h>\n#include \"ws.h\"\n"
+        "int main(void) { printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(ws_item), "
+        "offsetof(ws_item, grad), offsetof(ws_item, nx), offsetof(ws_item, ny), offsetof(ws_item, nz), "
+        "offsetof(ws_item, conn), offsetof(ws_item, out), offsetof(ws_item, nregions)); return 0; }\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call([gcc, "-I" + os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(WsItem)] + [getattr(WsItem, f).offset
+                                       for f in ("grad", "nx", "ny", "nz", "conn", "out", "nregions")]
+    assert got == want

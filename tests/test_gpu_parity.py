@@ -216,12 +216,40 @@ def _check_gradient(ctx, img, sigma, dtype, offset=0):
     mx = mag_ref.max()
     assert np.abs(m - mag_ref).max() <= GRAD_RTOL * mx
     Q = 255 if dtype == "u8" else 65535
+    qh = to_host(q).astype(np.int64)
+    # the kernel's rounding rule, exactly, on the magnitude it returned:
+    # rint(fp32(mag * Q) / max(mag)) in float32, ties to even
+    m32 = to_host(mag).astype(np.float32)
+    mx32 = m32.max()
+    if mx32 > 0:
+        rule = np.rint((m32 * np.float32(Q)) / mx32).astype(np.int64)
+    else:
+        rule = np.zeros(m32.shape, np.int64)
+    assert np.array_equal(qh, np.clip(rule, 0, Q)), "quantised bytes do not follow rint(mag*Q/max)"
+    # against the oracle: the magnitudes agree to GRAD_RTOL * max, so a byte
+    # may differ by one level only where the oracle's unrounded value lies
+    # within GRAD_RTOL * Q (plus float32 rounding) of a .5 boundary
     exact = mag_ref * Q / mx if mx > 0 else np.zeros_like(mag_ref)
-    dq = np.abs(to_host(q).astype(np.int64) - q_ref.astype(np.int64))
-    near = np.abs(exact - np.floor(exact) - 0.5) <= 2 * GRAD_RTOL * Q
+    dq = np.abs(qh - q_ref.astype(np.int64))
+    near = np.abs(exact - np.floor(exact) - 0.5) <= GRAD_RTOL * Q + 1e-6 * Q
     assert dq.max() <= 1
     assert (dq[~near] == 0).all()
+    say("  gradient bytes differing from the oracle: %d of %d (near a boundary: %d)" %
+        (int((dq != 0).sum()), dq.size, int(near.sum())))
     return to_host(q)
+
+
+@pytest.mark.parametrize("Q,dtype", [(255, "u8"), (65535, "u16")])
+def test_gradient_quantisation_ties(ctx, Q, dtype):
+    """Magnitudes that scale exactly onto k + 1/2 (the fixture's Sobel values
+    are exact in float32) are rounded half to even by the quantisation kernel."""
+    import torch
+    from tests.quant_fixture import tie_image
+    img, mag_exact, expect = tie_image(Q)
+    mag = torch.empty(img.shape, dtype=torch.float32, device="cuda:0")
+    q = ctx.gradient(torch.from_numpy(img).to("cuda:0"), 0.0, dtype, mag=mag)
+    assert np.array_equal(to_host(mag).astype(np.float64), mag_exact)
+    assert np.array_equal(to_host(q).astype(np.int64), expect)
 
 
 def test_gradient(ctx):
@@ -324,6 +352,15 @@ def test_batch_2d_uneven(ctx):
     _batch_case(ctx, grads, 4, 3)
 
 
+def test_batch_with_largest_batch_image(ctx):
+    """An image at the largest side of the uneven batch (2048^2, the blob
+    recipe) batched with small ones equals the oracle."""
+    grads = [oracle.gradient(gen.blobs2d(2048, 2048, seed=3777), 0.0, "u8"),
+             oracle.gradient(gen.blobs2d(130, 1900, seed=3778), 0.0, "u8"),
+             oracle.gradient(gen.blobs2d(128, 128, seed=3779), 0.0, "u8")]
+    _batch_case(ctx, grads, 8, 4)
+
+
 def test_batch_matches_single_calls(ctx):
     rng = np.random.default_rng(5)
     grads = [rng.integers(0, 30, size=(int(rng.integers(20, 200)), int(rng.integers(20, 200)))).astype(np.uint16)
@@ -347,15 +384,82 @@ def test_batch_3d_and_plateaux(ctx):
     _batch_case(ctx, serp, 4, 3)
 
 
+def test_batch_mixed_connectivities(ctx):
+    """One ws_batch call over 2D 4- and 8-connected and 3D 6- and 26-connected
+    images, interleaved: every image equals the oracle."""
+    import torch
+    rng = np.random.default_rng(41)
+    items = []
+    for i in range(14):
+        kind = i % 4
+        if kind == 0:
+            g = oracle.gradient(gen.blobs2d(int(rng.integers(30, 200)), int(rng.integers(30, 200)), seed=900 + i),
+                                0.0, "u8")
+            items.append((g, 8))
+        elif kind == 1:
+            s3 = tuple(int(v) for v in rng.integers(3, 40, size=3))
+            items.append((rng.integers(0, 5, size=s3).astype(np.uint8), 6))
+        elif kind == 2:
+            items.append((rng.integers(0, 4, size=(int(rng.integers(1, 90)), int(rng.integers(1, 90))))
+                          .astype(np.uint8), 4))
+        else:
+            s3 = tuple(int(v) for v in rng.integers(2, 25, size=3))
+            items.append((rng.integers(0, 6, size=s3).astype(np.uint8), 26))
+    items.append((oracle.gradient(gen.blobs3d(128, 128, 128, seed=4_100_777, n_blobs=13), 0.0, "u8"), 6))
+    items.append((oracle.gradient(gen.blobs2d(512, 512, seed=4_000_777), 0.0, "u8"), 8))
+    NL = 4
+    say("  mixed batch", len(items), "images")
+    outs, nregs = ctx.batch([to_dev(g) for g, _ in items], [c for _, c in items], NL)
+    for (g, c), o, n in zip(items, outs, nregs):
+        ref, refn = oracle.waterfall_g1(oracle.watershed(g, c), g, c, NL)
+        assert np.array_equal(to_host(o), ref), (g.shape, c)
+        assert to_host(n).tolist() == refn.tolist()
+    torch.cuda.synchronize()
+
+
+def test_scratch_budget():
+    """ws_create's scratch budget: a call whose scratch exceeds it returns
+    WS_ENOMEM and writes nothing; calls that fit still run and equal the
+    oracle."""
+    import torch
+
+    import paper_2410_08946_amd as ws
+    small = oracle.gradient(gen.blobs2d(64, 80, seed=3), 0.0, "u8")
+    big = np.zeros((1500, 1500), np.uint8)
+    c = ws.Context(0, scratch_budget=4 << 20)
+    try:
+        g = to_dev(big)
+        lab = torch.full(big.shape, -7, dtype=torch.int32, device="cuda:0")
+        with pytest.raises(ws.WSError) as e:
+            c.watershed(g, 4, out=lab)
+        assert e.value.code == ws.binding.WS_ENOMEM
+        torch.cuda.synchronize()
+        assert bool((lab == -7).all())  # nothing was launched
+        with pytest.raises(ws.WSError) as e:
+            c.batch([g, to_dev(small)], 8, 3)
+        assert e.value.code == ws.binding.WS_ENOMEM
+        d = to_dev(small)
+        lab = c.watershed(d, 8)
+        out, n = c.waterfall(lab, d, 8, 3)
+        ref, refn = oracle.waterfall_g1(oracle.watershed(small, 8), small, 8, 3)
+        assert np.array_equal(to_host(out), ref) and to_host(n).tolist() == refn.tolist()
+    finally:
+        c.close()
+
+
 def test_batch_errors(ctx):
     import torch
     import paper_2410_08946_amd as ws
     g = torch.zeros((16, 16), dtype=torch.uint8, device="cuda:0")
     g3 = torch.zeros((4, 16, 16), dtype=torch.uint8, device="cuda:0")
     with pytest.raises(ws.WSError):
-        ctx.batch([g, g3], 8, 3)
+        ctx.batch([g, g3], 8, 3)          # 8-connectivity on a volume
+    with pytest.raises(ws.WSError):
+        ctx.batch([g, g3], [8, 4], 3)
     with pytest.raises(ws.WSError):
         ctx.batch([g], 8, 0)
+    with pytest.raises(ValueError):
+        ctx.batch([g, g3], [8], 3)        # one connectivity per image
     with pytest.raises(ValueError):
         ctx.batch([], 8, 3)
 
@@ -366,6 +470,9 @@ def test_batch_errors(ctx):
 # --------------------------------------------------------------------------
 
 def test_serving_mix_identity(ctx):
+    """Jobs of the serving mix (2D 8-connected and 3D 6-connected, including
+    the smallest sizes of the served workload, 512^2 and 128^3) give the
+    oracle's layers when served in a mix, and the same as when run alone."""
     import torch
     from paper_2410_08946_amd import serve
     rng = np.random.default_rng(21)
@@ -379,13 +486,20 @@ def test_serving_mix_identity(ctx):
             ny, nx = int(rng.integers(16, 300)), int(rng.integers(16, 300))
             g = oracle.gradient(gen.blobs2d(ny, nx, seed=500 + i), 0.0, "u8")
             jobs_in.append((g, 8))
+    # the served workload's content at its smallest sizes: the 2D blob recipe
+    # (32 blobs, 1 % salt) at 512^2 and the volume recipe's blob density at 128^3
+    jobs_in.insert(7, (oracle.gradient(gen.blobs2d(512, 512, seed=4_000_123), 0.0, "u8"), 8))
+    jobs_in.insert(20, (oracle.gradient(gen.blobs3d(128, 128, 128, seed=4_100_123, n_blobs=13), 0.0, "u8"), 6))
+    say("  serving mix: %d jobs, %d voxels" % (len(jobs_in), sum(g.size for g, _ in jobs_in)))
     devs = [(to_dev(g), c) for g, c in jobs_in]
     solo = []
-    for d, c in devs:
+    for (g, c), (d, _) in zip(jobs_in, devs):
         lab = ctx.watershed(d, c)
         out, n = ctx.waterfall(lab, d, c, 4)
         solo.append((to_host(out), to_host(n)))
-    srv = serve.Server(slots=3, budget_bytes=64 << 20, max_batch_jobs=6)
+        ref, refn = oracle.waterfall_g1(oracle.watershed(g, c), g, c, 4)
+        assert np.array_equal(solo[-1][0], ref) and solo[-1][1].tolist() == refn.tolist()
+    srv = serve.Server(slots=3, budget_bytes=1 << 30, max_batch_jobs=6)
     try:
         jobs = [srv.submit(serve.Job(grad=d, conn=c, NL=4, jid=k)) for k, (d, c) in enumerate(devs)]
         assert srv.drain(timeout=120)

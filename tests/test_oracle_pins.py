@@ -373,10 +373,29 @@ def test_gradient_vs_scipy(shape, sigma):
     f = (rng.normal(0, 100, size=shape) + 1000).astype(np.float32)
     q, mag = oracle.gradient(f, sigma, "u16", return_mag=True)
     ref = _scipy_grad(f, sigma)
-    assert np.allclose(mag, ref, rtol=0, atol=1e-9 * ref.max())
-    expect = np.rint(ref * 65535.0 / ref.max())
-    assert np.abs(q.astype(np.int64) - expect).max() <= 1
+    assert np.allclose(mag, ref, rtol=0, atol=1e-12 * ref.max())
+    # quantisation: rint(mag * Q / max) ties to even, exactly, except where the
+    # scaled value lies within the float64 disagreement of the two magnitudes
+    # (1e-12 * Q) of a .5 boundary, where one level either way is allowed
+    exact = ref * 65535.0 / ref.max()
+    near = np.abs(exact - np.floor(exact) - 0.5) <= 1e-12 * 65535.0
+    assert near.mean() < 0.01  # the allowance covers almost nothing
+    d = np.abs(q.astype(np.int64) - np.rint(exact).astype(np.int64))
+    assert (d[~near] == 0).all() and d.max() <= 1
     assert q.max() == 65535
+
+
+@pytest.mark.parametrize("Q,dtype", [(255, "u8"), (65535, "u16")])
+def test_gradient_quantisation_ties(Q, dtype):
+    """Magnitudes that scale exactly onto k + 1/2 are rounded half to even: a
+    flooring, truncating or round-half-up quantiser fails here."""
+    from tests.quant_fixture import tie_image
+    img, mag_exact, expect = tie_image(Q)
+    q, mag = oracle.gradient(img, 0.0, dtype, return_mag=True)
+    assert np.array_equal(mag, mag_exact)
+    ties = (mag_exact * Q / mag_exact.max()) % 1.0 == 0.5
+    assert ties.mean() > 0.9
+    assert np.array_equal(q.astype(np.int64), expect)
 
 
 def test_gradient_closed_forms():

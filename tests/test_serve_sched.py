@@ -45,8 +45,12 @@ def test_batch_groups_compatible_jobs_in_order():
     slot, allow_big = s._pick_slot()
     assert slot["k"] == 1 and not allow_big  # ordinary work prefers the slots other than 0
     batch, foot = s._take_batch(allow_big)
-    assert ids(batch) == [0, 2, 4] and foot == 3
-    assert [j.jid for j in s.queue] == [1, 3]  # skipped jobs keep their order
+    # 2D and 3D jobs of any connectivity share a micro-batch; NL must match
+    assert ids(batch) == [0, 1, 2, 4] and foot == 4
+    assert [j.jid for j in s.queue] == [3]  # skipped jobs keep their order
+    s.queue.extend([job(5, (4, 4, 4), conn=26, dtype=torch.uint16), job(6, (9, 9), NL=3)])
+    batch, _ = s._take_batch(allow_big)
+    assert ids(batch) == [3, 6] and [j.jid for j in s.queue] == [5]  # one grey type per micro-batch
 
 
 def test_pixel_cap_closes_the_batch():
