@@ -205,6 +205,15 @@ def parse():
     ap.add_argument("--images", type=int, default=512, help="batch workload: number of images")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
                     help="1: the library replays launch graphs of the gradient and waterfall calls")
+    ap.add_argument("--graph-batch", type=int, default=1, choices=(0, 1),
+                    help="batch workload: 1 (default) replays the batched call as one launch graph per step")
+    ap.add_argument("--autotune", type=int, default=1, choices=(0, 1),
+                    help="1 (default): tune tile shape and Step II / III schedule before timing (cached per input "
+                         "class)")
+    ap.add_argument("--autotune-cache", default=None, help="autotune JSON cache (default: the user's cache dir)")
+    ap.add_argument("--retune", action="store_true", help="ignore cached autotune choices")
+    ap.add_argument("--volume-cache", default=None,
+                    help="c2: float32 file of the generated 928^3 volume (read if present, else written)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (counter calibration)")
     return ap.parse_args()
@@ -241,8 +250,19 @@ def bench_batch(args):
     outs_s = [torch.empty((NL,) + tuple(g.shape), dtype=torch.int32, device=dev) for g in grads]
     nreg_s = [torch.zeros(NL, dtype=torch.int64, device=dev) for _ in grads]
 
+    # the batched call replays one launch graph per step (captured on its
+    # second use); the per-image calls run directly on a context of their own
+    bctx = ws.Context(0)
+    tuned = None
+    if args.autotune:
+        from paper_2410_08946_amd import autotune
+        tuned = autotune.tune_batch(bctx, grads, conn, NL, reps=2, cache=args.autotune_cache, force=args.retune)
+        print("bench: batch autotune %s -> %s (%.1f s)" % (tuned["key"], tuned["options"], tuned["tuning_s"]),
+              file=sys.stderr, flush=True)
+    bctx.set_option("graph", args.graph_batch)
+
     def step_batch():
-        ctx.batch(grads, conn, NL, outs=outs_b, nregions=nreg_b)
+        bctx.batch(grads, conn, NL, outs=outs_b, nregions=nreg_b)
 
     def step_single():
         for g, o, n in zip(grads, outs_s, nreg_s):
@@ -266,7 +286,9 @@ def bench_batch(args):
         step_single()
     torch.cuda.synchronize()
     print("bench: timing", file=sys.stderr, flush=True)
+    r0 = bctx.stats()["graph_replays"]
     ms_b = timed(step_batch, args.steps)
+    graph_launches = (bctx.stats()["graph_replays"] - r0) / args.steps
     ms_s = timed(step_single, max(1, args.steps // 4))
     same = all(torch.equal(a, b) for a, b in zip(outs_b, outs_s)) and \
         all(torch.equal(a, b) for a, b in zip(nreg_b, nreg_s))
@@ -288,6 +310,8 @@ def bench_batch(args):
                    "parallelism": "single GPU"},
         "per_image_calls": {"value": round(N / (ms_s / 1e3) / 1e6, 2), "unit": "Mvoxel/s", "ms_per_step": round(ms_s, 3)},
         "batched_over_per_image": round(ms_s / ms_b, 3),
+        "batched_graph_launches_per_step": graph_launches,
+        "autotune": tuned,
         "identical_outputs": bool(same),
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_batch(args.images),
         "host": host_info(),
@@ -607,9 +631,22 @@ def measure_single(args, name, steps, warmup, kernel_timing, cpu_baseline):
     dev = torch.device("cuda:0")
     img = None
     if name == "c2":
-        # too large for the host generator: the same recipe evaluated on the device
-        print("bench: generating the 928^3 volume on the device", file=sys.stderr, flush=True)
-        img_d = gen.synth.blobs3d_device(shape, seed=cfg["seed"], device=dev)
+        # too large for the host generator: the same recipe evaluated on the
+        # device (or read back from a file an earlier run of this recipe wrote)
+        img_d = None
+        cache = args.volume_cache
+        if cache and os.path.exists(cache) and os.path.getsize(cache) == 4 * N:
+            print("bench: reading the 928^3 volume from %s" % cache, file=sys.stderr, flush=True)
+            import numpy as np
+            host = np.fromfile(cache, dtype=np.float32).reshape(shape)
+            img_d = torch.from_numpy(host).to(dev)
+            del host
+        if img_d is None:
+            print("bench: generating the 928^3 volume on the device", file=sys.stderr, flush=True)
+            img_d = gen.synth.blobs3d_device(shape, seed=cfg["seed"], device=dev)
+            if cache:
+                img_d.cpu().numpy().tofile(cache)
+                print("bench: wrote the volume to %s" % cache, file=sys.stderr, flush=True)
     else:
         print("bench: generating the 4096x4096 image", file=sys.stderr, flush=True)
         img = gen.config_image(name)
@@ -618,6 +655,22 @@ def measure_single(args, name, steps, warmup, kernel_timing, cpu_baseline):
     out_d = torch.empty((NL,) + shape, dtype=torch.int32, device=dev)
     nreg_d = torch.zeros(NL, dtype=torch.int64, device=dev)
     ctx = ws.Context(0)
+    tuned = None
+    if args.autotune:
+        # tile shape and Step II / III schedule for this input class (labels
+        # checked equal for every candidate); reported, not timed
+        from paper_2410_08946_amd import autotune
+        key = autotune.key_for(len(shape), gdt, conn, N)
+        hit = None if args.retune else autotune.load_cache(args.autotune_cache).get(key)
+        if hit and "options" in hit:
+            autotune.apply(ctx, hit["options"])
+            tuned = {"key": key, "options": hit["options"], "ms": hit.get("ms"), "cached": True, "candidates": [],
+                     "tuning_s": 0.0}
+        else:
+            ctx.gradient(img_d, sigma, gdt, out=grad_d)
+            tuned = autotune.tune_watershed(ctx, grad_d, conn, reps=3, cache=args.autotune_cache, force=True)
+        print("bench: %s autotune %s -> %s (%.1f s)" % (name, tuned["key"], tuned["options"], tuned["tuning_s"]),
+              file=sys.stderr, flush=True)
     ctx.set_option("graph", args.graph)
 
     def step():
@@ -717,6 +770,7 @@ def measure_single(args, name, steps, warmup, kernel_timing, cpu_baseline):
                            "ms": round(ws_wf_ms, 4), "achieved": round(used / (ws_wf_ms / 1e3) / 1e9, 1),
                            "frac": round(used / (ws_wf_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "cpu_baseline": cpu,
+        "autotune": tuned,
     }
     del img_d, grad_d, out_d
     ctx.close()
@@ -810,7 +864,7 @@ def main():
         # the 4096^2 image: a smaller, partly cache-resident workload
         e = measure_single(args, "c1", max(1, args.steps // 2), 2, False, False)
         line["extra"] = {"c1": {k: e[k] for k in ("value", "ms_per_step", "step_ms", "config", "stages_ms",
-                                                  "nregions", "hbm_path", "hbm_path_ws_wf")}}
+                                                  "nregions", "hbm_path", "hbm_path_ws_wf", "autotune")}}
     print(json.dumps(line), flush=True)
 
 

@@ -254,14 +254,31 @@ int ws_watershed_stages(ws_ctx *ctx, const void *grad, int dtype, int64_t nx, in
  *   "max_sweeps"   cap on Step II sweeps; reaching it returns WS_ENOCONV
  *                  (default 2^31-1).
  *   "timing"       1 = record a HIP event pair around every kernel launch.
- *   "graph"        1 = ws_gradient and ws_waterfall replay launch graphs: a
- *                  call is captured (hipStreamBeginCapture on a stream of the
- *                  context) the second time the same arguments (pointers,
- *                  sizes, options) are seen, and its instantiated graph is
- *                  launched on `stream` for every later identical call.
- *                  Buffers are read when the graph runs, so their contents
- *                  may change between calls. Any scratch reallocation drops
+ *   "graph"        1 = ws_gradient, ws_watershed, ws_waterfall and ws_batch
+ *                  replay launch graphs: a call is captured
+ *                  (hipStreamBeginCapture on a stream of the context) the
+ *                  second time the same arguments (pointers, sizes, options)
+ *                  are seen, and its instantiated graph is launched on
+ *                  `stream` for every later identical call. Buffers are read
+ *                  when the graph runs, so their contents may change between
+ *                  calls. A captured ws_watershed / ws_batch launches a fixed
+ *                  number of Step II sweeps (each returns at once after a sweep
+ *                  that changed nothing): one more than the previous direct
+ *                  run of the same arguments needed, plus one; the call then
+ *                  waits once for `stream` and reads the last sweep's counter,
+ *                  and if that sweep still changed distances it runs again
+ *                  directly (result unchanged) and the next identical call is
+ *                  captured anew. ws_batch's captured graph reads a device copy
+ *                  of its image tables that it owns. With "step3" = 1 the
+ *                  watershed is never captured. Any scratch reallocation drops
  *                  the graphs. Ignored while "timing" is on. Default 0.
+ *   "tile2d", "tile3d"  watershed tile shape of 2D / 3D images (shape ids):
+ *                  2D 2 = 64x32 (default), 12 = 128x16, 22 = 32x32,
+ *                  32 = 64x64; 3D 3 = 32x8x8 (default), 13 = 16x16x8,
+ *                  23 = 32x16x8, 33 = 16x16x16 (x fastest). Tiles of 64x64,
+ *                  32x16x8 and 16x16x16 keep up to 512 unresolved plateau
+ *                  pixels in their Step II list, the others 256. Block size
+ *                  changes only time (Section 5, parameters paragraph).
  *   "reserve_pixels"  allocate now the scratch (device buffers, batch tables
  *                  and the pinned staging) of calls covering up to this many
  *                  pixels, so later calls do not allocate (allocation waits

@@ -38,6 +38,8 @@ def _load():
         build()
         lib = ctypes.CDLL(_LIB)
         i64, i32, ptr, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_double
+        lib.or_set_progress.argtypes = [i32]
+        lib.or_set_progress.restype = None
         lib.or_step1.argtypes = [ptr, i64, i64, i64, i32, ptr, ptr]
         lib.or_watershed.argtypes = [ptr, i64, i64, i64, i32, i32, i64, ptr, ptr, ptr, ptr, ptr]
         lib.or_waterfall_g1.argtypes = [ptr, ptr, i64, i64, i64, i32, i32, ptr, ptr]
@@ -48,6 +50,12 @@ def _load():
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def set_progress(on: bool) -> None:
+    """Progress lines on stderr after each step of the watershed (for runs
+    over hundreds of millions of pixels)."""
+    _load().or_set_progress(1 if on else 0)
 
 
 def _dims(shape):

@@ -36,8 +36,20 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Progress lines on stderr after each step of a long run (off by default). */
+static int or_progress = 0;
+void or_set_progress(int on) { or_progress = on; }
+#define OR_SAY(...)                           \
+    do {                                      \
+        if (or_progress) {                    \
+            fprintf(stderr, __VA_ARGS__);     \
+            fflush(stderr);                   \
+        }                                     \
+    } while (0)
 
 #define OR_OK 0
 #define OR_EINVAL (-1)
@@ -218,15 +230,18 @@ int or_watershed(const uint16_t *I, int64_t nx, int64_t ny, int64_t nz, int conn
     /* Step I */
     or_step1(I, nx, ny, nz, conn, S, L);
     if (S1_out) memcpy(S1_out, S, sizeof(int32_t) * (size_t)N);
+    OR_SAY("oracle: Step I done (%lld pixels)\n", (long long)N);
 
     /* Step II */
     int64_t sweeps = step2_sync(I, nx, ny, nz, conn, S, L, dist, max_step2_sweeps);
+    OR_SAY("oracle: Step II done (%lld sweeps)\n", (long long)sweeps);
     if (bal_out)
         for (int64_t p = 0; p < N; ++p) bal_out[p] = dist[p] > 0 ? -dist[p] : S[p];
     if (arrow_out) memcpy(arrow_out, L, sizeof(int32_t) * (size_t)N);
 
     /* Step III */
     int64_t syncs = step3_reduce(L, N, RR);
+    OR_SAY("oracle: Step III done (%lld synchronisations)\n", (long long)syncs);
 
     /* Step IV: union over neighbouring pixels that both still have S >= 2
      * (half neighbourhood, q > p), then Find for every pixel. */
@@ -237,6 +252,7 @@ int or_watershed(const uint16_t *I, int64_t nx, int64_t ny, int64_t nz, int conn
             if (nb[k] > p && S[nb[k]] >= 2) uf_union(L, (int32_t)p, (int32_t)nb[k]);
     }
     for (int64_t p = 0; p < N; ++p) L[p] = uf_find(L, L[p]);
+    OR_SAY("oracle: Step IV done\n");
 
     /* Canonical label: the smallest pixel index of each basin. */
     int32_t *cmin = dist;  /* reuse */

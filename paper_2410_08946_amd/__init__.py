@@ -14,9 +14,11 @@ Functions named like the C entry points take and return torch tensors:
   ws_rag(labels, grad, conn)                       -> (a, b, h) region adjacency graph, sorted by (a, b)
   ws_batch([grad, ...], conn, NL)                  -> ([int32 [NL, ...]], [int64 [NL]])
 Image tensors are C-contiguous (nx,), (ny, nx) or (nz, ny, nx) with x fastest.
+`autotune` picks tile shapes and Step II / III schedules per input class.
 """
 from __future__ import annotations
 
+from . import autotune  # noqa: F401
 from .binding import (  # noqa: F401
     Context,
     WSError,

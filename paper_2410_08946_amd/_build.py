@@ -16,6 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libws.so")
 SOURCES = ["api.hip", "watershed.hip", "waterfall.hip", "gradient.hip", "rag.hip", "pixel.hip"]
+# ws_shape.hip is compiled once per watershed tile shape id (TileShape in ws_device.h)
+SHAPES = [2, 12, 22, 32, 3, 13, 23, 33]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
@@ -30,7 +32,7 @@ def hipcc() -> str:
 
 def _jobs() -> int:
     n = os.cpu_count() or 1
-    return max(1, min(len(SOURCES), n, int(os.environ.get("MAX_JOBS", n))))
+    return max(1, min(len(SOURCES) + len(SHAPES), n, int(os.environ.get("MAX_JOBS", n))))
 
 
 def build(verbose: bool = False) -> str:
@@ -39,10 +41,12 @@ def build(verbose: bool = False) -> str:
     cc = hipcc()
     inc = ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
     objs, cmds = [], []
-    for s in SOURCES:
-        o = os.path.join(OBJ, os.path.splitext(s)[0] + ".o")
+    units = [(s, os.path.splitext(s)[0], []) for s in SOURCES]
+    units += [("ws_shape.hip", "ws_shape_%d" % sh, ["-DWS_SHAPE=%d" % sh]) for sh in SHAPES]
+    for s, stem, defs in units:
+        o = os.path.join(OBJ, stem + ".o")
         objs.append(o)
-        cmds.append([cc] + FLAGS + inc + ["-c", "-o", o, os.path.join(CSRC, s)])
+        cmds.append([cc] + FLAGS + defs + inc + ["-c", "-o", o, os.path.join(CSRC, s)])
     if verbose:
         for c in cmds:
             print(" ".join(c), flush=True)

@@ -52,6 +52,7 @@ struct ws_ctx {
     hipEvent_t stage_ev = nullptr;        // last upload from `stage`
     bool stage_pending = false;
     int step3 = 0, rr = 6, sweep_batch = 4;
+    int tile2 = 2, tile3 = 3;             // watershed tile shape ids of 2D / 3D images
     int schedule = 0, step4 = 0;           // per-pixel schedule, PRW Step IV
     int64_t max_sweeps = 0x7fffffff;
     bool timing = false;
@@ -66,9 +67,17 @@ struct ws_ctx {
         uint64_t gen;
         uint64_t used;
         hipGraphExec_t exec;
+        void *owned = nullptr;   // device buffer only this graph's kernels read (batch tables)
+        size_t owned_n = 0;
+        int32_t sweeps = 0;      // Step II sweeps it launches after the initial pass (0: none)
     };
     std::vector<Graph> graphs;
     std::map<std::string, uint64_t> seen;
+    // Step II sweeps (after the initial tile pass) a captured watershed call
+    // launches: one more than the sweeps that changed something when the
+    // signature last ran directly
+    std::map<std::string, int32_t> graph_sweeps;
+    int32_t cap_sweeps = 0;               // while capturing a watershed: that count
     uint64_t tick = 0;
     wsk::TimingSink sink;
     int64_t stats[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -156,15 +165,16 @@ bool valid_conn(int64_t nz, int conn) {
     return nz == 1 ? (conn == 4 || conn == 8) : (conn == 6 || conn == 26);
 }
 
-Geom make_geom(int64_t nx, int64_t ny, int64_t nz, int ndim) {
+// Sizes and the watershed tiling of tile shape `shape` (an id of TileShape;
+// the defaults are 2 for 2D and 3 for 3D images).
+Geom make_geom(int64_t nx, int64_t ny, int64_t nz, int shape) {
     Geom g;
     g.nx = (int32_t)nx;
     g.ny = (int32_t)ny;
     g.nz = (int32_t)nz;
     g.n = (int32_t)(nx * ny * nz);
-    int TX = ndim == 3 ? wsk::TileShape<3>::X : wsk::TileShape<2>::X;
-    int TY = ndim == 3 ? wsk::TileShape<3>::Y : wsk::TileShape<2>::Y;
-    int TZ = ndim == 3 ? wsk::TileShape<3>::Z : wsk::TileShape<2>::Z;
+    int TX = 1, TY = 1, TZ = 1;
+    if (!wsk::tile_dims(shape, TX, TY, TZ)) wsk::tile_dims(nz > 1 ? 3 : 2, TX, TY, TZ);
     g.ntx = (int32_t)((nx + TX - 1) / TX);
     g.nty = (int32_t)((ny + TY - 1) / TY);
     g.ntz = (int32_t)((nz + TZ - 1) / TZ);
@@ -172,6 +182,9 @@ Geom make_geom(int64_t nx, int64_t ny, int64_t nz, int ndim) {
     g.dny = wsk::FastDiv((uint32_t)ny);
     return g;
 }
+
+// The watershed tile shape the context uses for images of `ndim` dimensions.
+int shape_of(const ws_ctx *c, int ndim) { return ndim == 3 ? c->tile3 : c->tile2; }
 
 int set_device(ws_ctx *c) {
     hipError_t e = hipSetDevice(c->device);
@@ -186,25 +199,58 @@ Launch make_launch(ws_ctx *c, void *stream) {
     return lc;
 }
 
+// A graphed call's verdict after a graph launch: the graph's result does not
+// hold (its Step II sweep count was too small), run the call directly.
+constexpr int kRerun = 1;
+
+void drop_graph(ws_ctx *c, size_t i) {
+    ws_ctx::Graph &g = c->graphs[i];
+    (void)hipGraphExecDestroy(g.exec);
+    if (g.owned) {
+        (void)hipFree(g.owned);   // waits for the device: no replay still reads it
+        c->held -= std::min(c->held, g.owned_n);
+    }
+    c->graphs.erase(c->graphs.begin() + (long)i);
+}
+
+struct NoPrep {
+    int operator()(void **, size_t *) const { return WS_OK; }
+};
+struct NoCheck {
+    int operator()(const ws_ctx::Graph &) const { return WS_OK; }
+};
+
 // Enqueues through `enqueue(Launch&)`, or replays its captured graph. Without
 // the graph option (or with per-launch timing) it simply enqueues on `stream`.
 // A signature's first use runs directly (allocating what it needs); its
 // second use is captured on the context's own stream (the caller's may be
 // the legacy stream, which cannot be captured), instantiated and launched on
 // `stream`; later uses replay. If capture fails the call runs directly.
-template <class F>
-int run_graphed(ws_ctx *c, void *stream, const std::string &sig, F &&enqueue) {
+// `prep(&owned, &bytes)` runs before a capture: it may allocate a device
+// buffer the graph alone reads (freed with the graph), or return kRerun to
+// run the call directly instead. `check(graph)` runs after every launch of
+// the graph; kRerun drops the graph and runs the call directly (the next
+// identical call is captured again).
+template <class F, class P = NoPrep, class K = NoCheck>
+int run_graphed(ws_ctx *c, void *stream, const std::string &sig, F &&enqueue, P &&prep = P(), K &&check = K()) {
     if (!c->graph || c->timing) {
         Launch lc = make_launch(c, stream);
         return enqueue(lc);
     }
-    for (auto &g : c->graphs)
-        if (g.sig == sig && g.gen == c->gen) {
-            g.used = ++c->tick;
-            ++c->stats[4];
-            hipError_t e = hipGraphLaunch(g.exec, (hipStream_t)stream);
-            return e == hipSuccess ? WS_OK : hip_fail(c, e, "hipGraphLaunch");
-        }
+    auto launch_checked = [&](size_t gi) -> int {
+        ws_ctx::Graph &g = c->graphs[gi];
+        g.used = ++c->tick;
+        ++c->stats[4];
+        hipError_t e = hipGraphLaunch(g.exec, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+        int v = check(g);
+        if (v != kRerun) return v;
+        drop_graph(c, gi);
+        Launch lc = make_launch(c, stream);
+        return enqueue(lc);
+    };
+    for (size_t i = 0; i < c->graphs.size(); ++i)
+        if (c->graphs[i].sig == sig && c->graphs[i].gen == c->gen) return launch_checked(i);
     auto it = c->seen.find(sig);
     if (it == c->seen.end() || it->second != c->gen) {
         c->seen[sig] = c->gen;
@@ -214,16 +260,35 @@ int run_graphed(ws_ctx *c, void *stream, const std::string &sig, F &&enqueue) {
     hipError_t e;
     if (!c->cap && (e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking)) != hipSuccess)
         return hip_fail(c, e, "hipStreamCreateWithFlags");
+    void *owned = nullptr;
+    size_t owned_n = 0;
+    int rc = prep(&owned, &owned_n);
+    auto release = [&]() {
+        if (owned) {
+            (void)hipFree(owned);
+            c->held -= std::min(c->held, owned_n);
+        }
+        owned = nullptr;
+        c->cap_sweeps = 0;
+    };
+    if (rc != WS_OK) {
+        release();
+        if (rc != kRerun) return rc;
+        Launch lc = make_launch(c, stream);
+        return enqueue(lc);
+    }
     if ((e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
         (void)hipGetLastError();
+        release();
         Launch lc = make_launch(c, stream);
         return enqueue(lc);
     }
     c->capturing = true;
     Launch cl = make_launch(c, c->cap);
     cl.timing = nullptr;
-    int rc = enqueue(cl);
+    rc = enqueue(cl);
     c->capturing = false;
+    const int32_t sweeps = c->cap_sweeps;
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(c->cap, &graph);
     hipGraphExec_t exec = nullptr;
@@ -232,18 +297,27 @@ int run_graphed(ws_ctx *c, void *stream, const std::string &sig, F &&enqueue) {
     if (rc != WS_OK || e != hipSuccess || !exec) {
         (void)hipGetLastError();
         c->err.clear();
+        release();
         Launch lc = make_launch(c, stream);
         return enqueue(lc);
     }
+    c->cap_sweeps = 0;
     if (c->graphs.size() >= kMaxGraphs) {
-        auto old = std::min_element(c->graphs.begin(), c->graphs.end(),
-                                    [](const ws_ctx::Graph &a, const ws_ctx::Graph &b) { return a.used < b.used; });
-        (void)hipGraphExecDestroy(old->exec);
-        c->graphs.erase(old);
+        size_t old = 0;
+        for (size_t i = 1; i < c->graphs.size(); ++i)
+            if (c->graphs[i].used < c->graphs[old].used) old = i;
+        drop_graph(c, old);
     }
-    c->graphs.push_back({sig, c->gen, ++c->tick, exec});
-    e = hipGraphLaunch(exec, (hipStream_t)stream);
-    return e == hipSuccess ? WS_OK : hip_fail(c, e, "hipGraphLaunch");
+    ws_ctx::Graph g;
+    g.sig = sig;
+    g.gen = c->gen;
+    g.used = ++c->tick;
+    g.exec = exec;
+    g.owned = owned;
+    g.owned_n = owned_n;
+    g.sweeps = sweeps;
+    c->graphs.push_back(g);
+    return launch_checked(c->graphs.size() - 1);
 }
 
 std::string sig_of(const char *what, std::initializer_list<uint64_t> v) {
@@ -271,6 +345,7 @@ struct Part {
     int32_t nws = 0, nwf = 0;
     int32_t ws0 = 0, wf0 = 0;
     int conn = 0, ndim = 0;
+    int shape = 0;   // watershed tile shape id
 };
 
 wsk::TileGrid full_grid(int32_t ntiles) {
@@ -291,7 +366,7 @@ int32_t ws_tiles_of(const std::vector<Part<Src>> &parts) {
 template <class Src>
 size_t rec_ints(const std::vector<Part<Src>> &parts) {
     size_t n = 0;
-    for (auto &p : parts) n += (size_t)p.nws * (size_t)wsk::border_cells(p.ndim);
+    for (auto &p : parts) n += (size_t)p.nws * (size_t)wsk::border_cells(p.shape);
     return n;
 }
 
@@ -329,7 +404,21 @@ int run_distances(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, bo
     int32_t *D = ws.D, *stamp = ws.stamp, *cnt = ws.cnt;
     WS_TRY(wsk::launch_fill2_i32(lc, stamp, 4 * nt, -1, cnt, kCounterSlots, 0));
     for (auto &p : parts)
-        WS_TRY(wsk::launch_ws_init(lc, p.ws, full_grid(p.nws), p.conn, u16, D, stamp + 4 * (size_t)p.ws0, cnt));
+        WS_TRY(wsk::launch_ws_init(lc, p.ws, full_grid(p.nws), p.conn, p.shape, u16, D, stamp + 4 * (size_t)p.ws0, cnt));
+    if (c->capturing) {
+        // a captured call cannot read counters back: it launches a fixed
+        // number of sweeps (a sweep after one that changed nothing returns at
+        // once), and the graph's check reads the count of the last one
+        const int32_t K = c->cap_sweeps;
+        if (K < 1 || K >= kCounterSlots) return fail(c, WS_EUNSUPPORTED, "sweep count of a captured call");
+        for (int32_t s = 1; s <= K; ++s)
+            for (auto &p : parts)
+                WS_TRY(wsk::launch_ws_sweep(lc, p.ws, full_grid(p.nws), p.conn, p.shape, u16, D, stamp + 4 * (size_t)p.ws0,
+                                            cnt + s, cnt + (s - 1), s));
+        c->stats[0] = K + 1;
+        c->stats[3] = nt;
+        return WS_OK;
+    }
     int64_t launched = 1, changing = 0;
     int32_t s = 1;
     bool first = true;
@@ -345,7 +434,7 @@ int run_distances(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, bo
         int32_t s0 = s;
         for (int b = 0; b < batch; ++b, ++s)
             for (auto &p : parts)
-                WS_TRY(wsk::launch_ws_sweep(lc, p.ws, full_grid(p.nws), p.conn, u16, D, stamp + 4 * (size_t)p.ws0,
+                WS_TRY(wsk::launch_ws_sweep(lc, p.ws, full_grid(p.nws), p.conn, p.shape, u16, D, stamp + 4 * (size_t)p.ws0,
                                             cnt + (s % kCounterSlots), cnt + ((s - 1) % kCounterSlots), s));
         launched += batch;
         hipError_t e = hipMemcpyAsync(c->host_cnt, cnt, kCounterSlots * 4, hipMemcpyDeviceToHost, lc.stream);
@@ -387,18 +476,18 @@ int run_watershed(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, bo
     const int32_t *D = ws.D;
     size_t ro = 0;
     for (auto &p : parts) {
-        WS_TRY(wsk::launch_ws_label(lc, p.ws, full_grid(p.nws), p.conn, u16, D, rec + ro));
-        WS_TRY(wsk::launch_ws_merge(lc, p.ws, full_grid(p.nws), p.conn, u16, rec + ro));
-        ro += (size_t)p.nws * (size_t)wsk::border_cells(p.ndim);
+        WS_TRY(wsk::launch_ws_label(lc, p.ws, full_grid(p.nws), p.conn, p.shape, u16, D, rec + ro));
+        WS_TRY(wsk::launch_ws_merge(lc, p.ws, full_grid(p.nws), p.conn, p.shape, u16, rec + ro));
+        ro += (size_t)p.nws * (size_t)wsk::border_cells(p.shape);
     }
     if (c->step3 == 0) {
-        for (auto &p : parts) WS_TRY(wsk::launch_ws_find(lc, p.ws, full_grid(p.nws), p.conn));
+        for (auto &p : parts) WS_TRY(wsk::launch_ws_find(lc, p.ws, full_grid(p.nws), p.conn, p.shape));
     } else {
         int32_t *cnt = ws.cnt;
         int64_t syncs = 0;
         for (;;) {
             WS_TRY(wsk::launch_fill_i32(lc, cnt, 1, 0));
-            for (auto &p : parts) WS_TRY(wsk::launch_ws_jump(lc, p.ws, full_grid(p.nws), p.conn, c->rr, cnt));
+            for (auto &p : parts) WS_TRY(wsk::launch_ws_jump(lc, p.ws, full_grid(p.nws), p.conn, p.shape, c->rr, cnt));
             hipError_t e = hipMemcpyAsync(c->host_cnt, cnt, 4, hipMemcpyDeviceToHost, lc.stream);
             if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
             if ((e = hipStreamSynchronize(lc.stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
@@ -408,6 +497,34 @@ int run_watershed(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, bo
         c->stats[2] = syncs;
     }
     return WS_OK;
+}
+
+// After a direct watershed run of signature `sig`: the sweeps a captured
+// replay launches (one more than the initial pass and the sweeps that changed
+// something, plus one spare; the counter ring bounds it).
+void note_sweeps(ws_ctx *c, const std::string &sig) {
+    c->graph_sweeps[sig] = (int32_t)std::min<int64_t>(c->stats[1] + 2, kCounterSlots);
+}
+
+// Before capturing a watershed signature: its sweep count, or kRerun when it
+// has not run directly yet or needs more sweeps than a graph holds.
+int prep_sweeps(ws_ctx *c, const std::string &sig) {
+    auto it = c->graph_sweeps.find(sig);
+    if (it == c->graph_sweeps.end() || it->second < 1 || it->second >= kCounterSlots) return kRerun;
+    c->cap_sweeps = it->second;
+    return WS_OK;
+}
+
+// After a launch of a watershed graph: its last sweep changed nothing, so
+// Step II had converged (one read-back and wait), or kRerun.
+int check_sweeps(ws_ctx *c, const ws_ctx::Graph &g, void *stream) {
+    if (g.sweeps <= 0) return WS_OK;
+    const int32_t *cnt = (const int32_t *)c->cnt.p;
+    hipError_t e = hipMemcpyAsync(c->host_cnt, cnt + g.sweeps, 4, hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    c->stats[0] = g.sweeps + 1;
+    return c->host_cnt[0] == 0 ? WS_OK : kRerun;
 }
 
 // Launches launch(i, counter) for i = 1, 2, ... in batches of sweep_batch,
@@ -643,9 +760,11 @@ int reserve(ws_ctx *c, int64_t n) {
 }
 
 // The one part of a single-image call.
-std::vector<Part<wsk::OneImg>> one_part(const wsk::OneImg &src, int conn) {
+// `src` must have been made by single_img with the same shape.
+std::vector<Part<wsk::OneImg>> one_part(const wsk::OneImg &src, int conn, int shape) {
     Part<wsk::OneImg> p;
     p.ws = p.wf = src;
+    p.shape = shape;
     p.ndim = src.im.g.nz > 1 ? 3 : 2;
     p.nws = src.im.g.ntx * src.im.g.nty * src.im.g.ntz;
     p.nwf = wsk::wf_tiles(src.im.g, p.ndim);
@@ -653,9 +772,9 @@ std::vector<Part<wsk::OneImg>> one_part(const wsk::OneImg &src, int conn) {
     return {p};
 }
 
-wsk::Img single_img(int64_t nx, int64_t ny, int64_t nz, const void *grad, int32_t *lab) {
+wsk::Img single_img(int64_t nx, int64_t ny, int64_t nz, const void *grad, int32_t *lab, int shape) {
     wsk::Img im{};
-    im.g = make_geom(nx, ny, nz, nz > 1 ? 3 : 2);
+    im.g = make_geom(nx, ny, nz, shape);
     im.pix0 = 0;
     im.tile0[0] = im.tile0[1] = im.tile0[2] = im.tile0[3] = 0;
     im.slot0 = 0;
@@ -698,7 +817,10 @@ void ws_destroy(ws_ctx *c) {
                    &c->tilecnt, &c->tab};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
-    for (auto &gr : c->graphs) (void)hipGraphExecDestroy(gr.exec);
+    for (auto &gr : c->graphs) {
+        (void)hipGraphExecDestroy(gr.exec);
+        if (gr.owned) (void)hipFree(gr.owned);
+    }
     if (c->cap) (void)hipStreamDestroy(c->cap);
     for (auto &r : c->sink.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (auto e : c->sink.pool) (void)hipEventDestroy(e);
@@ -727,8 +849,9 @@ size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int conn, int dtyp
     size_t N = (size_t)(nx * ny * nz);
     size_t b = dtype == WS_U8 ? 1 : 2;
     size_t job = N * (b + 4 * (size_t)NL);
-    size_t ws = N * 4 /* D */ + (size_t)make_geom(nx, ny, nz, ndim).ntx * make_geom(nx, ny, nz, ndim).nty *
-                                    make_geom(nx, ny, nz, ndim).ntz * (16 + 4 * (size_t)wsk::border_cells(ndim));
+    // at the default tile shapes (2 and 3), which have the most border records per pixel
+    const Geom gd = make_geom(nx, ny, nz, ndim);
+    size_t ws = N * 4 /* D */ + (size_t)gd.ntx * gd.nty * gd.ntz * (16 + 4 * (size_t)wsk::border_cells(ndim));
     size_t wf = 0;
     if (NL >= 2) {
         size_t tiles = (size_t)wsk::wf_tiles(make_geom(nx, ny, nz, ndim), ndim);
@@ -750,6 +873,8 @@ int ws_set_option(ws_ctx *c, const char *name, int64_t v) {
     else if (k == "max_sweeps" && v >= 1) c->max_sweeps = v;
     else if (k == "timing" && (v == 0 || v == 1)) c->timing = v != 0;
     else if (k == "graph" && (v == 0 || v == 1)) c->graph = v != 0;
+    else if (k == "tile2d" && (v == 2 || v == 12 || v == 22 || v == 32)) c->tile2 = (int)v;
+    else if (k == "tile3d" && (v == 3 || v == 13 || v == 23 || v == 33)) c->tile3 = (int)v;
     else if (k == "reserve_pixels" && v >= 0 && v < (1LL << 31)) {
         int rc = set_device(c);
         if (rc) return rc;
@@ -779,7 +904,7 @@ int ws_gradient(ws_ctx *c, const float *img, int64_t nx, int64_t ny, int64_t nz,
     int rc = set_device(c);
     if (rc) return rc;
     int ndim = nz > 1 ? 3 : 2;
-    Geom g = make_geom(nx, ny, nz, ndim);
+    Geom g = make_geom(nx, ny, nz, ndim);  // the default shape of this dimensionality (tiling unused)
     size_t N = (size_t)g.n;
     uint32_t sbits;
     memcpy(&sbits, &sigma, 4);
@@ -846,15 +971,31 @@ int ws_watershed(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny,
     if ((rc = set_device(c))) return rc;
     int ndim = nz > 1 ? 3 : 2;
     Launch lc = make_launch(c, stream);
-    wsk::OneImg src{single_img(nx, ny, nz, grad, labels)};
+    const int shape = shape_of(c, ndim);
+    wsk::OneImg src{single_img(nx, ny, nz, grad, labels, shape)};
     const wsk::Geom &g = src.im.g;
-    (void)ndim;
     if (c->schedule == 1) return run_watershed_px(c, lc, g, grad, conn, dtype == WS_U16, labels, nullptr);
     if (c->step4 == 1) return fail(c, WS_EUNSUPPORTED, "ws_watershed: step4 = 1 (PRW) needs schedule = 1");
-    auto parts = one_part(src, conn);
-    WsScratch ws;
-    if ((rc = prepare_watershed(c, parts, (size_t)g.n, true, ws)) != WS_OK) return rc;
-    return run_watershed(c, lc, parts, dtype == WS_U16, ws);
+    auto parts = one_part(src, conn, shape);
+    auto enqueue = [&](Launch &l) -> int {
+        WsScratch ws;
+        int rc2 = prepare_watershed(c, parts, (size_t)g.n, true, ws);
+        if (rc2 != WS_OK) return rc2;
+        return run_watershed(c, l, parts, dtype == WS_U16, ws);
+    };
+    // PRUF reads a counter back after every synchronisation: never captured
+    if (c->step3 != 0) return enqueue(lc);
+    std::string sig = sig_of("ws", {(uint64_t)(uintptr_t)grad, (uint64_t)dtype, (uint64_t)nx, (uint64_t)ny,
+                                    (uint64_t)nz, (uint64_t)conn, (uint64_t)(uintptr_t)labels, (uint64_t)shape});
+    return run_graphed(
+        c, stream, sig,
+        [&](Launch &l) -> int {
+            int rc2 = enqueue(l);
+            if (rc2 == WS_OK && !c->capturing) note_sweeps(c, sig);
+            return rc2;
+        },
+        [&](void **, size_t *) { return prep_sweeps(c, sig); },
+        [&](const ws_ctx::Graph &gr) { return check_sweeps(c, gr, stream); });
 }
 
 int ws_watershed_stages(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz, int conn,
@@ -865,10 +1006,11 @@ int ws_watershed_stages(ws_ctx *c, const void *grad, int dtype, int64_t nx, int6
     if ((rc = set_device(c))) return rc;
     Launch lc = make_launch(c, stream);
     bool u16 = dtype == WS_U16;
-    wsk::OneImg src{single_img(nx, ny, nz, grad, nullptr)};
+    const int shape = shape_of(c, nz > 1 ? 3 : 2);
+    wsk::OneImg src{single_img(nx, ny, nz, grad, nullptr, shape)};
     const wsk::Geom &g = src.im.g;
     if (c->schedule == 1) return run_watershed_px(c, lc, g, grad, conn, u16, arrow, bal);
-    auto parts = one_part(src, conn);
+    auto parts = one_part(src, conn, shape);
     WsScratch ws;
     if ((rc = prepare_watershed(c, parts, (size_t)g.n, false, ws)) != WS_OK) return rc;
     if ((rc = run_distances(c, lc, parts, u16, ws)) != WS_OK) return rc;
@@ -884,14 +1026,15 @@ int ws_waterfall(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, 
     if (NL < 1) return fail(c, WS_EINVAL, "ws_waterfall: NL must be >= 1");
     if ((rc = set_device(c))) return rc;
     int ndim = nz > 1 ? 3 : 2;
-    wsk::OneImg src{single_img(nx, ny, nz, grad, out)};
+    const int shape = shape_of(c, ndim);
+    wsk::OneImg src{single_img(nx, ny, nz, grad, out, shape)};
     const wsk::Geom &g = src.im.g;
     std::string sig = sig_of("wf", {(uint64_t)(uintptr_t)labels, (uint64_t)(uintptr_t)grad, (uint64_t)dtype,
                                     (uint64_t)nx, (uint64_t)ny, (uint64_t)nz, (uint64_t)conn, (uint64_t)NL,
                                     (uint64_t)(uintptr_t)out, (uint64_t)(uintptr_t)nregions});
     (void)ndim;
     return run_graphed(c, stream, sig, [&](Launch &lc) -> int {
-        auto parts = one_part(src, conn);
+        auto parts = one_part(src, conn, shape);
         const int32_t nchunks = wsk::wf_chunks(g.n);
         WfBufs b;
         int rc2 = wf_buffers(c, (size_t)g.n, wf_tiles_of(parts), nchunks, slab_cap_of(parts), NL, NL >= 2, b);
@@ -914,7 +1057,8 @@ int ws_waterfall_recon(ws_ctx *c, const int32_t *labels, const void *grad, int d
     if ((rc = set_device(c))) return rc;
     const int ndim = nz > 1 ? 3 : 2;
     Launch lc = make_launch(c, stream);
-    const Geom g = make_geom(nx, ny, nz, ndim);
+    const int shape = shape_of(c, ndim);
+    const Geom g = make_geom(nx, ny, nz, shape);
     const size_t N = (size_t)g.n;
     const int32_t nchunks = wsk::wf_chunks(g.n), bound = g.n;
     const wsk::TileGrid tgw = full_grid(wsk::wf_tiles(g, ndim));
@@ -923,8 +1067,8 @@ int ws_waterfall_recon(ws_ctx *c, const int32_t *labels, const void *grad, int d
     if ((rc = ensure(c, c->rimg, N * 2, "raised image")) != WS_OK) return rc;
     WsScratch ws;
     {
-        wsk::OneImg probe{single_img(nx, ny, nz, grad, out)};
-        if ((rc = prepare_watershed(c, one_part(probe, conn), N, true, ws)) != WS_OK) return rc;
+        wsk::OneImg probe{single_img(nx, ny, nz, grad, out, shape)};
+        if ((rc = prepare_watershed(c, one_part(probe, conn, shape), N, true, ws)) != WS_OK) return rc;
     }
     uint16_t *I = (uint16_t *)c->rimg.p;
     if (labels != out) {
@@ -933,7 +1077,7 @@ int ws_waterfall_recon(ws_ctx *c, const int32_t *labels, const void *grad, int d
     }
     WS_TRY(wsk::launch_grey_u16(lc, grad, dtype == WS_U16, I, g.n));
     for (int k = 0; k < NL; ++k) {
-        wsk::OneImg src{single_img(nx, ny, nz, I, out + (size_t)k * N)};
+        wsk::OneImg src{single_img(nx, ny, nz, I, out + (size_t)k * N, shape)};
         // region ids and the layer's region count
         WS_TRY(wsk::launch_wf_ids(lc, src, nchunks, bound, b.ids, b.scan_tmp, b.nreg0, k + 1 < NL ? b.key : nullptr,
                                   b.par));
@@ -946,8 +1090,8 @@ int ws_waterfall_recon(ws_ctx *c, const int32_t *labels, const void *grad, int d
         // the current image, Step VI (raise), then the watershed again
         WS_TRY(wsk::launch_wf_pix(lc, src, tgw, conn, true, b.ids, b.nreg0, b.cimg, b.rlist, b.key, b.es));
         WS_TRY(wsk::launch_recon_raise(lc, I, b.cimg, b.key, b.nreg0, g.n));
-        wsk::OneImg next{single_img(nx, ny, nz, I, out + (size_t)(k + 1) * N)};
-        if ((rc = run_watershed(c, lc, one_part(next, conn), true, ws)) != WS_OK) return rc;
+        wsk::OneImg next{single_img(nx, ny, nz, I, out + (size_t)(k + 1) * N, shape)};
+        if ((rc = run_watershed(c, lc, one_part(next, conn, shape), true, ws)) != WS_OK) return rc;
     }
     return WS_OK;
 }
@@ -961,14 +1105,14 @@ int ws_rag(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, int64_
     if ((rc = set_device(c))) return rc;
     const int ndim = nz > 1 ? 3 : 2;
     Launch lc = make_launch(c, stream);
-    const Geom g = make_geom(nx, ny, nz, ndim);
+    const Geom g = make_geom(nx, ny, nz, shape_of(c, ndim));
     const size_t N = (size_t)g.n;
     const int32_t nchunks = wsk::wf_chunks(g.n), bound = g.n;
     const wsk::TileGrid tg = full_grid(wsk::wf_tiles(g, ndim));
     WfBufs b;
     if ((rc = wf_buffers(c, N, tg.ntiles, nchunks, wsk::wf_slab_cap(conn), 1, true, b)) != WS_OK) return rc;
     // the labels are read, never written (the pixel pass only reads its layer 0)
-    wsk::OneImg src{single_img(nx, ny, nz, grad, const_cast<int32_t *>(labels))};
+    wsk::OneImg src{single_img(nx, ny, nz, grad, const_cast<int32_t *>(labels), shape_of(c, ndim))};
     WS_TRY(wsk::launch_wf_ids(lc, src, nchunks, bound, b.ids, b.scan_tmp, b.nreg0, b.key, b.par));
     WS_TRY(wsk::launch_wf_pix(lc, src, tg, conn, dtype == WS_U16, b.ids, b.nreg0, b.cimg, b.rlist, b.key, b.es));
     // offsets of the tiles' edges in one list, and their total (read back once)
@@ -1022,7 +1166,7 @@ int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int NL, vo
         arena += (it.nx * it.ny * it.nz + 63) / 64 * 64;  // image offsets stay 64-pixel aligned
         const int ndim = it.nz > 1 ? 3 : 2;
         const int gi = (int)(std::find(kConns, kConns + 4, it.conn) - kConns);
-        wsk::Geom g = make_geom(it.nx, it.ny, it.nz, ndim);
+        wsk::Geom g = make_geom(it.nx, it.ny, it.nz, shape_of(c, ndim));
         tws[gi] += (int64_t)g.ntx * g.nty * g.ntz;
         twf[gi] += wsk::wf_tiles(g, ndim);
         tch += wsk::wf_chunks(g.n);
@@ -1031,94 +1175,152 @@ int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int NL, vo
     int64_t ws_all = tws[0] + tws[1] + tws[2] + tws[3], wf_all = twf[0] + twf[1] + twf[2] + twf[3];
     int rc;
     if ((rc = set_device(c))) return rc;
-    Launch lc = make_launch(c, stream);
-    // host staging: [Img table][ws tile map][wf tile map][chunk map][nregions pointers]
+    // tables: [Img table][ws tile map][wf tile map][chunk map][nregions pointers]
     size_t tab_b = sizeof(wsk::Img) * (size_t)n_items;
     size_t off_ws = (tab_b + 255) & ~(size_t)255;
     size_t off_wf = (off_ws + 4 * (size_t)ws_all + 255) & ~(size_t)255;
     size_t off_ch = (off_wf + 4 * (size_t)wf_all + 255) & ~(size_t)255;
     size_t off_outs = (off_ch + 4 * (size_t)tch + 255) & ~(size_t)255;
     size_t total = off_outs + sizeof(int64_t *) * (size_t)n_items;
-    // every buffer of the call before anything is launched
-    if ((rc = ensure_stage(c, total)) != WS_OK) return rc;
-    if ((rc = ensure(c, c->tab, total, "batch tables")) != WS_OK) return rc;
-    char *d = (char *)c->tab.p;
-    const wsk::Img *tab_dev = (const wsk::Img *)d;
-    std::vector<Part<wsk::ImgTable>> parts;
+    // parts in connectivity order; tile ranges relative to the part's first tile
+    struct PartSpec {
+        int conn, ndim, gi;
+        int32_t ws0, wf0, nws, nwf;
+    };
+    std::vector<PartSpec> specs;
     int32_t ws0 = 0, wf0 = 0;
     for (int gi = 0; gi < 4; ++gi) {
         if (tws[gi] == 0) continue;
-        Part<wsk::ImgTable> p;
-        p.conn = kConns[gi];
-        p.ndim = gi < 2 ? 2 : 3;
-        p.ws0 = ws0;
-        p.wf0 = wf0;
-        p.nws = (int32_t)tws[gi];
-        p.nwf = (int32_t)twf[gi];
-        p.ws = wsk::ImgTable{tab_dev, (const int32_t *)(d + off_ws) + ws0};
-        p.wf = wsk::ImgTable{tab_dev, (const int32_t *)(d + off_wf) + wf0};
-        ws0 += p.nws;
-        wf0 += p.nwf;
-        parts.push_back(p);
+        specs.push_back({kConns[gi], gi < 2 ? 2 : 3, gi, ws0, wf0, (int32_t)tws[gi], (int32_t)twf[gi]});
+        ws0 += (int32_t)tws[gi];
+        wf0 += (int32_t)twf[gi];
     }
-    const int32_t nchunks = (int32_t)tch;
-    WfBufs wb;
-    WsScratch ws;
-    if ((rc = prepare_watershed(c, parts, (size_t)arena, true, ws)) != WS_OK) return rc;
-    if ((rc = wf_buffers(c, (size_t)arena, (int32_t)wf_all, nchunks, slab_cap_of(parts), NL, NL >= 2, wb)) != WS_OK)
-        return rc;
-    char *h = (char *)c->stage;
-    wsk::Img *tab = (wsk::Img *)h;
-    int32_t *mws = (int32_t *)(h + off_ws), *mwf = (int32_t *)(h + off_wf), *mch = (int32_t *)(h + off_ch);
-    int64_t **outs = (int64_t **)(h + off_outs);
-    // tile ranges: the part's first tile plus the images of that part before it
-    int32_t next_ws[4], next_wf[4];
-    for (auto &p : parts) {
-        const int gi = (int)(std::find(kConns, kConns + 4, p.conn) - kConns);
-        next_ws[gi] = 0;  // relative to the part's range
-        next_wf[gi] = 0;
+    // the tables on the host (no device pointers of the context in them)
+    std::vector<char> host(total, 0);
+    {
+        char *h = host.data();
+        wsk::Img *tab = (wsk::Img *)h;
+        int32_t *mws = (int32_t *)(h + off_ws), *mwf = (int32_t *)(h + off_wf), *mch = (int32_t *)(h + off_ch);
+        int64_t **outs = (int64_t **)(h + off_outs);
+        int32_t next_ws[4] = {0, 0, 0, 0}, next_wf[4] = {0, 0, 0, 0};
+        int32_t pix = 0, t2 = 0;
+        for (int i = 0; i < n_items; ++i) {
+            const ws_item &it = items[i];
+            const int ndim = it.nz > 1 ? 3 : 2;
+            const int gi = (int)(std::find(kConns, kConns + 4, it.conn) - kConns);
+            const PartSpec *pp = nullptr;
+            for (auto &p : specs)
+                if (p.gi == gi) pp = &p;
+            wsk::Img im{};
+            im.g = make_geom(it.nx, it.ny, it.nz, shape_of(c, ndim));
+            im.pix0 = pix;
+            im.tile0[wsk::TK_WS] = next_ws[gi];
+            im.tile0[wsk::TK_WF] = next_wf[gi];
+            im.tile0[wsk::TK_GR] = 0;
+            im.tile0[wsk::TK_CH] = t2;
+            im.slot0 = 0;
+            im.grey = it.grad;
+            im.lab = it.out;
+            tab[i] = im;
+            int32_t nws = im.g.ntx * im.g.nty * im.g.ntz, nwf = wsk::wf_tiles(im.g, ndim),
+                    nch = wsk::wf_chunks(im.g.n);
+            for (int32_t k = 0; k < nws; ++k) mws[pp->ws0 + next_ws[gi] + k] = i;
+            for (int32_t k = 0; k < nwf; ++k) mwf[pp->wf0 + next_wf[gi] + k] = i;
+            for (int32_t k = 0; k < nch; ++k) mch[t2 + k] = i;
+            outs[i] = it.nregions;
+            pix += (im.g.n + 63) / 64 * 64;
+            next_ws[gi] += nws;
+            next_wf[gi] += nwf;
+            t2 += nch;
+        }
     }
-    int32_t pix = 0, t2 = 0;
     bool any_counts = false;
+    for (int i = 0; i < n_items; ++i) any_counts = any_counts || items[i].nregions;
+    const int32_t nchunks = (int32_t)tch;
+    const bool u16 = dtype == WS_U16;
+    void *cap_tab = nullptr;  // the tables a graph being captured reads (its own device copy)
+    auto enqueue = [&](Launch &lc) -> int {
+        int rc2;
+        char *d;
+        if (c->capturing) {
+            d = (char *)cap_tab;
+        } else {
+            // every buffer of the call before anything is launched
+            if ((rc2 = ensure_stage(c, total)) != WS_OK) return rc2;
+            if ((rc2 = ensure(c, c->tab, total, "batch tables")) != WS_OK) return rc2;
+            d = (char *)c->tab.p;
+        }
+        const wsk::Img *tab_dev = (const wsk::Img *)d;
+        std::vector<Part<wsk::ImgTable>> parts;
+        for (auto &sp : specs) {
+            Part<wsk::ImgTable> p;
+            p.conn = sp.conn;
+            p.ndim = sp.ndim;
+            p.shape = shape_of(c, sp.ndim);
+            p.ws0 = sp.ws0;
+            p.wf0 = sp.wf0;
+            p.nws = sp.nws;
+            p.nwf = sp.nwf;
+            p.ws = wsk::ImgTable{tab_dev, (const int32_t *)(d + off_ws) + sp.ws0};
+            p.wf = wsk::ImgTable{tab_dev, (const int32_t *)(d + off_wf) + sp.wf0};
+            parts.push_back(p);
+        }
+        WfBufs wb;
+        WsScratch ws;
+        if ((rc2 = prepare_watershed(c, parts, (size_t)arena, true, ws)) != WS_OK) return rc2;
+        if ((rc2 = wf_buffers(c, (size_t)arena, (int32_t)wf_all, nchunks, slab_cap_of(parts), NL, NL >= 2, wb)) !=
+            WS_OK)
+            return rc2;
+        if (!c->capturing) {
+            memcpy(c->stage, host.data(), total);
+            hipError_t e = hipMemcpyAsync(c->tab.p, c->stage, total, hipMemcpyHostToDevice, lc.stream);
+            if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+            if ((e = hipEventRecord(c->stage_ev, lc.stream)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
+            c->stage_pending = true;
+        }
+        wsk::ImgTable src_ch{tab_dev, (const int32_t *)(d + off_ch)};
+        if ((rc2 = run_watershed(c, lc, parts, u16, ws)) != WS_OK) return rc2;
+        wsk::Img none{};
+        return run_waterfall(c, lc, parts, src_ch, nchunks, u16, NL, (size_t)arena, wb, tab_dev, none, n_items,
+                             any_counts ? (int64_t *const *)(d + off_outs) : nullptr, nullptr);
+    };
+    Launch lc = make_launch(c, stream);
+    if (c->step3 != 0) return enqueue(lc);
+    // signature: the items as given, the grey type, NL
+    std::string sig = sig_of("bt", {(uint64_t)n_items, (uint64_t)dtype, (uint64_t)NL, (uint64_t)c->tile2,
+                                    (uint64_t)c->tile3});
     for (int i = 0; i < n_items; ++i) {
         const ws_item &it = items[i];
-        const int ndim = it.nz > 1 ? 3 : 2;
-        const int gi = (int)(std::find(kConns, kConns + 4, it.conn) - kConns);
-        const Part<wsk::ImgTable> *pp = nullptr;
-        for (auto &p : parts)
-            if (p.conn == it.conn) pp = &p;
-        wsk::Img im{};
-        im.g = make_geom(it.nx, it.ny, it.nz, ndim);
-        im.pix0 = pix;
-        im.tile0[wsk::TK_WS] = next_ws[gi];
-        im.tile0[wsk::TK_WF] = next_wf[gi];
-        im.tile0[wsk::TK_GR] = 0;
-        im.tile0[wsk::TK_CH] = t2;
-        im.slot0 = 0;
-        im.grey = it.grad;
-        im.lab = it.out;
-        tab[i] = im;
-        int32_t nws = im.g.ntx * im.g.nty * im.g.ntz, nwf = wsk::wf_tiles(im.g, ndim), nch = wsk::wf_chunks(im.g.n);
-        for (int32_t k = 0; k < nws; ++k) mws[pp->ws0 + next_ws[gi] + k] = i;
-        for (int32_t k = 0; k < nwf; ++k) mwf[pp->wf0 + next_wf[gi] + k] = i;
-        for (int32_t k = 0; k < nch; ++k) mch[t2 + k] = i;
-        outs[i] = it.nregions;
-        any_counts = any_counts || it.nregions;
-        pix += (im.g.n + 63) / 64 * 64;
-        next_ws[gi] += nws;
-        next_wf[gi] += nwf;
-        t2 += nch;
+        const uint64_t f[7] = {(uint64_t)(uintptr_t)it.grad, (uint64_t)it.nx, (uint64_t)it.ny, (uint64_t)it.nz,
+                               (uint64_t)it.conn, (uint64_t)(uintptr_t)it.out, (uint64_t)(uintptr_t)it.nregions};
+        sig.append((const char *)f, sizeof(f));
     }
-    hipError_t e = hipMemcpyAsync(c->tab.p, c->stage, total, hipMemcpyHostToDevice, lc.stream);
-    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
-    if ((e = hipEventRecord(c->stage_ev, lc.stream)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
-    c->stage_pending = true;
-    wsk::ImgTable src_ch{tab_dev, (const int32_t *)(d + off_ch)};
-    bool u16 = dtype == WS_U16;
-    if ((rc = run_watershed(c, lc, parts, u16, ws)) != WS_OK) return rc;
-    wsk::Img none{};
-    return run_waterfall(c, lc, parts, src_ch, nchunks, u16, NL, (size_t)arena, wb, tab_dev, none, n_items,
-                         any_counts ? (int64_t *const *)(d + off_outs) : nullptr, nullptr);
+    return run_graphed(
+        c, stream, sig,
+        [&](Launch &l) -> int {
+            int rc2 = enqueue(l);
+            if (rc2 == WS_OK && !c->capturing) note_sweeps(c, sig);
+            return rc2;
+        },
+        [&](void **owned, size_t *owned_n) -> int {
+            int v = prep_sweeps(c, sig);
+            if (v != WS_OK) return v;
+            if (c->budget && c->held + total > c->budget) return kRerun;
+            hipError_t e = hipMalloc(owned, total);
+            ++c->stats[5];
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                *owned = nullptr;
+                return kRerun;
+            }
+            *owned_n = total;
+            c->held += total;
+            if ((e = hipMemcpy(*owned, host.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
+                return hip_fail(c, e, "hipMemcpy");
+            cap_tab = *owned;
+            return WS_OK;
+        },
+        [&](const ws_ctx::Graph &gr) { return check_sweeps(c, gr, stream); });
 }
 
 int ws_timing_reset(ws_ctx *c) {

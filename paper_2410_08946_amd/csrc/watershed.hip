@@ -1,852 +1,14 @@
-// watershed.hip -- gfx950 kernels of the watershed transform (Alg. 1).
-//
-// Data on the device (int32 unless noted, per image):
-//   I  grey values (uint8/uint16), read only
-//   D  Step II distance field (arena-wide scratch): 0 for pixels with a lower
-//      neighbour (state 0) and for strict local minima (state 1); d >= 1 for a
-//      non-minimal plateau pixel at geodesic distance d from its plateau's
-//      lower border; INF for pixels of minimal plateaux (states 2/3 that Step
-//      II never resolves).
-//   L  labels / union-find parents (parent <= pixel, roots are self loops).
+// watershed.hip -- generic parts of the watershed transform (Alg. 1) on
+// gfx950: the step-level output kernel, fills, and the launchers that pick
+// the tile kernels of a tile shape (ws_tiles.h; each shape's kernels are
+// compiled in ws_shape.hip).
 //
 // Step II is computed as the unique fixpoint of
 //   D(p) = 1 + min{ D(q) : q in N(p), I(q) = I(p) }      (plateau pixels)
-// which both the synchronous sweeps of Section 3.3 and the balanced
-// block-asynchronous sweeps of Section 3.4 (Alg. 3) converge to. Tiles relax
-// to a local fixpoint in LDS with frozen halos; a tile re-runs only when a
-// neighbouring tile changed border distances next to it (tile "stamps" with
-// the faces that changed).
-//
-// Arrows (Eq. (1) for pixels with a lower neighbour; the equal neighbour at
-// distance d-1 with the smallest index for resolved plateau pixels) are then
-// contracted inside each tile by pointer jumping (Step III), minimal plateaux
-// are joined by union-find (Step IV), and every tile-local component is named
-// by its smallest pixel. Crossings between tiles go through a global
-// union-find that always hooks the larger root below the smaller, so every
-// basin ends with its smallest pixel index as root: the canonical label.
-//
-// Every tile kernel handles one tile per workgroup, of one image or of a batch
-// of images (through a tile -> image table); the same code serves both.
-#include <type_traits>
-
-#include "ws_device.h"
-#include "ws_kernels.h"
+// (see ws_tiles.h for the data on the device and the tile schedule).
+#include "ws_tiles.h"
 
 namespace wsk {
-
-// LDS cells of grey values: 16-bit for uint8 images (out-of-image sentinel
-// 0x100, above every uint8 value), int32 for uint16 images (SENT, above every
-// uint16 value). Smaller cells let more 3D tiles share a CU's LDS.
-template <typename T> struct GreyCell { using type = int; };
-template <> struct GreyCell<uint8_t> { using type = uint16_t; };
-template <typename GC> __host__ __device__ constexpr int sent_of() { return sizeof(GC) == 2 ? 0x100 : SENT; }
-
-// Loads grey values of the tile plus a ring of width R into LDS; cells
-// outside the image get the sentinel.
-template <int NDIM, int R, typename T, typename GC>
-__device__ __forceinline__ void load_grey(const Geom &g, const T *__restrict__ I, GC *sI, int ox, int oy, int oz) {
-    using S = Lds<NDIM, R>;
-    load_box<S::SX, S::SY, S::SZ, T, GC>(g, ox - R, oy - R, oz - S::RZ, I, sI, (GC)sent_of<GC>());
-}
-
-// Loads D of the tile plus a ring of width 1; cells outside the image get INF.
-template <int NDIM>
-__device__ __forceinline__ void load_dist(const Geom &g, const int32_t *__restrict__ D, int *sD, int ox, int oy, int oz) {
-    using S = Lds<NDIM, 1>;
-    load_box<S::SX, S::SY, S::SZ, int32_t, int>(g, ox - 1, oy - 1, oz - S::RZ, D, sD, INF);
-}
-
-// Grey values and D of the tile plus a ring of width 1 in one batch of loads
-// (one wait for both arrays instead of one each); cells outside the image get
-// SENT and INF.
-template <int NDIM, typename T, typename GC>
-__device__ __forceinline__ void load_grey_dist(const Geom &g, const T *__restrict__ I, const int32_t *__restrict__ D,
-                                               GC *sI, int *sD, int ox, int oy, int oz) {
-    using S = Lds<NDIM, 1>;
-    constexpr int PER = (S::CELLS + NTHREADS - 1) / NTHREADS;
-    int32_t idx[PER];
-    uint32_t okm = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        int c = threadIdx.x + j * NTHREADS;
-        int cx = c % S::SX, cy = (c / S::SX) % S::SY, cz = c / (S::SX * S::SY);
-        int x = ox - 1 + cx, y = oy - 1 + cy, z = oz - S::RZ + cz;
-        bool ok = c < S::CELLS && in_image(g, x, y, z);
-        okm |= (ok ? 1u : 0u) << j;
-        idx[j] = ok ? x + g.nx * (y + g.ny * z) : 0;
-    }
-    T v[PER];
-    int32_t d[PER];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) v[j] = I[idx[j]];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) d[j] = D[idx[j]];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        int c = threadIdx.x + j * NTHREADS;
-        if (c < S::CELLS) {
-            bool ok = okm >> j & 1u;
-            sI[c] = ok ? (GC)v[j] : (GC)sent_of<GC>();
-            sD[c] = ok ? d[j] : INF;
-        }
-    }
-}
-
-// Unresolved distance in an LDS distance cell: INF in int32 cells; 0xffff in
-// the 16-bit cells of the initial tile pass, whose finite distances never
-// exceed the tile's pixel count (its ring holds 0 or unresolved only).
-template <typename DC> __device__ __forceinline__ constexpr int dinf_of() { return sizeof(DC) == 2 ? 0xffff : INF; }
-
-// Smallest of d and 1 + the distance of every equal-grey neighbour of LDS
-// cell s, branch-free: in unsigned arithmetic an unresolved neighbour
-// (INF + 1 or 0xffff + 1) lands above every finite candidate and above d.
-template <int CONN, class S, typename GC, typename DC>
-__device__ __forceinline__ int relax_best(const GC *sI, const DC *sD, int s, int v, int d) {
-    uint32_t best = (uint32_t)d;
-#pragma unroll
-    for (int k = 0; k < CONN; ++k) {
-        const int o = s + S::template off<CONN>(k);
-        const uint32_t c = (uint32_t)sD[o] + 1u;
-        best = ((int)sI[o] == v && c < best) ? c : best;
-    }
-    return (int)best;
-}
-
-// Relaxes the plateau distances of the tile's pixels to a local fixpoint
-// (ring cells frozen). Returns after an iteration in which no thread changed
-// anything. Gauss-Seidel order inside LDS; any order reaches the same fixpoint
-// because distances only decrease and every value stays an upper bound.
-template <int NDIM, int CONN, int R, typename GC, typename DC>
-__device__ __forceinline__ void relax_tile(const GC *sI, DC *sD) {
-    using TS = TileShape<NDIM>;
-    using S = Lds<NDIM, R>;
-    constexpr int PIX = TS::X * TS::Y * TS::Z;
-    for (;;) {
-        int changed = 0;
-        for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
-            int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-            int s = S::at(x, y, z);
-            int d = sD[s];
-            if (d == 0) continue;          // fixed (lower neighbour / minimum) or
-            int v = sI[s];                 // out of image (d == INF, v == sentinel)
-            if (v == sent_of<GC>()) continue;
-            const int best = relax_best<CONN, S>(sI, sD, s, v, d);
-            if (best < d) { sD[s] = (DC)best; changed = 1; }
-        }
-        if (!__syncthreads_or(changed)) break;
-    }
-}
-
-template <int NDIM>
-__device__ __forceinline__ bool on_tile_border(int x, int y, int z) {
-    using TS = TileShape<NDIM>;
-    bool b = x == 0 || x == TS::X - 1 || y == 0 || y == TS::Y - 1;
-    if (NDIM == 3) b = b || z == 0 || z == TS::Z - 1;
-    return b;
-}
-
-// Faces of the tile a pixel lies on: bit 0 / 1 the low / high x face, 2 / 3
-// y, 4 / 5 z.
-template <int NDIM>
-__device__ __forceinline__ uint32_t face_bits(int x, int y, int z) {
-    using TS = TileShape<NDIM>;
-    uint32_t b = (x == 0 ? 1u : 0u) | (x == TS::X - 1 ? 2u : 0u) | (y == 0 ? 4u : 0u) | (y == TS::Y - 1 ? 8u : 0u);
-    if (NDIM == 3) b |= (z == 0 ? 16u : 0u) | (z == TS::Z - 1 ? 32u : 0u);
-    return b;
-}
-
-// Faces across which a border pixel's new distance d can shorten a neighbour's:
-// for every neighbour q of the pixel (LDS cell sc) outside the tile, with the
-// same grey value and a ring distance above d + 1 (the ring holds upper
-// bounds: distances only decrease), the faces that step crosses. A tile whose
-// neighbours report no such face cannot change in the next sweep.
-template <int NDIM, int CONN, int R, typename GC, typename DC>
-__device__ __forceinline__ uint32_t cross_faces(const GC *sI, const DC *sD, int sc, int x, int y, int z, int d) {
-    using TS = TileShape<NDIM>;
-    using S = Lds<NDIM, R>;
-    const int v = sI[sc];
-    uint32_t b = 0;
-#pragma unroll
-    for (int k = 0; k < CONN; ++k) {
-        const int dx = nb_dx<CONN>(k), dy = nb_dy<CONN>(k), dz = nb_dz<CONN>(k);
-        const int xx = x + dx, yy = y + dy, zz = z + dz;
-        const bool out = xx < 0 || xx >= TS::X || yy < 0 || yy >= TS::Y || zz < 0 || zz >= TS::Z;
-        if (!out) continue;
-        const int o = sc + S::template off<CONN>(k);
-        if ((int)sI[o] != v || sD[o] <= d + 1) continue;  // d + 1 cannot overflow: d < INF here
-        b |= (xx < 0 ? 1u : 0u) | (xx >= TS::X ? 2u : 0u) | (yy < 0 ? 4u : 0u) | (yy >= TS::Y ? 8u : 0u) |
-             (zz < 0 ? 16u : 0u) | (zz >= TS::Z ? 32u : 0u);
-    }
-    return b;
-}
-
-template <int NDIM>
-__device__ __forceinline__ void tile_pixel(int i, int &x, int &y, int &z) {
-    using TS = TileShape<NDIM>;
-    x = i % TS::X;
-    y = (i / TS::X) % TS::Y;
-    z = i / (TS::X * TS::Y);
-}
-
-template <int NDIM>
-__device__ __forceinline__ void ws_tile(const Geom &g, int lt, int &ox, int &oy, int &oz) {
-    using TS = TileShape<NDIM>;
-    tile_xyz<TS::X, TS::Y, TS::Z>(g, lt, ox, oy, oz);
-}
-
-// Step II relaxes only the pixels whose distance can still change: the
-// unresolved plateau pixels of a tile are compacted once into an LDS list (in
-// index order), and every relaxation pass visits the list instead of the whole
-// tile. Plateau pixels are a few per cent of a tile on natural gradients; a
-// tile with more than LCAP of them relaxes the whole tile instead.
-constexpr int LCAP = NTHREADS;  // one list entry per thread
-
-// Tile pixels i in the image and with (sweep ? D != 0 : D == INF) into lst, in
-// index order; returns their number (entries beyond LCAP are not stored).
-template <int NDIM, int R, typename GC, typename DC>
-__device__ __forceinline__ int build_list(const GC *sI, const DC *sD, unsigned short *lst, bool sweep) {
-    using TS = TileShape<NDIM>;
-    using S = Lds<NDIM, R>;
-    constexpr int PIX = TS::X * TS::Y * TS::Z;
-    constexpr int PER = PIX / NTHREADS;
-    static_assert(PIX % NTHREADS == 0 && PER <= 32, "pixels per thread fit one mask");
-    uint32_t m = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        int x, y, z;
-        tile_pixel<NDIM>(threadIdx.x + j * NTHREADS, x, y, z);
-        int sc = S::at(x, y, z), d = sD[sc];
-        bool take = (int)sI[sc] != sent_of<GC>() && (sweep ? d != 0 : d == dinf_of<DC>());
-        m |= (take ? 1u : 0u) << j;
-    }
-    int excl;
-    const int total = block_scan_excl(__popc(m), excl);
-    if (total <= LCAP) {
-#pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (m >> j & 1u) lst[excl++] = (unsigned short)(threadIdx.x + j * NTHREADS);
-    }
-    __syncthreads();
-    return total;
-}
-
-// relax_tile restricted to the n <= LCAP listed pixels (entry threadIdx.x).
-template <int NDIM, int CONN, int R, typename GC, typename DC>
-__device__ __forceinline__ void relax_list(const GC *sI, DC *sD, const unsigned short *lst, int n) {
-    using S = Lds<NDIM, R>;
-    int sc = -1, v = 0;
-    if ((int)threadIdx.x < n) {
-        int x, y, z;
-        tile_pixel<NDIM>(lst[threadIdx.x], x, y, z);
-        sc = S::at(x, y, z);
-        v = sI[sc];
-    }
-    for (;;) {
-        int changed = 0;
-        if (sc >= 0) {
-            const int d = sD[sc], best = relax_best<CONN, S>(sI, sD, sc, v, d);
-            if (best < d) {
-                sD[sc] = (DC)best;
-                changed = 1;
-            }
-        }
-        if (!__syncthreads_or(changed)) break;
-    }
-}
-
-// Stamps are double-buffered by sweep parity: stamp[(s & 1) * n + t] holds
-// the last sweep of parity s & 1 in which tile t changed distances that a
-// neighbour can use, stamp[(2 + (s & 1)) * n + t] the faces concerned. Sweep s
-// reads only the buffers of sweep s - 1, which no tile writes during sweep s
-// (with one buffer, a neighbour that re-stamped earlier in the same sweep hid
-// its previous sweep's faces from the tiles next to them).
-__device__ __forceinline__ int32_t *stamp_of(int32_t *stamp, int32_t n, int32_t s) { return stamp + (size_t)(s & 1) * n; }
-__device__ __forceinline__ int32_t *faces_of(int32_t *stamp, int32_t n, int32_t s) {
-    return stamp + (size_t)(2 + (s & 1)) * n;
-}
-
-// Tile t changed border distances in sweep s: record s and the faces.
-__device__ __forceinline__ void stamp_tile(int *smk, int32_t *stamp, int32_t n, int32_t *changed, int t, int32_t s,
-                                           uint32_t faces) {
-    if (faces) atomicOr(smk, (int)faces);
-    __syncthreads();
-    if (threadIdx.x == 0 && *smk) {
-        stamp_of(stamp, n, s)[t] = s;
-        faces_of(stamp, n, s)[t] = *smk;
-        atomicAdd(changed, 1);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Step I + first Step II pass: initial distances of the tile and its ring
-// (0 = has a lower neighbour or no equal one, INF = plateau pixel), then a
-// local fixpoint. Stamps the tile with sweep 0, and the faces concerned, when
-// a border pixel obtained a finite distance its neighbours could not have
-// known.
-// ---------------------------------------------------------------------------
-template <int NDIM, int CONN, typename T, class Src>
-__global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, int32_t *__restrict__ Darena,
-                                                      int32_t *__restrict__ stamp, int32_t *__restrict__ changed) {
-    using TS = TileShape<NDIM>;
-    using S2 = Lds<NDIM, 2>;
-    using S1 = Lds<NDIM, 1>;
-    constexpr int PIX = TS::X * TS::Y * TS::Z;
-    using GC = typename GreyCell<T>::type;
-    // Volumes keep 16-bit distance cells (the finite distances of the tile
-    // pass stay below the tile's pixel count) to fit more workgroups per CU;
-    // 2D tiles already fit eight with int32 cells, and their 16-bit LDS
-    // accesses measured slower on plateau-heavy tiles.
-    using DC = typename std::conditional<NDIM == 3, uint16_t, int>::type;
-    static_assert(PIX < 0xffff, "16-bit distance cells");
-    __shared__ GC sI[S2::CELLS];
-    __shared__ DC sD[S2::CELLS];
-    __shared__ unsigned short lst[LCAP];
-    __shared__ int smk;
-    {
-        if ((int)blockIdx.x >= ntiles) return;
-        const int t = xcd_tile(blockIdx.x, ntiles);
-        Img im;
-        int lt;
-        fetch(src, t, TK_WS, im, lt);
-        const Geom &g = im.g;
-        int32_t *D = Darena + im.pix0;
-        int ox, oy, oz;
-        ws_tile<NDIM>(g, lt, ox, oy, oz);
-        if (threadIdx.x == 0) smk = 0;
-        load_grey<NDIM, 2, T>(g, (const T *)im.grey, sI, ox, oy, oz);
-        __syncthreads();
-        // Initial distances on the tile plus a ring of width 1 (Step I state test).
-        for (int c = threadIdx.x; c < S1::CELLS; c += NTHREADS) {
-            int cx = c % S1::SX, cy = (c / S1::SX) % S1::SY, cz = c / (S1::SX * S1::SY);
-            int s = S2::at(cx - 1, cy - 1, cz - S1::RZ);
-            int v = sI[s];
-            int d = dinf_of<DC>();
-            if (v != sent_of<GC>()) {
-                int m = sent_of<GC>();
-#pragma unroll
-                for (int k = 0; k < CONN; ++k) m = min(m, (int)sI[s + S2::template off<CONN>(k)]);
-                d = (m == v) ? dinf_of<DC>() : 0;
-            }
-            sD[s] = (DC)d;
-        }
-        __syncthreads();
-        const int n = build_list<NDIM, 2>(sI, sD, lst, false);
-        if (n <= LCAP) relax_list<NDIM, CONN, 2>(sI, sD, lst, n);
-        else relax_tile<NDIM, CONN, 2>(sI, sD);
-        uint32_t faces = 0;
-        for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
-            int x, y, z;
-            tile_pixel<NDIM>(i, x, y, z);
-            int gx = ox + x, gy = oy + y, gz = oz + z;
-            if (!in_image(g, gx, gy, gz)) continue;
-            const int sc = S2::at(x, y, z);
-            int d = sD[sc];
-            const bool fin = d != dinf_of<DC>();
-            D[gx + g.nx * (gy + g.ny * gz)] = fin ? d : INF;
-            if (d != 0 && fin && face_bits<NDIM>(x, y, z)) faces |= cross_faces<NDIM, CONN, 2>(sI, sD, sc, x, y, z, d);
-        }
-        stamp_tile(&smk, stamp, ntiles, changed, t, 0, faces);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Step II sweep s >= 1: tiles next to a tile that changed, in sweep s-1, the
-// distances on the face (4/6-connectivity) or anywhere on the border (8/26)
-// next to them reload their ring from global memory and relax again.
-// ---------------------------------------------------------------------------
-template <int NDIM, int CONN, typename T, class Src>
-__global__ __launch_bounds__(NTHREADS) void k_ws_sweep(Src src, int32_t ntiles, int32_t *__restrict__ Darena,
-                                                       int32_t *__restrict__ stamp, int32_t *__restrict__ changed,
-                                                       const int32_t *__restrict__ prev, int32_t s) {
-    using TS = TileShape<NDIM>;
-    using S = Lds<NDIM, 1>;
-    constexpr int PIX = TS::X * TS::Y * TS::Z;
-    constexpr int PER = (PIX + NTHREADS - 1) / NTHREADS;
-    constexpr bool FACES = CONN == 4 || CONN == 6;  // only face neighbours interact
-    using GC = typename GreyCell<T>::type;
-    __shared__ GC sI[S::CELLS];
-    __shared__ int sD[S::CELLS];
-    __shared__ unsigned short lst[LCAP];
-    __shared__ int smk;
-    {
-        // no tile changed in sweep s - 1 (its counter is final: the launches
-        // are ordered on the stream): nothing can change now
-        if ((int)blockIdx.x >= ntiles || *prev == 0) return;
-        const int t = xcd_tile(blockIdx.x, ntiles);
-        Img im;
-        int lt;
-        fetch(src, t, TK_WS, im, lt);
-        const Geom &g = im.g;
-        int tx = lt % g.ntx, ty = (lt / g.ntx) % g.nty, tz = lt / (g.ntx * g.nty);
-        int active = 0;
-        {
-            int j = threadIdx.x;  // one neighbouring tile per thread
-            if (j < 27) {
-                int dx = j % 3 - 1, dy = (j / 3) % 3 - 1, dz = j / 9 - 1;
-                int ux = tx + dx, uy = ty + dy, uz = tz + dz;
-                bool face = (dx != 0) + (dy != 0) + (dz != 0) == 1;
-                bool used = (NDIM == 3 || dz == 0) && (dx != 0 || dy != 0 || dz != 0) && (!FACES || face);
-                if (used && ux >= 0 && ux < g.ntx && uy >= 0 && uy < g.nty && uz >= 0 && uz < g.ntz) {
-                    int32_t u = im.tile0[TK_WS] + ux + g.ntx * (uy + g.nty * uz);
-                    if (stamp_of(stamp, ntiles, s - 1)[u] == s - 1) {
-                        // the neighbour's face towards this tile
-                        uint32_t need = !FACES ? 63u
-                                        : dx > 0 ? 1u : dx < 0 ? 2u : dy > 0 ? 4u : dy < 0 ? 8u : dz > 0 ? 16u : 32u;
-                        active = ((uint32_t)faces_of(stamp, ntiles, s - 1)[u] & need) != 0;
-                    }
-                }
-            }
-        }
-        if (!__syncthreads_or(active)) return;
-        if (threadIdx.x == 0) smk = 0;
-        int32_t *D = Darena + im.pix0;
-        int ox = tx * TS::X, oy = ty * TS::Y, oz = tz * TS::Z;
-        load_grey_dist<NDIM, T>(g, (const T *)im.grey, D, sI, sD, ox, oy, oz);
-        __syncthreads();
-        const int n = build_list<NDIM, 1>(sI, sD, lst, true);
-        uint32_t faces = 0;
-        if (n <= LCAP) {
-            int x = 0, y = 0, z = 0, sc = -1, before = 0;
-            if ((int)threadIdx.x < n) {
-                tile_pixel<NDIM>(lst[threadIdx.x], x, y, z);
-                sc = S::at(x, y, z);
-                before = sD[sc];
-            }
-            relax_list<NDIM, CONN, 1>(sI, sD, lst, n);
-            if (sc >= 0) {
-                int d = sD[sc];
-                if (d != before) {
-                    D[(ox + x) + g.nx * ((oy + y) + g.ny * (oz + z))] = d;  // listed pixels are in the image
-                    if (face_bits<NDIM>(x, y, z)) faces |= cross_faces<NDIM, CONN, 1>(sI, sD, sc, x, y, z, d);
-                }
-            }
-        } else {
-            int before[PER];
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                int i = threadIdx.x + j * NTHREADS;
-                before[j] = INF;
-                if (i < PIX) {
-                    int x, y, z;
-                    tile_pixel<NDIM>(i, x, y, z);
-                    before[j] = sD[S::at(x, y, z)];
-                }
-            }
-            relax_tile<NDIM, CONN, 1>(sI, sD);
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                int i = threadIdx.x + j * NTHREADS;
-                if (i >= PIX) continue;
-                int x, y, z;
-                tile_pixel<NDIM>(i, x, y, z);
-                int gx = ox + x, gy = oy + y, gz = oz + z;
-                if (!in_image(g, gx, gy, gz)) continue;
-                const int sc = S::at(x, y, z);
-                int d = sD[sc];
-                if (d != before[j]) {
-                    D[gx + g.nx * (gy + g.ny * gz)] = d;
-                    if (face_bits<NDIM>(x, y, z)) faces |= cross_faces<NDIM, CONN, 1>(sI, sD, sc, x, y, z, d);
-                }
-            }
-        }
-        stamp_tile(&smk, stamp, ntiles, changed, t, s, faces);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Arrow of one pixel from LDS (ring width 1). Returns the neighbour index k
-// the pixel points to, -1 for a root (local minimum), -2 for a minimal
-// plateau pixel (joined with its equal neighbours instead).
-// ---------------------------------------------------------------------------
-template <int NDIM, int CONN, typename GC>
-__device__ __forceinline__ int lds_arrow(const GC *sI, const int *sD, int s) {
-    using S = Lds<NDIM, 1>;
-    int v = sI[s], d = sD[s];
-    if (d == INF) return -2;
-    if (d == 0) {
-        int m = sent_of<GC>(), kq = -1;
-#pragma unroll
-        for (int k = 0; k < CONN; ++k) {
-            int w = sI[s + S::template off<CONN>(k)];  // promoted to int
-            if (w <= m) { m = w; kq = k; }     // Eq. (1): last of the lowest
-        }
-        return (m < v) ? kq : -1;
-    }
-#pragma unroll
-    for (int k = 0; k < CONN; ++k) {           // first (smallest index) equal
-        int o = s + S::template off<CONN>(k);  // neighbour one step closer
-        if (sI[o] == v && sD[o] == d - 1) return k;
-    }
-    return -1;  // unreachable for a converged distance field
-}
-
-// ---------------------------------------------------------------------------
-// Border cells of a tile, enumerated face by face: NB(2D) = 2X + 2(Y-2),
-// NB(3D) = 2XY + (Z-2)(2X + 2(Y-2)). border_cell maps b -> (x, y, z) and
-// border_index is its inverse for cells on the border.
-// ---------------------------------------------------------------------------
-template <int NDIM> struct Border {
-    using TS = TileShape<NDIM>;
-    static constexpr int RING = 2 * TS::X + 2 * (TS::Y - 2);
-    static constexpr int FACE = TS::X * TS::Y;
-    static constexpr int NB = NDIM == 2 ? RING : 2 * FACE + (TS::Z - 2) * RING;
-};
-
-template <int NDIM>
-__device__ __forceinline__ void border_cell(int b, int &x, int &y, int &z) {
-    using TS = TileShape<NDIM>;
-    using B = Border<NDIM>;
-    z = 0;
-    if (NDIM == 3) {
-        if (b < 2 * B::FACE) {
-            x = b % TS::X;
-            y = (b / TS::X) % TS::Y;
-            z = b < B::FACE ? 0 : TS::Z - 1;
-            return;
-        }
-        b -= 2 * B::FACE;
-        z = 1 + b / B::RING;
-        b %= B::RING;
-    }
-    if (b < 2 * TS::X) {
-        x = b % TS::X;
-        y = b < TS::X ? 0 : TS::Y - 1;
-        return;
-    }
-    b -= 2 * TS::X;
-    y = 1 + (b >> 1);
-    x = (b & 1) ? TS::X - 1 : 0;
-}
-
-template <int NDIM>
-__device__ __forceinline__ int border_index(int x, int y, int z) {
-    using TS = TileShape<NDIM>;
-    using B = Border<NDIM>;
-    int base = 0;
-    if (NDIM == 3) {
-        if (z == 0) return x + TS::X * y;
-        if (z == TS::Z - 1) return B::FACE + x + TS::X * y;
-        base = 2 * B::FACE + (z - 1) * B::RING;
-    }
-    if (y == 0) return base + x;
-    if (y == TS::Y - 1) return base + TS::X + x;
-    return base + 2 * TS::X + 2 * (y - 1) + (x == TS::X - 1 ? 1 : 0);
-}
-
-// ---------------------------------------------------------------------------
-// Tile-local labelling. Every pixel's arrow inside the tile is contracted by
-// pointer jumping (path reduction, Step III) to its terminal: a local minimum,
-// a minimal-plateau pixel, or an exit whose arrow leaves the tile. Minimal-
-// plateau pixels are then joined with their equal neighbours by union-find
-// (Step IV). Each tile-local component is named by its smallest pixel (LDS
-// atomicMin), written into L. For every border pixel the crossing it needs in
-// the global merge is recorded in rec: the target of an arrow that leaves the
-// tile, -2 for a minimal-plateau pixel with an equal neighbour outside the
-// tile, -1 otherwise.
-// ---------------------------------------------------------------------------
-template <int NDIM, int CONN, typename T, class Src>
-__global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, const int32_t *__restrict__ Darena,
-                                                       int32_t *__restrict__ rec) {
-    using TS = TileShape<NDIM>;
-    using S = Lds<NDIM, 1>;
-    constexpr int PIX = TS::X * TS::Y * TS::Z;
-    constexpr int PER = PIX / NTHREADS;
-    static_assert(PIX % NTHREADS == 0, "tile must be a multiple of the workgroup");
-    static_assert(S::CELLS >= PIX, "the parent array fits the distance array");
-    using GC = typename GreyCell<T>::type;
-    // two LDS arrays: grey values, and distances that become the tile's
-    // parent array once every arrow is known
-    __shared__ GC sI[S::CELLS];
-    __shared__ int sD[S::CELLS];
-    __shared__ int sany[3];
-    int *sP = sD;
-    {
-        if ((int)blockIdx.x >= ntiles) return;
-        const int t = xcd_tile(blockIdx.x, ntiles);
-        Img im;
-        int lt;
-        fetch(src, t, TK_WS, im, lt);
-        const Geom &g = im.g;
-        int32_t *L = im.lab;
-        int ox, oy, oz;
-        ws_tile<NDIM>(g, lt, ox, oy, oz);
-        if (threadIdx.x < 3) sany[threadIdx.x] = 0;
-        load_grey_dist<NDIM, T>(g, (const T *)im.grey, Darena + im.pix0, sI, sD, ox, oy, oz);
-        __syncthreads();
-        uint32_t minzone = 0, inimg = 0;
-        int tos[PER];
-        int32_t *trec = rec + (size_t)t * Border<NDIM>::NB;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            int i = threadIdx.x + j * NTHREADS;
-            int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-            int gx = ox + x, gy = oy + y, gz = oz + z;
-            int to = i;
-            if (in_image(g, gx, gy, gz)) {
-                inimg |= 1u << j;
-                int s = S::at(x, y, z);
-                int k = lds_arrow<NDIM, CONN>(sI, sD, s);
-                int code = -1;
-                if (k >= 0) {
-                    int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
-                    if (xx >= 0 && xx < TS::X && yy >= 0 && yy < TS::Y && zz >= 0 && zz < TS::Z)
-                        to = xx + TS::X * (yy + TS::Y * zz);
-                    else
-                        code = (gx + nb_dx<CONN>(k)) + g.nx * ((gy + nb_dy<CONN>(k)) + g.ny * (gz + nb_dz<CONN>(k)));
-                } else if (k == -2) {
-                    minzone |= 1u << j;
-                    int v = sI[s];
-#pragma unroll
-                    for (int k2 = CONN / 2; k2 < CONN; ++k2) {  // neighbours after p
-                        int xx = x + nb_dx<CONN>(k2), yy = y + nb_dy<CONN>(k2), zz = z + nb_dz<CONN>(k2);
-                        bool inside = xx >= 0 && xx < TS::X && yy >= 0 && yy < TS::Y && zz >= 0 && zz < TS::Z;
-                        if (!inside && sI[s + S::template off<CONN>(k2)] == v) code = -2;
-                    }
-                }
-                if (on_tile_border<NDIM>(x, y, z)) trec[border_index<NDIM>(x, y, z)] = code;
-            }
-            tos[j] = to;
-        }
-        __syncthreads();  // every distance read: the array becomes the parents
-#pragma unroll
-        for (int j = 0; j < PER; ++j) sP[threadIdx.x + j * NTHREADS] = tos[j];
-        __syncthreads();
-        // pointer jumping to the in-tile terminals
-        BlockAny any{sany};
-        for (;;) {
-            int changed = 0;
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                int i = threadIdx.x + j * NTHREADS;
-                int p = sP[i];
-                int pp = sP[p];
-                if (pp != p) { sP[i] = pp; changed = 1; }
-            }
-            if (!any(changed)) break;
-        }
-        // minimal plateaux: join equal neighbours after p inside the tile
-        if (minzone) {
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                if (!(minzone >> j & 1u)) continue;
-                int i = threadIdx.x + j * NTHREADS;
-                int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-                int s = S::at(x, y, z);
-                int v = sI[s];
-#pragma unroll
-                for (int k2 = CONN / 2; k2 < CONN; ++k2) {
-                    int xx = x + nb_dx<CONN>(k2), yy = y + nb_dy<CONN>(k2), zz = z + nb_dz<CONN>(k2);
-                    if (xx < 0 || xx >= TS::X || yy < 0 || yy >= TS::Y || zz < 0 || zz >= TS::Z) continue;
-                    if (sI[s + S::template off<CONN>(k2)] == v) lunion(sP, i, xx + TS::X * (yy + TS::Y * zz));
-                }
-            }
-        }
-        __syncthreads();
-        // smallest pixel of every tile-local component, in the root's own
-        // parent entry once every root is known: a root holds its own index,
-        // and the root of an in-image pixel is itself in the image (arrows and
-        // plateau unions never reach a cell outside), so it is a candidate
-        int root[PER];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) root[j] = lfind(sP, threadIdx.x + j * NTHREADS);
-        __syncthreads();
-        int *cm = sP;
-#pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (inimg >> j & 1u) atomicMin(&cm[root[j]], (int)(threadIdx.x + j * NTHREADS));
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            if (!(inimg >> j & 1u)) continue;
-            int i = threadIdx.x + j * NTHREADS;
-            int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-            int r = cm[root[j]];
-            int rx = r % TS::X, ry = (r / TS::X) % TS::Y, rz = r / (TS::X * TS::Y);
-            L[(ox + x) + g.nx * ((oy + y) + g.ny * (oz + z))] = (ox + rx) + g.nx * ((oy + ry) + g.ny * (oz + rz));
-        }
-        __syncthreads();
-    }
-}
-
-// Union of p and r for the lanes with `want`, once per distinct pair of the
-// roots they had after the tile pass: border cells next to each other mostly
-// join the same two tile-local components, so a wave first elects one lane
-// per distinct (L[p], L[r]) pair (ballots, no memory traffic) and only those
-// lanes run the global union, all at once.
-__device__ __forceinline__ void wave_unique_union(int32_t *L, bool want, int32_t p, int32_t r) {
-    uint64_t pending = __ballot(want);
-    if (pending == 0) return;  // wave-uniform
-    int32_t a = -1, b = -1;
-    if (want) {
-        const int32_t lp = ld_par(L + p), lr = ld_par(L + r);
-        a = lp < lr ? lp : lr;
-        b = lp < lr ? lr : lp;
-    }
-    bool lead = false;
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int32_t la = __shfl(a, leader), lb = __shfl(b, leader);
-        const uint64_t same = __ballot(want && a == la && b == lb);
-        if (__lane_id() == leader) lead = true;
-        pending &= ~same;
-    }
-    if (lead && a != b) gunion(L, a, b);
-}
-
-// ---------------------------------------------------------------------------
-// Unions for every arrow / minimal-plateau adjacency that crosses a tile
-// border, driven by the records of k_ws_label. One thread per border cell.
-// ---------------------------------------------------------------------------
-template <int NDIM, int CONN, typename T, class Src>
-__global__ __launch_bounds__(NTHREADS) void k_ws_merge(Src src, int32_t ntiles, const int32_t *__restrict__ rec) {
-    using TS = TileShape<NDIM>;
-    constexpr int NB = Border<NDIM>::NB;
-    {
-        if ((int)blockIdx.x >= ntiles) return;
-        const int t = xcd_tile(blockIdx.x, ntiles);
-        Img im;
-        int lt;
-        fetch(src, t, TK_WS, im, lt);
-        const Geom &g = im.g;
-        const T *I = (const T *)im.grey;
-        int32_t *L = im.lab;
-        int ox, oy, oz;
-        ws_tile<NDIM>(g, lt, ox, oy, oz);
-        const int32_t *trec = rec + (size_t)t * NB;
-        // all of this thread's records are loaded in one batch (cells past
-        // the border count read record 0 and are skipped)
-        constexpr int MU = (NB + NTHREADS - 1) / NTHREADS;
-        int32_t codes[MU];
-#pragma unroll
-        for (int u = 0; u < MU; ++u) {
-            int b = threadIdx.x + u * NTHREADS;
-            codes[u] = trec[b < NB ? b : 0];
-        }
-        // candidate slot 0: the arrow that leaves the tile; slots 1 .. CONN/2:
-        // equal minimal-plateau neighbours after p outside the tile
-#pragma unroll
-        for (int u = 0; u < MU; ++u) {
-            const int b = threadIdx.x + u * NTHREADS;
-            int x = 0, y = 0, z = 0;
-            if (b < NB) border_cell<NDIM>(b, x, y, z);
-            const int gx = ox + x, gy = oy + y, gz = oz + z;
-            const int32_t code = b < NB && in_image(g, gx, gy, gz) ? codes[u] : -1;
-            const int32_t p = gx + g.nx * (gy + g.ny * gz);
-            const int v = code == -2 ? (int)I[p] : 0;
-#pragma unroll
-            for (int k = CONN / 2 - 1; k < CONN; ++k) {
-                int32_t r = -1;
-                if (k == CONN / 2 - 1) {
-                    r = code >= 0 ? code : -1;
-                } else if (code == -2) {
-                    int xx = gx + nb_dx<CONN>(k), yy = gy + nb_dy<CONN>(k), zz = gz + nb_dz<CONN>(k);
-                    bool outside = !(xx >= ox && xx < ox + TS::X && yy >= oy && yy < oy + TS::Y && zz >= oz &&
-                                     zz < oz + TS::Z);
-                    if (outside && in_image(g, xx, yy, zz)) {
-                        int32_t q = xx + g.nx * (yy + g.ny * zz);
-                        if ((int)I[q] == v) r = q;
-                    }
-                }
-                // volumes (47 % border cells, many per component pair) elect
-                // one lane per pair; 2D tiles measured faster without
-                if constexpr (NDIM == 3) wave_unique_union(L, r >= 0, p, r);
-                else if (r >= 0) gunion(L, p, r);
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Final Find of every pixel (APRUF form: each pixel follows its own path), per
-// watershed tile.
-// ---------------------------------------------------------------------------
-template <int NDIM, class Src>
-__global__ __launch_bounds__(NTHREADS) void k_ws_find(Src src, int32_t ntiles) {
-    using TS = TileShape<NDIM>;
-    constexpr int PIX = TS::X * TS::Y * TS::Z;
-    constexpr int PER = PIX / NTHREADS;
-    {
-        if ((int)blockIdx.x >= ntiles) return;
-        const int t = xcd_tile(blockIdx.x, ntiles);
-        Img im;
-        int lt;
-        fetch(src, t, TK_WS, im, lt);
-        const Geom &g = im.g;
-        int32_t *L = im.lab;
-        int ox, oy, oz;
-        ws_tile<NDIM>(g, lt, ox, oy, oz);
-        int32_t p[PER], r[PER];
-        bool ok[PER];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            int i = threadIdx.x + j * NTHREADS;
-            int x = ox + i % TS::X, y = oy + (i / TS::X) % TS::Y, z = oz + i / (TS::X * TS::Y);
-            ok[j] = in_image(g, x, y, z);
-            p[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
-        }
-        int32_t l0[PER];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) r[j] = l0[j] = L[p[j]];
-        // chase all PER paths together so their loads overlap
-        uint32_t live = 0;
-#pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (ok[j]) live |= 1u << j;
-        while (live) {
-            int32_t nxt[PER];
-#pragma unroll
-            for (int j = 0; j < PER; ++j) nxt[j] = (live >> j & 1u) ? L[r[j]] : r[j];
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                if (!(live >> j & 1u)) continue;
-                if (nxt[j] == r[j]) live &= ~(1u << j);
-                else r[j] = nxt[j];
-            }
-        }
-        // a pixel whose label already is its root keeps it (no store)
-#pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (ok[j] && r[j] != l0[j]) L[p[j]] = r[j];
-    }
-}
-
-// RR pointer jumps per synchronisation (PRUF form of Step III), per tile.
-template <int NDIM, class Src>
-__global__ __launch_bounds__(NTHREADS) void k_ws_jump(Src src, int32_t ntiles, int32_t rr,
-                                                      int32_t *__restrict__ changed) {
-    using TS = TileShape<NDIM>;
-    constexpr int PIX = TS::X * TS::Y * TS::Z;
-    {
-        if ((int)blockIdx.x >= ntiles) return;
-        const int t = xcd_tile(blockIdx.x, ntiles);
-        Img im;
-        int lt;
-        fetch(src, t, TK_WS, im, lt);
-        const Geom &g = im.g;
-        int32_t *L = im.lab;
-        int ox, oy, oz;
-        ws_tile<NDIM>(g, lt, ox, oy, oz);
-        int ch = 0;
-        for (int i = threadIdx.x; i < PIX; i += NTHREADS) {
-            int x = ox + i % TS::X, y = oy + (i / TS::X) % TS::Y, z = oz + i / (TS::X * TS::Y);
-            if (!in_image(g, x, y, z)) continue;
-            int32_t p = x + g.nx * (y + g.ny * z);
-            int32_t l = L[p];
-            bool moved = false;
-            for (int k = 0; k < rr; ++k) {
-                int32_t ll = ld_par(L + l);
-                if (ll == l) break;
-                l = ll;
-                moved = true;
-            }
-            if (moved) {
-                L[p] = l;
-                ch = 1;
-            }
-        }
-        if (__syncthreads_or(ch) && threadIdx.x == 0) atomicAdd(changed, 1);
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Arrow of one pixel from global memory (same rules as lds_arrow), used by
@@ -920,42 +82,8 @@ __global__ void k_fill2_i32(int32_t *a, int32_t na, int32_t va, int32_t *b, int3
 }
 
 // ---------------------------------------------------------------------------
-// Host-side launchers (instantiated per connectivity, grey type and source).
+// Host-side launchers.
 // ---------------------------------------------------------------------------
-template <int CONN, typename T, class Src>
-static int launch_ws_init_t(Launch &lc, const Src &src, const TileGrid &tg, int32_t *D, int32_t *stamp,
-                            int32_t *changed) {
-    constexpr int ND = ndim_of<CONN>();
-    return lc.run("ws_init", k_ws_init<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, D, stamp,
-                  changed);
-}
-template <int CONN, typename T, class Src>
-static int launch_ws_sweep_t(Launch &lc, const Src &src, const TileGrid &tg, int32_t *D, int32_t *stamp,
-                             int32_t *changed, const int32_t *prev, int32_t s) {
-    constexpr int ND = ndim_of<CONN>();
-    return lc.run("ws_sweep", k_ws_sweep<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, D, stamp,
-                  changed, prev, s);
-}
-template <int CONN, typename T, class Src>
-static int launch_ws_label_t(Launch &lc, const Src &src, const TileGrid &tg, const int32_t *D, int32_t *rec) {
-    constexpr int ND = ndim_of<CONN>();
-    return lc.run("ws_label", k_ws_label<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, D, rec);
-}
-template <int CONN, typename T, class Src>
-static int launch_ws_merge_t(Launch &lc, const Src &src, const TileGrid &tg, const int32_t *rec) {
-    constexpr int ND = ndim_of<CONN>();
-    return lc.run("ws_merge", k_ws_merge<ND, CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, rec);
-}
-template <int CONN, typename T, class Src>
-static int launch_ws_find_t(Launch &lc, const Src &src, const TileGrid &tg) {
-    constexpr int ND = ndim_of<CONN>();
-    return lc.run("ws_find", k_ws_find<ND, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles);
-}
-template <int CONN, typename T, class Src>
-static int launch_ws_jump_t(Launch &lc, const Src &src, const TileGrid &tg, int32_t rr, int32_t *changed) {
-    constexpr int ND = ndim_of<CONN>();
-    return lc.run("ws_jump", k_ws_jump<ND, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles, rr, changed);
-}
 template <int CONN, typename T>
 static int launch_ws_stages_t(Launch &lc, const Geom &g, const void *I, const int32_t *D, int32_t *bal, int32_t *arrow) {
     return lc.run("ws_stages", k_ws_stages<CONN, T>, dim3((g.n + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), g,
@@ -971,27 +99,43 @@ static int launch_ws_stages_t(Launch &lc, const Geom &g, const void *I, const in
     default: return -1;                                                                  \
     }
 
+// The launcher `FN` of the shape's WsShape.
+#define WS_BY_SHAPE(FN, shape, ...)                         \
+    switch (shape) {                                        \
+    case 2: return WsShape<2>::FN(__VA_ARGS__);             \
+    case 12: return WsShape<12>::FN(__VA_ARGS__);           \
+    case 22: return WsShape<22>::FN(__VA_ARGS__);           \
+    case 32: return WsShape<32>::FN(__VA_ARGS__);           \
+    case 3: return WsShape<3>::FN(__VA_ARGS__);             \
+    case 13: return WsShape<13>::FN(__VA_ARGS__);           \
+    case 23: return WsShape<23>::FN(__VA_ARGS__);           \
+    case 33: return WsShape<33>::FN(__VA_ARGS__);           \
+    default: return -1;                                     \
+    }
+
 #define WS_SRC_FUNCS(Src)                                                                                          \
-    int launch_ws_init(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,            \
+    int launch_ws_init(Launch &lc, const Src &src, const TileGrid &tg, int conn, int shape, bool u16, int32_t *D, \
                        int32_t *stamp, int32_t *changed) {                                                         \
-        WS_DISPATCH(launch_ws_init_t, conn, u16, lc, src, tg, D, stamp, changed)                                   \
+        WS_BY_SHAPE(init, shape, lc, src, tg, conn, u16, D, stamp, changed)                                        \
     }                                                                                                              \
-    int launch_ws_sweep(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,           \
-                        int32_t *stamp, int32_t *changed, const int32_t *prev, int32_t s) {                        \
-        WS_DISPATCH(launch_ws_sweep_t, conn, u16, lc, src, tg, D, stamp, changed, prev, s)                         \
+    int launch_ws_sweep(Launch &lc, const Src &src, const TileGrid &tg, int conn, int shape, bool u16,            \
+                        int32_t *D, int32_t *stamp, int32_t *changed, const int32_t *prev, int32_t s) {            \
+        WS_BY_SHAPE(sweep, shape, lc, src, tg, conn, u16, D, stamp, changed, prev, s)                              \
     }                                                                                                              \
-    int launch_ws_label(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *D,     \
-                        int32_t *rec) {                                                                            \
-        WS_DISPATCH(launch_ws_label_t, conn, u16, lc, src, tg, D, rec)                                             \
+    int launch_ws_label(Launch &lc, const Src &src, const TileGrid &tg, int conn, int shape, bool u16,            \
+                        const int32_t *D, int32_t *rec) {                                                          \
+        WS_BY_SHAPE(label, shape, lc, src, tg, conn, u16, D, rec)                                                  \
     }                                                                                                              \
-    int launch_ws_merge(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *rec) { \
-        WS_DISPATCH(launch_ws_merge_t, conn, u16, lc, src, tg, rec)                                                \
+    int launch_ws_merge(Launch &lc, const Src &src, const TileGrid &tg, int conn, int shape, bool u16,            \
+                        const int32_t *rec) {                                                                      \
+        WS_BY_SHAPE(merge, shape, lc, src, tg, conn, u16, rec)                                                     \
     }                                                                                                              \
-    int launch_ws_find(Launch &lc, const Src &src, const TileGrid &tg, int conn) {                                \
-        WS_DISPATCH(launch_ws_find_t, conn, false, lc, src, tg)                                                    \
+    int launch_ws_find(Launch &lc, const Src &src, const TileGrid &tg, int conn, int shape) {                     \
+        WS_BY_SHAPE(find, shape, lc, src, tg, conn)                                                                \
     }                                                                                                              \
-    int launch_ws_jump(Launch &lc, const Src &src, const TileGrid &tg, int conn, int32_t rr, int32_t *changed) {  \
-        WS_DISPATCH(launch_ws_jump_t, conn, false, lc, src, tg, rr, changed)                                       \
+    int launch_ws_jump(Launch &lc, const Src &src, const TileGrid &tg, int conn, int shape, int32_t rr,           \
+                       int32_t *changed) {                                                                         \
+        WS_BY_SHAPE(jump, shape, lc, src, tg, conn, rr, changed)                                                   \
     }
 
 WS_SRC_FUNCS(OneImg)
@@ -1010,6 +154,18 @@ int launch_fill2_i32(Launch &lc, int32_t *a, int32_t na, int32_t va, int32_t *b,
     if (n <= 0) return 0;
     return lc.run("fill", k_fill2_i32, dim3((uint32_t)((n + 255) / 256)), dim3(256), a, na, va, b, nb, vb);
 }
-int border_cells(int ndim) { return ndim == 3 ? Border<3>::NB : Border<2>::NB; }
+int border_cells(int shape) {
+    switch (shape) {
+    case 2: return Border<2>::NB;
+    case 12: return Border<12>::NB;
+    case 22: return Border<22>::NB;
+    case 32: return Border<32>::NB;
+    case 3: return Border<3>::NB;
+    case 13: return Border<13>::NB;
+    case 23: return Border<23>::NB;
+    case 33: return Border<33>::NB;
+    default: return 0;
+    }
+}
 
 }  // namespace wsk

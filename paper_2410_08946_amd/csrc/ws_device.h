@@ -141,18 +141,47 @@ template <int CONN> __host__ __device__ constexpr int nb_dy(int k) { return (nb_
 template <int CONN> __host__ __device__ constexpr int nb_dz(int k) { return nb_j<CONN>(k) / 9 - 1; }
 template <int CONN> __host__ __device__ constexpr int ndim_of() { return (CONN == 4 || CONN == 8) ? 2 : 3; }
 
-// Tile shapes (pixels per workgroup) and LDS layout with a ring of width R.
-template <int NDIM> struct TileShape;
-template <> struct TileShape<2> { static constexpr int X = 64, Y = 32, Z = 1; };
-template <> struct TileShape<3> { static constexpr int X = 32, Y = 8, Z = 8; };
+// Watershed tile shapes (pixels per workgroup), by shape id: the id's last
+// decimal digit is the dimensionality (2 and 3 are the defaults). LPER is the
+// number of plateau-list entries per thread in Step II (tiles with more
+// unresolved plateau pixels relax every pixel instead).
+template <int SH> struct TileShape;
+template <> struct TileShape<2> { static constexpr int X = 64, Y = 32, Z = 1, LPER = 1; };
+template <> struct TileShape<12> { static constexpr int X = 128, Y = 16, Z = 1, LPER = 1; };
+template <> struct TileShape<22> { static constexpr int X = 32, Y = 32, Z = 1, LPER = 1; };
+template <> struct TileShape<32> { static constexpr int X = 64, Y = 64, Z = 1, LPER = 2; };
+template <> struct TileShape<3> { static constexpr int X = 32, Y = 8, Z = 8, LPER = 1; };
+template <> struct TileShape<13> { static constexpr int X = 16, Y = 16, Z = 8, LPER = 1; };
+template <> struct TileShape<23> { static constexpr int X = 32, Y = 16, Z = 8, LPER = 2; };
+template <> struct TileShape<33> { static constexpr int X = 16, Y = 16, Z = 16, LPER = 2; };
+template <int SH> __host__ __device__ constexpr int shape_ndim() { return SH % 10; }
 
-template <int NDIM, int R>
+// The same table for host code: the sizes of shape `sh`, false for an
+// unknown id.
+inline bool tile_dims(int sh, int &X, int &Y, int &Z) {
+    switch (sh) {
+#define WS_TILE_CASE(S)     \
+    case S:                 \
+        X = TileShape<S>::X; \
+        Y = TileShape<S>::Y; \
+        Z = TileShape<S>::Z; \
+        return true;
+        WS_TILE_CASE(2) WS_TILE_CASE(12) WS_TILE_CASE(22) WS_TILE_CASE(32)
+        WS_TILE_CASE(3) WS_TILE_CASE(13) WS_TILE_CASE(23) WS_TILE_CASE(33)
+#undef WS_TILE_CASE
+    default:
+        return false;
+    }
+}
+
+// LDS layout of a tile of shape SH with a ring of width R.
+template <int SH, int R>
 struct Lds {
-    using T = TileShape<NDIM>;
+    using T = TileShape<SH>;
     static constexpr int SX = T::X + 2 * R;
     static constexpr int SY = T::Y + 2 * R;
-    static constexpr int SZ = NDIM == 3 ? T::Z + 2 * R : 1;
-    static constexpr int RZ = NDIM == 3 ? R : 0;
+    static constexpr int SZ = shape_ndim<SH>() == 3 ? T::Z + 2 * R : 1;
+    static constexpr int RZ = shape_ndim<SH>() == 3 ? R : 0;
     static constexpr int CELLS = SX * SY * SZ;
     __device__ static constexpr int at(int x, int y, int z) { return ((z + RZ) * SY + (y + R)) * SX + (x + R); }
     template <int CONN> __device__ static constexpr int off(int k) {

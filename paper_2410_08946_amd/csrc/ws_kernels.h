@@ -101,17 +101,49 @@ struct EdgeSlabs {
     }
 };
 
-// watershed.hip
+// Launchers of the watershed tile kernels of one tile shape (ws_tiles.h),
+// instantiated per shape id in ws_shape.hip; conn must have the shape's
+// dimensionality (-1 otherwise).
+template <int SH>
+struct WsShape {
+#define WS_SHAPE_SRC(Src)                                                                                        \
+    static int init(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,             \
+                    int32_t *stamp, int32_t *changed);                                                           \
+    static int sweep(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,            \
+                     int32_t *stamp, int32_t *changed, const int32_t *prev, int32_t s);                          \
+    static int label(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *D,      \
+                     int32_t *rec);                                                                              \
+    static int merge(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *rec);   \
+    static int find(Launch &lc, const Src &src, const TileGrid &tg, int conn);                                  \
+    static int jump(Launch &lc, const Src &src, const TileGrid &tg, int conn, int32_t rr, int32_t *changed);
+    WS_SHAPE_SRC(OneImg)
+    WS_SHAPE_SRC(ImgTable)
+#undef WS_SHAPE_SRC
+    static int border_cells();
+};
+extern template struct WsShape<2>;
+extern template struct WsShape<12>;
+extern template struct WsShape<22>;
+extern template struct WsShape<32>;
+extern template struct WsShape<3>;
+extern template struct WsShape<13>;
+extern template struct WsShape<23>;
+extern template struct WsShape<33>;
+
+// watershed.hip: the tile kernels of any shape id (-1 for an unknown shape or
+// a connectivity of the other dimensionality)
 #define WS_DECL_SRC(Src)                                                                                          \
-    int launch_ws_init(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,           \
+    int launch_ws_init(Launch &lc, const Src &src, const TileGrid &tg, int conn, int shape, bool u16, int32_t *D, \
                        int32_t *stamp, int32_t *changed);                                                         \
-    int launch_ws_sweep(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, int32_t *D,          \
-                        int32_t *stamp, int32_t *changed, const int32_t *prev, int32_t s);                       \
-    int launch_ws_label(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *D,    \
-                        int32_t *rec);                                                                            \
-    int launch_ws_merge(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const int32_t *rec); \
-    int launch_ws_find(Launch &lc, const Src &src, const TileGrid &tg, int conn);                                \
-    int launch_ws_jump(Launch &lc, const Src &src, const TileGrid &tg, int conn, int32_t rr, int32_t *changed);  \
+    int launch_ws_sweep(Launch &lc, const Src &src, const TileGrid &tg, int conn, int shape, bool u16,           \
+                        int32_t *D, int32_t *stamp, int32_t *changed, const int32_t *prev, int32_t s);           \
+    int launch_ws_label(Launch &lc, const Src &src, const TileGrid &tg, int conn, int shape, bool u16,           \
+                        const int32_t *D, int32_t *rec);                                                          \
+    int launch_ws_merge(Launch &lc, const Src &src, const TileGrid &tg, int conn, int shape, bool u16,           \
+                        const int32_t *rec);                                                                      \
+    int launch_ws_find(Launch &lc, const Src &src, const TileGrid &tg, int conn, int shape);                     \
+    int launch_ws_jump(Launch &lc, const Src &src, const TileGrid &tg, int conn, int shape, int32_t rr,          \
+                       int32_t *changed);                                                                         \
     int launch_wf_ids(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t bound, const WfIds &ids,           \
                       int32_t *scan_tmp, int32_t *nreg0, uint64_t *key, int32_t *par);                            \
     int launch_wf_pix(Launch &lc, const Src &src, const TileGrid &tg, int conn, bool u16, const WfIds &ids,      \
@@ -123,7 +155,7 @@ WS_DECL_SRC(OneImg)
 WS_DECL_SRC(ImgTable)
 #undef WS_DECL_SRC
 
-int border_cells(int ndim);
+int border_cells(int shape);   // border records per tile of a shape (0 for an unknown shape)
 int launch_ws_stages(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *bal,
                      int32_t *arrow);
 int launch_fill_i32(Launch &lc, int32_t *a, int32_t n, int32_t v);

@@ -293,4 +293,8 @@ def test_c2_slab_oracle(c2):
 def test_c2_full_oracle(c2):
     """The whole 928^3 volume: labels of the watershed and of all six layers,
     as the benchmark computes them, equal the oracle's element by element."""
-    _compare_with_oracle(c2["grad"], c2["out"], c2["nreg"], gen.CONFIGS["c2"]["conn"], "c2 full")
+    oracle.set_progress(True)
+    try:
+        _compare_with_oracle(c2["grad"], c2["out"], c2["nreg"], gen.CONFIGS["c2"]["conn"], "c2 full")
+    finally:
+        oracle.set_progress(False)

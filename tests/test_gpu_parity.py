@@ -617,6 +617,92 @@ def test_graph_replay_matches_direct():
         dctx.close()
 
 
+def _long_plateau(ny, nx, dtype=np.uint8):
+    """One non-minimal plateau covering the image, drained through its corner
+    pixel: Step II needs about one sweep per tile along the longest geodesic."""
+    g = np.full((ny, nx), 9, dtype=dtype)
+    g[0, 0] = 8
+    return g
+
+
+def test_graph_watershed_sweep_fallback():
+    """ws_watershed under the graph option: replays of the captured call (a
+    fixed number of Step II sweeps) equal the direct path; when the buffer's
+    new contents need more sweeps than the graph holds, the call runs directly
+    and the next identical call is captured again."""
+    import torch
+
+    import paper_2410_08946_amd as ws
+    gctx = ws.Context(0)
+    gctx.set_option("graph", 1)
+    ny, nx, conn = 257, 700, 8
+    grad = torch.empty((ny, nx), dtype=torch.uint8, device="cuda:0")
+    lab = torch.empty((ny, nx), dtype=torch.int32, device="cuda:0")
+    blob = oracle.gradient(gen.blobs2d(ny, nx, seed=11), 0.0, "u8")
+    flat = _long_plateau(ny, nx)
+    refs = {"blob": oracle.watershed(blob, conn), "flat": oracle.watershed(flat, conn)}
+    try:
+        for rep, name in enumerate(["blob"] * 4 + ["flat"] * 4 + ["blob", "flat"]):
+            grad.copy_(to_dev(blob if name == "blob" else flat))
+            gctx.watershed(grad, conn, out=lab)
+            got = to_host(lab)
+            st = gctx.stats()
+            say("  round", rep, name, "replays", st["graph_replays"], "sweeps", st["sweeps_launched"])
+            assert np.array_equal(got, refs[name]), "round %d (%s) differs from the oracle" % (rep, name)
+            float(grad.float().sum())  # eager work between replays
+            torch.cuda.synchronize()
+        assert gctx.stats()["graph_replays"] >= 4
+    finally:
+        gctx.close()
+
+
+def test_batch_graph_replay():
+    """ws_batch under the graph option (one graph launch per call once
+    captured): mixed 4/8-connected images whose contents change between calls,
+    one change needing more Step II sweeps than the graph holds; every call
+    equals the direct context's output, and the last one the oracle's."""
+    import torch
+
+    import paper_2410_08946_amd as ws
+    gctx, dctx = ws.Context(0), ws.Context(0)
+    gctx.set_option("graph", 1)
+    dev = "cuda:0"
+    shapes, conns, NL = [(200, 310), (130, 129), (257, 640)], [8, 4, 8], 4
+    blobs = [[oracle.gradient(gen.blobs2d(ny, nx, seed=100 * r + i), 0.0, "u8") for i, (ny, nx) in enumerate(shapes)]
+             for r in range(2)]
+    flat = _long_plateau(*shapes[2])
+    grads = [torch.empty(s, dtype=torch.uint8, device=dev) for s in shapes]
+    outs = {k: [torch.empty((NL,) + s, dtype=torch.int32, device=dev) for s in shapes] for k in "gd"}
+    nreg = {k: [torch.zeros(NL, dtype=torch.int64, device=dev) for _ in shapes] for k in "gd"}
+    try:
+        plan = [0, 1, 0, 1, "flat", "flat", "flat", 0]
+        for rep, what in enumerate(plan):
+            host = list(blobs[0 if what == "flat" else what])
+            if what == "flat":
+                host[2] = flat
+            for g, h in zip(grads, host):
+                g.copy_(to_dev(h))
+            gctx.batch(grads, conns, NL, outs=outs["g"], nregions=nreg["g"])
+            dctx.batch(grads, conns, NL, outs=outs["d"], nregions=nreg["d"])
+            torch.cuda.synchronize()
+            st = gctx.stats()
+            say("  batch round", rep, what, "replays", st["graph_replays"], "sweeps", st["sweeps_launched"])
+            for i in range(len(shapes)):
+                assert torch.equal(outs["g"][i], outs["d"][i]), "round %d image %d differs" % (rep, i)
+                assert torch.equal(nreg["g"][i], nreg["d"][i])
+            float(grads[0].float().sum())  # eager work between replays
+            torch.cuda.synchronize()
+        assert gctx.stats()["graph_replays"] >= 4
+        for i, h in enumerate(host):
+            lab = oracle.watershed(h, conns[i])
+            ref, refn = oracle.waterfall_g1(lab, h, conns[i], NL)
+            assert np.array_equal(to_host(outs["g"][i]), ref)
+            assert to_host(nreg["g"][i]).tolist() == refn.tolist()
+    finally:
+        gctx.close()
+        dctx.close()
+
+
 def check_recon(ctx, grad, conn, NL):
     import torch
     say("  recon", grad.shape, grad.dtype, "conn", conn, "NL", NL)
