@@ -914,20 +914,29 @@ __global__ __launch_bounds__(OUT_T) void k_wf_out_p(Src src_ch, int32_t nchunks,
     }
     int32_t V[NLM][OUT_RUNS][4];
     wf_gather(V[0], off, table_rsrc(tabs.t[0], tabs.bytes), need);  // layer 1, by region id
+    // layers >= 2 are gathered by the rank of the layer-1 root, once per
+    // change of that rank along the run (layer-1 regions are larger, so its
+    // runs are longer than the region id's)
+    uint32_t need_r = need;
     if constexpr (NLM >= 2) {
-        int32_t rk[OUT_RUNS][4];  // layers >= 2, by the rank of the layer-1 root
+        int32_t rk[OUT_RUNS][4];
         wf_gather(rk, off, table_rsrc(tabs.t[1], tabs.bytes), need);
+        wf_fill(rk, need);
+        need_r = 0;
 #pragma unroll
         for (int r = 0; r < OUT_RUNS; ++r)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) off[r][e] = (uint32_t)rk[r][e] * 4u;
+            for (int e = 0; e < 4; ++e) {
+                off[r][e] = (uint32_t)rk[r][e] * 4u;
+                if (e == 0 || rk[r][e] != rk[r][e - 1]) need_r |= 1u << (4 * r + e);
+            }
 #pragma unroll
-        for (int k = 2; k <= NLM; ++k) wf_gather(V[k - 1], off, table_rsrc(tabs.t[k], tabs.bytes), need);
+        for (int k = 2; k <= NLM; ++k) wf_gather(V[k - 1], off, table_rsrc(tabs.t[k], tabs.bytes), need_r);
     }
     int own[NLM];
 #pragma unroll
     for (int k = 1; k <= NLM; ++k) {
-        wf_fill(V[k - 1], need);
+        wf_fill(V[k - 1], k == 1 ? need : need_r);
         own[k - 1] = wf_emit(V[k - 1], p0, n, vec, im.lab + (size_t)k * (size_t)n);
     }
     if (__lane_id() == 0) {

@@ -6,9 +6,10 @@ then runs in the launch configuration the benchmark times. Two kinds of check:
 * oracle parity: the device's gradient bytes go to the host, where the CPU
   oracle computes the watershed and the NL - 1 waterfall levels, and every
   layer is compared element by element. The whole volume takes the oracle
-  about ten minutes of host time, so that comparison runs when
-  WS_FULLSIZE_ORACLE=1 is set; by default a 32-plane slab of the same
-  gradient (27.6 Mvoxel, several thousand tiles) is compared instead;
+  about four minutes of one host core (and some 30 GB of host memory), so
+  that comparison runs when WS_FULLSIZE_ORACLE=1 is set; by default a
+  32-plane slab of the same gradient (27.6 Mvoxel, several thousand tiles)
+  is compared instead;
 * at full size, with torch operations that share nothing with the library,
   the properties the paper's definitions fix at any size:
   * gradient: the float64 3D Sobel magnitude of the same float volume, quantised
@@ -288,7 +289,7 @@ def test_c2_slab_oracle(c2):
 
 
 @pytest.mark.skipif(os.environ.get("WS_FULLSIZE_ORACLE") != "1",
-                    reason="the full 928^3 oracle comparison takes about ten minutes of host time "
+                    reason="the full 928^3 oracle comparison takes about four minutes of host time "
                            "(set WS_FULLSIZE_ORACLE=1)")
 def test_c2_full_oracle(c2):
     """The whole 928^3 volume: labels of the watershed and of all six layers,
