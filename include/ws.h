@@ -126,6 +126,29 @@ int ws_watershed(ws_ctx *ctx, const void *grad, int dtype, int64_t nx, int64_t n
                  int conn, int32_t *labels, void *stream);
 
 /*
+ * ws_watershed for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, result and options as ws_watershed under the tile
+ * schedule, but its scratch (distances, tile stamps, counters, border
+ * records) lives in a fixed device area of WS_NOALLOC_SCRATCH_MIB MiB that
+ * the library holds on every device it runs on until the process ends; the
+ * call allocates nothing (no hipMalloc, hipFree or allocating library call),
+ * and it is never captured into a launch graph.
+ *   Limit: the image's scratch (4 bytes per pixel plus 16 bytes per tile plus
+ *   4 bytes per tile border cell) must fit the area: WS_EINVAL (nothing
+ *   launched) otherwise. At the default tile shapes that holds up to about
+ *   30 Mpx in 2D and 22 Mvoxel in 3D (4096 x 4096 and 256^3 fit).
+ *   Every call on one device shares that device's area and leaves its
+ *   contents behind (each call clears what it reads before use): calls that
+ *   overlap in time on one device, from any context or stream, race.
+ *   WS_EUNSUPPORTED for options "schedule" = 1 or "step4" = 1.
+ * Waits on `stream` like ws_watershed.
+ */
+#define WS_NOALLOC_SCRATCH_MIB 128
+int ws_watershed_noalloc(ws_ctx *ctx, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz,
+                         int conn, int32_t *labels, void *stream);
+
+/*
  * Hierarchical waterfall (Section 4 / Alg. 5 layer loop): NL layers.
  *   labels     int32[N] canonical watershed labels (layer 0); may alias out.
  *   grad       the grey values the watershed was computed from (read only).

@@ -31,6 +31,7 @@ SIGNATURES = {
     "ws_footprint_bytes": (ctypes.c_size_t, [_i64, _i64, _i64, _int, _int, _int]),
     "ws_gradient": (_int, [_ptr, _ptr, _i64, _i64, _i64, _f32, _int, _ptr, _ptr, _ptr]),
     "ws_watershed": (_int, [_ptr, _ptr, _int, _i64, _i64, _i64, _int, _ptr, _ptr]),
+    "ws_watershed_noalloc": (_int, [_ptr, _ptr, _int, _i64, _i64, _i64, _int, _ptr, _ptr]),
     "ws_waterfall": (_int, [_ptr, _ptr, _ptr, _int, _i64, _i64, _i64, _int, _int, _ptr, _ptr, _ptr]),
     "ws_waterfall_recon": (_int, [_ptr, _ptr, _ptr, _int, _i64, _i64, _i64, _int, _int, _ptr, _ptr, _ptr]),
     "ws_rag": (_int, [_ptr, _ptr, _ptr, _int, _i64, _i64, _i64, _int, _i64, _ptr, _ptr, _ptr, _ptr, _ptr]),
@@ -185,6 +186,17 @@ class Context:
             out = torch.empty(grad.shape, dtype=torch.int32, device=grad.device)
         self._check(self._lib.ws_watershed(self._h, _dev(grad, "gradient"), _grey_code(grad), nx, ny, nz, int(conn),
                                            _dev(out, "labels"), _stream(grad)))
+        return out
+
+    def watershed_noalloc(self, grad, conn: int, out):
+        """ws_watershed_noalloc: the watershed into the caller's `out` (int32,
+        the gradient's shape) using the library's fixed device scratch."""
+        import torch
+        nx, ny, nz = _dims(grad.shape)
+        if out.shape != grad.shape or out.dtype != torch.int32:
+            raise ValueError("out must be int32 with the gradient's shape")
+        self._check(self._lib.ws_watershed_noalloc(self._h, _dev(grad, "gradient"), _grey_code(grad), nx, ny, nz,
+                                                   int(conn), _dev(out, "labels"), _stream(grad)))
         return out
 
     def watershed_stages(self, grad, conn: int):

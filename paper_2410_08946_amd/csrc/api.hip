@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -30,6 +31,46 @@ struct Buf {
 };
 
 thread_local std::string g_noctx_error;
+
+}  // namespace
+
+// Fixed device scratch of ws_watershed_noalloc, one copy per device, held
+// until the process ends. Host code never uses this name as an address (on
+// the host it only stands for the symbol): kernels get the per-device address
+// that hipGetSymbolAddress returned (noalloc_scratch_of).
+constexpr size_t kNoAllocBytes = (size_t)WS_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
+std::string g_noalloc_why;   // why the last set-up failed
+
+// Looks up the address of `scratch` on `device`, which must be current; once
+// per device.
+int noalloc_setup(int device, std::string &why) {
+    if (device < 0 || device >= kMaxDevices) {
+        why = "device index above the fixed scratch table";
+        return WS_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return WS_OK;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return WS_EDEVICE;
+    }
+    g_noalloc_ptr[device] = ptr;
+    return WS_OK;
+}
+
+void *noalloc_scratch_of(int device) {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    return device >= 0 && device < kMaxDevices ? g_noalloc_ptr[device] : nullptr;
+}
 
 }  // namespace
 
@@ -805,6 +846,16 @@ int ws_create(ws_ctx **out, int device, size_t scratch_budget_bytes) {
         delete c;
         return fail(nullptr, WS_EDEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
     }
+    {
+        // the address of the fixed scratch of ws_watershed_noalloc on this
+        // device; a failure only disables that entry point (it reports why)
+        std::string why;
+        if (noalloc_setup(device, why) != WS_OK) {
+            (void)hipGetLastError();
+            std::lock_guard<std::mutex> lock(g_noalloc_mu);
+            g_noalloc_why = why;
+        }
+    }
     *out = c;
     return WS_OK;
 }
@@ -996,6 +1047,39 @@ int ws_watershed(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny,
         },
         [&](void **, size_t *) { return prep_sweeps(c, sig); },
         [&](const ws_ctx::Graph &gr) { return check_sweeps(c, gr, stream); });
+}
+
+int ws_watershed_noalloc(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz, int conn,
+                         int32_t *labels, void *stream) {
+    int rc = ws_validate_ws(c, grad, dtype, nx, ny, nz, conn, labels, "ws_watershed_noalloc");
+    if (rc) return rc;
+    if (c->schedule != 0)
+        return fail(c, WS_EUNSUPPORTED, "ws_watershed_noalloc: only the tile schedule (schedule = 0)");
+    if (c->step4 != 0) return fail(c, WS_EUNSUPPORTED, "ws_watershed_noalloc: step4 = 1 (PRW) needs schedule = 1");
+    const int shape = shape_of(c, nz > 1 ? 3 : 2);
+    wsk::OneImg src{single_img(nx, ny, nz, grad, labels, shape)};
+    const wsk::Geom &g = src.im.g;
+    auto parts = one_part(src, conn, shape);
+    // [distances | stamps | counters | border records], 256-byte aligned parts
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t oD = 0, oS = oD + up((size_t)g.n * 4), oC = oS + up((size_t)ws_tiles_of(parts) * 16),
+                 oR = oC + up((size_t)kCounterSlots * 4), need = oR + up(rec_ints(parts) * 4);
+    if (need > kNoAllocBytes)
+        return fail(c, WS_EINVAL, "ws_watershed_noalloc: this image needs " + std::to_string(need) +
+                                      " bytes of scratch, the fixed area holds " + std::to_string(kNoAllocBytes));
+    if ((rc = set_device(c))) return rc;
+    char *base = (char *)noalloc_scratch_of(c->device);
+    if (!base) {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        return fail(c, WS_EDEVICE, "ws_watershed_noalloc: no fixed scratch on this device: " + g_noalloc_why);
+    }
+    WsScratch ws;
+    ws.D = (int32_t *)(base + oD);
+    ws.stamp = (int32_t *)(base + oS);
+    ws.cnt = (int32_t *)(base + oC);
+    ws.rec = (int32_t *)(base + oR);
+    Launch lc = make_launch(c, stream);
+    return run_watershed(c, lc, parts, dtype == WS_U16, ws);
 }
 
 int ws_watershed_stages(ws_ctx *c, const void *grad, int dtype, int64_t nx, int64_t ny, int64_t nz, int conn,
