@@ -87,7 +87,9 @@ struct ws_ctx {
     Buf g0, g1, mag, gmax;                // gradient scratch
     Buf chunks, tilecnt;                  // region-id rank tables + scan scratch, per-tile counts
     Buf tab;                              // batch descriptor table + tile maps
-    int32_t *host_cnt = nullptr;          // pinned readback of counters
+    int32_t *host_cnt = nullptr;          // pinned readback of counters (kCounterSlots + 1 words;
+                                          // the last one is written by captured watershed graphs)
+    hipEvent_t sweep_ev = nullptr;        // recorded by captured watershed graphs after their sweeps
     void *stage = nullptr;                // pinned staging of batch tables
     size_t stage_n = 0;
     hipEvent_t stage_ev = nullptr;        // last upload from `stage`
@@ -282,6 +284,8 @@ int run_graphed(ws_ctx *c, void *stream, const std::string &sig, F &&enqueue, P 
         ws_ctx::Graph &g = c->graphs[gi];
         g.used = ++c->tick;
         ++c->stats[4];
+        // a watershed graph writes its last sweep's count here; -1 until it has
+        if (g.sweeps > 0) ((volatile int32_t *)c->host_cnt)[kCounterSlots] = -1;
         hipError_t e = hipGraphLaunch(g.exec, (hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
         int v = check(g);
@@ -456,6 +460,11 @@ int run_distances(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, bo
             for (auto &p : parts)
                 WS_TRY(wsk::launch_ws_sweep(lc, p.ws, full_grid(p.nws), p.conn, p.shape, u16, D, stamp + 4 * (size_t)p.ws0,
                                             cnt + s, cnt + (s - 1), s));
+        // the last sweep's count to pinned host memory, then an event: the
+        // call waits for that much of the graph only, the rest keeps running
+        hipError_t e = hipMemcpyAsync(c->host_cnt + kCounterSlots, cnt + K, 4, hipMemcpyDeviceToHost, lc.stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+        if ((e = hipEventRecord(c->sweep_ev, lc.stream)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
         c->stats[0] = K + 1;
         c->stats[3] = nt;
         return WS_OK;
@@ -552,20 +561,32 @@ void note_sweeps(ws_ctx *c, const std::string &sig) {
 int prep_sweeps(ws_ctx *c, const std::string &sig) {
     auto it = c->graph_sweeps.find(sig);
     if (it == c->graph_sweeps.end() || it->second < 1 || it->second >= kCounterSlots) return kRerun;
+    if (!c->sweep_ev) {
+        hipError_t e = hipEventCreateWithFlags(&c->sweep_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            c->sweep_ev = nullptr;
+            return kRerun;
+        }
+    }
     c->cap_sweeps = it->second;
     return WS_OK;
 }
 
-// After a launch of a watershed graph: its last sweep changed nothing, so
-// Step II had converged (one read-back and wait), or kRerun.
+// After a launch of a watershed graph: waits until the graph's sweeps are
+// done (the rest of the graph keeps running) and reads the last sweep's
+// count: zero means Step II had converged; otherwise kRerun. If the count has
+// not arrived when the event reports completion, the call waits for the whole
+// stream; a count still missing then counts as not converged.
 int check_sweeps(ws_ctx *c, const ws_ctx::Graph &g, void *stream) {
     if (g.sweeps <= 0) return WS_OK;
-    const int32_t *cnt = (const int32_t *)c->cnt.p;
-    hipError_t e = hipMemcpyAsync(c->host_cnt, cnt + g.sweeps, 4, hipMemcpyDeviceToHost, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
-    if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    volatile int32_t *flag = (volatile int32_t *)c->host_cnt + kCounterSlots;
+    hipError_t e = hipEventSynchronize(c->sweep_ev);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    if (*flag < 0 && (e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess)
+        return hip_fail(c, e, "hipStreamSynchronize");
     c->stats[0] = g.sweeps + 1;
-    return c->host_cnt[0] == 0 ? WS_OK : kRerun;
+    return *flag == 0 ? WS_OK : kRerun;
 }
 
 // Launches launch(i, counter) for i = 1, 2, ... in batches of sweep_batch,
@@ -655,17 +676,22 @@ struct WfBufs {
     wsk::EdgeSlabs es;
 };
 
-// Layer tables: layer 1 by region id; for NL >= 3 also the ranks of the
-// layer-1 roots, the root list, the tables of layers 2 .. NL-1 by rank (each
-// arena ints: the counts are only known on the device) and the root scan's
-// scratch.
-size_t mlab_ints(size_t arena, int NL) {
+// Layer tables: layer 1 by region id (arena ints: region counts are only
+// known on the device); for NL >= 3 also the rank of every region's layer-1
+// root (arena ints), the list of layer-1 roots and the tables of layers
+// 2 .. NL-1 by that rank (rank_ints each), and the root scan's scratch.
+// Every layer at least halves the regions of an image with two or more
+// (each region joins the neighbour across its lowest pass), so an arena of
+// nimg images has at most arena / 2 + nimg layer-1 roots.
+size_t rank_ints(size_t arena, int nimg) { return arena / 2 + (size_t)nimg + 1; }
+size_t mlab_ints(size_t arena, int NL, int nimg) {
     if (NL < 3) return arena;
-    return (size_t)(NL + 1) * arena + (size_t)wsk::root_list_tmp_len((int32_t)arena);
+    return 2 * arena + (size_t)(NL - 1) * rank_ints(arena, nimg) + (size_t)wsk::root_list_tmp_len((int32_t)arena);
 }
 
 // `cap`: edge slab entries per waterfall tile (the largest any part needs).
-int wf_buffers(ws_ctx *c, size_t arena, int32_t ntiles, int32_t nchunks, int32_t cap, int NL, bool tables, WfBufs &b) {
+int wf_buffers(ws_ctx *c, size_t arena, int nimg, int32_t ntiles, int32_t nchunks, int32_t cap, int NL, bool tables,
+               WfBufs &b) {
     int rc;
     if ((rc = ensure(c, c->wfcnt, 8, "region counts")) != WS_OK) return rc;
     if ((rc = ensure(c, c->tilecnt, (size_t)NL * nchunks * 4, "chunk counts")) != WS_OK) return rc;
@@ -688,7 +714,7 @@ int wf_buffers(ws_ctx *c, size_t arena, int32_t ntiles, int32_t nchunks, int32_t
     if ((rc = ensure(c, c->par, arena * 4, "region parents")) != WS_OK) return rc;
     if ((rc = ensure(c, c->cimg, arena * 4, "pixel region ids")) != WS_OK) return rc;
     if ((rc = ensure(c, c->rlist, arena * 4, "region labels")) != WS_OK) return rc;
-    if (NL >= 2 && (rc = ensure(c, c->mlab, mlab_ints(arena, NL) * 4, "layer labels")) != WS_OK) return rc;
+    if (NL >= 2 && (rc = ensure(c, c->mlab, mlab_ints(arena, NL, nimg) * 4, "layer labels")) != WS_OK) return rc;
     if ((rc = ensure(c, c->edges, 3 * E * 4, "edge slabs")) != WS_OK) return rc;
     if ((rc = ensure(c, c->ecnt, (size_t)ntiles * 4, "edge counts")) != WS_OK) return rc;
     b.key = (uint64_t *)c->key.p;
@@ -743,9 +769,10 @@ int run_waterfall(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, co
             WS_TRY(wsk::launch_wf_compress(lc, bound, b.nreg0, b.par, b.rlist, b.mlab));
         } else {
             // later layers only concern the roots of layer 1: list them
+            const size_t H = rank_ints(arena, nimg);
             int32_t *id1 = b.mlab + arena, *R1 = b.mlab + 2 * arena, *n1 = b.nreg0 + 1;
-            int32_t *scr = b.mlab + (size_t)(NL + 1) * arena;
-            WS_TRY(wsk::launch_root_list(lc, bound, b.nreg0, b.par, R1, id1, scr, n1));
+            int32_t *scr = b.mlab + 2 * arena + (size_t)(NL - 1) * H;
+            WS_TRY(wsk::launch_root_list(lc, bound, b.nreg0, b.par, R1, id1, (int32_t)H, scr, n1));
             WS_TRY(wsk::launch_wf_compress1(lc, bound, b.nreg0, b.par, b.rlist, b.mlab, id1));
             int32_t gin = 1;
             for (int k = 2; k < NL; ++k) {
@@ -755,12 +782,14 @@ int run_waterfall(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, co
                 int32_t f = gin >= wft ? 1 : 4;
                 WS_TRY(wsk::launch_wf_level(lc, wft, gin, f, b.es.cap, b.par, b.key, b.es.a, b.es.cnt));
                 gin *= f;
-                WS_TRY(wsk::launch_wf_union_l(lc, bound, n1, R1, b.key, b.par));
-                WS_TRY(wsk::launch_wf_compress_l(lc, bound, n1, R1, b.par, b.rlist, b.mlab + (size_t)(k + 1) * arena));
+                WS_TRY(wsk::launch_wf_union_l(lc, bound, n1, (int32_t)H, R1, b.key, b.par));
+                WS_TRY(wsk::launch_wf_compress_l(lc, bound, n1, (int32_t)H, R1, b.par, b.rlist,
+                                                 b.mlab + 2 * arena + (size_t)(k - 1) * H));
             }
         }
     }
-    WS_TRY(wsk::launch_wf_out(lc, src_ch, nchunks, NL, b.cimg, b.nreg0, b.ids.coff, b.mlab, (int64_t)arena, b.cnt));
+    WS_TRY(wsk::launch_wf_out(lc, src_ch, nchunks, NL, b.cimg, b.nreg0, b.ids.coff, b.mlab, (int64_t)arena,
+                              (int64_t)rank_ints(arena, nimg), b.cnt));
     if (outs_dev || one_out)
         WS_TRY(wsk::launch_img_counts(lc, tab_dev, one, nimg, NL, nchunks, b.cnt, outs_dev, one_out));
     return WS_OK;
@@ -781,7 +810,8 @@ int reserve(ws_ctx *c, int64_t n) {
     for (Buf *b : four)
         if ((rc = ensure(c, *b, N * 4, "reserved scratch")) != WS_OK) return rc;
     if ((rc = ensure(c, c->key, N * 8, "reserved keys")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->mlab, mlab_ints(N, kLayers) * 4, "reserved layer labels")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->mlab, mlab_ints(N, kLayers, kReserveItems) * 4, "reserved layer labels")) != WS_OK)
+        return rc;
     if ((rc = ensure(c, c->edges, wft * (size_t)wsk::wf_slab_cap(8) * 12, "reserved edge slabs")) != WS_OK) return rc;
     if ((rc = ensure(c, c->ecnt, wft * 4, "reserved edge counts")) != WS_OK) return rc;
     if ((rc = ensure(c, c->stamp, tiles * 16, "reserved stamps")) != WS_OK) return rc;
@@ -842,7 +872,7 @@ int ws_create(ws_ctx **out, int device, size_t scratch_budget_bytes) {
         delete c;
         return fail(nullptr, WS_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
     }
-    if ((e = hipHostMalloc((void **)&c->host_cnt, kCounterSlots * 4, hipHostMallocDefault)) != hipSuccess) {
+    if ((e = hipHostMalloc((void **)&c->host_cnt, (kCounterSlots + 1) * 4, hipHostMallocDefault)) != hipSuccess) {
         delete c;
         return fail(nullptr, WS_EDEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
     }
@@ -876,6 +906,7 @@ void ws_destroy(ws_ctx *c) {
     for (auto &r : c->sink.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (auto e : c->sink.pool) (void)hipEventDestroy(e);
     if (c->host_cnt) (void)hipHostFree(c->host_cnt);
+    if (c->sweep_ev) (void)hipEventDestroy(c->sweep_ev);
     if (c->stage) (void)hipHostFree(c->stage);
     if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
     delete c;
@@ -906,7 +937,7 @@ size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int conn, int dtyp
     size_t wf = 0;
     if (NL >= 2) {
         size_t tiles = (size_t)wsk::wf_tiles(make_geom(nx, ny, nz, ndim), ndim);
-        wf = N * (8 /* keys */ + 4 /* parents */ + 4 /* ids */ + 4 /* labels */) + mlab_ints(N, NL) * 4 /* layers */ +
+        wf = N * (8 /* keys */ + 4 /* parents */ + 4 /* ids */ + 4 /* labels */) + mlab_ints(N, NL, 1) * 4 /* layers */ +
              tiles * (12 * (size_t)wsk::wf_slab_cap(conn) + 4 + 4 * (size_t)NL) +
              ((size_t)wsk::wf_chunks((int32_t)N) + 2) * (64 * 16 + 8) /* region-id rank tables */;
     }
@@ -1121,7 +1152,7 @@ int ws_waterfall(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, 
         auto parts = one_part(src, conn, shape);
         const int32_t nchunks = wsk::wf_chunks(g.n);
         WfBufs b;
-        int rc2 = wf_buffers(c, (size_t)g.n, wf_tiles_of(parts), nchunks, slab_cap_of(parts), NL, NL >= 2, b);
+        int rc2 = wf_buffers(c, (size_t)g.n, 1, wf_tiles_of(parts), nchunks, slab_cap_of(parts), NL, NL >= 2, b);
         if (rc2 != WS_OK) return rc2;
         if (labels != out) {
             hipError_t e = hipMemcpyAsync(out, labels, (size_t)g.n * 4, hipMemcpyDeviceToDevice, lc.stream);
@@ -1147,7 +1178,7 @@ int ws_waterfall_recon(ws_ctx *c, const int32_t *labels, const void *grad, int d
     const int32_t nchunks = wsk::wf_chunks(g.n), bound = g.n;
     const wsk::TileGrid tgw = full_grid(wsk::wf_tiles(g, ndim));
     WfBufs b;
-    if ((rc = wf_buffers(c, N, tgw.ntiles, nchunks, wsk::wf_slab_cap(conn), 1, NL >= 2, b)) != WS_OK) return rc;
+    if ((rc = wf_buffers(c, N, 1, tgw.ntiles, nchunks, wsk::wf_slab_cap(conn), 1, NL >= 2, b)) != WS_OK) return rc;
     if ((rc = ensure(c, c->rimg, N * 2, "raised image")) != WS_OK) return rc;
     WsScratch ws;
     {
@@ -1166,7 +1197,7 @@ int ws_waterfall_recon(ws_ctx *c, const int32_t *labels, const void *grad, int d
         WS_TRY(wsk::launch_wf_ids(lc, src, nchunks, bound, b.ids, b.scan_tmp, b.nreg0, k + 1 < NL ? b.key : nullptr,
                                   b.par));
         if (nregions) {
-            WS_TRY(wsk::launch_wf_out(lc, src, nchunks, 1, nullptr, b.nreg0, b.ids.coff, nullptr, 0, b.cnt));
+            WS_TRY(wsk::launch_wf_out(lc, src, nchunks, 1, nullptr, b.nreg0, b.ids.coff, nullptr, 0, 0, b.cnt));
             WS_TRY(wsk::launch_img_counts(lc, nullptr, src.im, 1, 1, nchunks, b.cnt, nullptr, nregions + k));
         }
         if (k + 1 == NL) break;
@@ -1194,7 +1225,7 @@ int ws_rag(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, int64_
     const int32_t nchunks = wsk::wf_chunks(g.n), bound = g.n;
     const wsk::TileGrid tg = full_grid(wsk::wf_tiles(g, ndim));
     WfBufs b;
-    if ((rc = wf_buffers(c, N, tg.ntiles, nchunks, wsk::wf_slab_cap(conn), 1, true, b)) != WS_OK) return rc;
+    if ((rc = wf_buffers(c, N, 1, tg.ntiles, nchunks, wsk::wf_slab_cap(conn), 1, true, b)) != WS_OK) return rc;
     // the labels are read, never written (the pixel pass only reads its layer 0)
     wsk::OneImg src{single_img(nx, ny, nz, grad, const_cast<int32_t *>(labels), shape_of(c, ndim))};
     WS_TRY(wsk::launch_wf_ids(lc, src, nchunks, bound, b.ids, b.scan_tmp, b.nreg0, b.key, b.par));
@@ -1352,7 +1383,8 @@ int ws_batch(ws_ctx *c, const ws_item *items, int n_items, int dtype, int NL, vo
         WfBufs wb;
         WsScratch ws;
         if ((rc2 = prepare_watershed(c, parts, (size_t)arena, true, ws)) != WS_OK) return rc2;
-        if ((rc2 = wf_buffers(c, (size_t)arena, (int32_t)wf_all, nchunks, slab_cap_of(parts), NL, NL >= 2, wb)) !=
+        if ((rc2 = wf_buffers(c, (size_t)arena, n_items, (int32_t)wf_all, nchunks, slab_cap_of(parts), NL, NL >= 2,
+                              wb)) !=
             WS_OK)
             return rc2;
         if (!c->capturing) {

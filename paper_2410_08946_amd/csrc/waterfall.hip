@@ -634,11 +634,13 @@ __global__ __launch_bounds__(NTHREADS) void k_root_count(const int32_t *__restri
     if (threadIdx.x == 0) bcnt[blockIdx.x] = total;
 }
 
-// R1[rank] = root and id1[root] = rank, from the scanned block counts.
+// R1[rank] = root and id1[root] = rank, from the scanned block counts. The
+// list holds at most `cap` roots (a layer at least halves the regions of every
+// image, so valid labels never reach it); ranks past it are clamped.
 __global__ __launch_bounds__(NTHREADS) void k_root_scatter(const int32_t *__restrict__ nreg0,
                                                            const int32_t *__restrict__ par,
                                                            const int32_t *__restrict__ bcnt, int32_t *__restrict__ R1,
-                                                           int32_t *__restrict__ id1) {
+                                                           int32_t *__restrict__ id1, int32_t cap) {
     const int32_t n = *nreg0;
     if ((int64_t)blockIdx.x * SCAN_B >= n) return;
     const int32_t c0 = blockIdx.x * SCAN_B + threadIdx.x * 16;
@@ -648,8 +650,9 @@ __global__ __launch_bounds__(NTHREADS) void k_root_scatter(const int32_t *__rest
     int32_t rank = bcnt[blockIdx.x] + excl;
     for (uint32_t b = m; b; b &= b - 1) {
         const int32_t c = c0 + __ffs(b) - 1;
-        R1[rank] = c;
-        id1[c] = rank++;
+        if (rank < cap) R1[rank] = c;
+        id1[c] = rank < cap ? rank : cap - 1;
+        ++rank;
     }
 }
 
@@ -667,9 +670,10 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_compress1(const int32_t *__rest
     }
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_wf_hook_l(const int32_t *__restrict__ n1p, const int32_t *__restrict__ R1,
+__global__ __launch_bounds__(NTHREADS) void k_wf_hook_l(const int32_t *__restrict__ n1p, int32_t cap,
+                                                        const int32_t *__restrict__ R1,
                                                         const uint64_t *__restrict__ key, int32_t *__restrict__ par) {
-    const int32_t n = *n1p;
+    const int32_t n = min(*n1p, cap);
     for (int32_t i = xcd_group(blockIdx.x, gridDim.x, XG_REG) * NTHREADS + threadIdx.x; i < n;
          i += gridDim.x * NTHREADS) {
         const int32_t c = R1[i];
@@ -679,9 +683,10 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_hook_l(const int32_t *__restric
     }
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_wf_union_l(const int32_t *__restrict__ n1p, const int32_t *__restrict__ R1,
+__global__ __launch_bounds__(NTHREADS) void k_wf_union_l(const int32_t *__restrict__ n1p, int32_t cap,
+                                                         const int32_t *__restrict__ R1,
                                                          uint64_t *__restrict__ key, int32_t *__restrict__ par) {
-    const int32_t n = *n1p;
+    const int32_t n = min(*n1p, cap);
     for (int32_t i = xcd_group(blockIdx.x, gridDim.x, XG_REG) * NTHREADS + threadIdx.x; i < n;
          i += gridDim.x * NTHREADS) {
         const int32_t c = R1[i];
@@ -693,11 +698,11 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_union_l(const int32_t *__restri
     }
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_wf_compress_l(const int32_t *__restrict__ n1p,
+__global__ __launch_bounds__(NTHREADS) void k_wf_compress_l(const int32_t *__restrict__ n1p, int32_t cap,
                                                             const int32_t *__restrict__ R1, int32_t *__restrict__ par,
                                                             const int32_t *__restrict__ rlist,
                                                             int32_t *__restrict__ Mk) {
-    const int32_t n = *n1p;
+    const int32_t n = min(*n1p, cap);
     for (int32_t i = xcd_group(blockIdx.x, gridDim.x, XG_REG) * NTHREADS + threadIdx.x; i < n;
          i += gridDim.x * NTHREADS) {
         const int32_t c = R1[i];
@@ -709,9 +714,10 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_compress_l(const int32_t *__res
 
 // ---------------------------------------------------------------------------
 // 4. Layers 1 .. nl-1 of every pixel from its region id, chunk by chunk. The
-// label tables (mstride ints apart): layer 1 by region id at mlab; for
-// nl >= 3 the rank of every region's layer-1 root at mlab + mstride, and
-// layer k >= 2 by that rank at mlab + (k + 1) mstride.
+// label tables: layer 1 by region id at mlab (mstride ints); for nl >= 3 the
+// rank of every region's layer-1 root at mlab + mstride, then the root list
+// and the layers k >= 2 by that rank, hstride ints each: layer k at
+// mlab + 2 mstride + (k - 1) hstride.
 // (RCH consecutive pixels of one image), and per chunk the number of pixels
 // carrying their own label in each layer, cnt[k * nchunks + t]. Layer 0's
 // count is the chunk's root count, the difference of consecutive chunk
@@ -727,7 +733,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks
                                                      const int32_t *__restrict__ nreg0,
                                                      const int32_t *__restrict__ coff,
                                                      const int32_t *__restrict__ mlab, int64_t mstride,
-                                                     int32_t *__restrict__ cnt) {
+                                                     int64_t hstride, int32_t *__restrict__ cnt) {
     constexpr int RUNS = RCH / (4 * NTHREADS);  // runs of 4 pixels per thread
     static_assert(RUNS * 4 * NTHREADS == RCH, "whole runs per chunk");
     __shared__ int kc;
@@ -771,7 +777,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks
     }
 #pragma unroll 1
     for (int k = 1; k < nl; ++k) {
-        const int32_t *m = mlab + (k == 1 ? 0 : (size_t)(k + 1) * (size_t)mstride);
+        const int32_t *m = mlab + (k == 1 ? 0 : 2 * (size_t)mstride + (size_t)(k - 1) * (size_t)hstride);
         int32_t *out = im.lab + (size_t)k * (size_t)n;
         if (threadIdx.x == 0) kc = 0;
         __syncthreads();
@@ -866,7 +872,9 @@ __device__ __forceinline__ int wf_emit(const int32_t (&v)[OUT_RUNS][4], const in
 // table as base + 32-bit offset.
 struct WfTabs {
     const int32_t *t[WF_OUT_MAXNL];
-    uint32_t bytes;  // size of each table (< 4 GiB: larger arenas take the layer-by-layer kernel)
+    uint32_t bytes;    // size of the tables by region id, t[0] and t[1] (< 4 GiB: larger arenas take the
+                       // layer-by-layer kernel)
+    uint32_t bytes_r;  // size of each table by rank, t[2] ..
 };
 
 template <class Src, int NLM>
@@ -931,7 +939,7 @@ __global__ __launch_bounds__(OUT_T) void k_wf_out_p(Src src_ch, int32_t nchunks,
                 if (e == 0 || rk[r][e] != rk[r][e - 1]) need_r |= 1u << (4 * r + e);
             }
 #pragma unroll
-        for (int k = 2; k <= NLM; ++k) wf_gather(V[k - 1], off, table_rsrc(tabs.t[k], tabs.bytes), need_r);
+        for (int k = 2; k <= NLM; ++k) wf_gather(V[k - 1], off, table_rsrc(tabs.t[k], tabs.bytes_r), need_r);
     }
     int own[NLM];
 #pragma unroll
@@ -951,13 +959,15 @@ __global__ __launch_bounds__(OUT_T) void k_wf_out_p(Src src_ch, int32_t nchunks,
 template <class Src>
 static int wf_out_pipelined(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t nl, const int32_t *cimg,
                             const int32_t *nreg0, const int32_t *coff, const int32_t *mlab, int64_t mstride,
-                            int32_t *cnt) {
+                            int64_t hstride, int32_t *cnt) {
     dim3 grid(nchunks > 0 ? nchunks : 1);
     WfTabs tabs{};
     tabs.bytes = (uint32_t)((size_t)mstride * 4);
+    tabs.bytes_r = (uint32_t)((size_t)hstride * 4);
     tabs.t[0] = mlab;
     if (nl >= 3) tabs.t[1] = mlab + mstride;
-    for (int k = 2; k < nl && k < WF_OUT_MAXNL; ++k) tabs.t[k] = mlab + (size_t)(k + 1) * (size_t)mstride;
+    for (int k = 2; k < nl && k < WF_OUT_MAXNL; ++k)
+        tabs.t[k] = mlab + 2 * (size_t)mstride + (size_t)(k - 1) * (size_t)hstride;
     switch (nl - 1) {
 #define WF_OUT_P(M)                                                                                               \
     case M:                                                                                                       \
@@ -1080,13 +1090,14 @@ int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, int32_t 
 }
 
 int launch_root_list(Launch &lc, int32_t bound, const int32_t *nreg0, const int32_t *par, int32_t *R1, int32_t *id1,
-                     int32_t *scratch, int32_t *n1) {
+                     int32_t cap, int32_t *scratch, int32_t *n1) {
     const int32_t nb = (bound + SCAN_B - 1) / SCAN_B > 0 ? (bound + SCAN_B - 1) / SCAN_B : 1;
     int32_t *bcnt = scratch, *tmp = scratch + nb;
     int rc = lc.run("wf_union", k_root_count, dim3(nb), dim3(NTHREADS), nreg0, par, bcnt);
     if (rc) return rc;
     if ((rc = launch_scan(lc, nb, bcnt, tmp, n1))) return rc;
-    return lc.run("wf_union", k_root_scatter, dim3(nb), dim3(NTHREADS), nreg0, par, (const int32_t *)bcnt, R1, id1);
+    return lc.run("wf_union", k_root_scatter, dim3(nb), dim3(NTHREADS), nreg0, par, (const int32_t *)bcnt, R1, id1,
+                  cap);
 }
 int root_list_tmp_len(int32_t bound) {
     const int32_t nb = (bound + SCAN_B - 1) / SCAN_B > 0 ? (bound + SCAN_B - 1) / SCAN_B : 1;
@@ -1100,14 +1111,16 @@ int launch_wf_compress1(Launch &lc, int32_t bound, const int32_t *nreg0, int32_t
 // grids are sized for bound / 32 ids (grid-stride loops cover any length), so
 // later layers do not dispatch thousands of empty workgroups.
 static inline dim3 root_grid(int32_t bound) { return list_grid(bound / 32 > 0 ? bound / 32 : 1); }
-int launch_wf_union_l(Launch &lc, int32_t bound, const int32_t *n1, const int32_t *R1, uint64_t *key, int32_t *par) {
-    int rc = lc.run("wf_union", k_wf_hook_l, root_grid(bound), dim3(NTHREADS), n1, R1, (const uint64_t *)key, par);
+int launch_wf_union_l(Launch &lc, int32_t bound, const int32_t *n1, int32_t cap, const int32_t *R1, uint64_t *key,
+                      int32_t *par) {
+    int rc = lc.run("wf_union", k_wf_hook_l, root_grid(bound), dim3(NTHREADS), n1, cap, R1, (const uint64_t *)key,
+                    par);
     if (rc) return rc;
-    return lc.run("wf_union", k_wf_union_l, root_grid(bound), dim3(NTHREADS), n1, R1, key, par);
+    return lc.run("wf_union", k_wf_union_l, root_grid(bound), dim3(NTHREADS), n1, cap, R1, key, par);
 }
-int launch_wf_compress_l(Launch &lc, int32_t bound, const int32_t *n1, const int32_t *R1, int32_t *par,
+int launch_wf_compress_l(Launch &lc, int32_t bound, const int32_t *n1, int32_t cap, const int32_t *R1, int32_t *par,
                          const int32_t *rlist, int32_t *Mk) {
-    return lc.run("wf_compress", k_wf_compress_l, root_grid(bound), dim3(NTHREADS), n1, R1, par, rlist, Mk);
+    return lc.run("wf_compress", k_wf_compress_l, root_grid(bound), dim3(NTHREADS), n1, cap, R1, par, rlist, Mk);
 }
 int launch_wf_union(Launch &lc, int32_t bound, const int32_t *nreg0, uint64_t *key, int32_t *par) {
     int rc = lc.run("wf_union", k_wf_hook, list_grid(bound), dim3(NTHREADS), nreg0, (const uint64_t *)key, par);
@@ -1170,11 +1183,12 @@ static int wf_pix_dispatch(Launch &lc, const Src &src, const TileGrid &tg, int c
     }                                                                                                              \
     int launch_wf_out(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t nl, const int32_t *cimg,            \
                       const int32_t *nreg0, const int32_t *coff, const int32_t *mlab, int64_t mstride,           \
-                      int32_t *cnt) {                                                                             \
+                      int64_t hstride, int32_t *cnt) {                                                            \
         if (nl >= 2 && nl <= WF_OUT_MAXNL && (size_t)mstride * 4 <= 0xffffffffu)                                 \
-            return wf_out_pipelined<Src>(lc, src_ch, nchunks, nl, cimg, nreg0, coff, mlab, mstride, cnt);        \
+            return wf_out_pipelined<Src>(lc, src_ch, nchunks, nl, cimg, nreg0, coff, mlab, mstride, hstride,     \
+                                         cnt);                                                                    \
         return lc.run("wf_out", k_wf_out<Src>, dim3(nchunks > 0 ? nchunks : 1), dim3(NTHREADS), src_ch, nchunks, \
-                      nl, cimg, nreg0, coff, mlab, mstride, cnt);                                                 \
+                      nl, cimg, nreg0, coff, mlab, mstride, hstride, cnt);                                        \
     }
 
 WF_SRC_FUNCS(OneImg)

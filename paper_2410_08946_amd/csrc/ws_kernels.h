@@ -150,7 +150,7 @@ extern template struct WsShape<33>;
                       const int32_t *nreg0, int32_t *cimg, int32_t *rlist, uint64_t *key, const EdgeSlabs &es);  \
     int launch_wf_out(Launch &lc, const Src &src_ch, int32_t nchunks, int32_t nl, const int32_t *cimg,           \
                       const int32_t *nreg0, const int32_t *coff, const int32_t *mlab, int64_t mstride,          \
-                      int32_t *cnt);
+                      int64_t hstride, int32_t *cnt);
 WS_DECL_SRC(OneImg)
 WS_DECL_SRC(ImgTable)
 #undef WS_DECL_SRC
@@ -185,12 +185,13 @@ int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, int32_t 
 // list R1 with ranks in id1 and its length in *n1 (scratch: root_list_tmp_len
 // ints); layer 1's compression with ranks; union and compression over R1.
 int launch_root_list(Launch &lc, int32_t bound, const int32_t *nreg0, const int32_t *par, int32_t *R1, int32_t *id1,
-                     int32_t *scratch, int32_t *n1);
+                     int32_t cap, int32_t *scratch, int32_t *n1);
 int root_list_tmp_len(int32_t bound);
 int launch_wf_compress1(Launch &lc, int32_t bound, const int32_t *nreg0, int32_t *par, const int32_t *rlist,
                         int32_t *mlab1, int32_t *id1);
-int launch_wf_union_l(Launch &lc, int32_t bound, const int32_t *n1, const int32_t *R1, uint64_t *key, int32_t *par);
-int launch_wf_compress_l(Launch &lc, int32_t bound, const int32_t *n1, const int32_t *R1, int32_t *par,
+int launch_wf_union_l(Launch &lc, int32_t bound, const int32_t *n1, int32_t cap, const int32_t *R1, uint64_t *key,
+                      int32_t *par);
+int launch_wf_compress_l(Launch &lc, int32_t bound, const int32_t *n1, int32_t cap, const int32_t *R1, int32_t *par,
                          const int32_t *rlist, int32_t *Mk);
 int launch_wf_union(Launch &lc, int32_t bound, const int32_t *nreg0, uint64_t *key, int32_t *par);
 int launch_grey_u16(Launch &lc, const void *in, bool u16, uint16_t *out, int32_t n);
