@@ -676,17 +676,22 @@ struct WfBufs {
     wsk::EdgeSlabs es;
 };
 
-// Layer tables: layer 1 by region id (arena ints: region counts are only
-// known on the device); for NL >= 3 also the rank of every region's layer-1
-// root (arena ints), the list of layer-1 roots and the tables of layers
-// 2 .. NL-1 by that rank (rank_ints each), and the root scan's scratch.
+// Layer tables: for NL == 2 layer 1 by region id (arena ints: region counts
+// are only known on the device). For NL >= 3 one record per region id
+// {layer-1 label, rank of its layer-1 root}, the list of layer-1 roots
+// (rank_ints), one record per rank of layers 2 .. NL-1 (layer_ints(NL) each)
+// and the root scan's scratch.
 // Every layer at least halves the regions of an image with two or more
 // (each region joins the neighbour across its lowest pass), so an arena of
 // nimg images has at most arena / 2 + nimg layer-1 roots.
 size_t rank_ints(size_t arena, int nimg) { return arena / 2 + (size_t)nimg + 1; }
+// Ints per rank record of layers 2 .. NL-1 (whole 16-byte groups).
+size_t layer_ints(int NL) { return NL < 3 ? 0 : (size_t)(NL - 2 + 3) / 4 * 4; }
 size_t mlab_ints(size_t arena, int NL, int nimg) {
     if (NL < 3) return arena;
-    return 2 * arena + (size_t)(NL - 1) * rank_ints(arena, nimg) + (size_t)wsk::root_list_tmp_len((int32_t)arena);
+    // [region records {layer 1, rank}: 2 arena][root list: H][rank records: layer_ints(NL) H][scan scratch]
+    const size_t H = rank_ints(arena, nimg);
+    return 2 * arena + H + layer_ints(NL) * H + (size_t)wsk::root_list_tmp_len((int32_t)arena);
 }
 
 // `cap`: edge slab entries per waterfall tile (the largest any part needs).
@@ -769,11 +774,11 @@ int run_waterfall(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, co
             WS_TRY(wsk::launch_wf_compress(lc, bound, b.nreg0, b.par, b.rlist, b.mlab));
         } else {
             // later layers only concern the roots of layer 1: list them
-            const size_t H = rank_ints(arena, nimg);
-            int32_t *id1 = b.mlab + arena, *R1 = b.mlab + 2 * arena, *n1 = b.nreg0 + 1;
-            int32_t *scr = b.mlab + 2 * arena + (size_t)(NL - 1) * H;
-            WS_TRY(wsk::launch_root_list(lc, bound, b.nreg0, b.par, R1, id1, (int32_t)H, scr, n1));
-            WS_TRY(wsk::launch_wf_compress1(lc, bound, b.nreg0, b.par, b.rlist, b.mlab, id1));
+            const size_t H = rank_ints(arena, nimg), LS = layer_ints(NL);
+            int32_t *id1 = b.mlab + 1, *R1 = b.mlab + 2 * arena, *n1 = b.nreg0 + 1;
+            int32_t *lay = R1 + H, *scr = lay + LS * H;
+            WS_TRY(wsk::launch_root_list(lc, bound, b.nreg0, b.par, R1, id1, 2, (int32_t)H, scr, n1));
+            WS_TRY(wsk::launch_wf_compress1(lc, bound, b.nreg0, b.par, b.rlist, b.mlab, id1, 2));
             int32_t gin = 1;
             for (int k = 2; k < NL; ++k) {
                 // groups grow fourfold per layer: regions spanning several tiles
@@ -783,8 +788,8 @@ int run_waterfall(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, co
                 WS_TRY(wsk::launch_wf_level(lc, wft, gin, f, b.es.cap, b.par, b.key, b.es.a, b.es.cnt));
                 gin *= f;
                 WS_TRY(wsk::launch_wf_union_l(lc, bound, n1, (int32_t)H, R1, b.key, b.par));
-                WS_TRY(wsk::launch_wf_compress_l(lc, bound, n1, (int32_t)H, R1, b.par, b.rlist,
-                                                 b.mlab + 2 * arena + (size_t)(k - 1) * H));
+                WS_TRY(wsk::launch_wf_compress_l(lc, bound, n1, (int32_t)H, R1, b.par, b.rlist, lay + (k - 2),
+                                                 (int32_t)LS));
             }
         }
     }

@@ -60,6 +60,8 @@ constexpr int MAX_F = NTHREADS;     // tile groups merged per workgroup (one cou
 // (measured best: fully contiguous ranges per XCD leave the 8 XCDs writing
 // far-apart streams, runs of 1 re-fetch every table line into all 8 L2s).
 constexpr int XG_OUT = 64;          // chunks per run in the output pass
+// Ints per rank record of layers 2 .. nl-1 (whole 16-byte groups).
+__host__ __device__ constexpr int layer_stride(int nl) { return nl < 3 ? 0 : (nl - 2 + 3) / 4 * 4; }
 constexpr int XG_REG = 64;          // workgroups of 256 region ids per run
 
 // Forward half of a neighbourhood: the neighbours with a larger linear index.
@@ -634,13 +636,13 @@ __global__ __launch_bounds__(NTHREADS) void k_root_count(const int32_t *__restri
     if (threadIdx.x == 0) bcnt[blockIdx.x] = total;
 }
 
-// R1[rank] = root and id1[root] = rank, from the scanned block counts. The
+// R1[rank] = root and id1[root * ids] = rank, from the scanned block counts. The
 // list holds at most `cap` roots (a layer at least halves the regions of every
 // image, so valid labels never reach it); ranks past it are clamped.
 __global__ __launch_bounds__(NTHREADS) void k_root_scatter(const int32_t *__restrict__ nreg0,
                                                            const int32_t *__restrict__ par,
                                                            const int32_t *__restrict__ bcnt, int32_t *__restrict__ R1,
-                                                           int32_t *__restrict__ id1, int32_t cap) {
+                                                           int32_t *__restrict__ id1, int32_t ids, int32_t cap) {
     const int32_t n = *nreg0;
     if ((int64_t)blockIdx.x * SCAN_B >= n) return;
     const int32_t c0 = blockIdx.x * SCAN_B + threadIdx.x * 16;
@@ -651,22 +653,25 @@ __global__ __launch_bounds__(NTHREADS) void k_root_scatter(const int32_t *__rest
     for (uint32_t b = m; b; b &= b - 1) {
         const int32_t c = c0 + __ffs(b) - 1;
         if (rank < cap) R1[rank] = c;
-        id1[c] = rank < cap ? rank : cap - 1;
+        id1[(size_t)c * ids] = rank < cap ? rank : cap - 1;
         ++rank;
     }
 }
 
-// Layer 1's compression, also giving every region the rank of its root.
+// Layer 1's compression, also giving every region the rank of its root:
+// region c's layer-1 label at mlab1[c * ms], that rank at id1[c * ms] (the
+// two interleave in one record per region).
 __global__ __launch_bounds__(NTHREADS) void k_wf_compress1(const int32_t *__restrict__ nreg0, int32_t *__restrict__ par,
                                                            const int32_t *__restrict__ rlist,
-                                                           int32_t *__restrict__ mlab1, int32_t *__restrict__ id1) {
+                                                           int32_t *__restrict__ mlab1, int32_t *__restrict__ id1,
+                                                           int32_t ms) {
     const int32_t n = *nreg0;
     for (int32_t c = xcd_group(blockIdx.x, gridDim.x, XG_REG) * NTHREADS + threadIdx.x; c < n;
          c += gridDim.x * NTHREADS) {
         int32_t r = gfind_ro(par, c);
         par[c] = r;
-        mlab1[c] = rlist[r];
-        if (r != c) id1[c] = id1[r];  // roots already hold their rank
+        mlab1[(size_t)c * ms] = rlist[r];
+        if (r != c) id1[(size_t)c * ms] = id1[(size_t)r * ms];  // roots already hold their rank
     }
 }
 
@@ -701,23 +706,23 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_union_l(const int32_t *__restri
 __global__ __launch_bounds__(NTHREADS) void k_wf_compress_l(const int32_t *__restrict__ n1p, int32_t cap,
                                                             const int32_t *__restrict__ R1, int32_t *__restrict__ par,
                                                             const int32_t *__restrict__ rlist,
-                                                            int32_t *__restrict__ Mk) {
+                                                            int32_t *__restrict__ Mk, int32_t ls) {
     const int32_t n = min(*n1p, cap);
     for (int32_t i = xcd_group(blockIdx.x, gridDim.x, XG_REG) * NTHREADS + threadIdx.x; i < n;
          i += gridDim.x * NTHREADS) {
         const int32_t c = R1[i];
         int32_t r = gfind_ro(par, c);
         par[c] = r;
-        Mk[i] = rlist[r];
+        Mk[(size_t)i * ls] = rlist[r];
     }
 }
 
 // ---------------------------------------------------------------------------
 // 4. Layers 1 .. nl-1 of every pixel from its region id, chunk by chunk. The
-// label tables: layer 1 by region id at mlab (mstride ints); for nl >= 3 the
-// rank of every region's layer-1 root at mlab + mstride, then the root list
-// and the layers k >= 2 by that rank, hstride ints each: layer k at
-// mlab + 2 mstride + (k - 1) hstride.
+// label tables: for nl == 2 layer 1 by region id at mlab; for nl >= 3 one
+// record {layer-1 label, rank of the layer-1 root} per region id at mlab
+// (mstride records), then the root list (hstride ints), then per rank one
+// record of layers 2 .. nl-1 (layer_stride(nl) ints, a multiple of 4).
 // (RCH consecutive pixels of one image), and per chunk the number of pixels
 // carrying their own label in each layer, cnt[k * nchunks + t]. Layer 0's
 // count is the chunk's root count, the difference of consecutive chunk
@@ -768,16 +773,19 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks
 #pragma unroll
         for (int e = 0; e < 4; ++e) c[r][e] = (uint32_t)c[r][e] <= cmax ? c[r][e] : (int32_t)cmax;
     }
+    // nl >= 3: one record per region id {layer-1 label, rank of the layer-1
+    // root}, then per rank a record of the layers 2 .. nl-1 (lstride ints)
+    const int lstride = layer_stride(nl);
     int32_t rk[RUNS][4];  // rank of the layer-1 root (tables of layers >= 2)
     if (nl >= 3) {
 #pragma unroll
         for (int r = 0; r < RUNS; ++r)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) rk[r][e] = mlab[(size_t)mstride + c[r][e]];
+            for (int e = 0; e < 4; ++e) rk[r][e] = mlab[2 * (size_t)c[r][e] + 1];
     }
+    const int32_t *lay = mlab + 2 * (size_t)mstride + (size_t)hstride;
 #pragma unroll 1
     for (int k = 1; k < nl; ++k) {
-        const int32_t *m = mlab + (k == 1 ? 0 : 2 * (size_t)mstride + (size_t)(k - 1) * (size_t)hstride);
         int32_t *out = im.lab + (size_t)k * (size_t)n;
         if (threadIdx.x == 0) kc = 0;
         __syncthreads();
@@ -786,7 +794,9 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_out(Src src_ch, int32_t nchunks
         for (int r = 0; r < RUNS; ++r) {
             int32_t v[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = m[k == 1 ? c[r][e] : rk[r][e]];
+            for (int e = 0; e < 4; ++e)
+                v[e] = k == 1 ? mlab[(nl >= 3 ? 2 : 1) * (size_t)c[r][e]]
+                              : lay[(size_t)rk[r][e] * lstride + (k - 2)];
 #pragma unroll
             for (int e = 0; e < 4; ++e) own += (p0[r] + e < n && v[e] == p0[r] + e) ? 1 : 0;
             if (vec && p0[r] + 3 < n) {
@@ -867,14 +877,13 @@ __device__ __forceinline__ int wf_emit(const int32_t (&v)[OUT_RUNS][4], const in
     return own;
 }
 
-// Table bases passed one by one (t[0] layer 1 by id, t[1] the ranks, t[k]
-// layer k by rank): unrelated scalar bases, so every gather addresses its
-// table as base + 32-bit offset.
+// Table bases: t[0] layer 1 by region id (nl == 2, gathered as raw buffer
+// loads) or the 8-byte region records (nl >= 3); t[1] the 16-byte rank
+// records of layers 2 .. nl-1. Records cut the gathers of a pixel from nl to
+// 1 + ceil((nl - 2) / 4), each to one cache line.
 struct WfTabs {
-    const int32_t *t[WF_OUT_MAXNL];
-    uint32_t bytes;    // size of the tables by region id, t[0] and t[1] (< 4 GiB: larger arenas take the
-                       // layer-by-layer kernel)
-    uint32_t bytes_r;  // size of each table by rank, t[2] ..
+    const int32_t *t[2];
+    uint32_t bytes;    // size of t[0] when nl == 2 (< 4 GiB: larger arenas take the layer-by-layer kernel)
 };
 
 template <class Src, int NLM>
@@ -921,25 +930,47 @@ __global__ __launch_bounds__(OUT_T) void k_wf_out_p(Src src_ch, int32_t nchunks,
         }
     }
     int32_t V[NLM][OUT_RUNS][4];
-    wf_gather(V[0], off, table_rsrc(tabs.t[0], tabs.bytes), need);  // layer 1, by region id
-    // layers >= 2 are gathered by the rank of the layer-1 root, once per
-    // change of that rank along the run (layer-1 regions are larger, so its
-    // runs are longer than the region id's)
     uint32_t need_r = need;
-    if constexpr (NLM >= 2) {
+    if constexpr (NLM == 1) {
+        wf_gather(V[0], off, table_rsrc(tabs.t[0], tabs.bytes), need);  // layer 1, by region id
+    } else {
+        // one 8-byte record per region id: {layer-1 label, rank of the
+        // layer-1 root}; then, by that rank, 16-byte records of four later
+        // layers each (once per change of the rank along the run: layer-1
+        // regions are larger, so its runs are longer than the region id's)
+        const int2 *T1 = (const int2 *)tabs.t[0];
+        const int4 *TL = (const int4 *)tabs.t[1];
+        constexpr int G = (NLM - 1 + 3) / 4;  // 16-byte groups per rank record
         int32_t rk[OUT_RUNS][4];
-        wf_gather(rk, off, table_rsrc(tabs.t[1], tabs.bytes), need);
+#pragma unroll
+        for (int r = 0; r < OUT_RUNS; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (need >> (4 * r + e) & 1u) {
+                    const int2 q = T1[off[r][e] >> 2];
+                    V[0][r][e] = q.x;
+                    rk[r][e] = q.y;
+                }
         wf_fill(rk, need);
         need_r = 0;
 #pragma unroll
         for (int r = 0; r < OUT_RUNS; ++r)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                off[r][e] = (uint32_t)rk[r][e] * 4u;
+            for (int e = 0; e < 4; ++e)
                 if (e == 0 || rk[r][e] != rk[r][e - 1]) need_r |= 1u << (4 * r + e);
-            }
 #pragma unroll
-        for (int k = 2; k <= NLM; ++k) wf_gather(V[k - 1], off, table_rsrc(tabs.t[k], tabs.bytes_r), need_r);
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int r = 0; r < OUT_RUNS; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (need_r >> (4 * r + e) & 1u) {
+                        const int4 q = TL[(size_t)(uint32_t)rk[r][e] * G + g];
+                        if (1 + 4 * g < NLM) V[1 + 4 * g][r][e] = q.x;
+                        if (2 + 4 * g < NLM) V[2 + 4 * g][r][e] = q.y;
+                        if (3 + 4 * g < NLM) V[3 + 4 * g][r][e] = q.z;
+                        if (4 + 4 * g < NLM) V[4 + 4 * g][r][e] = q.w;
+                    }
     }
     int own[NLM];
 #pragma unroll
@@ -963,11 +994,8 @@ static int wf_out_pipelined(Launch &lc, const Src &src_ch, int32_t nchunks, int3
     dim3 grid(nchunks > 0 ? nchunks : 1);
     WfTabs tabs{};
     tabs.bytes = (uint32_t)((size_t)mstride * 4);
-    tabs.bytes_r = (uint32_t)((size_t)hstride * 4);
     tabs.t[0] = mlab;
-    if (nl >= 3) tabs.t[1] = mlab + mstride;
-    for (int k = 2; k < nl && k < WF_OUT_MAXNL; ++k)
-        tabs.t[k] = mlab + 2 * (size_t)mstride + (size_t)(k - 1) * (size_t)hstride;
+    if (nl >= 3) tabs.t[1] = mlab + 2 * (size_t)mstride + (size_t)hstride;
     switch (nl - 1) {
 #define WF_OUT_P(M)                                                                                               \
     case M:                                                                                                       \
@@ -1090,22 +1118,22 @@ int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, int32_t 
 }
 
 int launch_root_list(Launch &lc, int32_t bound, const int32_t *nreg0, const int32_t *par, int32_t *R1, int32_t *id1,
-                     int32_t cap, int32_t *scratch, int32_t *n1) {
+                     int32_t ids, int32_t cap, int32_t *scratch, int32_t *n1) {
     const int32_t nb = (bound + SCAN_B - 1) / SCAN_B > 0 ? (bound + SCAN_B - 1) / SCAN_B : 1;
     int32_t *bcnt = scratch, *tmp = scratch + nb;
     int rc = lc.run("wf_union", k_root_count, dim3(nb), dim3(NTHREADS), nreg0, par, bcnt);
     if (rc) return rc;
     if ((rc = launch_scan(lc, nb, bcnt, tmp, n1))) return rc;
     return lc.run("wf_union", k_root_scatter, dim3(nb), dim3(NTHREADS), nreg0, par, (const int32_t *)bcnt, R1, id1,
-                  cap);
+                  ids, cap);
 }
 int root_list_tmp_len(int32_t bound) {
     const int32_t nb = (bound + SCAN_B - 1) / SCAN_B > 0 ? (bound + SCAN_B - 1) / SCAN_B : 1;
     return nb + scan_tmp_len(nb);
 }
 int launch_wf_compress1(Launch &lc, int32_t bound, const int32_t *nreg0, int32_t *par, const int32_t *rlist,
-                        int32_t *mlab1, int32_t *id1) {
-    return lc.run("wf_compress", k_wf_compress1, list_grid(bound), dim3(NTHREADS), nreg0, par, rlist, mlab1, id1);
+                        int32_t *mlab1, int32_t *id1, int32_t ms) {
+    return lc.run("wf_compress", k_wf_compress1, list_grid(bound), dim3(NTHREADS), nreg0, par, rlist, mlab1, id1, ms);
 }
 // The root list holds a few per cent of the pixels on natural images: its
 // grids are sized for bound / 32 ids (grid-stride loops cover any length), so
@@ -1119,8 +1147,8 @@ int launch_wf_union_l(Launch &lc, int32_t bound, const int32_t *n1, int32_t cap,
     return lc.run("wf_union", k_wf_union_l, root_grid(bound), dim3(NTHREADS), n1, cap, R1, key, par);
 }
 int launch_wf_compress_l(Launch &lc, int32_t bound, const int32_t *n1, int32_t cap, const int32_t *R1, int32_t *par,
-                         const int32_t *rlist, int32_t *Mk) {
-    return lc.run("wf_compress", k_wf_compress_l, root_grid(bound), dim3(NTHREADS), n1, cap, R1, par, rlist, Mk);
+                         const int32_t *rlist, int32_t *Mk, int32_t ls) {
+    return lc.run("wf_compress", k_wf_compress_l, root_grid(bound), dim3(NTHREADS), n1, cap, R1, par, rlist, Mk, ls);
 }
 int launch_wf_union(Launch &lc, int32_t bound, const int32_t *nreg0, uint64_t *key, int32_t *par) {
     int rc = lc.run("wf_union", k_wf_hook, list_grid(bound), dim3(NTHREADS), nreg0, (const uint64_t *)key, par);

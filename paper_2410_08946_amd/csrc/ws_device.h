@@ -302,26 +302,6 @@ __device__ __forceinline__ void lunion(int *par, int a, int b) {
     }
 }
 
-// Block-wide "did any thread change something" for loops that run until a
-// pass changes nothing, in 12 bytes of LDS (the library's reduction behind
-// __syncthreads_or takes 256). Three flags are used in turn: pass `it` sets
-// and reads flag it % 3 and clears flag (it + 2) % 3, which every thread read
-// before this pass's barrier and none sets before the next one. The flags
-// must be zero, and a barrier passed, before the first pass.
-struct BlockAny {
-    int *f;
-    int it = 0;
-    __device__ __forceinline__ bool operator()(bool pred) {
-        if (pred) f[it] = 1;
-        __syncthreads();
-        const bool any = f[it] != 0;
-        const int next = it == 2 ? 0 : it + 1;
-        if (threadIdx.x == 0) f[next == 2 ? 0 : next + 1] = 0;
-        it = next;
-        return any;
-    }
-};
-
 // Appends `value` to list[] for every lane with pred set; one atomic per wave.
 __device__ __forceinline__ void wave_append(bool pred, int32_t value, int32_t *list, int32_t *counter) {
     uint64_t m = __ballot(pred);

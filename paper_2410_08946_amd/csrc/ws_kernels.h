@@ -185,14 +185,14 @@ int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, int32_t 
 // list R1 with ranks in id1 and its length in *n1 (scratch: root_list_tmp_len
 // ints); layer 1's compression with ranks; union and compression over R1.
 int launch_root_list(Launch &lc, int32_t bound, const int32_t *nreg0, const int32_t *par, int32_t *R1, int32_t *id1,
-                     int32_t cap, int32_t *scratch, int32_t *n1);
+                     int32_t ids, int32_t cap, int32_t *scratch, int32_t *n1);
 int root_list_tmp_len(int32_t bound);
 int launch_wf_compress1(Launch &lc, int32_t bound, const int32_t *nreg0, int32_t *par, const int32_t *rlist,
-                        int32_t *mlab1, int32_t *id1);
+                        int32_t *mlab1, int32_t *id1, int32_t ms);
 int launch_wf_union_l(Launch &lc, int32_t bound, const int32_t *n1, int32_t cap, const int32_t *R1, uint64_t *key,
                       int32_t *par);
 int launch_wf_compress_l(Launch &lc, int32_t bound, const int32_t *n1, int32_t cap, const int32_t *R1, int32_t *par,
-                         const int32_t *rlist, int32_t *Mk);
+                         const int32_t *rlist, int32_t *Mk, int32_t ls);
 int launch_wf_union(Launch &lc, int32_t bound, const int32_t *nreg0, uint64_t *key, int32_t *par);
 int launch_grey_u16(Launch &lc, const void *in, bool u16, uint16_t *out, int32_t n);
 int launch_recon_raise(Launch &lc, uint16_t *I, const int32_t *cimg, const uint64_t *key, const int32_t *nreg0,

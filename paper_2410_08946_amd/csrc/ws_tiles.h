@@ -21,7 +21,7 @@
 //
 // Arrows (Eq. (1) for pixels with a lower neighbour; the equal neighbour at
 // distance d-1 with the smallest index for resolved plateau pixels) are then
-// contracted inside each tile by pointer jumping (Step III), minimal plateaux
+// contracted inside each tile by path-halving Finds (Step III), minimal plateaux
 // are joined by union-find (Step IV), and every tile-local component is named
 // by its smallest pixel. Crossings between tiles go through a global
 // union-find that always hooks the larger root below the smaller, so every
@@ -566,8 +566,8 @@ __device__ __forceinline__ int border_index(int x, int y, int z) {
 }
 
 // ---------------------------------------------------------------------------
-// Tile-local labelling. Every pixel's arrow inside the tile is contracted by
-// pointer jumping (path reduction, Step III) to its terminal: a local minimum,
+// Tile-local labelling. Every pixel's arrow inside the tile is contracted (a
+// Find with path halving, Step III) to its terminal: a local minimum,
 // a minimal-plateau pixel, or an exit whose arrow leaves the tile. Minimal-
 // plateau pixels are then joined with their equal neighbours by union-find
 // (Step IV). Each tile-local component is named by its smallest pixel (LDS
@@ -590,7 +590,6 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
     // parent array once every arrow is known
     __shared__ GC sI[S::CELLS];
     __shared__ int sD[S::CELLS];
-    __shared__ int sany[3];
     int *sP = sD;
     {
         if ((int)blockIdx.x >= ntiles) return;
@@ -602,7 +601,6 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
         int32_t *L = im.lab;
         int ox, oy, oz;
         ws_tile<SH>(g, lt, ox, oy, oz);
-        if (threadIdx.x < 3) sany[threadIdx.x] = 0;
         load_grey_dist<SH, T>(g, (const T *)im.grey, Darena + im.pix0, sI, sD, ox, oy, oz);
         __syncthreads();
         uint32_t minzone = 0, inimg = 0;
@@ -643,20 +641,10 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
 #pragma unroll
         for (int j = 0; j < PER; ++j) sP[threadIdx.x + j * NTHREADS] = tos[j];
         __syncthreads();
-        // pointer jumping to the in-tile terminals
-        BlockAny any{sany};
-        for (;;) {
-            int changed = 0;
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                int i = threadIdx.x + j * NTHREADS;
-                int p = sP[i];
-                int pp = sP[p];
-                if (pp != p) { sP[i] = pp; changed = 1; }
-            }
-            if (!any(changed)) break;
-        }
-        // minimal plateaux: join equal neighbours after p inside the tile
+        // The arrows form an in-tile forest whose roots are the terminals (a
+        // local minimum, a minimal-plateau pixel, or an exit); the Finds below
+        // reach them, halving the paths they walk (Step III inside the tile).
+        // Minimal plateaux: join equal neighbours after p inside the tile.
         if (minzone) {
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
