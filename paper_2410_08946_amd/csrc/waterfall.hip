@@ -670,8 +670,14 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_compress1(const int32_t *__rest
          c += gridDim.x * NTHREADS) {
         int32_t r = gfind_ro(par, c);
         par[c] = r;
-        mlab1[(size_t)c * ms] = rlist[r];
-        if (r != c) id1[(size_t)c * ms] = id1[(size_t)r * ms];  // roots already hold their rank
+        if (ms == 2 && id1 == mlab1 + 1) {
+            // one 8-byte store of the region's record (the root's rank was
+            // set by the root list; its record's rank is rewritten unchanged)
+            ((int2 *)mlab1)[c] = make_int2(rlist[r], id1[(size_t)r * 2]);
+        } else {
+            mlab1[(size_t)c * ms] = rlist[r];
+            if (r != c) id1[(size_t)c * ms] = id1[(size_t)r * ms];  // roots already hold their rank
+        }
     }
 }
 

@@ -776,8 +776,26 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_merge(Src src, int32_t ntiles, 
     }
 }
 
+// Walks r[j] to its root for every j with bit j of `live`, all paths of the
+// thread together so that their loads overlap.
+template <int PER>
+__device__ __forceinline__ void find_walk(const int32_t *L, int32_t (&r)[PER], uint32_t live) {
+    while (live) {
+        int32_t nxt[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) nxt[j] = (live >> j & 1u) ? L[r[j]] : r[j];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            if (!(live >> j & 1u)) continue;
+            if (nxt[j] == r[j]) live &= ~(1u << j);
+            else r[j] = nxt[j];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Final Find of every pixel (APRUF form: each pixel follows its own path), per
+// Final Find of every pixel (APRUF form: every pixel, or in volumes one pixel
+// per tile-local component name, follows its path to the root), per
 // watershed tile.
 // ---------------------------------------------------------------------------
 template <int SH, class Src>
@@ -807,21 +825,47 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_find(Src src, int32_t ntiles) {
         int32_t l0[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) r[j] = l0[j] = L[p[j]];
-        // chase all PER paths together so their loads overlap
         uint32_t live = 0;
+        if constexpr (shape_ndim<SH>() == 3) {
+            // Volumes: most pixels still name their tile-local component by
+            // its smallest pixel, a pixel of this tile, and paths across tiles
+            // are long. One pixel per such name walks to the root (claimed in
+            // LDS by the name's in-tile index) and the others read the
+            // result; a pixel whose name lies outside the tile walks on its
+            // own. (2D tiles measured faster walking every pixel.)
+            __shared__ int owner[PIX];
+            __shared__ int32_t root_of[PIX];
 #pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (ok[j]) live |= 1u << j;
-        while (live) {
-            int32_t nxt[PER];
-#pragma unroll
-            for (int j = 0; j < PER; ++j) nxt[j] = (live >> j & 1u) ? L[r[j]] : r[j];
+            for (int j = 0; j < PER; ++j) owner[threadIdx.x + j * NTHREADS] = -1;
+            __syncthreads();
+            int ci[PER];  // in-tile index of the name, -1 outside the tile
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
-                if (!(live >> j & 1u)) continue;
-                if (nxt[j] == r[j]) live &= ~(1u << j);
-                else r[j] = nxt[j];
+                ci[j] = -1;
+                if (!ok[j]) continue;
+                int x, y, z;
+                pixel_coords(g, l0[j], x, y, z);
+                x -= ox;
+                y -= oy;
+                z -= oz;
+                if (x >= 0 && x < TS::X && y >= 0 && y < TS::Y && z >= 0 && z < TS::Z)
+                    ci[j] = x + TS::X * (y + TS::Y * z);
+                if (ci[j] < 0 || atomicCAS(&owner[ci[j]], -1, (int)threadIdx.x + j * NTHREADS) == -1)
+                    live |= 1u << j;
             }
+            find_walk<PER>(L, r, live);
+#pragma unroll
+            for (int j = 0; j < PER; ++j)
+                if (ok[j] && ci[j] >= 0 && owner[ci[j]] == (int)threadIdx.x + j * NTHREADS) root_of[ci[j]] = r[j];
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < PER; ++j)
+                if (ok[j] && ci[j] >= 0) r[j] = root_of[ci[j]];
+        } else {
+#pragma unroll
+            for (int j = 0; j < PER; ++j)
+                if (ok[j]) live |= 1u << j;
+            find_walk<PER>(L, r, live);
         }
         // a pixel whose label already is its root keeps it (no store)
 #pragma unroll
