@@ -411,7 +411,7 @@ int32_t ws_tiles_of(const std::vector<Part<Src>> &parts) {
 template <class Src>
 size_t rec_ints(const std::vector<Part<Src>> &parts) {
     size_t n = 0;
-    for (auto &p : parts) n += (size_t)p.nws * (size_t)wsk::border_cells(p.shape);
+    for (auto &p : parts) n += (size_t)p.nws * (size_t)wsk::record_ints(p.shape);
     return n;
 }
 
@@ -528,7 +528,7 @@ int run_watershed(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, bo
     for (auto &p : parts) {
         WS_TRY(wsk::launch_ws_label(lc, p.ws, full_grid(p.nws), p.conn, p.shape, u16, D, rec + ro));
         WS_TRY(wsk::launch_ws_merge(lc, p.ws, full_grid(p.nws), p.conn, p.shape, u16, rec + ro));
-        ro += (size_t)p.nws * (size_t)wsk::border_cells(p.shape);
+        ro += (size_t)p.nws * (size_t)wsk::record_ints(p.shape);
     }
     if (c->step3 == 0) {
         for (auto &p : parts) WS_TRY(wsk::launch_ws_find(lc, p.ws, full_grid(p.nws), p.conn, p.shape));
@@ -820,7 +820,7 @@ int reserve(ws_ctx *c, int64_t n) {
     if ((rc = ensure(c, c->edges, wft * (size_t)wsk::wf_slab_cap(8) * 12, "reserved edge slabs")) != WS_OK) return rc;
     if ((rc = ensure(c, c->ecnt, wft * 4, "reserved edge counts")) != WS_OK) return rc;
     if ((rc = ensure(c, c->stamp, tiles * 16, "reserved stamps")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->rec, tiles * (size_t)wsk::border_cells(3) * 4, "reserved records")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->rec, tiles * (size_t)wsk::record_ints(3) * 4, "reserved records")) != WS_OK) return rc;
     if ((rc = ensure(c, c->tilecnt, tiles * 16 * 4, "reserved tile counts")) != WS_OK) return rc;
     int32_t nch = (int32_t)std::min<int64_t>((int64_t)N / 4096 + 2 * kReserveItems, 0x7fffffff / 2);
     size_t tbl = (((size_t)nch + wsk::scan_tmp_len(nch)) * 4 + 15) / 16 * 16 + (size_t)nch * 64 * sizeof(wsk::RankWord);
@@ -938,7 +938,7 @@ size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int conn, int dtyp
     size_t job = N * (b + 4 * (size_t)NL);
     // at the default tile shapes (2 and 3), which have the most border records per pixel
     const Geom gd = make_geom(nx, ny, nz, ndim);
-    size_t ws = N * 4 /* D */ + (size_t)gd.ntx * gd.nty * gd.ntz * (16 + 4 * (size_t)wsk::border_cells(ndim));
+    size_t ws = N * 4 /* D */ + (size_t)gd.ntx * gd.nty * gd.ntz * (16 + 4 * (size_t)wsk::record_ints(ndim));
     size_t wf = 0;
     if (NL >= 2) {
         size_t tiles = (size_t)wsk::wf_tiles(make_geom(nx, ny, nz, ndim), ndim);

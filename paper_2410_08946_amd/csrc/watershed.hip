@@ -154,16 +154,16 @@ int launch_fill2_i32(Launch &lc, int32_t *a, int32_t na, int32_t va, int32_t *b,
     if (n <= 0) return 0;
     return lc.run("fill", k_fill2_i32, dim3((uint32_t)((n + 255) / 256)), dim3(256), a, na, va, b, nb, vb);
 }
-int border_cells(int shape) {
+int record_ints(int shape) {
     switch (shape) {
-    case 2: return Border<2>::NB;
-    case 12: return Border<12>::NB;
-    case 22: return Border<22>::NB;
-    case 32: return Border<32>::NB;
-    case 3: return Border<3>::NB;
-    case 13: return Border<13>::NB;
-    case 23: return Border<23>::NB;
-    case 33: return Border<33>::NB;
+    case 2: return Border<2>::RS;
+    case 12: return Border<12>::RS;
+    case 22: return Border<22>::RS;
+    case 32: return Border<32>::RS;
+    case 3: return Border<3>::RS;
+    case 13: return Border<13>::RS;
+    case 23: return Border<23>::RS;
+    case 33: return Border<33>::RS;
     default: return 0;
     }
 }

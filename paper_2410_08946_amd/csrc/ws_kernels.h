@@ -119,7 +119,7 @@ struct WsShape {
     WS_SHAPE_SRC(OneImg)
     WS_SHAPE_SRC(ImgTable)
 #undef WS_SHAPE_SRC
-    static int border_cells();
+    static int record_ints();
 };
 extern template struct WsShape<2>;
 extern template struct WsShape<12>;
@@ -155,7 +155,7 @@ WS_DECL_SRC(OneImg)
 WS_DECL_SRC(ImgTable)
 #undef WS_DECL_SRC
 
-int border_cells(int shape);   // border records per tile of a shape (0 for an unknown shape)
+int record_ints(int shape);   // record ints per tile of a shape: a count and at most one entry per border cell (0 for an unknown shape)
 int launch_ws_stages(Launch &lc, const Geom &g, int conn, bool u16, const void *I, const int32_t *D, int32_t *bal,
                      int32_t *arrow);
 int launch_fill_i32(Launch &lc, int32_t *a, int32_t n, int32_t v);

@@ -141,14 +141,6 @@ __device__ __forceinline__ void relax_tile(const GC *sI, DC *sD) {
     }
 }
 
-template <int SH>
-__device__ __forceinline__ bool on_tile_border(int x, int y, int z) {
-    using TS = TileShape<SH>;
-    bool b = x == 0 || x == TS::X - 1 || y == 0 || y == TS::Y - 1;
-    if (shape_ndim<SH>() == 3) b = b || z == 0 || z == TS::Z - 1;
-    return b;
-}
-
 // Faces of the tile a pixel lies on: bit 0 / 1 the low / high x face, 2 / 3
 // y, 4 / 5 z.
 template <int SH>
@@ -513,57 +505,24 @@ __device__ __forceinline__ int lds_arrow(const GC *sI, const int *sD, int s) {
 }
 
 // ---------------------------------------------------------------------------
-// Border cells of a tile, enumerated face by face: NB(2D) = 2X + 2(Y-2),
-// NB(3D) = 2XY + (Z-2)(2X + 2(Y-2)). border_cell maps b -> (x, y, z) and
-// border_index is its inverse for cells on the border.
+// Border cells of a tile: NB(2D) = 2X + 2(Y-2), NB(3D) = 2XY + (Z-2)(2X +
+// 2(Y-2)). A tile's crossing records take RS = NB + 1 ints: a count, then at
+// most one entry per border cell (only border pixels have a neighbour outside
+// the tile).
 // ---------------------------------------------------------------------------
 template <int SH> struct Border {
     using TS = TileShape<SH>;
     static constexpr int RING = 2 * TS::X + 2 * (TS::Y - 2);
     static constexpr int FACE = TS::X * TS::Y;
     static constexpr int NB = shape_ndim<SH>() == 2 ? RING : 2 * FACE + (TS::Z - 2) * RING;
+    static constexpr int RS = NB + 1;
 };
 
-template <int SH>
-__device__ __forceinline__ void border_cell(int b, int &x, int &y, int &z) {
-    using TS = TileShape<SH>;
-    using B = Border<SH>;
-    z = 0;
-    if (shape_ndim<SH>() == 3) {
-        if (b < 2 * B::FACE) {
-            x = b % TS::X;
-            y = (b / TS::X) % TS::Y;
-            z = b < B::FACE ? 0 : TS::Z - 1;
-            return;
-        }
-        b -= 2 * B::FACE;
-        z = 1 + b / B::RING;
-        b %= B::RING;
-    }
-    if (b < 2 * TS::X) {
-        x = b % TS::X;
-        y = b < TS::X ? 0 : TS::Y - 1;
-        return;
-    }
-    b -= 2 * TS::X;
-    y = 1 + (b >> 1);
-    x = (b & 1) ? TS::X - 1 : 0;
-}
-
-template <int SH>
-__device__ __forceinline__ int border_index(int x, int y, int z) {
-    using TS = TileShape<SH>;
-    using B = Border<SH>;
-    int base = 0;
-    if (shape_ndim<SH>() == 3) {
-        if (z == 0) return x + TS::X * y;
-        if (z == TS::Z - 1) return B::FACE + x + TS::X * y;
-        base = 2 * B::FACE + (z - 1) * B::RING;
-    }
-    if (y == 0) return base + x;
-    if (y == TS::Y - 1) return base + TS::X + x;
-    return base + 2 * TS::X + 2 * (y - 1) + (x == TS::X - 1 ? 1 : 0);
-}
+// A crossing record: the pixel's in-tile index and the neighbour its arrow
+// leaves the tile through, or REC_PLATEAU for a minimal-plateau pixel with an
+// equal neighbour outside the tile (after it in the neighbourhood order).
+constexpr int REC_PLATEAU = 31;
+__host__ __device__ constexpr int32_t rec_entry(int i, int k) { return (int32_t)((i << 5) | k); }
 
 // ---------------------------------------------------------------------------
 // Tile-local labelling. Every pixel's arrow inside the tile is contracted (a
@@ -571,10 +530,9 @@ __device__ __forceinline__ int border_index(int x, int y, int z) {
 // a minimal-plateau pixel, or an exit whose arrow leaves the tile. Minimal-
 // plateau pixels are then joined with their equal neighbours by union-find
 // (Step IV). Each tile-local component is named by its smallest pixel (LDS
-// atomicMin), written into L. For every border pixel the crossing it needs in
-// the global merge is recorded in rec: the target of an arrow that leaves the
-// tile, -2 for a minimal-plateau pixel with an equal neighbour outside the
-// tile, -1 otherwise.
+// atomicMin), written into L. The crossings the global merge needs are
+// appended to the tile's records (rec_entry): every arrow that leaves the
+// tile, and every minimal-plateau pixel with an equal neighbour outside it.
 // ---------------------------------------------------------------------------
 template <int SH, int CONN, typename T, class Src>
 __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, const int32_t *__restrict__ Darena,
@@ -590,9 +548,11 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
     // parent array once every arrow is known
     __shared__ GC sI[S::CELLS];
     __shared__ int sD[S::CELLS];
+    __shared__ int nrec;
     int *sP = sD;
     {
         if ((int)blockIdx.x >= ntiles) return;
+        if (threadIdx.x == 0) nrec = 0;
         const int t = xcd_tile(blockIdx.x, ntiles);
         Img im;
         int lt;
@@ -605,24 +565,24 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
         __syncthreads();
         uint32_t minzone = 0, inimg = 0;
         int tos[PER];
-        int32_t *trec = rec + (size_t)t * Border<SH>::NB;
+        int32_t *trec = rec + (size_t)t * Border<SH>::RS;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             int i = threadIdx.x + j * NTHREADS;
             int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
             int gx = ox + x, gy = oy + y, gz = oz + z;
             int to = i;
+            int32_t ent = -1;  // crossing record of this pixel, if any
             if (in_image(g, gx, gy, gz)) {
                 inimg |= 1u << j;
                 int s = S::at(x, y, z);
                 int k = lds_arrow<SH, CONN>(sI, sD, s);
-                int code = -1;
                 if (k >= 0) {
                     int xx = x + nb_dx<CONN>(k), yy = y + nb_dy<CONN>(k), zz = z + nb_dz<CONN>(k);
                     if (xx >= 0 && xx < TS::X && yy >= 0 && yy < TS::Y && zz >= 0 && zz < TS::Z)
                         to = xx + TS::X * (yy + TS::Y * zz);
                     else
-                        code = (gx + nb_dx<CONN>(k)) + g.nx * ((gy + nb_dy<CONN>(k)) + g.ny * (gz + nb_dz<CONN>(k)));
+                        ent = rec_entry(i, k);
                 } else if (k == -2) {
                     minzone |= 1u << j;
                     int v = sI[s];
@@ -630,14 +590,22 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
                     for (int k2 = CONN / 2; k2 < CONN; ++k2) {  // neighbours after p
                         int xx = x + nb_dx<CONN>(k2), yy = y + nb_dy<CONN>(k2), zz = z + nb_dz<CONN>(k2);
                         bool inside = xx >= 0 && xx < TS::X && yy >= 0 && yy < TS::Y && zz >= 0 && zz < TS::Z;
-                        if (!inside && sI[s + S::template off<CONN>(k2)] == v) code = -2;
+                        if (!inside && sI[s + S::template off<CONN>(k2)] == v) ent = rec_entry(i, REC_PLATEAU);
                     }
                 }
-                if (on_tile_border<SH>(x, y, z)) trec[border_index<SH>(x, y, z)] = code;
+            }
+            // append the wave's records with one LDS reservation
+            const uint64_t m = __ballot(ent >= 0);
+            if (m) {  // wave-uniform
+                int wbase = 0;
+                if (__lane_id() == 0) wbase = atomicAdd(&nrec, __popcll(m));
+                wbase = __shfl(wbase, 0);
+                if (ent >= 0) trec[1 + wbase + __popcll(m & lanes_below())] = ent;
             }
             tos[j] = to;
         }
         __syncthreads();  // every distance read: the array becomes the parents
+        if (threadIdx.x == 0) trec[0] = nrec;
 #pragma unroll
         for (int j = 0; j < PER; ++j) sP[threadIdx.x + j * NTHREADS] = tos[j];
         __syncthreads();
@@ -715,12 +683,15 @@ __device__ __forceinline__ void wave_unique_union(int32_t *L, bool want, int32_t
 
 // ---------------------------------------------------------------------------
 // Unions for every arrow / minimal-plateau adjacency that crosses a tile
-// border, driven by the records of k_ws_label. One thread per border cell.
+// border, driven by the tile's records from k_ws_label: one thread per record.
+// Each exit record starts its own tile-local component (an exit is the
+// terminal of its in-tile path), so its pair of roots is distinct and it
+// unites directly; plateau records of volumes first elect one lane per pair.
 // ---------------------------------------------------------------------------
 template <int SH, int CONN, typename T, class Src>
 __global__ __launch_bounds__(NTHREADS) void k_ws_merge(Src src, int32_t ntiles, const int32_t *__restrict__ rec) {
     using TS = TileShape<SH>;
-    constexpr int NB = Border<SH>::NB;
+    constexpr int RS = Border<SH>::RS;
     {
         if ((int)blockIdx.x >= ntiles) return;
         const int t = xcd_tile(blockIdx.x, ntiles);
@@ -732,34 +703,29 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_merge(Src src, int32_t ntiles, 
         int32_t *L = im.lab;
         int ox, oy, oz;
         ws_tile<SH>(g, lt, ox, oy, oz);
-        const int32_t *trec = rec + (size_t)t * NB;
-        // all of this thread's records are loaded in one batch (cells past
-        // the border count read record 0 and are skipped)
-        constexpr int MU = (NB + NTHREADS - 1) / NTHREADS;
-        int32_t codes[MU];
-#pragma unroll
-        for (int u = 0; u < MU; ++u) {
-            int b = threadIdx.x + u * NTHREADS;
-            codes[u] = trec[b < NB ? b : 0];
-        }
-        // candidate slot 0: the arrow that leaves the tile; slots 1 .. CONN/2:
-        // equal minimal-plateau neighbours after p outside the tile
-#pragma unroll
-        for (int u = 0; u < MU; ++u) {
-            const int b = threadIdx.x + u * NTHREADS;
-            int x = 0, y = 0, z = 0;
-            if (b < NB) border_cell<SH>(b, x, y, z);
-            const int gx = ox + x, gy = oy + y, gz = oz + z;
-            const int32_t code = b < NB && in_image(g, gx, gy, gz) ? codes[u] : -1;
+        const int32_t *trec = rec + (size_t)t * RS;
+        const int n = trec[0];
+        for (int e0 = 0; e0 < n; e0 += NTHREADS) {  // uniform trip count
+            const int e = e0 + (int)threadIdx.x;
+            const int32_t ent = e < n ? trec[1 + e] : -1;
+            int gx = 0, gy = 0, gz = 0, k = -1;
+            if (ent >= 0) {
+                const int i = ent >> 5;
+                k = ent & 31;
+                gx = ox + i % TS::X;
+                gy = oy + (i / TS::X) % TS::Y;
+                gz = oz + i / (TS::X * TS::Y);
+            }
             const int32_t p = gx + g.nx * (gy + g.ny * gz);
-            const int v = code == -2 ? (int)I[p] : 0;
+            if (k >= 0 && k != REC_PLATEAU)
+                gunion(L, p, (gx + nb_dx<CONN>(k)) + g.nx * ((gy + nb_dy<CONN>(k)) + g.ny * (gz + nb_dz<CONN>(k))));
+            const bool plat = k == REC_PLATEAU;
+            const int v = plat ? (int)I[p] : 0;
 #pragma unroll
-            for (int k = CONN / 2 - 1; k < CONN; ++k) {
+            for (int k2 = CONN / 2; k2 < CONN; ++k2) {  // equal neighbours after p outside the tile
                 int32_t r = -1;
-                if (k == CONN / 2 - 1) {
-                    r = code >= 0 ? code : -1;
-                } else if (code == -2) {
-                    int xx = gx + nb_dx<CONN>(k), yy = gy + nb_dy<CONN>(k), zz = gz + nb_dz<CONN>(k);
+                if (plat) {
+                    int xx = gx + nb_dx<CONN>(k2), yy = gy + nb_dy<CONN>(k2), zz = gz + nb_dz<CONN>(k2);
                     bool outside = !(xx >= ox && xx < ox + TS::X && yy >= oy && yy < oy + TS::Y && zz >= oz &&
                                      zz < oz + TS::Z);
                     if (outside && in_image(g, xx, yy, zz)) {
@@ -767,8 +733,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_merge(Src src, int32_t ntiles, 
                         if ((int)I[q] == v) r = q;
                     }
                 }
-                // volumes (47 % border cells, many per component pair) elect
-                // one lane per pair; 2D tiles measured faster without
+                // volumes (many plateau records per component pair) elect one
+                // lane per pair; 2D tiles measured faster without
                 if constexpr (shape_ndim<SH>() == 3) wave_unique_union(L, r >= 0, p, r);
                 else if (r >= 0) gunion(L, p, r);
             }
@@ -995,8 +961,8 @@ WS_SHAPE_DEFS(ImgTable)
 #undef WS_SHAPE_DISPATCH
 
 template <int SH>
-int WsShape<SH>::border_cells() {
-    return Border<SH>::NB;
+int WsShape<SH>::record_ints() {
+    return Border<SH>::RS;
 }
 
 }  // namespace wsk
