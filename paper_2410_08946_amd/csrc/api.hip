@@ -720,17 +720,15 @@ int wf_buffers(ws_ctx *c, size_t arena, int nimg, int32_t ntiles, int32_t nchunk
     if ((rc = ensure(c, c->cimg, arena * 4, "pixel region ids")) != WS_OK) return rc;
     if ((rc = ensure(c, c->rlist, arena * 4, "region labels")) != WS_OK) return rc;
     if (NL >= 2 && (rc = ensure(c, c->mlab, mlab_ints(arena, NL, nimg) * 4, "layer labels")) != WS_OK) return rc;
-    if ((rc = ensure(c, c->edges, 3 * E * 4, "edge slabs")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->edges, E * wsk::EdgeSlabs::kEntryBytes, "edge slabs")) != WS_OK) return rc;
     if ((rc = ensure(c, c->ecnt, (size_t)ntiles * 4, "edge counts")) != WS_OK) return rc;
     b.key = (uint64_t *)c->key.p;
     b.par = (int32_t *)c->par.p;
     b.cimg = (int32_t *)c->cimg.p;
     b.rlist = (int32_t *)c->rlist.p;
     b.mlab = (int32_t *)c->mlab.p;
-    int32_t *edges = (int32_t *)c->edges.p;
-    b.es.a = edges;
-    b.es.b = edges + E;
-    b.es.w = edges + 2 * E;
+    b.es.p = (uint64_t *)c->edges.p;
+    b.es.w = (uint16_t *)(b.es.p + E);
     b.es.cnt = (int32_t *)c->ecnt.p;
     b.es.cap = cap;
     return WS_OK;
@@ -785,7 +783,7 @@ int run_waterfall(ws_ctx *c, Launch &lc, const std::vector<Part<Src>> &parts, co
                 // then share one group (fewer key atomics) while a group's
                 // distinct edges still fit its LDS hash
                 int32_t f = gin >= wft ? 1 : 4;
-                WS_TRY(wsk::launch_wf_level(lc, wft, gin, f, b.es.cap, b.par, b.key, b.es.a, b.es.cnt));
+                WS_TRY(wsk::launch_wf_level(lc, wft, gin, f, b.par, b.key, b.es));
                 gin *= f;
                 WS_TRY(wsk::launch_wf_union_l(lc, bound, n1, (int32_t)H, R1, b.key, b.par));
                 WS_TRY(wsk::launch_wf_compress_l(lc, bound, n1, (int32_t)H, R1, b.par, b.rlist, lay + (k - 2),
@@ -817,7 +815,7 @@ int reserve(ws_ctx *c, int64_t n) {
     if ((rc = ensure(c, c->key, N * 8, "reserved keys")) != WS_OK) return rc;
     if ((rc = ensure(c, c->mlab, mlab_ints(N, kLayers, kReserveItems) * 4, "reserved layer labels")) != WS_OK)
         return rc;
-    if ((rc = ensure(c, c->edges, wft * (size_t)wsk::wf_slab_cap(8) * 12, "reserved edge slabs")) != WS_OK) return rc;
+    if ((rc = ensure(c, c->edges, wft * (size_t)wsk::wf_slab_cap(8) * wsk::EdgeSlabs::kEntryBytes, "reserved edge slabs")) != WS_OK) return rc;
     if ((rc = ensure(c, c->ecnt, wft * 4, "reserved edge counts")) != WS_OK) return rc;
     if ((rc = ensure(c, c->stamp, tiles * 16, "reserved stamps")) != WS_OK) return rc;
     if ((rc = ensure(c, c->rec, tiles * (size_t)wsk::record_ints(3) * 4, "reserved records")) != WS_OK) return rc;
@@ -943,7 +941,7 @@ size_t ws_footprint_bytes(int64_t nx, int64_t ny, int64_t nz, int conn, int dtyp
     if (NL >= 2) {
         size_t tiles = (size_t)wsk::wf_tiles(make_geom(nx, ny, nz, ndim), ndim);
         wf = N * (8 /* keys */ + 4 /* parents */ + 4 /* ids */ + 4 /* labels */) + mlab_ints(N, NL, 1) * 4 /* layers */ +
-             tiles * (12 * (size_t)wsk::wf_slab_cap(conn) + 4 + 4 * (size_t)NL) +
+             tiles * (wsk::EdgeSlabs::kEntryBytes * (size_t)wsk::wf_slab_cap(conn) + 4 + 4 * (size_t)NL) +
              ((size_t)wsk::wf_chunks((int32_t)N) + 2) * (64 * 16 + 8) /* region-id rank tables */;
     }
     return job + ws + wf + (1 <<20);
@@ -1259,7 +1257,7 @@ int ws_rag(ws_ctx *c, const int32_t *labels, const void *grad, int dtype, int64_
     auto *ucount = (unsigned int *)(rb + o_cnt);
     WS_TRY(wsk::launch_fill_i32(lc, (int32_t *)ucount, 1, 0));
     if (total > 0) {
-        WS_TRY(wsk::launch_rag_gather(lc, nt, b.es.cap, b.es.a, b.es.cnt, eoff, keys, h));
+        WS_TRY(wsk::launch_rag_gather(lc, nt, b.es, eoff, keys, h));
         WS_TRY(wsk::rag_sort_reduce(lc, total, keys, h, keys2, h2, ukeys, uh, ucount, rb + o_tmp, tmp_bytes));
     }
     WS_TRY(wsk::launch_rag_final(lc, ukeys, uh, ucount, b.rlist, capacity, edge_a, edge_b, edge_h, n_edges));

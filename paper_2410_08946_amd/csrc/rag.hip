@@ -19,8 +19,8 @@
 namespace wsk {
 
 // Edges of tile t (ecnt[t] of them, at t * cap in the slabs) to eoff[t] ...
-__global__ __launch_bounds__(NTHREADS) void k_rag_gather(int32_t ntiles, int32_t cap, const int32_t *__restrict__ ea,
-                                                         const int32_t *__restrict__ eb, const int32_t *__restrict__ ew,
+__global__ __launch_bounds__(NTHREADS) void k_rag_gather(int32_t ntiles, int32_t cap, const uint64_t *__restrict__ ep,
+                                                         const uint16_t *__restrict__ ew,
                                                          const int32_t *__restrict__ ecnt,
                                                          const int32_t *__restrict__ eoff,
                                                          unsigned long long *__restrict__ keys,
@@ -30,8 +30,8 @@ __global__ __launch_bounds__(NTHREADS) void k_rag_gather(int32_t ntiles, int32_t
     const int32_t n = ecnt[t], o = eoff[t];
     const size_t base = (size_t)t * (size_t)cap;
     for (int32_t i = threadIdx.x; i < n; i += NTHREADS) {
-        keys[o + i] = ((unsigned long long)(uint32_t)ea[base + i] << 32) | (uint32_t)eb[base + i];
-        h[o + i] = ew[base + i];
+        keys[o + i] = (unsigned long long)ep[base + i];
+        h[o + i] = (int32_t)ew[base + i];
     }
 }
 
@@ -53,11 +53,10 @@ __global__ __launch_bounds__(NTHREADS) void k_rag_final(const unsigned long long
     }
 }
 
-int launch_rag_gather(Launch &lc, int32_t ntiles, int32_t cap, const int32_t *edges, const int32_t *ecnt,
-                      const int32_t *eoff, unsigned long long *keys, int32_t *h) {
-    size_t E = (size_t)ntiles * (size_t)cap;
-    return lc.run("rag", k_rag_gather, dim3(ntiles > 0 ? ntiles : 1), dim3(NTHREADS), ntiles, cap, edges, edges + E,
-                  edges + 2 * E, ecnt, eoff, keys, h);
+int launch_rag_gather(Launch &lc, int32_t ntiles, const EdgeSlabs &es, const int32_t *eoff, unsigned long long *keys,
+                      int32_t *h) {
+    return lc.run("rag", k_rag_gather, dim3(ntiles > 0 ? ntiles : 1), dim3(NTHREADS), ntiles, es.cap,
+                  (const uint64_t *)es.p, (const uint16_t *)es.w, (const int32_t *)es.cnt, eoff, keys, h);
 }
 
 size_t rag_sort_tmp_bytes(int32_t n) {

@@ -127,13 +127,12 @@ __device__ __forceinline__ void edge_keys(int *hk, unsigned long long *hv, uint6
 }
 
 // An edge that found no hash slot: straight to the slab and the global keys.
-__device__ __forceinline__ void edge_direct(int *ectr, uint64_t *__restrict__ key, int32_t *__restrict__ ea,
-                                            int32_t *__restrict__ eb, int32_t *__restrict__ eww, size_t base,
-                                            int32_t lo, int32_t hi, uint32_t w) {
+__device__ __forceinline__ void edge_direct(int *ectr, uint64_t *__restrict__ key, uint64_t *__restrict__ ep,
+                                            uint16_t *__restrict__ eww, size_t base, int32_t lo, int32_t hi,
+                                            uint32_t w) {
     size_t pos = base + atomicAdd(ectr, 1);
-    ea[pos] = lo;
-    eb[pos] = hi;
-    eww[pos] = (int32_t)w;
+    ep[pos] = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi;
+    eww[pos] = (uint16_t)w;
     atomicMin((unsigned long long *)(key + lo), (unsigned long long)(((uint64_t)w << 32) | (uint32_t)hi));
     atomicMin((unsigned long long *)(key + hi), (unsigned long long)(((uint64_t)w << 32) | (uint32_t)lo));
 }
@@ -143,8 +142,7 @@ __device__ __forceinline__ void edge_direct(int *ectr, uint64_t *__restrict__ ke
 template <int BITS>
 __device__ __forceinline__ void emit_edges(const unsigned long long *ek, const unsigned int *ew, int *hk,
                                            unsigned long long *hv, int *ectr, uint64_t *__restrict__ key,
-                                           int32_t *__restrict__ ea, int32_t *__restrict__ eb,
-                                           int32_t *__restrict__ eww, size_t base) {
+                                           uint64_t *__restrict__ ep, uint16_t *__restrict__ eww, size_t base) {
     for (int h0 = 0; h0 < ESLOTS; h0 += NTHREADS) {
         int h = h0 + threadIdx.x;
         unsigned long long pk = ek[h];
@@ -158,9 +156,8 @@ __device__ __forceinline__ void emit_edges(const unsigned long long *ek, const u
         size_t pos = base + wbase + __popcll(m & lanes_below());
         int32_t lo = (int32_t)(pk >> 32), hi = (int32_t)(uint32_t)pk;
         uint32_t w = ew[h];
-        ea[pos] = lo;
-        eb[pos] = hi;
-        eww[pos] = (int32_t)w;
+        ep[pos] = (uint64_t)pk;
+        eww[pos] = (uint16_t)w;
         edge_keys<BITS>(hk, hv, key, lo, hi, w);
     }
 }
@@ -322,8 +319,7 @@ template <int CONN, typename T, class Src>
 __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, const RankWord *__restrict__ words,
                                                      const int32_t *__restrict__ nreg0, int32_t *__restrict__ cimg,
                                                      int32_t *__restrict__ rlist, uint64_t *__restrict__ key,
-                                                     int32_t *__restrict__ ea,
-                                                     int32_t *__restrict__ eb, int32_t *__restrict__ eww,
+                                                     uint64_t *__restrict__ ep, uint16_t *__restrict__ eww,
                                                      int32_t *__restrict__ ecnt, int32_t cap) {
     constexpr int NDIM = ndim_of<CONN>();
     using TS = WfTile<NDIM>;
@@ -366,23 +362,23 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
     const uint32_t cmax = nr > 0 ? (uint32_t)(nr - 1) : 0u;
     {
         constexpr int PER = (CELLS + NTHREADS - 1) / NTHREADS;
-        int32_t idx[PER];
+        int32_t idx[PER], lv[PER];
+        T gv[PER];
         bool ok[PER], own[PER];
+        uint64_t ownm;
+        const uint64_t okm = box_cells<SX, SY, SZ, PER, LX, LY, TS::X, TS::Y, TS::Z>(
+            g, ox - LX, oy - LY, oz,
+            [&](int j, int32_t i) {
+                idx[j] = i;
+                lv[j] = L0[i];
+                gv[j] = I[i];
+            },
+            &ownm);
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            int c = threadIdx.x + j * NTHREADS;
-            int cx = c % SX, cy = (c / SX) % SY, cz = c / (SX * SY);
-            int x = ox + cx - LX, y = oy + cy - LY, z = oz + cz;
-            ok[j] = c < CELLS && in_image(g, x, y, z);
-            own[j] = ok[j] && cx >= LX && cx < LX + TS::X && cy >= LY && cy < LY + TS::Y && cz < TS::Z;
-            idx[j] = ok[j] ? x + g.nx * (y + g.ny * z) : 0;
+            ok[j] = okm >> j & 1;
+            own[j] = ownm >> j & 1;
         }
-        int32_t lv[PER];
-        T gv[PER];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) lv[j] = L0[idx[j]];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) gv[j] = I[idx[j]];
         // region ids by rank, one record load per cell
         const size_t w0 = (size_t)im.tile0[TK_CH] * 64;
         RankWord rw[PER];
@@ -430,7 +426,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
             uint32_t w = v > wq ? v : wq;
             int32_t lo = a < b ? a : b, hi = a < b ? b : a;
             uint64_t pair = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi;
-            if (!edge_insert(ek, ew, pair, w)) edge_direct(&ectr, key, ea, eb, eww, base, lo, hi, w);
+            if (!edge_insert(ek, ew, pair, w)) edge_direct(&ectr, key, ep, eww, base, lo, hi, w);
         }
     }
     __syncthreads();
@@ -439,7 +435,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
         hv[h] = NOKEY;
     }
     __syncthreads();
-    emit_edges<RBITS>(ek, ew, hk, hv, &ectr, key, ea, eb, eww, base);
+    emit_edges<RBITS>(ek, ew, hk, hv, &ectr, key, ep, eww, base);
     __syncthreads();
     flush_keys<RBITS>(hk, hv, key);
     if (threadIdx.x == 0) ecnt[t] = ectr;
@@ -458,8 +454,8 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NTHREADS) void k_wf_level(int32_t ntiles, int32_t gin, int32_t f, int32_t cap,
                                                        const int32_t *__restrict__ par, uint64_t *__restrict__ key,
-                                                       int32_t *__restrict__ ea, int32_t *__restrict__ eb,
-                                                       int32_t *__restrict__ eww, int32_t *__restrict__ ecnt) {
+                                                       uint64_t *__restrict__ ep, uint16_t *__restrict__ eww,
+                                                       int32_t *__restrict__ ecnt) {
     constexpr int RBITS = 10;
     __shared__ unsigned long long ek[ESLOTS];
     __shared__ unsigned int ew[ESLOTS];
@@ -514,18 +510,17 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_level(int32_t ntiles, int32_t g
         }
         // branch-free: lanes past the end read slab entry 0 (allocated, any
         // contents) and parent 0, and use neither
-        int32_t a[LEV_U], b[LEV_U];
+        uint64_t pr[LEV_U];
 #pragma unroll
         for (int u = 0; u < LEV_U; ++u) {
-            a[u] = ea[at[u]];
-            b[u] = eb[at[u]];
+            pr[u] = ep[at[u]];
             w[u] = (uint32_t)eww[at[u]];
         }
 #pragma unroll
         for (int u = 0; u < LEV_U; ++u) {
             const bool ok = e0 + u * NTHREADS + (int)threadIdx.x < total;
-            ra[u] = par[ok ? a[u] : 0];
-            rb[u] = par[ok ? b[u] : 0];
+            ra[u] = par[ok ? (int32_t)(pr[u] >> 32) : 0];
+            rb[u] = par[ok ? (int32_t)(uint32_t)pr[u] : 0];
         }
         // this batch's reads precede every write below: a workgroup's vector
         // memory operations pass through its CU's cache in issue order, so a
@@ -537,12 +532,12 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_level(int32_t ntiles, int32_t g
             if (e < total && ra[u] != rb[u]) {
                 int32_t lo = ra[u] < rb[u] ? ra[u] : rb[u], hi = ra[u] < rb[u] ? rb[u] : ra[u];
                 uint64_t pair = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi;
-                if (!edge_insert(ek, ew, pair, w[u])) edge_direct(&ectr, key, ea, eb, eww, base, lo, hi, w[u]);
+                if (!edge_insert(ek, ew, pair, w[u])) edge_direct(&ectr, key, ep, eww, base, lo, hi, w[u]);
             }
         }
     }
     __syncthreads();
-    emit_edges<RBITS>(ek, ew, hk, hv, &ectr, key, ea, eb, eww, base);
+    emit_edges<RBITS>(ek, ew, hk, hv, &ectr, key, ep, eww, base);
     __syncthreads();
     flush_keys<RBITS>(hk, hv, key);
     if (threadIdx.x == 0) ecnt[t0] = ectr;
@@ -1113,14 +1108,13 @@ int launch_scan(Launch &lc, int32_t n, int32_t *data, int32_t *tmp, int32_t *tot
     return lc.run("wf_ids", k_scan_apply, dim3(nb), dim3(NTHREADS), n, data, (const int32_t *)tmp);
 }
 
-int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, int32_t cap, const int32_t *par, uint64_t *key,
-                    int32_t *edges, int32_t *ecnt) {
+int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, const int32_t *par, uint64_t *key,
+                    const EdgeSlabs &es) {
     if (f < 1 || f > MAX_F || gin < 1) return -1;
     int64_t gout = (int64_t)gin * f;
     int64_t ng = ((int64_t)ntiles + gout - 1) / gout;
-    size_t E = (size_t)ntiles * (size_t)cap;
-    return lc.run("wf_level", k_wf_level, dim3((uint32_t)(ng > 0 ? ng : 1)), dim3(NTHREADS), ntiles, gin, f, cap, par,
-                  key, edges, edges + E, edges + 2 * E, ecnt);
+    return lc.run("wf_level", k_wf_level, dim3((uint32_t)(ng > 0 ? ng : 1)), dim3(NTHREADS), ntiles, gin, f, es.cap,
+                  par, key, es.p, es.w, es.cnt);
 }
 
 int launch_root_list(Launch &lc, int32_t bound, const int32_t *nreg0, const int32_t *par, int32_t *R1, int32_t *id1,
@@ -1189,7 +1183,7 @@ static int wf_pix_t(Launch &lc, const Src &src, const TileGrid &tg, const WfIds 
                     int32_t *cimg, int32_t *rlist, uint64_t *key, const EdgeSlabs &es) {
     if (es.cap < wf_slab_cap(CONN)) return -1;  // a tile's forward pairs must fit its slab
     return lc.run("wf_pix", k_wf_pix<CONN, T, Src>, dim3(tg.grid), dim3(NTHREADS), src, tg.ntiles,
-                  (const RankWord *)ids.words, nreg0, cimg, rlist, key, es.a, es.b, es.w, es.cnt, es.cap);
+                  (const RankWord *)ids.words, nreg0, cimg, rlist, key, es.p, es.w, es.cnt, es.cap);
 }
 
 template <class Src>

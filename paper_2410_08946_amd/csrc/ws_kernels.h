@@ -83,18 +83,21 @@ struct TileGrid {
     int32_t grid = 0;
 };
 
-// The waterfall's per-tile edge slabs: entry j of tile t's slab is
-// (a[t * cap + j], b[t * cap + j], w[t * cap + j]); cnt[t] holds the tile's
-// edge count. A launch over a sub-range of the tiles gets pointers advanced
-// to its first tile (same cap).
+// The waterfall's per-tile edge slabs: entry j of tile t's slab is the
+// region pair p[t * cap + j] (smaller id in the high word) and its pass
+// height w[t * cap + j] (grey values are at most 16 bits); cnt[t] holds the
+// tile's edge count. 10 bytes per entry. A launch over a sub-range of the
+// tiles gets pointers advanced to its first tile (same cap).
 struct EdgeSlabs {
-    int32_t *a = nullptr, *b = nullptr, *w = nullptr, *cnt = nullptr;
+    uint64_t *p = nullptr;
+    uint16_t *w = nullptr;
+    int32_t *cnt = nullptr;
     int32_t cap = 0;
+    static constexpr size_t kEntryBytes = 10;
     EdgeSlabs at(int32_t t0) const {
         EdgeSlabs e = *this;
         const size_t o = (size_t)t0 * (size_t)cap;
-        e.a += o;
-        e.b += o;
+        e.p += o;
         e.w += o;
         e.cnt += t0;
         return e;
@@ -179,8 +182,8 @@ int wf_slab_cap(int conn);              // edge slab entries per tile
 int wf_max_merge();                     // largest group merge factor of launch_wf_level
 int scan_tmp_len(int32_t n);            // ints of scratch launch_scan needs for n
 int launch_scan(Launch &lc, int32_t n, int32_t *data, int32_t *tmp, int32_t *total_out);
-int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, int32_t cap, const int32_t *par, uint64_t *key,
-                    int32_t *edges, int32_t *ecnt);
+int launch_wf_level(Launch &lc, int32_t ntiles, int32_t gin, int32_t f, const int32_t *par, uint64_t *key,
+                    const EdgeSlabs &es);
 // Layers >= 2 over the layer-1 roots (see waterfall.hip, 2b): the sorted root
 // list R1 with ranks in id1 and its length in *n1 (scratch: root_list_tmp_len
 // ints); layer 1's compression with ranks; union and compression over R1.
@@ -203,8 +206,8 @@ int launch_img_counts(Launch &lc, const Img *tab, const Img &one, int32_t nimg, 
                       const int32_t *tile_cnt, int64_t *const *outs, int64_t *one_out);
 
 // rag.hip
-int launch_rag_gather(Launch &lc, int32_t ntiles, int32_t cap, const int32_t *edges, const int32_t *ecnt,
-                      const int32_t *eoff, unsigned long long *keys, int32_t *h);
+int launch_rag_gather(Launch &lc, int32_t ntiles, const EdgeSlabs &es, const int32_t *eoff, unsigned long long *keys,
+                      int32_t *h);
 size_t rag_sort_tmp_bytes(int32_t n);
 int rag_sort_reduce(Launch &lc, int32_t n, unsigned long long *keys, int32_t *h, unsigned long long *keys2,
                     int32_t *h2, unsigned long long *ukeys, int32_t *uh, unsigned int *ucount, void *tmp,

@@ -68,23 +68,12 @@ __device__ __forceinline__ void load_grey_dist(const Geom &g, const T *__restric
                                                GC *sI, int *sD, int ox, int oy, int oz) {
     using S = Lds<SH, 1>;
     constexpr int PER = (S::CELLS + NTHREADS - 1) / NTHREADS;
-    int32_t idx[PER];
-    uint32_t okm = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        int c = threadIdx.x + j * NTHREADS;
-        int cx = c % S::SX, cy = (c / S::SX) % S::SY, cz = c / (S::SX * S::SY);
-        int x = ox - 1 + cx, y = oy - 1 + cy, z = oz - S::RZ + cz;
-        bool ok = c < S::CELLS && in_image(g, x, y, z);
-        okm |= (ok ? 1u : 0u) << j;
-        idx[j] = ok ? x + g.nx * (y + g.ny * z) : 0;
-    }
     T v[PER];
     int32_t d[PER];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) v[j] = I[idx[j]];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) d[j] = D[idx[j]];
+    const uint64_t okm = box_cells<S::SX, S::SY, S::SZ, PER>(g, ox - 1, oy - 1, oz - S::RZ, [&](int j, int32_t i) {
+        v[j] = I[i];
+        d[j] = D[i];
+    });
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         int c = threadIdx.x + j * NTHREADS;
