@@ -413,17 +413,27 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_pix(Src src, int32_t ntiles, co
     for (int i = threadIdx.x; i < PIX; i += NTHREADS) {  // uniform trip count
         int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
         int s = (z * SY + (y + LY)) * SX + (x + LX);
-        int a = sL[s];
-        if (a < 0) continue;
-        uint32_t v = (uint32_t)sI[s];
+        const int a = sL[s];
+        const uint32_t v = (uint32_t)sI[s];
+        // every forward neighbour's id and grey value is read before any
+        // test (one LDS wait, no branch per neighbour)
+        int nbL[CONN];
+        uint32_t nbI[CONN];
 #pragma unroll
         for (int k = 0; k < CONN; ++k) {
             if (!forward<CONN>(k)) continue;
-            int o = s + nb_dx<CONN>(k) + SX * (nb_dy<CONN>(k) + SY * nb_dz<CONN>(k));
-            int b = sL[o];
+            const int o = s + nb_dx<CONN>(k) + SX * (nb_dy<CONN>(k) + SY * nb_dz<CONN>(k));
+            nbL[k] = sL[o];
+            nbI[k] = (uint32_t)sI[o];
+        }
+        if (a < 0) continue;
+#pragma unroll
+        for (int k = 0; k < CONN; ++k) {
+            if (!forward<CONN>(k)) continue;
+            const int b = nbL[k];
             if (b < 0 || b == a) continue;
-            uint32_t wq = (uint32_t)sI[o];
-            uint32_t w = v > wq ? v : wq;
+            const uint32_t wq = nbI[k];
+            const uint32_t w = v > wq ? v : wq;
             int32_t lo = a < b ? a : b, hi = a < b ? b : a;
             uint64_t pair = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi;
             if (!edge_insert(ek, ew, pair, w)) edge_direct(&ectr, key, ep, eww, base, lo, hi, w);

@@ -158,9 +158,12 @@ __device__ __forceinline__ uint32_t cross_faces(const GC *sI, const DC *sD, int 
         const bool out = xx < 0 || xx >= TS::X || yy < 0 || yy >= TS::Y || zz < 0 || zz >= TS::Z;
         if (!out) continue;
         const int o = sc + S::template off<CONN>(k);
-        if ((int)sI[o] != v || sD[o] <= d + 1) continue;  // d + 1 cannot overflow: d < INF here
-        b |= (xx < 0 ? 1u : 0u) | (xx >= TS::X ? 2u : 0u) | (yy < 0 ? 4u : 0u) | (yy >= TS::Y ? 8u : 0u) |
-             (zz < 0 ? 16u : 0u) | (zz >= TS::Z ? 32u : 0u);
+        // both reads unconditional (no branch per neighbour); d + 1 cannot
+        // overflow: d < INF here
+        const int wi = sI[o], wd = sD[o];
+        const uint32_t f = (xx < 0 ? 1u : 0u) | (xx >= TS::X ? 2u : 0u) | (yy < 0 ? 4u : 0u) | (yy >= TS::Y ? 8u : 0u) |
+                           (zz < 0 ? 16u : 0u) | (zz >= TS::Z ? 32u : 0u);
+        b |= ((wi == v) & (wd > d + 1)) ? f : 0u;
     }
     return b;
 }
@@ -321,6 +324,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_init(Src src, int32_t ntiles, i
         load_grey<SH, 2, T>(g, (const T *)im.grey, sI, ox, oy, oz);
         __syncthreads();
         // Initial distances on the tile plus a ring of width 1 (Step I state test).
+        // (An unrolled form with stepped coordinates measured slower.)
         for (int c = threadIdx.x; c < S1::CELLS; c += NTHREADS) {
             int cx = c % S1::SX, cy = (c / S1::SX) % S1::SY, cz = c / (S1::SX * S1::SY);
             int s = S2::at(cx - 1, cy - 1, cz - S1::RZ);
@@ -485,12 +489,18 @@ __device__ __forceinline__ int lds_arrow(const GC *sI, const int *sD, int s) {
         }
         return (m < v) ? kq : -1;
     }
+    // first (smallest index) equal neighbour one step closer; all neighbours
+    // are read, without an early exit (no per-neighbour branch), and the
+    // reverse order leaves the smallest match. -1 is unreachable for a
+    // converged distance field.
+    int ke = -1;
 #pragma unroll
-    for (int k = 0; k < CONN; ++k) {           // first (smallest index) equal
-        int o = s + S::template off<CONN>(k);  // neighbour one step closer
-        if (sI[o] == v && sD[o] == d - 1) return k;
+    for (int k = CONN - 1; k >= 0; --k) {
+        const int o = s + S::template off<CONN>(k);
+        const int wi = sI[o], wd = sD[o];
+        if ((wi == v) & (wd == d - 1)) ke = k;  // both reads unconditional: no branch per neighbour
     }
-    return -1;  // unreachable for a converged distance field
+    return ke;
 }
 
 // ---------------------------------------------------------------------------
@@ -623,9 +633,32 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
         // parent entry once every root is known: a root holds its own index,
         // and the root of an in-image pixel is itself in the image (arrows and
         // plateau unions never reach a cell outside), so it is a candidate
+        // All PER paths of the thread advance together (their LDS reads
+        // overlap), each by path halving: x moves to its grandparent, which
+        // also becomes its parent.
         int root[PER];
+        uint32_t live = 0;
 #pragma unroll
-        for (int j = 0; j < PER; ++j) root[j] = lfind(sP, threadIdx.x + j * NTHREADS);
+        for (int j = 0; j < PER; ++j) {
+            root[j] = threadIdx.x + j * NTHREADS;
+            live |= 1u << j;
+        }
+        while (live) {
+            int px[PER], ppx[PER];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) px[j] = sP[root[j]];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) ppx[j] = sP[px[j]];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                if (px[j] == root[j]) {
+                    live &= ~(1u << j);
+                } else {
+                    if (ppx[j] != px[j]) sP[root[j]] = ppx[j];
+                    root[j] = ppx[j];
+                }
+            }
+        }
         __syncthreads();
         int *cm = sP;
 #pragma unroll
