@@ -583,7 +583,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_union(const int32_t *__restrict
         if (kk == NOKEY) continue;
         key[c] = NOKEY;
         int32_t tg = (int32_t)(uint32_t)(kk & 0xffffffffull);
-        if (tg > c) gunion(par, c, tg);
+        if (tg > c) gunion_halve(par, c, tg);
     }
 }
 
@@ -710,7 +710,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_union_l(const int32_t *__restri
         if (kk == NOKEY) continue;
         key[c] = NOKEY;
         int32_t tg = (int32_t)(uint32_t)(kk & 0xffffffffull);
-        if (tg > c) gunion(par, c, tg);
+        if (tg > c) gunion_halve(par, c, tg);
     }
 }
 

@@ -309,16 +309,7 @@ __device__ __forceinline__ int32_t ld_par(const int32_t *a) {
 // smaller one, so a tree's root is the smallest index in it. Every chase
 // moves to strictly smaller indices, so finds end even on stale parents, and
 // every failed CAS returns a smaller parent, so unions end too.
-__device__ __forceinline__ int32_t gfind(int32_t *par, int32_t x) {
-    for (;;) {
-        int32_t px = ld_par(par + x);
-        if (px == x) return x;
-        int32_t ppx = ld_par(par + px);
-        if (ppx != px) __hip_atomic_store(par + x, ppx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        x = px;
-    }
-}
-
+//
 // Root of x without writing: safe while other threads store final roots into
 // the same array (a path-halving write could replace a final root by an
 // intermediate ancestor).
@@ -330,6 +321,21 @@ __device__ __forceinline__ int32_t gfind_ro(const int32_t *par, int32_t x) {
     }
 }
 
+// Root of x, splitting the path on the way: every visited node's parent
+// moves to its grandparent (a plain store; it only ever moves a parent to an
+// ancestor).
+__device__ __forceinline__ int32_t gfind(int32_t *par, int32_t x) {
+    for (;;) {
+        int32_t px = ld_par(par + x);
+        if (px == x) return x;
+        int32_t ppx = ld_par(par + px);
+        if (ppx != px) __hip_atomic_store(par + x, ppx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        x = px;
+    }
+}
+
+// Union of the trees of a and b: one find after the other (the watershed's
+// crossings, whose paths are one to three steps long).
 __device__ __forceinline__ void gunion(int32_t *par, int32_t a, int32_t b) {
     a = gfind(par, a);
     b = gfind(par, b);
@@ -339,6 +345,37 @@ __device__ __forceinline__ void gunion(int32_t *par, int32_t a, int32_t b) {
         if (old == a) return;
         a = gfind(par, old);
         b = gfind(par, b);
+    }
+}
+
+// Union of the trees of a and b with both finds advancing together, so their
+// loads overlap, by path halving: x moves to its grandparent, which also
+// becomes its parent. Faster for the waterfall's region unions, whose paths
+// are longer; slower for the watershed's short crossing paths.
+__device__ __forceinline__ void gunion_halve(int32_t *par, int32_t a, int32_t b) {
+    for (;;) {
+        for (;;) {
+            const int32_t pa = ld_par(par + a), pb = ld_par(par + b);
+            if (pa == a && pb == b) break;
+            const int32_t ppa = ld_par(par + pa), ppb = ld_par(par + pb);
+            if (pa != a) {
+                if (ppa != pa) __hip_atomic_store(par + a, ppa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                a = ppa;
+            }
+            if (pb != b) {
+                if (ppb != pb) __hip_atomic_store(par + b, ppb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                b = ppb;
+            }
+        }
+        if (a == b) return;
+        if (a < b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        const int32_t old = atomicCAS(par + a, a, b);
+        if (old == a) return;
+        a = old;  // a was hooked meanwhile: continue from its new parent
     }
 }
 
