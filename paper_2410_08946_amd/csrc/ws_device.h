@@ -323,13 +323,15 @@ __device__ __forceinline__ int32_t gfind_ro(const int32_t *par, int32_t x) {
 
 // Root of x, splitting the path on the way: every visited node's parent
 // moves to its grandparent (a plain store; it only ever moves a parent to an
-// ancestor).
+// ancestor). A grandparent equal to the parent ends the walk at once (the
+// parent is a root), one load earlier than re-reading it.
 __device__ __forceinline__ int32_t gfind(int32_t *par, int32_t x) {
     for (;;) {
         int32_t px = ld_par(par + x);
         if (px == x) return x;
         int32_t ppx = ld_par(par + px);
-        if (ppx != px) __hip_atomic_store(par + x, ppx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (ppx == px) return px;
+        __hip_atomic_store(par + x, ppx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         x = px;
     }
 }

@@ -517,11 +517,14 @@ template <int SH> struct Border {
     static constexpr int RS = NB + 1;
 };
 
-// A crossing record: the pixel's in-tile index and the neighbour its arrow
-// leaves the tile through, or REC_PLATEAU for a minimal-plateau pixel with an
-// equal neighbour outside the tile (after it in the neighbourhood order).
+// A crossing record: the in-tile index of the smallest pixel of the pixel's
+// tile-local component (bits 17..28), the pixel's in-tile index (5..16) and
+// the neighbour its arrow leaves the tile through, or REC_PLATEAU for a
+// minimal-plateau pixel with an equal neighbour outside the tile (after it in
+// the neighbourhood order) (0..4). Tiles hold at most 4096 pixels.
 constexpr int REC_PLATEAU = 31;
 __host__ __device__ constexpr int32_t rec_entry(int i, int k) { return (int32_t)((i << 5) | k); }
+__host__ __device__ constexpr int32_t rec_with_min(int32_t e, int cm) { return (int32_t)(cm << 17) | e; }
 
 // ---------------------------------------------------------------------------
 // Tile-local labelling. Every pixel's arrow inside the tile is contracted (a
@@ -565,6 +568,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
         uint32_t minzone = 0, inimg = 0;
         int tos[PER];
         int32_t *trec = rec + (size_t)t * Border<SH>::RS;
+        static_assert(PIX <= 4096, "in-tile indices fit the records' 12-bit fields");
+        int32_t ents[PER];  // crossing record of each pixel (without its component), -1 if none
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             int i = threadIdx.x + j * NTHREADS;
@@ -593,18 +598,10 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
                     }
                 }
             }
-            // append the wave's records with one LDS reservation
-            const uint64_t m = __ballot(ent >= 0);
-            if (m) {  // wave-uniform
-                int wbase = 0;
-                if (__lane_id() == 0) wbase = atomicAdd(&nrec, __popcll(m));
-                wbase = __shfl(wbase, 0);
-                if (ent >= 0) trec[1 + wbase + __popcll(m & lanes_below())] = ent;
-            }
+            ents[j] = ent;
             tos[j] = to;
         }
         __syncthreads();  // every distance read: the array becomes the parents
-        if (threadIdx.x == 0) trec[0] = nrec;
 #pragma unroll
         for (int j = 0; j < PER; ++j) sP[threadIdx.x + j * NTHREADS] = tos[j];
         __syncthreads();
@@ -667,28 +664,40 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            if (!(inimg >> j & 1u)) continue;
-            int i = threadIdx.x + j * NTHREADS;
-            int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
-            int r = cm[root[j]];
-            int rx = r % TS::X, ry = (r / TS::X) % TS::Y, rz = r / (TS::X * TS::Y);
-            L[(ox + x) + g.nx * ((oy + y) + g.ny * (oz + z))] = (ox + rx) + g.nx * ((oy + ry) + g.ny * (oz + rz));
+            const int i = threadIdx.x + j * NTHREADS;
+            const int r = cm[root[j]];
+            if (inimg >> j & 1u) {
+                int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
+                int rx = r % TS::X, ry = (r / TS::X) % TS::Y, rz = r / (TS::X * TS::Y);
+                L[(ox + x) + g.nx * ((oy + y) + g.ny * (oz + z))] = (ox + rx) + g.nx * ((oy + ry) + g.ny * (oz + rz));
+            }
+            // append the wave's records, each with its component's smallest
+            // pixel, with one LDS reservation
+            const uint64_t m = __ballot(ents[j] >= 0);
+            if (m) {  // wave-uniform
+                int wbase = 0;
+                if (__lane_id() == 0) wbase = atomicAdd(&nrec, __popcll(m));
+                wbase = __shfl(wbase, 0);
+                if (ents[j] >= 0) trec[1 + wbase + __popcll(m & lanes_below())] = rec_with_min(ents[j], r);
+            }
         }
         __syncthreads();
+        if (threadIdx.x == 0) trec[0] = nrec;
     }
 }
 
-// Union of p and r for the lanes with `want`, once per distinct pair of the
-// roots they had after the tile pass: border cells next to each other mostly
-// join the same two tile-local components, so a wave first elects one lane
-// per distinct (L[p], L[r]) pair (ballots, no memory traffic) and only those
-// lanes run the global union, all at once.
-__device__ __forceinline__ void wave_unique_union(int32_t *L, bool want, int32_t p, int32_t r) {
+// Union of lp (the tile-pass root of a pixel, from its record) and the root
+// L[r] of its neighbour r for the lanes with `want`, once per distinct pair:
+// border cells next to each other mostly join the same two tile-local
+// components, so a wave first elects one lane per distinct (lp, L[r]) pair
+// (ballots, no memory traffic) and only those lanes run the global union, all
+// at once.
+__device__ __forceinline__ void wave_unique_union(int32_t *L, bool want, int32_t lp, int32_t r) {
     uint64_t pending = __ballot(want);
     if (pending == 0) return;  // wave-uniform
     int32_t a = -1, b = -1;
     if (want) {
-        const int32_t lp = ld_par(L + p), lr = ld_par(L + r);
+        const int32_t lr = ld_par(L + r);
         a = lp < lr ? lp : lr;
         b = lp < lr ? lr : lp;
     }
@@ -731,16 +740,18 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_merge(Src src, int32_t ntiles, 
             const int e = e0 + (int)threadIdx.x;
             const int32_t ent = e < n ? trec[1 + e] : -1;
             int gx = 0, gy = 0, gz = 0, k = -1;
+            int32_t pm = 0;  // smallest pixel of p's tile-local component (its tile-pass root)
             if (ent >= 0) {
-                const int i = ent >> 5;
+                const int i = (ent >> 5) & 0xfff, c = ent >> 17;
                 k = ent & 31;
                 gx = ox + i % TS::X;
                 gy = oy + (i / TS::X) % TS::Y;
                 gz = oz + i / (TS::X * TS::Y);
+                pm = (ox + c % TS::X) + g.nx * ((oy + (c / TS::X) % TS::Y) + g.ny * (oz + c / (TS::X * TS::Y)));
             }
             const int32_t p = gx + g.nx * (gy + g.ny * gz);
             if (k >= 0 && k != REC_PLATEAU)
-                gunion(L, p, (gx + nb_dx<CONN>(k)) + g.nx * ((gy + nb_dy<CONN>(k)) + g.ny * (gz + nb_dz<CONN>(k))));
+                gunion(L, pm, (gx + nb_dx<CONN>(k)) + g.nx * ((gy + nb_dy<CONN>(k)) + g.ny * (gz + nb_dz<CONN>(k))));
             const bool plat = k == REC_PLATEAU;
             const int v = plat ? (int)I[p] : 0;
 #pragma unroll
@@ -757,8 +768,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_merge(Src src, int32_t ntiles, 
                 }
                 // volumes (many plateau records per component pair) elect one
                 // lane per pair; 2D tiles measured faster without
-                if constexpr (shape_ndim<SH>() == 3) wave_unique_union(L, r >= 0, p, r);
-                else if (r >= 0) gunion(L, p, r);
+                if constexpr (shape_ndim<SH>() == 3) wave_unique_union(L, r >= 0, pm, r);
+                else if (r >= 0) gunion(L, pm, r);
             }
         }
     }
