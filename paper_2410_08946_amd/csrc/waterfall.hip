@@ -466,7 +466,7 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_level(int32_t ntiles, int32_t g
                                                        const int32_t *__restrict__ par, uint64_t *__restrict__ key,
                                                        uint64_t *__restrict__ ep, uint16_t *__restrict__ eww,
                                                        int32_t *__restrict__ ecnt) {
-    constexpr int RBITS = 10;
+    constexpr int RBITS = 9;  // 512 region slots: with 1024 edge slots the pass fits eight workgroups per CU
     __shared__ unsigned long long ek[ESLOTS];
     __shared__ unsigned int ew[ESLOTS];
     __shared__ int hk[1 << RBITS];
