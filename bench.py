@@ -202,6 +202,8 @@ def parse():
     ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="serve workload: request rates (req/s)")
     ap.add_argument("--requests", type=int, default=200, help="serve workload: requests per rate")
     ap.add_argument("--slots", type=int, default=4, help="serve workload: execution slots")
+    ap.add_argument("--burst", type=int, default=64,
+                    help="serve workload: jobs of the served-against-direct comparison (0 skips it)")
     ap.add_argument("--images", type=int, default=512, help="batch workload: number of images")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
                     help="1: the library replays launch graphs of the gradient and waterfall calls")
@@ -425,6 +427,7 @@ def bench_serve(args):
         del srv, jobs
         torch.cuda.empty_cache()
     best = max(r["throughput_mvox_s"] for r in results)
+    direct = serve_vs_direct(args, ctx, pool2, pool3, NL) if args.burst > 0 else None
     line = {
         "metric": "Mvoxel/s watershed+NL waterfall (served), p50/p99 latency",
         "value": best,
@@ -442,8 +445,56 @@ def bench_serve(args):
                                "NL=4, %d slots, device-memory admission" % args.slots,
                    "parallelism": "single GPU"},
         "rates": results,
+        "served_vs_direct": direct,
     }
     print(json.dumps(line), flush=True)
+
+
+def serve_vs_direct(args, ctx, pool2, pool3, NL):
+    """The same job sequence (the serving mix, args.burst jobs) run once as one
+    ws_watershed + ws_waterfall call per job on one stream and once through the
+    server with every job submitted at once; both timed from the first call to
+    the last result on the device, outputs compared job by job."""
+    import numpy as np
+    import torch
+
+    from paper_2410_08946_amd import serve
+
+    rng = np.random.default_rng(5)
+    picks, idx = rng.random(args.burst), rng.integers(0, 1 << 30, size=args.burst)
+    seq = [pool2[idx[k] % len(pool2)] if picks[k] < 0.7 else pool3[idx[k] % len(pool3)] for k in range(args.burst)]
+    vox = sum(int(g.numel()) for g, _ in seq)
+
+    def run_direct():
+        res = []
+        for g, conn in seq:
+            lab = ctx.watershed(g, conn)
+            res.append(ctx.waterfall(lab, g, conn, NL))
+        return res
+
+    run_direct()  # grows the context's buffers to the largest job
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    direct = run_direct()
+    torch.cuda.synchronize()
+    t_direct = time.perf_counter() - t0
+    srv = serve.Server(slots=args.slots, max_job_pixels=max(int(g.numel()) for g, _ in pool2 + pool3))
+    t0 = time.perf_counter()
+    jobs = [srv.submit(serve.Job(grad=g, conn=conn, NL=NL, jid=k)) for k, (g, conn) in enumerate(seq)]
+    srv.drain()
+    t_served = max(j.t_done for j in jobs) - t0
+    torch.cuda.synchronize()  # every slot's stream, before comparing on the default one
+    same = all(j.error is None and torch.equal(j.out, o) and torch.equal(j.nregions, n)
+               for j, (o, n) in zip(jobs, direct))
+    srv.close()
+    r = {"jobs": args.burst, "voxels": vox, "direct_ms": round(1e3 * t_direct, 2),
+         "served_ms": round(1e3 * t_served, 2), "direct_mvox_s": round(vox / t_direct / 1e6, 1),
+         "served_mvox_s": round(vox / t_served / 1e6, 1), "served_over_direct": round(t_direct / t_served, 3),
+         "identical_outputs": bool(same)}
+    print("bench: served vs direct: %s" % r, file=sys.stderr, flush=True)
+    del jobs, direct
+    torch.cuda.empty_cache()
+    return r
 
 
 def bench_recon(args):
