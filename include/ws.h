@@ -134,7 +134,7 @@ int ws_watershed(ws_ctx *ctx, const void *grad, int dtype, int64_t nx, int64_t n
  * the library holds on every device it runs on until the process ends; the
  * call allocates nothing (no hipMalloc, hipFree or allocating library call),
  * and it is never captured into a launch graph.
- *   Limit: the image's scratch (4 bytes per pixel plus 16 bytes per tile plus
+ *   Limit: the image's scratch (4 bytes per pixel plus 20 bytes per tile plus
  *   4 bytes per tile border cell) must fit the area: WS_EINVAL (nothing
  *   launched) otherwise. At the default tile shapes that holds up to about
  *   30 Mpx in 2D and 22 Mvoxel in 3D (4096 x 4096 and 256^3 fit).
