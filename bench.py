@@ -80,10 +80,19 @@ def path_roofline(b, NL, N, ms_step, counter_bytes):
     per = 4 + 3 * b + 52 + (NL - 1) * (b + 12)
     alg = per * N
     used = min(alg, counter_bytes) if counter_bytes else alg
-    achieved = used / (ms_step / 1e3) / 1e9
-    return {"bound": "hbm", "bytes_per_pixel": per, "algorithmic_bytes": alg,
-            "counter_bytes": counter_bytes, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    sec = ms_step / 1e3
+    achieved = used / sec / 1e9
+    io = b + 4 * NL  # compulsory floor: read the grey values once, write the NL layers
+    r = {"bound": "hbm", "bytes_per_pixel": per, "algorithmic_bytes": alg,
+         "counter_bytes": counter_bytes, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4),
+         "floor_io": {"bytes_per_pixel": io, "frac": round(io * N / sec / 1e9 / HBM_PEAK_GBS, 4)}}
+    if counter_bytes:
+        # the kernels' measured traffic as a rate (streaming efficiency) and
+        # against the method's bytes (traffic amplification)
+        r["counter_frac"] = round(counter_bytes / sec / 1e9 / HBM_PEAK_GBS, 4)
+        r["amplification"] = round(counter_bytes / alg, 3)
+    return r
 
 
 def recorded_traffic(kernel, workload):
