@@ -779,6 +779,18 @@ def measure_single(args, name, steps, warmup, kernel_timing, cpu_baseline):
         torch.cuda.synchronize()
         stages[stage] = round(a.elapsed_time(z) / reps, 4)
 
+    # Input structure that drives the time (outside the timed region): basins,
+    # plateau pixels resolved by Step II and their largest geodesic distance,
+    # minimal-plateau pixels, Step II sweeps.
+    bal, arrow = ctx.watershed_stages(grad_d, conn)
+    neg = bal < 0
+    structure = {"basins": nregions[0], "plateau_pixels": int(neg.sum()),
+                 "max_geodesic_distance": int(-bal.min()) if bool(neg.any()) else 0,
+                 "minimal_plateau_pixels": int(((bal == 2) | (bal == 3)).sum()),
+                 "step2_sweeps": stats.get("sweeps_launched"), "step2_sweeps_changing": stats.get("sweeps_changing")}
+    del bal, arrow, neg
+    torch.cuda.empty_cache()
+
     roofline = None
     kernels = {}
     if kernel_timing:
@@ -823,6 +835,7 @@ def measure_single(args, name, steps, warmup, kernel_timing, cpu_baseline):
         "stages_ms": stages,
         "step2_sweeps": stats.get("sweeps_launched"),
         "nregions": nregions,
+        "input_structure": structure,
         "kernels": kernels,
         "roofline": roofline,
         "hbm_path": path_roofline(b, NL, N, ms_step, recorded_traffic("step", name)),
@@ -924,7 +937,8 @@ def main():
         # the 4096^2 image: a smaller, partly cache-resident workload
         e = measure_single(args, "c1", max(1, args.steps // 2), 2, False, False)
         line["extra"] = {"c1": {k: e[k] for k in ("value", "ms_per_step", "step_ms", "config", "stages_ms",
-                                                  "nregions", "hbm_path", "hbm_path_ws_wf", "autotune")}}
+                                                  "nregions", "input_structure", "hbm_path", "hbm_path_ws_wf",
+                                                  "autotune")}}
     print(json.dumps(line), flush=True)
 
 
