@@ -706,7 +706,7 @@ __device__ __forceinline__ void wave_unique_union(int32_t *L, bool want, int32_t
         const int leader = __ffsll((unsigned long long)pending) - 1;
         const int32_t la = __shfl(a, leader), lb = __shfl(b, leader);
         const uint64_t same = __ballot(want && a == la && b == lb);
-        if (__lane_id() == leader) lead = true;
+        if ((int)__lane_id() == leader) lead = true;
         pending &= ~same;
     }
     if (lead && a != b) gunion(L, a, b);
