@@ -609,10 +609,15 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
         // local minimum, a minimal-plateau pixel, or an exit); the Finds below
         // reach them, halving the paths they walk (Step III inside the tile).
         // Minimal plateaux: join equal neighbours after p inside the tile.
-        if (minzone) {
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                if (!(minzone >> j & 1u)) continue;
+        // Minimal-plateau pixels are few (about 1.6 % on the volume recipe) and
+        // scattered over the thread's PER pixels: each thread walks only its
+        // own, so the wave runs as many rounds as its busiest lane has pixels
+        // (mostly one or two) instead of one round per j.
+        {
+            uint32_t mz = minzone;
+            while (mz) {
+                const int j = __ffs(mz) - 1;
+                mz &= mz - 1;
                 int i = threadIdx.x + j * NTHREADS;
                 int x = i % TS::X, y = (i / TS::X) % TS::Y, z = i / (TS::X * TS::Y);
                 int s = S::at(x, y, z);
