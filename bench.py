@@ -201,6 +201,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 4096^2 figures reported under 'extra'")
+    ap.add_argument("--no-structure", action="store_true",
+                    help="skip the input-structure figures (one extra watershed_stages call; counter runs skip it)")
     ap.add_argument("--workload", choices=("c2", "c1", "batch", "serve", "recon", "schedules"), default="c2",
                     help="c2: the 928^3 uint8 volume (default); c1: the 4096x4096 uint16 image; batch: 512 uneven "
                          "2D images, one batched call vs one call per image; serve: Poisson arrivals of mixed "
@@ -782,14 +784,17 @@ def measure_single(args, name, steps, warmup, kernel_timing, cpu_baseline):
     # Input structure that drives the time (outside the timed region): basins,
     # plateau pixels resolved by Step II and their largest geodesic distance,
     # minimal-plateau pixels, Step II sweeps.
-    bal, arrow = ctx.watershed_stages(grad_d, conn)
-    neg = bal < 0
-    structure = {"basins": nregions[0], "plateau_pixels": int(neg.sum()),
-                 "max_geodesic_distance": int(-bal.min()) if bool(neg.any()) else 0,
-                 "minimal_plateau_pixels": int(((bal == 2) | (bal == 3)).sum()),
-                 "step2_sweeps": stats.get("sweeps_launched"), "step2_sweeps_changing": stats.get("sweeps_changing")}
-    del bal, arrow, neg
-    torch.cuda.empty_cache()
+    structure = None
+    if not args.no_structure:
+        bal, arrow = ctx.watershed_stages(grad_d, conn)
+        neg = bal < 0
+        structure = {"basins": nregions[0], "plateau_pixels": int(neg.sum()),
+                     "max_geodesic_distance": int(-bal.min()) if bool(neg.any()) else 0,
+                     "minimal_plateau_pixels": int(((bal == 2) | (bal == 3)).sum()),
+                     "step2_sweeps": stats.get("sweeps_launched"),
+                     "step2_sweeps_changing": stats.get("sweeps_changing")}
+        del bal, arrow, neg
+        torch.cuda.empty_cache()
 
     roofline = None
     kernels = {}
