@@ -893,7 +893,7 @@ def cpu_baseline_single(name, cfg, img, img_d):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+        print("bench.py: the library runs on one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr, flush=True)
         sys.exit(2)
     if args.workload == "batch":
