@@ -151,3 +151,47 @@ def test_autotune_choices_match_oracle(tmp_path):
             assert np.array_equal(to_host(o), wf) and to_host(n).tolist() == wn.tolist()
     finally:
         ctx.close()
+
+
+_TILE = {2: (64, 32, 1), 12: (128, 16, 1), 22: (32, 32, 1), 32: (64, 64, 1),
+         3: (32, 8, 8), 13: (16, 16, 8), 23: (32, 16, 8), 33: (16, 16, 16)}
+
+
+def _peaks(shape_zyx, tile_xyz, shift):
+    """Grey values that fall with the L1 distance from the centre of every
+    tile-sized cell of a grid offset by `shift` (shift 0: the cells are the
+    tiles, so the lowest values lie on the tile seams)."""
+    nz, ny, nx = shape_zyx
+    tx, ty, tz = tile_xyz
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    d = np.abs((x + shift) % tx - (tx - 1) / 2.0) + np.abs((y + shift) % ty - (ty - 1) / 2.0)
+    if nz > 1:
+        d = d + np.abs((z + shift) % tz - (tz - 1) / 2.0)
+    return np.clip(np.rint(200.0 - 4.0 * d), 0, 255).astype(np.uint8)
+
+
+@pytest.mark.parametrize("shape", [2, 32, 3, 33])
+def test_tile_scale_structure(shape):
+    """Tile-scale structure: peaks at the tile centres (minimal plateaux
+    where the tiles' corners meet, arrows along the faces) and on a shifted
+    grid (valleys and exits inside and across tiles), at every tile shape's
+    own size, with both connectivities. Every crossing a tile records must
+    reach the global merge: labels equal the oracle's (Sections 3.1-3.2)."""
+    import paper_2410_08946_amd as ws
+    tx, ty, tz = _TILE[shape]
+    ndim = 3 if tz > 1 else 2
+    dims = (2 * tz + 3, 2 * ty + 1, 2 * tx + 5) if ndim == 3 else (1, 3 * ty + 1, 2 * tx + 5)
+    ctx = ws.Context(0)
+    ctx.set_option("tile3d" if ndim == 3 else "tile2d", shape)
+    try:
+        for shift in (0, 3):
+            grad = _peaks(dims, (tx, ty, tz), shift)
+            if ndim == 2:
+                grad = grad[0]
+            for conn in ((6, 26) if ndim == 3 else (4, 8)):
+                say("  shape %d shift %d conn %d %s" % (shape, shift, conn, grad.shape))
+                got = to_host(ctx.watershed(to_dev(grad), conn))
+                ref = oracle.watershed(grad, conn)
+                assert np.array_equal(got, ref), "%d labels differ" % int((got != ref).sum())
+    finally:
+        ctx.close()
