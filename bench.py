@@ -7,7 +7,7 @@ watershed (Alg. 1, 6-connectivity, int32 labels) -> waterfall, NL = 6 layers
 (layer 0 = the watershed). Default workload: the 928 x 928 x 928 (799 Mvoxel)
 synthetic volume (5000 seeded Gaussian blobs, sigma 4-32 voxels, plus
 Gaussian noise of std 2), the largest single-volume configuration, evaluated
-on the device. `--workload c1` runs the 4096 x 4096 uint16 image instead
+on the device. `--workload ellipses4096` runs the 4096 x 4096 uint16 image instead
 (blur sigma 1 + Sobel, 8-connectivity, NL = 6); by default its figures are
 also reported under "extra".
 
@@ -35,14 +35,14 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 TRAFFIC_FILES = {
-    "c1": "c1_4096x4096_u16_conn8_nl6_traffic.md",
-    "c2": "c2_928x928x928_u8_conn6_nl6_traffic.md",
+    "ellipses4096": "ellipses2d_4096x4096_u16_conn8_nl6_traffic.md",
+    "blobs928": "blobs3d_928x928x928_u8_conn6_nl6_traffic.md",
 }
 
 WORKLOAD_NAMES = {
-    "c1": ("2D 4096x4096 uint16 gradient (f32 ellipses+noise, blur sigma=1, Sobel), 8-connectivity, "
+    "ellipses4096": ("2D 4096x4096 uint16 gradient (f32 ellipses+noise, blur sigma=1, Sobel), 8-connectivity, "
            "watershed + NL=6 waterfall"),
-    "c2": ("3D 928x928x928 uint8 gradient (f32 5000 blobs + N(0,2^2), 3D Sobel), 6-connectivity, int32 labels, "
+    "blobs928": ("3D 928x928x928 uint8 gradient (f32 5000 blobs + N(0,2^2), 3D Sobel), 6-connectivity, int32 labels, "
            "watershed + NL=6 waterfall"),
 }
 
@@ -203,10 +203,12 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the 4096^2 figures reported under 'extra'")
     ap.add_argument("--no-structure", action="store_true",
                     help="skip the input-structure figures (one extra watershed_stages call; counter runs skip it)")
-    ap.add_argument("--workload", choices=("c2", "c1", "batch", "serve", "recon", "schedules"), default="c2",
-                    help="c2: the 928^3 uint8 volume (default); c1: the 4096x4096 uint16 image; batch: 512 uneven "
-                         "2D images, one batched call vs one call per image; serve: Poisson arrivals of mixed "
-                         "2D/3D jobs through the continuous-batching server; recon: the reconstruction waterfall "
+    ap.add_argument("--workload", choices=("blobs928", "ellipses4096", "batch", "serve", "recon", "schedules"),
+                    default="blobs928",
+                    help="blobs928: the 928^3 uint8 volume (default); ellipses4096: the 4096x4096 uint16 image; "
+                         "batch: 512 uneven 2D images, one batched call vs one call per image; serve: Poisson "
+                         "arrivals of mixed 2D/3D jobs through the continuous-batching server; recon: the "
+                         "reconstruction waterfall "
                          "against the graph waterfall on the three single-image workloads (differing pixels per "
                          "layer, time per layer); schedules: the watershed alone under the tile schedule and the "
                          "per-pixel synchronous schedule (APRUF / PRUF / PRW forms) on the same workloads")
@@ -226,7 +228,7 @@ def parse():
     ap.add_argument("--autotune-cache", default=None, help="autotune JSON cache (default: the user's cache dir)")
     ap.add_argument("--retune", action="store_true", help="ignore cached autotune choices")
     ap.add_argument("--volume-cache", default=None,
-                    help="c2: float32 file of the generated 928^3 volume (read if present, else written)")
+                    help="blobs928: float32 file of the generated 928^3 volume (read if present, else written)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (counter calibration)")
     return ap.parse_args()
@@ -537,11 +539,11 @@ def bench_recon(args):
         return a.elapsed_time(z) / reps
 
     results = {}
-    for name in ("c0", "c1", "c2"):
+    for name in ("blobs256", "ellipses4096", "blobs928"):
         cfg = gen.CONFIGS[name]
         shape = tuple(cfg["shape"])
         print("bench: recon %s %s" % (name, shape), file=sys.stderr, flush=True)
-        if name == "c2":
+        if name == "blobs928":
             img = gen.synth.blobs3d_device(shape, seed=cfg["seed"], device=dev)
         else:
             img = torch.from_numpy(gen.config_image(name)).to(dev)
@@ -569,12 +571,12 @@ def bench_recon(args):
         torch.cuda.empty_cache()
     line = {
         "metric": "reconstruction vs graph waterfall: differing pixels per layer",
-        "value": results["c1"]["differing_pixels"][-1],
+        "value": results["ellipses4096"]["differing_pixels"][-1],
         "unit": "pixels",
         "n_gpus": 1,
         "steps": reps,
         "warmup": 1,
-        "ms_per_step": results["c1"]["ms_recon_all_layers"],
+        "ms_per_step": results["ellipses4096"]["ms_recon_all_layers"],
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -619,10 +621,10 @@ def bench_schedules(args):
         return a.elapsed_time(z) / reps
 
     results = {}
-    for name in ("c0", "c1", "c2"):
+    for name in ("blobs256", "ellipses4096", "blobs928"):
         cfg = gen.CONFIGS[name]
         shape = tuple(cfg["shape"])
-        if name == "c2":
+        if name == "blobs928":
             img = gen.synth.blobs3d_device(shape, seed=cfg["seed"], device=dev)
         else:
             img = torch.from_numpy(gen.config_image(name)).to(dev)
@@ -653,15 +655,15 @@ def bench_schedules(args):
         results[name] = {"pixels": N, "conn": conn, "variants": per}
         del grad, ref, lab
         torch.cuda.empty_cache()
-    c1 = results["c1"]["variants"]
+    e2d = results["ellipses4096"]["variants"]
     line = {
         "metric": "watershed Mvoxel/s by schedule",
-        "value": c1["tile_apruf"]["mvoxel_s"],
+        "value": e2d["tile_apruf"]["mvoxel_s"],
         "unit": "Mvoxel/s",
         "n_gpus": 1,
         "steps": reps,
         "warmup": 1,
-        "ms_per_step": c1["tile_apruf"]["ms"],
+        "ms_per_step": e2d["tile_apruf"]["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -677,7 +679,7 @@ def bench_schedules(args):
 
 
 def measure_single(args, name, steps, warmup, kernel_timing, cpu_baseline):
-    """Times `steps` whole steps of workload `name` (c1 / c2) with the input
+    """Times `steps` whole steps of workload `name` (ellipses4096 / blobs928) with the input
     resident in HBM and returns the fields of its JSON line."""
     import numpy as np
     import torch
@@ -692,7 +694,7 @@ def measure_single(args, name, steps, warmup, kernel_timing, cpu_baseline):
     b = 2 if gdt == "u16" else 1
     dev = torch.device("cuda:0")
     img = None
-    if name == "c2":
+    if name == "blobs928":
         # too large for the host generator: the same recipe evaluated on the
         # device (or read back from a file an earlier run of this recipe wrote)
         img_d = None
@@ -863,7 +865,7 @@ def cpu_baseline_single(name, cfg, img, img_d):
     float planes copied to the host; about 20 s of CPU work)."""
     import oracle
     sigma, conn, NL, gdt = cfg["sigma"], cfg["conn"], cfg["NL"], cfg["dtype"]
-    if name == "c2":
+    if name == "blobs928":
         z0, z1 = 452, 476
         sample = img_d[z0:z1].cpu().numpy()
         what = "planes %d..%d of the 928^3 volume (928x928x%d = %d voxels)" % (z0, z1 - 1, z1 - z0, sample.size)
@@ -938,10 +940,10 @@ def main():
     line.update({k: v for k, v in r.items() if k not in ("value", "ms_per_step", "dtype")})
     line["copy_bandwidth_gbs"] = copy_bandwidth(dev)
     line["host"] = host_info()
-    if name == "c2" and not args.no_extra:
+    if name == "blobs928" and not args.no_extra:
         # the 4096^2 image: a smaller, partly cache-resident workload
-        e = measure_single(args, "c1", max(1, args.steps // 2), 2, False, False)
-        line["extra"] = {"c1": {k: e[k] for k in ("value", "ms_per_step", "step_ms", "config", "stages_ms",
+        e = measure_single(args, "ellipses4096", max(1, args.steps // 2), 2, False, False)
+        line["extra"] = {"ellipses4096": {k: e[k] for k in ("value", "ms_per_step", "step_ms", "config", "stages_ms",
                                                   "nregions", "input_structure", "hbm_path", "hbm_path_ws_wf",
                                                   "autotune")}}
     print(json.dumps(line), flush=True)

@@ -23,11 +23,11 @@ import numpy as np
 # the gradient pre-processing (0 = none), `dtype` the quantised gradient type.
 CONFIGS = {
     # 256x256 u8, 32 blobs + 1 % salt, Sobel only, 4-conn, NL = 3.
-    "c0": dict(kind="blobs2d", shape=(256, 256), seed=0, sigma=0.0, dtype="u8", conn=4, NL=3),
+    "blobs256": dict(kind="blobs2d", shape=(256, 256), seed=0, sigma=0.0, dtype="u8", conn=4, NL=3),
     # 4096x4096 u16, 2000 ellipses + N(0, 500^2), blur sigma 1 + Sobel, 8-conn, NL = 6.
-    "c1": dict(kind="ellipses2d", shape=(4096, 4096), seed=1, sigma=1.0, dtype="u16", conn=8, NL=6),
+    "ellipses4096": dict(kind="ellipses2d", shape=(4096, 4096), seed=1, sigma=1.0, dtype="u16", conn=8, NL=6),
     # 928^3 u8, 5000 blobs + N(0, 2^2), 3D Sobel, 6-conn, NL = 6.
-    "c2": dict(kind="blobs3d", shape=(928, 928, 928), seed=2, sigma=0.0, dtype="u8", conn=6, NL=6),
+    "blobs928": dict(kind="blobs3d", shape=(928, 928, 928), seed=2, sigma=0.0, dtype="u8", conn=6, NL=6),
 }
 
 
@@ -134,7 +134,7 @@ def blobs3d(nz: int, ny: int, nx: int, seed=2, n_blobs: int = 5000, sigma=(4.0, 
 
 
 def config_image(name: str) -> np.ndarray:
-    """The float image of a named workload (c0, c1; c2 is too large for numpy here)."""
+    """The float image of a named workload (blobs256, ellipses4096; blobs928 is too large for numpy here)."""
     c = CONFIGS[name]
     if c["kind"] == "blobs2d":
         return blobs2d(*c["shape"], seed=c["seed"])

@@ -50,25 +50,25 @@ def say(*a):
 
 
 @pytest.fixture(scope="module")
-def c2():
+def blobs928():
     import torch
 
     import paper_2410_08946_amd as ws
 
-    cfg = gen.CONFIGS["c2"]
+    cfg = gen.CONFIGS["blobs928"]
     shape = tuple(cfg["shape"])
-    say("c2: generating", shape)
+    say("blobs928: generating", shape)
     img = gen.synth.blobs3d_device(shape, seed=cfg["seed"], device="cuda:0")
     ctx = ws.Context(0)
-    say("c2: gradient")
+    say("blobs928: gradient")
     mag = torch.empty(shape, dtype=torch.float32, device="cuda:0")
     grad = ctx.gradient(img, 0.0, "u8", mag=mag)
-    say("c2: watershed")
+    say("blobs928: watershed")
     lab = ctx.watershed(grad, cfg["conn"])
-    say("c2: waterfall NL", cfg["NL"])
+    say("blobs928: waterfall NL", cfg["NL"])
     out, nreg = ctx.waterfall(lab, grad, cfg["conn"], cfg["NL"])
     torch.cuda.synchronize()
-    say("c2: regions per layer", nreg.cpu().tolist())
+    say("blobs928: regions per layer", nreg.cpu().tolist())
     yield dict(img=img, mag=mag, grad=grad, lab=lab, out=out, nreg=nreg.cpu().tolist(), shape=shape)
     ctx.close()
 
@@ -98,9 +98,9 @@ def _sobel64(img, z0, z1):
     return torch.sqrt(gx * gx + gy * gy + gz * gz)
 
 
-def test_c2_gradient(c2):
+def test_blobs928_gradient(blobs928):
     import torch
-    img, grad = c2["img"], c2["grad"]
+    img, grad = blobs928["img"], blobs928["grad"]
     nz = img.shape[0]
     mx = 0.0
     for z0 in range(0, nz, SLAB):
@@ -118,7 +118,7 @@ def test_c2_gradient(c2):
         bad += int(((d > 1) | ((d == 1) & ~near)).sum())
     assert bad == 0, "%d gradient bytes differ beyond the rounding allowance" % bad
     # the kernel's own rule, exactly: rint(fp32(mag * 255) / max(mag)) in float32
-    mag = c2["mag"]
+    mag = blobs928["mag"]
     mx32 = np.float32(float(mag.max()))
     off = 0
     for z0 in range(0, nz, SLAB):
@@ -142,10 +142,10 @@ def _canonical(lab_flat, n, chunk=1 << 26):
     return True
 
 
-def test_c2_watershed(c2):
+def test_blobs928_watershed(blobs928):
     import torch
-    lab, grad = c2["lab"], c2["grad"]
-    nz, ny, nx = c2["shape"]
+    lab, grad = blobs928["lab"], blobs928["grad"]
+    nz, ny, nx = blobs928["shape"]
     n = nz * ny * nx
     flat = lab.reshape(-1)
     assert _canonical(flat, n)
@@ -179,12 +179,12 @@ def test_c2_watershed(c2):
     assert bad == 0, "%d slope voxels do not share the label of their Eq. (1) target" % bad
 
 
-def test_c2_waterfall(c2):
+def test_blobs928_waterfall(blobs928):
     import torch
-    out, nreg = c2["out"], c2["nreg"]
-    nz, ny, nx = c2["shape"]
+    out, nreg = blobs928["out"], blobs928["nreg"]
+    nz, ny, nx = blobs928["shape"]
     n = nz * ny * nx
-    assert torch.equal(out[0], c2["lab"])
+    assert torch.equal(out[0], blobs928["lab"])
     for k in range(out.shape[0]):
         flat = out[k].reshape(-1)
         assert _canonical(flat, n), "layer %d not canonical" % k
@@ -202,12 +202,12 @@ def test_c2_waterfall(c2):
                 assert nreg[k] <= nreg[k - 1] // 2
 
 
-def test_c2_step2_fixpoint(c2):
+def test_blobs928_step2_fixpoint(blobs928):
     """Step II converged: the local fixpoint conditions on the balanced states."""
     import torch
     import paper_2410_08946_amd as ws
-    grad = c2["grad"]
-    nz, ny, nx = c2["shape"]
+    grad = blobs928["grad"]
+    nz, ny, nx = blobs928["shape"]
     ctx = ws.Context(0)
     try:
         bal, _ = ctx.watershed_stages(grad, 6)
@@ -269,7 +269,7 @@ def _compare_with_oracle(grad, out, nreg, conn, tag):
         del lay, got
 
 
-def test_c2_slab_oracle(c2):
+def test_blobs928_slab_oracle(blobs928):
     """A 32-plane slab of the full volume's gradient (same recipe, same
     bytes): watershed and NL = 6 layers equal the oracle's element by
     element."""
@@ -277,13 +277,13 @@ def test_c2_slab_oracle(c2):
 
     import paper_2410_08946_amd as ws
     z0, z1 = 448, 480
-    sub = c2["grad"][z0:z1].contiguous()
+    sub = blobs928["grad"][z0:z1].contiguous()
     ctx = ws.Context(0)
     try:
         lab = ctx.watershed(sub, 6)
-        out, nreg = ctx.waterfall(lab, sub, 6, gen.CONFIGS["c2"]["NL"])
+        out, nreg = ctx.waterfall(lab, sub, 6, gen.CONFIGS["blobs928"]["NL"])
         torch.cuda.synchronize()
-        _compare_with_oracle(sub, out, nreg.cpu().tolist(), 6, "c2 slab %d:%d" % (z0, z1))
+        _compare_with_oracle(sub, out, nreg.cpu().tolist(), 6, "blobs928 slab %d:%d" % (z0, z1))
     finally:
         ctx.close()
 
@@ -291,11 +291,12 @@ def test_c2_slab_oracle(c2):
 @pytest.mark.skipif(os.environ.get("WS_FULLSIZE_ORACLE") != "1",
                     reason="the full 928^3 oracle comparison takes about four minutes of host time "
                            "(set WS_FULLSIZE_ORACLE=1)")
-def test_c2_full_oracle(c2):
+def test_blobs928_full_oracle(blobs928):
     """The whole 928^3 volume: labels of the watershed and of all six layers,
     as the benchmark computes them, equal the oracle's element by element."""
     oracle.set_progress(True)
     try:
-        _compare_with_oracle(c2["grad"], c2["out"], c2["nreg"], gen.CONFIGS["c2"]["conn"], "c2 full")
+        _compare_with_oracle(blobs928["grad"], blobs928["out"], blobs928["nreg"], gen.CONFIGS["blobs928"]["conn"],
+                             "blobs928 full")
     finally:
         oracle.set_progress(False)

@@ -302,10 +302,10 @@ def test_c1_full_size(ctx):
     compared in full with the oracle, in the launch configuration of the
     benchmark."""
     import torch
-    img = gen.config_image("c1")
+    img = gen.config_image("ellipses4096")
     q = _check_gradient(ctx, img, 1.0, "u16")
     grad = oracle.gradient(img, 1.0, "u16")
-    say("  c1 watershed + waterfall")
+    say("  ellipses4096 watershed + waterfall")
     g = to_dev(grad)
     lab = ctx.watershed(g, 8)
     out, nreg = ctx.waterfall(lab, g, 8, 6)
