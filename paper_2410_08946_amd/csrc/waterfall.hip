@@ -91,15 +91,15 @@ __device__ __forceinline__ uint32_t mix24(uint32_t a, uint32_t b) {
 __device__ __forceinline__ bool edge_insert(unsigned long long *ek, unsigned int *ew, uint64_t pair, uint32_t w) {
     uint32_t h = mix24((uint32_t)(pair >> 32), (uint32_t)pair) & (ESLOTS - 1);
     // the first probe outside the loop: most inserts find their pair (or an
-    // empty slot) at once, and then run no loop code at all
-    unsigned long long cur = ek[h];
-    if (cur == NOPAIR) cur = atomicCAS(&ek[h], (unsigned long long)NOPAIR, (unsigned long long)pair);
+    // empty slot) at once, and then run no loop code at all. Each probe is a
+    // single compare-and-swap (it writes only into an empty slot): one LDS
+    // round trip whether the slot is empty or holds the pair
+    unsigned long long cur = atomicCAS(&ek[h], (unsigned long long)NOPAIR, (unsigned long long)pair);
     if (cur != NOPAIR && cur != pair) {
         bool found = false;
         for (int probe = 1; probe < MAXPROBE; ++probe) {
             h = (h + 1) & (ESLOTS - 1);
-            cur = ek[h];
-            if (cur == NOPAIR) cur = atomicCAS(&ek[h], (unsigned long long)NOPAIR, (unsigned long long)pair);
+            cur = atomicCAS(&ek[h], (unsigned long long)NOPAIR, (unsigned long long)pair);
             if (cur == NOPAIR || cur == pair) {
                 found = true;
                 break;
@@ -114,15 +114,14 @@ __device__ __forceinline__ bool edge_insert(unsigned long long *ek, unsigned int
 template <int BITS>
 __device__ __forceinline__ bool region_insert(int *hk, unsigned long long *hv, int l, uint64_t v) {
     uint32_t h = mix24((uint32_t)l, (uint32_t)l >> 16) & ((1 << BITS) - 1);
-    // first probe peeled, as in edge_insert
-    int cur = hk[h];
-    if (cur == -1) cur = atomicCAS(&hk[h], -1, l);
+    // first probe peeled and every probe one compare-and-swap, as in
+    // edge_insert
+    int cur = atomicCAS(&hk[h], -1, l);
     if (cur != -1 && cur != l) {
         bool found = false;
         for (int probe = 1; probe < MAXPROBE; ++probe) {
             h = (h + 1) & ((1 << BITS) - 1);
-            cur = hk[h];
-            if (cur == -1) cur = atomicCAS(&hk[h], -1, l);
+            cur = atomicCAS(&hk[h], -1, l);
             if (cur == -1 || cur == l) {
                 found = true;
                 break;
