@@ -97,6 +97,9 @@ __device__ __forceinline__ bool edge_insert(unsigned long long *ek, unsigned int
     unsigned long long cur = atomicCAS(&ek[h], (unsigned long long)NOPAIR, (unsigned long long)pair);
     if (cur != NOPAIR && cur != pair) {
         bool found = false;
+        // kept rolled: the loop is cold, and unrolled copies at every call
+        // site would spread the hot code over far more instruction cache
+#pragma unroll 1
         for (int probe = 1; probe < MAXPROBE; ++probe) {
             h = (h + 1) & (ESLOTS - 1);
             cur = atomicCAS(&ek[h], (unsigned long long)NOPAIR, (unsigned long long)pair);
@@ -119,6 +122,7 @@ __device__ __forceinline__ bool region_insert(int *hk, unsigned long long *hv, i
     int cur = atomicCAS(&hk[h], -1, l);
     if (cur != -1 && cur != l) {
         bool found = false;
+#pragma unroll 1
         for (int probe = 1; probe < MAXPROBE; ++probe) {
             h = (h + 1) & ((1 << BITS) - 1);
             cur = atomicCAS(&hk[h], -1, l);
