@@ -179,6 +179,33 @@ def test_waterfall_random(ctx, shape, conn):
     check_wf(ctx, np.full(shape, 4, np.uint8), conn, 3)
 
 
+def test_waterfall_hash_overflow(ctx):
+    """Inputs whose waterfall tiles hold more distinct region pairs and
+    regions than the pixel pass's LDS hashes have slots, so that inserts fall
+    back to direct slab entries and global keys (Alg. 4 Step V: the lowest
+    pass value per pair of adjacent regions must not depend on where a pair
+    was recorded; the level passes use the same fallback). A checkerboard of
+    zeros and random heights makes every other voxel a minimum: its 16 x 8 x 8
+    waterfall tiles hold up to 2560 distinct pairs (1024 edge slots) and 748
+    regions (512 region slots), and a 2D one's 64 x 16 tiles up to 1536 pairs
+    and 585 regions (counted on the oracle's layer 0); the random heights keep
+    hundreds of regions in the later layers. Sizes span several tiles with a
+    ragged tail; the batched call takes the same path."""
+    import torch
+    rng = np.random.default_rng(11)
+    zz, yy, xx = np.mgrid[0:20, 0:19, 0:37]
+    cb3 = np.where((xx + yy + zz) % 2 == 0, 0, rng.integers(1, 256, xx.shape)).astype(np.uint8)
+    yy, xx = np.mgrid[0:37, 0:150]
+    cb2 = np.where((xx + yy) % 2 == 0, 0, rng.integers(1, 65536, xx.shape)).astype(np.uint16)
+    check_wf(ctx, cb3, 6, 5)
+    check_wf(ctx, cb2, 4, 5)
+    outs, nreg = ctx.batch([to_dev(cb3), to_dev(cb3[:9])], [6, 6], 4)
+    torch.cuda.synchronize()
+    for grad, o, n in zip((cb3, cb3[:9]), outs, nreg):
+        wf, wn = oracle.waterfall_g1(oracle.watershed(grad, 6), grad, 6, 4)
+        assert np.array_equal(to_host(o), wf) and to_host(n).tolist() == wn.tolist()
+
+
 def test_schedule_invariance(ctx):
     img = gen.blobs2d(300, 280, seed=5)
     grad = oracle.gradient(img, 0.0, "u8")
@@ -297,7 +324,7 @@ def test_argument_errors(ctx):
     check_ws(ctx, gen.serpentine(70, 150), 4)
 
 
-def test_c1_full_size(ctx):
+def test_ellipses4096_full_size(ctx):
     """4096 x 4096 u16, blur sigma 1 + Sobel, 8-conn, NL = 6: every stage
     compared in full with the oracle, in the launch configuration of the
     benchmark."""
