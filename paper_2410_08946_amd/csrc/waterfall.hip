@@ -90,26 +90,25 @@ __device__ __forceinline__ uint32_t mix24(uint32_t a, uint32_t b) {
 
 __device__ __forceinline__ bool edge_insert(unsigned long long *ek, unsigned int *ew, uint64_t pair, uint32_t w) {
     uint32_t h = mix24((uint32_t)(pair >> 32), (uint32_t)pair) & (ESLOTS - 1);
-    // the first probe outside the loop: most inserts find their pair (or an
-    // empty slot) at once, and then run no loop code at all. Each probe is a
-    // single compare-and-swap (it writes only into an empty slot): one LDS
-    // round trip whether the slot is empty or holds the pair
+    // Each probe is a single compare-and-swap (it writes only into an empty
+    // slot): one LDS round trip whether the slot is empty or holds the pair.
+    // Most inserts succeed at the first probe. The probe loop has a single
+    // exit condition and stays rolled: a wave runs it whenever one of its
+    // lanes missed, and its exec-mask bookkeeping is scalar work per
+    // iteration (a loop with a separate found flag and break cost several
+    // times more), while unrolled copies at every call site would spread the
+    // hot code over far more instruction cache.
     unsigned long long cur = atomicCAS(&ek[h], (unsigned long long)NOPAIR, (unsigned long long)pair);
-    if (cur != NOPAIR && cur != pair) {
-        bool found = false;
-        // kept rolled: the loop is cold, and unrolled copies at every call
-        // site would spread the hot code over far more instruction cache
+    bool miss = (cur != NOPAIR) & (cur != pair);  // one predicate, no short-circuit branches
+    int probe = 1;
 #pragma unroll 1
-        for (int probe = 1; probe < MAXPROBE; ++probe) {
-            h = (h + 1) & (ESLOTS - 1);
-            cur = atomicCAS(&ek[h], (unsigned long long)NOPAIR, (unsigned long long)pair);
-            if (cur == NOPAIR || cur == pair) {
-                found = true;
-                break;
-            }
-        }
-        if (!found) return false;
+    while (miss & (probe < MAXPROBE)) {
+        h = (h + 1) & (ESLOTS - 1);
+        cur = atomicCAS(&ek[h], (unsigned long long)NOPAIR, (unsigned long long)pair);
+        miss = (cur != NOPAIR) & (cur != pair);
+        ++probe;
     }
+    if (miss) return false;
     atomicMin(&ew[h], w);
     return true;
 }
@@ -117,22 +116,18 @@ __device__ __forceinline__ bool edge_insert(unsigned long long *ek, unsigned int
 template <int BITS>
 __device__ __forceinline__ bool region_insert(int *hk, unsigned long long *hv, int l, uint64_t v) {
     uint32_t h = mix24((uint32_t)l, (uint32_t)l >> 16) & ((1 << BITS) - 1);
-    // first probe peeled and every probe one compare-and-swap, as in
-    // edge_insert
+    // probes as in edge_insert
     int cur = atomicCAS(&hk[h], -1, l);
-    if (cur != -1 && cur != l) {
-        bool found = false;
+    bool miss = (cur != -1) & (cur != l);
+    int probe = 1;
 #pragma unroll 1
-        for (int probe = 1; probe < MAXPROBE; ++probe) {
-            h = (h + 1) & ((1 << BITS) - 1);
-            cur = atomicCAS(&hk[h], -1, l);
-            if (cur == -1 || cur == l) {
-                found = true;
-                break;
-            }
-        }
-        if (!found) return false;
+    while (miss & (probe < MAXPROBE)) {
+        h = (h + 1) & ((1 << BITS) - 1);
+        cur = atomicCAS(&hk[h], -1, l);
+        miss = (cur != -1) & (cur != l);
+        ++probe;
     }
+    if (miss) return false;
     atomicMin(&hv[h], (unsigned long long)v);
     return true;
 }
