@@ -651,15 +651,20 @@ __global__ __launch_bounds__(NTHREADS) void k_ws_label(Src src, int32_t ntiles, 
             for (int j = 0; j < PER; ++j) px[j] = sP[root[j]];
 #pragma unroll
             for (int j = 0; j < PER; ++j) ppx[j] = sP[px[j]];
+            // Branch-free (per-path branches cost scalar exec-mask work): a
+            // finished path has px == root and ppx == px (a root's entry
+            // never changes here, every union is done), so every path moves
+            // to ppx, and the halving store may be unconditional: where
+            // ppx == px it writes back the parent read (or, if another lane
+            // halved that entry meanwhile, an ancestor of it: still valid).
+            uint32_t nl = 0;
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
-                if (px[j] == root[j]) {
-                    live &= ~(1u << j);
-                } else {
-                    if (ppx[j] != px[j]) sP[root[j]] = ppx[j];
-                    root[j] = ppx[j];
-                }
+                nl |= (px[j] != root[j] ? 1u : 0u) << j;
+                sP[root[j]] = ppx[j];
+                root[j] = ppx[j];
             }
+            live = nl;
         }
         __syncthreads();
         int *cm = sP;
