@@ -512,6 +512,17 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_level(int32_t ntiles, int32_t g
     __syncthreads();
     const int32_t total = stotal;
     const size_t base = (size_t)t0 * (size_t)cap;
+    // Up to four subgroups (the merge factor the host uses): an edge's
+    // subgroup is the number of later subgroup starts at or below it (the
+    // offsets are non-decreasing), from three offsets read once, without a
+    // search loop per edge
+    const bool few = f <= 4;
+    int o1 = 0x7fffffff, o2 = 0x7fffffff, o3 = 0x7fffffff;
+    if (few) {
+        if (nsub > 1) o1 = soff[1];
+        if (nsub > 2) o2 = soff[2];
+        if (nsub > 3) o3 = soff[3];
+    }
     // LEV_U edges per thread per batch: all their loads, then all their parent
     // gathers, are issued before the first wait (two round trips per batch)
     constexpr int LEV_U = 8;
@@ -524,13 +535,19 @@ __global__ __launch_bounds__(NTHREADS) void k_wf_level(int32_t ntiles, int32_t g
             int32_t e = e0 + u * NTHREADS + (int)threadIdx.x;
             at[u] = 0;
             if (e < total) {
-                int lo = 0, hi = nsub - 1;
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (soff[mid] <= e) lo = mid;
-                    else hi = mid - 1;
+                if (few) {
+                    const int lo = (o1 <= e ? 1 : 0) + (o2 <= e ? 1 : 0) + (o3 <= e ? 1 : 0);
+                    const int so = lo == 0 ? 0 : lo == 1 ? o1 : lo == 2 ? o2 : o3;  // soff[0] == 0
+                    at[u] = (size_t)(t0 + lo * gin) * (size_t)cap + (size_t)(e - so);
+                } else {
+                    int lo = 0, hi = nsub - 1;
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (soff[mid] <= e) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    at[u] = (size_t)(t0 + lo * gin) * (size_t)cap + (size_t)(e - soff[lo]);
                 }
-                at[u] = (size_t)(t0 + lo * gin) * (size_t)cap + (size_t)(e - soff[lo]);
             }
         }
         // branch-free: lanes past the end read slab entry 0 (allocated, any
